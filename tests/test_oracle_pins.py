@@ -1,0 +1,404 @@
+"""Pins of the FP64 oracle against facts the paper and the mathematics fix.
+
+None of these retypes an oracle formula: each compares the oracle with an
+independent closed form, an invariant, a library routine on a special case,
+or brute force on a tiny problem, so that a dropped term, a wrong sign or
+index, or a transposed operand in the oracle fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special
+
+from oracle import laguerre, operator, precond, krylov, harmonics, elastic
+from oracle import OK, NOT_CONVERGED, BREAKDOWN, NONFINITE
+from paper_1005_0542_amd import inputs
+
+
+# ---------------------------------------------------------------------------
+# Laguerre functions (Sec. 2.1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("alpha", [2, 8, 9])
+def test_laguerre_functions_orthonormal(alpha):
+    """int_0^inf l_m(ht) l_k(ht) dt = delta_mk  <=>  sum_q w_q e^{x_q} psi_m psi_k = delta
+    by Gauss-Laguerre quadrature for the weight x^alpha e^{-x} (exact for the
+    polynomial degrees involved)."""
+    n = 48
+    xq, wq = scipy.special.roots_genlaguerre(60, alpha)
+    ps = laguerre.psi(n, xq, alpha)                      # [n, q]
+    G = (ps * (wq * np.exp(xq))[None, :]) @ ps.T
+    assert np.max(np.abs(G - np.eye(n))) < 1e-12
+
+
+def test_laguerre_psi_low_orders_closed_form():
+    """psi_m for m = 0, 1, 2 against the explicit Laguerre polynomials."""
+    a = 9
+    x = np.linspace(0.0, 40.0, 17)
+    ps = laguerre.psi(3, x, a)
+    L = [np.ones_like(x), 1 + a - x, 0.5 * (x ** 2 - 2 * (a + 2) * x + (a + 1) * (a + 2))]
+    for m in range(3):
+        nm = math.sqrt(math.factorial(m) / math.factorial(m + a))
+        ref = nm * np.exp(-x / 2) * L[m]
+        assert np.allclose(ps[m], ref, rtol=1e-13, atol=1e-300)
+
+
+def _closed_form_coeffs(h, alpha, beta, n):
+    """Transform of g(t) = (ht)^alpha e^{-beta t}:
+    g_m = h^{-1/2} sqrt((m+alpha)!/m!) (s-1)^m / s^{m+alpha+1},  s = beta/h + 1/2,
+    from int_0^inf x^a e^{-sx} L_m^a(x) dx = Gamma(m+a+1) (s-1)^m / (m! s^{m+a+1})."""
+    s = beta / h + 0.5
+    m = np.arange(n)
+    lg = np.array([0.5 * (math.lgamma(k + alpha + 1) - math.lgamma(k + 1)) for k in m])
+    return h ** -0.5 * np.exp(lg) * (s - 1.0) ** m / s ** (m + alpha + 1)
+
+
+def test_source_coeffs_match_closed_form():
+    h, alpha, beta, n = 200.0, 9, 50.0, 80
+    g = lambda t: (h * np.asarray(t)) ** alpha * np.exp(-beta * np.asarray(t))
+    got = laguerre.source_coeffs(g, 2.5, h, alpha, n)
+    ref = _closed_form_coeffs(h, alpha, beta, n)
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_synthesis_reconstructs_closed_form():
+    """sum_m W_m(t) g_m = g(t) (geometric convergence, ratio |s-1|/s = 1/3)."""
+    h, alpha, beta, n = 200.0, 9, 50.0, 120
+    coef = _closed_form_coeffs(h, alpha, beta, n)
+    t = np.array([0.0, 0.01, 0.05, 0.18, 0.4, 1.0])
+    W = laguerre.synthesis_weights(t, h, alpha, n)
+    g = (h * t) ** alpha * np.exp(-beta * t)
+    assert np.max(np.abs(W @ coef - g)) < 1e-12 * np.max(np.abs(g))
+
+
+def test_synthesis_weights_large_ht_no_underflow():
+    """At h t = 1200 (h=600, t=2 s) the weights stay finite and obey the
+    Cauchy-Schwarz bound of orthonormal functions (|x^{a/2} psi_m| <= ~1)."""
+    h, alpha, n = 600.0, 9, 1024
+    W = laguerre.synthesis_weights(np.array([2.0]), h, alpha, n)[0]
+    assert np.all(np.isfinite(W))
+    x = h * 2.0
+    bound = math.sqrt(h) * x ** (alpha / 2.0)          # |psi_m| x^{a/2} <= 1-ish
+    assert np.max(np.abs(W)) < 2.0 * bound
+    assert np.max(np.abs(W)) > 1e-3 * bound             # not all underflowed
+
+
+# ---------------------------------------------------------------------------
+# Right-hand-side recurrence (eq. laguerre_h)
+# ---------------------------------------------------------------------------
+
+def test_recurrence_scalar_ode_closed_form():
+    """u'' + w^2 u = g with u = (ht)^a e^{-bt}: the oracle's recurrence with
+    A = w^2 (rho = 1, no source position) reproduces u's closed-form
+    coefficients from quadrature coefficients of g.  Pins h^2/4, the
+    (m-k) n_m/n_k weights and the sign of the history term."""
+    h, a, b, om2, n = 200.0, 9, 50.0, 3000.0, 60
+
+    def u(t):
+        t = np.asarray(t); return (h * t) ** a * np.exp(-b * t)
+
+    def g(t):
+        t = np.asarray(t)
+        upp = (a * (a - 1) * h * h * (h * t) ** (a - 2) - 2 * a * b * h * (h * t) ** (a - 1)
+               + b * b * (h * t) ** a) * np.exp(-b * t)
+        return upp + om2 * u(t)
+
+    gm = laguerre.source_coeffs(g, 3.0, h, a, n)
+    Rref = _closed_form_coeffs(h, a, b, n)
+    rho = np.ones((1, 1))
+    for direct in (True, False):
+        R = []
+        sums = harmonics.RunningSums((1, 1), a)
+        for m in range(n):
+            src = np.full((1, 1), gm[m])
+            if direct:
+                phi = harmonics.rhs_direct(m, R, rho, h, a, src)
+            else:
+                phi = harmonics.rhs_running(m, sums, R[m - 1] if m else None, rho, h, src)
+            R.append(phi / (h * h / 4.0 + om2))
+        R = np.array([r[0, 0] for r in R])
+        assert np.max(np.abs(R - Rref)) < 1e-11 * np.max(np.abs(Rref))
+
+
+def test_running_sums_equal_direct_double_sum():
+    rng = np.random.default_rng(0)
+    a, h, n = 9, 400.0, 40
+    rho = rng.uniform(0.5, 2.0, (5, 7))
+    Rs = [rng.standard_normal((5, 7)) for _ in range(n)]
+    sums = harmonics.RunningSums((5, 7), a)
+    for m in range(n):
+        src = rng.standard_normal((5, 7))
+        d = harmonics.rhs_direct(m, Rs, rho, h, a, src)
+        r = harmonics.rhs_running(m, sums, Rs[m - 1] if m else None, rho, h, src)
+        assert np.max(np.abs(d - r)) <= 1e-13 * max(1.0, np.max(np.abs(d)))
+
+
+# ---------------------------------------------------------------------------
+# Operator A (Sec. 2.3)
+# ---------------------------------------------------------------------------
+
+def _small_medium(nx, nz, seed=5):
+    rng = np.random.default_rng(seed)
+    kappa = rng.uniform(0.5, 2.0, (nz + 1, nx + 1))
+    rho = rng.uniform(1e-7, 5e-7, (nz + 1, nx + 1))
+    return kappa, rho
+
+
+def test_operator_matches_dense_assembly_and_is_symmetric():
+    nx, nz, dx, dz, h = 12, 16, 7.0, 5.0, 300.0      # non-square catches transposes
+    kappa, rho = _small_medium(nx, nz)
+    w = operator.shift_coeff(rho, h)
+    M = operator.assemble_A(kappa, w, dx, dz)
+    y = np.random.default_rng(1).standard_normal((nz - 1, nx - 1))
+    got = operator.apply_A(y, kappa, w, dx, dz)
+    assert np.max(np.abs(got.ravel() - M @ y.ravel())) < 1e-13 * np.max(np.abs(got))
+    assert np.max(np.abs(M - M.T)) == 0.0
+    assert np.min(np.linalg.eigvalsh(M)) > 0.0
+
+
+def test_operator_exact_on_separable_quadratics():
+    """With constant kappa, y = x(Lx-x) z(Lz-z) vanishes on the boundary and the
+    3-point second difference is exact on quadratics:
+    A y = kappa (2 z(Lz-z) + 2 x(Lx-x)) + w y."""
+    nx, nz, dx, dz = 10, 14, 3.0, 2.0
+    kap = 1.7
+    kappa = np.full((nz + 1, nx + 1), kap)
+    w = np.full((nz - 1, nx - 1), 0.25)
+    x = dx * np.arange(1, nx)[None, :]
+    z = dz * np.arange(1, nz)[:, None]
+    Lx, Lz = nx * dx, nz * dz
+    y = x * (Lx - x) * z * (Lz - z)
+    ref = kap * (2 * z * (Lz - z) + 2 * x * (Lx - x)) + w * y
+    got = operator.apply_A(y, kappa, w, dx, dz)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# DST-I and the Laplace preconditioner (Sec. 2.4)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nx", [8, 16, 64])
+def test_dst1_involution_and_eigenvectors(nx):
+    S = precond.sine_matrix(nx)
+    assert np.max(np.abs(S @ S - (nx / 2.0) * np.eye(nx - 1))) < 1e-13 * nx
+    T = -2 * np.eye(nx - 1) + np.eye(nx - 1, k=1) + np.eye(nx - 1, k=-1)
+    lam = -4 * np.sin(np.pi * np.arange(1, nx) / (2 * nx)) ** 2
+    assert np.max(np.abs(T @ S - S * lam[None, :])) < 1e-13 * nx
+
+
+@pytest.mark.parametrize("nx", [16, 128, 256])
+def test_dst1_direct_equals_library_fft(nx):
+    x = np.random.default_rng(nx).standard_normal((3, nx - 1))
+    a = precond.dst1_direct(x, nx)
+    b = precond.dst1_fft(x, nx)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(a)) * math.log2(nx)
+
+
+def test_thomas_matches_dense_solve():
+    rng = np.random.default_rng(3)
+    n, k = 37, 5
+    lower = rng.uniform(-1, 1, (n, k)); upper = rng.uniform(-1, 1, (n, k))
+    diag = np.abs(lower) + np.abs(upper) + rng.uniform(0.1, 1.0, (n, k))
+    rhs = rng.standard_normal((n, k))
+    x = precond.thomas(lower, diag, upper, rhs)
+    for c in range(k):
+        M = np.diag(diag[:, c]) + np.diag(lower[1:, c], -1) + np.diag(upper[:-1, c], 1)
+        assert np.max(np.abs(M @ x[:, c] - rhs[:, c])) < 1e-13 * np.max(np.abs(rhs))
+
+
+def test_thomas_toeplitz_inverse_closed_form():
+    """tridiag(-1, theta, -1)^{-1}_{ij} = (t^|i-j| - t^(i+j) - t^(2L-i-j) + t^(2L-|i-j|))
+    / ((1/t - t)(1 - t^(2L))) with t the root < 1 of t^2 - theta t + 1 (1-based i, j;
+    L = n+1)."""
+    n, theta = 9, 2.3
+    t = 0.5 * (theta - math.sqrt(theta * theta - 4))
+    Lb = n + 1
+    i = np.arange(1, n + 1)[:, None]; j = np.arange(1, n + 1)[None, :]
+    inv = (t ** abs(i - j) - t ** (i + j) - t ** (2 * Lb - i - j) + t ** (2 * Lb - abs(i - j))) \
+        / ((1 / t - t) * (1 - t ** (2 * Lb)))
+    eye = np.eye(n)
+    got = precond.thomas(np.full((n, 1), -1.0), np.full((n, 1), theta), np.full((n, 1), -1.0), eye)
+    assert np.max(np.abs(got - inv)) < 1e-13
+
+
+def test_laplace_inverse_matches_dense():
+    nx, nz, dx, dz, h = 16, 8, 4.0, 6.0, 300.0
+    kappa, rho = _small_medium(nx, nz)
+    B = precond.acoustic_preconditioner(kappa, rho, h, nx, nz, dx, dz)
+    kt, rt = precond.midrange(kappa), precond.midrange(rho)
+    Md = operator.assemble_A(np.full_like(kappa, kt), np.full((nz - 1, nx - 1), rt * h * h / 4),
+                             dx, dz)
+    r = np.random.default_rng(2).standard_normal((nz - 1, nx - 1))
+    z = B.solve(r)
+    ref = np.linalg.solve(Md, r.ravel()).reshape(r.shape)
+    assert np.max(np.abs(z - ref)) < 1e-13 * np.max(np.abs(ref))
+    assert np.max(np.abs(B.apply(z) - r)) < 1e-12 * np.max(np.abs(r))
+
+
+def test_laplace_anisotropic_blocks_match_dense():
+    """Elastic blocks have different x and z coefficients (eq. precond2)."""
+    nx, nz = 8, 16
+    B = precond.Laplace(nx, nz, 2.0, 3.0, 5.0, 1.5, 0.7)
+    n = (nx - 1) * (nz - 1)
+    M = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n); e[c] = 1
+        M[:, c] = B.apply(e.reshape(nz - 1, nx - 1)).ravel()
+    r = np.random.default_rng(9).standard_normal((nz - 1, nx - 1))
+    assert np.max(np.abs(B.solve(r).ravel() - np.linalg.solve(M, r.ravel()))) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# PCG (Sec. 2.3) with the Laplace preconditioner
+# ---------------------------------------------------------------------------
+
+def _acoustic_setup(nx, nz, kappa, rho, dx, dz, h):
+    w = operator.shift_coeff(rho, h)
+    B = precond.acoustic_preconditioner(kappa, rho, h, nx, nz, dx, dz)
+    return (lambda y: operator.apply_A(y, kappa, w, dx, dz)), B.solve, w
+
+
+def test_pcg_homogeneous_converges_in_one_iteration():
+    """Constant medium => B = A => PCG converges in exactly one iteration."""
+    nx = nz = 32
+    kappa = np.full((nz + 1, nx + 1), 1.0)
+    rho = np.full((nz + 1, nx + 1), 1.0 / 2500.0 ** 2)
+    A, Minv, _ = _acoustic_setup(nx, nz, kappa, rho, 10.0, 10.0, 200.0)
+    b = np.random.default_rng(4).standard_normal((nz - 1, nx - 1))
+    x, it, rr, st = krylov.pcg(A, Minv, b, 1e-10, 50)
+    assert st == OK and it == 1 and rr < 1e-13
+
+
+def test_pcg_heterogeneous_matches_dense_solve():
+    nx, nz, dx, dz, h = 16, 16, 10.0, 10.0, 200.0
+    v = inputs.two_layer_velocity(16, 8, 2000.0, 3000.0)
+    kappa, rho = inputs.variable_density_coeffs(v)
+    A, Minv, w = _acoustic_setup(nx, nz, kappa, rho, dx, dz, h)
+    b = np.random.default_rng(6).standard_normal((nz - 1, nx - 1))
+    x, it, rr, st = krylov.pcg(A, Minv, b, 1e-13, 200)
+    ref = np.linalg.solve(operator.assemble_A(kappa, w, dx, dz), b.ravel()).reshape(b.shape)
+    assert st == OK
+    assert np.max(np.abs(x - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+def test_preconditioned_spectrum_within_energy_bounds():
+    """For kappa = 1 the energy-equivalence constants of eq. energy_rel obey
+    gamma in [min(1, rho_min/rho~), max(1, rho_max/rho~)]."""
+    nx, nz, dx, dz, h = 12, 12, 10.0, 10.0, 400.0
+    v = inputs.two_layer_velocity(12, 6, 1500.0, 4000.0)
+    kappa, rho = inputs.acoustic_coeffs(v)
+    w = operator.shift_coeff(rho, h)
+    A = operator.assemble_A(kappa, w, dx, dz)
+    rt = precond.midrange(rho)
+    Bm = operator.assemble_A(kappa, np.full_like(w, rt * h * h / 4), dx, dz)
+    ev = np.real(np.linalg.eigvals(np.linalg.solve(Bm, A)))
+    lo, hi = min(1.0, rho.min() / rt), max(1.0, rho.max() / rt)
+    assert ev.min() >= lo * (1 - 1e-12) and ev.max() <= hi * (1 + 1e-12)
+
+
+def test_pcg_status_semantics():
+    nx = nz = 16
+    kappa, rho = _small_medium(nx, nz)
+    A, Minv, _ = _acoustic_setup(nx, nz, kappa, rho, 5.0, 5.0, 300.0)
+    b = np.random.default_rng(8).standard_normal((nz - 1, nx - 1))
+    x, it, rr, st = krylov.pcg(A, Minv, np.zeros_like(b), 1e-10, 10)
+    assert (it, st) == (0, OK) and not x.any()
+    x, it, rr, st = krylov.pcg(A, Minv, b, 1e-14, 1)
+    assert (it, st) == (1, NOT_CONVERGED)
+    bn = b.copy(); bn[3, 3] = np.nan
+    assert krylov.pcg(A, Minv, bn, 1e-10, 10)[3] == NONFINITE
+    neg = lambda y: -A(y)                                   # indefinite (negative) operator
+    assert krylov.pcg(neg, Minv, b, 1e-10, 10)[3] == BREAKDOWN
+
+
+def test_pcg_iterations_nearly_mesh_independent():
+    """Sec. 2.4: with this preconditioner the iteration count practically does
+    not depend on the number of mesh nodes (same medium, refined)."""
+    its = []
+    for n in (32, 64, 128):
+        v = inputs.perturbed_layered_velocity(n, 2560.0 / n, 1500.0, 4000.0, seed=1)
+        kappa, rho = inputs.acoustic_coeffs(v)
+        A, Minv, _ = _acoustic_setup(n, n, kappa, rho, 2560.0 / n, 2560.0 / n, 400.0)
+        b = np.zeros((n - 1, n - 1)); b[n // 8, n // 2] = 1.0
+        its.append(krylov.pcg(A, Minv, b, 1e-10, 500)[1])
+    assert max(its) - min(its) <= 6, its
+
+
+# ---------------------------------------------------------------------------
+# Reciprocity of whole harmonic chains (heterogeneous media)
+# ---------------------------------------------------------------------------
+
+def test_harmonic_chain_reciprocity():
+    """R_m(x_b; source a) = R_m(x_a; source b): each harmonic's source-to-field
+    map is a palindromic product of A^{-1} and diag(rho), hence symmetric."""
+    n = 24
+    v = inputs.perturbed_layered_velocity(n, 10.0, 1500.0, 4000.0, seed=2)
+    kappa, rho = inputs.variable_density_coeffs(v)
+    h, a = 300.0, 9
+    w = operator.shift_coeff(rho, h)
+    Ad = operator.assemble_A(kappa, w, 10.0, 10.0)
+    solve = lambda phi: (np.linalg.solve(Ad, phi.ravel()).reshape(phi.shape), 0, 0.0, OK)
+    f = np.linspace(1.0, -0.5, 12)
+    sa, sb = (5, 4), (17, 15)
+    ra = harmonics.harmonic_loop(12, solve, rho[1:-1, 1:-1], h, a, f, sa, 10.0, 10.0)
+    rb = harmonics.harmonic_loop(12, solve, rho[1:-1, 1:-1], h, a, f, sb, 10.0, 10.0)
+    for m in range(12):
+        x = ra["R"][m][sb[1] - 1, sb[0] - 1]
+        y = rb["R"][m][sa[1] - 1, sa[0] - 1]
+        assert abs(x - y) <= 1e-12 * max(abs(x), 1e-300) + 1e-300
+
+
+# ---------------------------------------------------------------------------
+# Elastic operator (parity against the paper unpinned; pinned internally)
+# ---------------------------------------------------------------------------
+
+def test_elastic_operator_dense_symmetric_positive():
+    nx, nz, d, h = 8, 10, 5.0, 300.0
+    vp = inputs.perturbed_layered_velocity(10, d, 2000.0, 4500.0, seed=1)[:, :9]
+    rho = inputs.perturbed_layered_velocity(10, d, 2000.0, 2600.0, seed=2)[:, :9]
+    lam, mu, rh = inputs.elastic_coeffs(vp, rho)
+    w = rh[1:-1, 1:-1] * h * h / 4
+    M = elastic.assemble_C(lam, mu, w, d, d)
+    u = np.random.default_rng(3).standard_normal((2, nz - 1, nx - 1))
+    got = elastic.apply_C(u, lam, mu, w, d, d)
+    assert np.max(np.abs(got.ravel() - M @ u.ravel())) < 1e-12 * np.max(np.abs(got))
+    assert np.max(np.abs(M - M.T)) < 1e-12 * np.max(np.abs(M))
+    assert np.min(np.linalg.eigvalsh(0.5 * (M + M.T))) > 0.0
+
+
+def test_elastic_gmres_matches_dense_solve():
+    nx = nz = 12
+    d, h = 5.0, 300.0
+    vp = inputs.perturbed_layered_velocity(12, d, 2000.0, 4500.0, seed=1)
+    rho = inputs.perturbed_layered_velocity(12, d, 2000.0, 2600.0, seed=2)
+    lam, mu, rh = inputs.elastic_coeffs(vp, rho)
+    w = rh[1:-1, 1:-1] * h * h / 4
+    B1, B2 = elastic.block_preconditioner(lam, mu, rh, h, nx, nz, d, d)
+    C = lambda u: elastic.apply_C(u, lam, mu, w, d, d)
+    K = lambda u: elastic.apply_Kinv(u, B1, B2)
+    b = np.random.default_rng(11).standard_normal((2, nz - 1, nx - 1))
+    x, it, rr, st = krylov.gmres(C, K, b, 1e-12, 10)
+    ref = np.linalg.solve(elastic.assemble_C(lam, mu, w, d, d), b.ravel()).reshape(b.shape)
+    assert st == OK
+    assert np.max(np.abs(x - ref)) < 1e-10 * np.max(np.abs(ref))
+    # GMRES(1) still converges (the operator is positive definite, Sec. 2.3)
+    x1, it1, rr1, st1 = krylov.gmres(C, K, b, 1e-8, 1, max_cycles=2000)
+    assert st1 == OK and np.max(np.abs(x1 - ref)) < 1e-6 * np.max(np.abs(ref))
+
+
+def test_elastic_block_preconditioner_is_diagonal_block_in_homogeneous_medium():
+    """For constant lambda, mu, rho the blocks of K (eq. precond2) equal the
+    diagonal blocks of C: (C (ux, 0))_x = B1 ux and (C (0, uz))_z = B2 uz."""
+    nx, nz, d, h = 10, 14, 5.0, 300.0
+    lam = np.full((nz + 1, nx + 1), 7.0e9)
+    mu = np.full((nz + 1, nx + 1), 4.0e9)
+    rho = np.full((nz + 1, nx + 1), 2300.0)
+    w = rho[1:-1, 1:-1] * h * h / 4
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, h, nx, nz, d, d)
+    u = np.random.default_rng(12).standard_normal((nz - 1, nx - 1))
+    z = np.zeros_like(u)
+    cx = elastic.apply_C(np.stack([u, z]), lam, mu, w, d, d)[0]
+    cz = elastic.apply_C(np.stack([z, u]), lam, mu, w, d, d)[1]
+    assert np.max(np.abs(B1.apply(u) - cx)) < 1e-12 * np.max(np.abs(cx))
+    assert np.max(np.abs(B2.apply(u) - cz)) < 1e-12 * np.max(np.abs(cz))
