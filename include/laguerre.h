@@ -1,0 +1,215 @@
+/*
+ * laguerre.h -- C ABI of the MI355X (gfx950) library for the Laguerre-harmonic
+ * Krylov solve of Fatyanov & Terekhov, "High-performance modeling acoustic and
+ * elastic waves using the Parallel Dichotomy Algorithm" (arXiv 1005.0542).
+ *
+ * The method (Sec. 2): an integral Laguerre transform in time turns the wave
+ * equation into a sequence of elliptic problems with ONE fixed operator and a
+ * right-hand side that depends on the earlier harmonics (eq. laguerre_h).
+ * Each problem is solved by a Krylov method (CG for acoustics, GMRES(k) for
+ * elasticity, Sec. 2.3) preconditioned by a constant-coefficient Laplace
+ * operator (Sec. 2.4, eqs. precond1/precond2), inverted by separation of
+ * variables: a sine transform along x, then one tridiagonal system per
+ * wavenumber along z, solved by a segmented Dichotomy-style solver.
+ *
+ * Geometry of this library: 2D Cartesian, nx x nz cells, nodes i = 0..nx,
+ * j = 0..nz, zero Dirichlet values on all boundary nodes.  The unknowns are the
+ * (nx-1)(nz-1) interior nodes.
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions for every call below
+ * ---------------------------------------------------------------------------
+ * Layout.   A "field" is (nz-1) rows of (nx-1) values, row-major, x fastest:
+ *           element (i, j) (1-based interior node) is at [(j-1)(nx-1) + (i-1)].
+ *           A "vector" is S shots x C components x field, contiguous
+ *           ([S][C][nz-1][nx-1]); C = 1 (acoustic) or 2 (elastic: x then z).
+ * Memory.   Vector and field pointers are DEVICE pointers owned by the caller
+ *           (contiguous, no padding, naturally aligned).  Pointers suffixed
+ *           _host are host pointers.  The plan owns only its tables and
+ *           workspace.
+ * Dtypes.   Arguments typed double* are FP64.  Arguments typed void* are the
+ *           plan's working type: FP64 for LG_FP64 plans, FP32 for LG_MIXED.
+ * Streams.  All device work is enqueued on the plan's stream (a hipStream_t
+ *           given at creation, or set later); calls return without waiting,
+ *           except those that fill a *_host output (they synchronise it).
+ * Errors.   Every argument is checked on the host before any device work; an
+ *           invalid call returns LG_ERR_INVALID_ARG (or LG_ERR_UNSUPPORTED for
+ *           a valid but unimplemented shape) and leaves outputs untouched.
+ *           HIP failures return LG_ERR_HIP; lg_last_error() describes the
+ *           last failure of the calling thread.
+ * Threads.  A plan must not be used by two threads at once; distinct plans
+ *           are independent.
+ */
+#ifndef LAGUERRE_H
+#define LAGUERRE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LG_OK = 0,
+    LG_ERR_INVALID_ARG = 1,
+    LG_ERR_NOT_CONVERGED = 2,   /* max_iter reached; x holds the last iterate   */
+    LG_ERR_BREAKDOWN = 3,       /* (p, Ap) <= 0 in CG, or an exact GMRES stall  */
+    LG_ERR_NONFINITE = 4,       /* NaN/Inf met in a residual or inner product   */
+    LG_ERR_HIP = 5,
+    LG_ERR_OOM = 6,
+    LG_ERR_UNSUPPORTED = 7
+} lg_status;
+
+typedef enum { LG_FP64 = 0, LG_MIXED = 1 } lg_precision;
+typedef enum { LG_ACOUSTIC = 0, LG_ELASTIC = 1 } lg_kind;
+typedef enum { LG_RICKER = 0, LG_GAUSS_SINE = 1 } lg_wavelet;
+
+/* Grid: nx, nz cells (powers of two, 2..4096), spacings dx, dz > 0 (metres). */
+typedef struct { int32_t nx, nz; double dx, dz; } lg_grid;
+
+/* Laguerre transform (Sec. 2.1): order alpha >= 2, scale h > 0 (1/s), n >= 1
+ * harmonics. */
+typedef struct { int32_t alpha; double h; int32_t n; } lg_laguerre;
+
+/* Krylov options: stop when ||r||_2 <= tol ||b||_2 (tol >= 0); max_iter >= 1
+ * (CG iterations, or GMRES inner iterations); restart = GMRES k >= 1. */
+typedef struct { double tol; int32_t max_iter; int32_t restart; } lg_solve_opts;
+
+/* Per-shot solver report. */
+typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
+
+/* Optional tuning (zero fields = library default).
+ *  segments     number P of Dichotomy segments per z-system (power of two,
+ *               1..64, with nz/P in {2,4,...,64}).
+ *  graph_iters  Krylov iterations captured per HIP graph (0: default 8,
+ *               -1: no graph, plain stream launches). */
+typedef struct { int32_t segments; int32_t graph_iters; int32_t reserved[6]; } lg_tuning;
+
+typedef struct lg_plan lg_plan;
+
+/* ---------------------------------------------------------------------------
+ * Plan (setup, not on the hot path)
+ * ------------------------------------------------------------------------ */
+
+/* Create a plan for S = nshots shots over one medium.
+ * medium_host: FP64 host array of node values, shape [F][nz+1][nx+1]:
+ *   acoustic F = 2: kappa, rho of  rho u_tt = div(kappa grad u) + f  (eq.
+ *            acoustic_problem); the operator A has face coefficients the mean
+ *            of the two node kappas and the shift w = rho h^2/4 (eq.
+ *            diff_approx1);
+ *   elastic  F = 3: lambda, mu, rho (Lame parameters and density).
+ * The preconditioner uses the midrange values (min+max)/2 of these arrays
+ * (footnote to eq. precond1).  hip_stream may be NULL (null stream).
+ * tuning may be NULL.  On success *out owns device tables and workspace. */
+lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid,
+                         const lg_laguerre* lag, lg_precision prec, int32_t nshots,
+                         const double* medium_host, const lg_tuning* tuning,
+                         void* hip_stream);
+lg_status lg_plan_destroy(lg_plan* plan);
+lg_status lg_plan_set_stream(lg_plan* plan, void* hip_stream);
+
+/* Source nodes, one (i, j) pair per shot, 1 <= i <= nx-1, 1 <= j <= nz-1. */
+lg_status lg_plan_set_sources(lg_plan* plan, const int32_t* src_ij_host /*[S][2]*/);
+
+/* Segments P and segment length nz/P actually used by the plan. */
+lg_status lg_plan_layout(const lg_plan* plan, int32_t* segments, int32_t* seg_len);
+
+/* ---------------------------------------------------------------------------
+ * Host helpers for the Laguerre transform (Sec. 2.1, eq. series_lag)
+ * ------------------------------------------------------------------------ */
+
+/* f_m = int_0^inf f(t) (ht)^{-alpha/2} l_m(ht) dt for m < n, where l_m are the
+ * orthonormal Laguerre functions; RICKER: f = (1-2a) e^{-a}, a = (pi f0 (t-t0))^2;
+ * GAUSS_SINE (eq. functiont): exp(-(2 pi f0 (t-t0))^2/gamma^2) sin(2 pi f0 (t-t0)).
+ * Composite Gauss-Legendre quadrature.  f_m_host: [n]. */
+lg_status lg_source_coeffs(lg_wavelet wavelet, double f0, double t0, double gamma,
+                           const lg_laguerre* lag, double* f_m_host);
+
+/* Synthesis weights W[q][m] with u(t_q) = sum_m W[q][m] R_m, i.e.
+ * W_m(t) = (ht)^{alpha/2} l_m(ht) (eq. series_lag).  W_host: [nt][n]. */
+lg_status lg_laguerre_weights(const lg_laguerre* lag, const double* t_host, int32_t nt,
+                              double* W_host);
+
+const char* lg_status_string(lg_status s);
+const char* lg_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * The hot path
+ * ------------------------------------------------------------------------ */
+
+/* Right-hand side of harmonic m (eq. laguerre_h, SPD sign convention):
+ *   rhs = delta_h f_m e_src - h^2 rho * n_m sum_{k<m} (m-k) R_k / n_k,
+ * n_m = sqrt(m!/(m+alpha)!), delta_h = 1/(dx dz) at the shot's source node (the
+ * z component for elastic plans: a vertical force).  The history sum is kept
+ * in two caller-owned running fields Phat, Qhat (FP64 vectors) updated in
+ * place: P_{m-1} = sqrt((m-1)/(m-1+alpha)) P_{m-2} + R_{m-1},
+ * Q_m = sqrt(m/(m+alpha)) (Q_{m-1} + P_{m-1}); the call with m = 0 zeroes them.
+ * Calls must be made for m = 0, 1, 2, ... in order.  R_prev = R_{m-1} (FP64
+ * vector; ignored, may be NULL, when m = 0).  fsrc_host: [S] values f_m.
+ * rhs: FP64 vector (output). */
+lg_status lg_laguerre_rhs(lg_plan* plan, int32_t m, const double* R_prev, double* Phat,
+                          double* Qhat, const double* fsrc_host, double* rhs);
+
+/* y = A x (acoustic, 5-point flux form of eq. poisson_diff_2 with the sign
+ * flipped so A is SPD) or y = C x (elastic, coupled 9-point second-order
+ * scheme) for every shot.  x, y: working-type vectors, x != y. */
+lg_status lg_stencil_apply(lg_plan* plan, const void* x, void* y);
+
+/* Row-wise DST-I along x of every field row (Sec. 2.4, variable separation):
+ *   forward:  out_k = sum_{i=1}^{nx-1} in_i sin(pi i k / nx),   k = 1..nx-1
+ *   inverse:  the same sum times 2/nx (exact inverse).
+ * in, out: working-type vectors (all shots and components), in != out. */
+lg_status lg_precond_dst(lg_plan* plan, int32_t inverse, const void* in, void* out);
+
+/* For every wavenumber k (column of the transformed field) solve the
+ * z-tridiagonal system of the preconditioner block
+ *   -(kz/dz^2) s_{j-1} + (2 kz/dz^2 + kx mu_k + d) s_j - (kz/dz^2) s_{j+1} = rhs_j,
+ *   mu_k = (4/dx^2) sin^2(pi k/(2 nx)),  s_0 = s_nz = 0,
+ * by the segmented Dichotomy solver (Thomas factors prepared once per plan).
+ * block 0: acoustic B (kx = kz = kappa~, d = rho~ h^2/4; eq. precond1);
+ * block 1: elastic B1 (kx = (lambda+2mu)~, kz = mu~) for the x component;
+ * block 2: elastic B2 (kx = mu~, kz = (lambda+2mu)~) for the z component.
+ * For acoustic plans rhs/sol are full vectors; for elastic plans they are
+ * vectors of ONE component per shot ([S][nz-1][nx-1]).  rhs != sol. */
+lg_status lg_precond_dichotomy_tdma(lg_plan* plan, int32_t block, const void* rhs_hat,
+                                    void* sol_hat);
+
+/* Composite preconditioner inverse z = B^{-1} r (forward DST, Dichotomy
+ * solve, inverse DST) for every shot (and both blocks of elastic plans). */
+lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z);
+
+/* Preconditioned CG (Sec. 2.3) for A x = b, every shot independently, from
+ * x0 = 0, stopping per shot when ||r||_2 <= tol ||b||_2 on the recursively
+ * updated residual.  A zero b gives x = 0, iters = 0.  Converged shots drop
+ * out by masking.  b, x: FP64 vectors.  info_host: [S] (may be NULL).
+ * Returns the worst per-shot status. */
+lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve_opts* opts,
+                       lg_solve_info* info_host);
+
+/* Right-preconditioned restarted GMRES(k) (Sec. 2.3) for the elastic C x = b,
+ * K = diag(B1, B2) (eq. precond2), from x0 = 0; stops when the Givens
+ * estimate of ||b - Cx|| <= tol ||b||.  b, x: FP64 vectors ([S][2][..]). */
+lg_status lg_gmres_solve(lg_plan* plan, const double* b, double* x, const lg_solve_opts* opts,
+                         lg_solve_info* info_host);
+
+/* Inverse-transform accumulation for harmonic m (eq. series_lag):
+ *   snap_accum[s] += W_snap_host[s] * R_m    for s < n_snap (<= 8),
+ *   rec_coeff[shot][c][m][:] = R_m[shot][c][row rec_row][:]  (1 <= rec_row <= nz-1),
+ * R_m: FP64 vector; snap_accum: FP64 [n_snap][S][C][nz-1][nx-1] (may be NULL
+ * when n_snap = 0); rec_coeff: FP64 [S][C][n][nx-1] (may be NULL). */
+lg_status lg_laguerre_synthesize(lg_plan* plan, int32_t m, const double* R_m,
+                                 const double* W_snap_host, int32_t n_snap, double* snap_accum,
+                                 int32_t rec_row, double* rec_coeff);
+
+/* Receiver traces from the stored coefficients:
+ *   traces[shot][c][q][i] = sum_m W_host[q][m] rec_coeff[shot][c][m][i].
+ * W_host: [nt][n] (host); rec_coeff: FP64 [S][C][n][nx-1]; traces: FP64
+ * [S][C][nt][nx-1] (device). */
+lg_status lg_trace_synthesize(lg_plan* plan, const double* rec_coeff, const double* W_host,
+                              int32_t nt, double* traces);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LAGUERRE_H */

@@ -1,0 +1,161 @@
+// Internal declarations of the gfx950 Laguerre-harmonic solver library.
+// Not part of the public ABI (see include/laguerre.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "laguerre.h"
+
+namespace lg {
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+lg_status fail(lg_status s, const std::string& msg);
+lg_status hip_fail(hipError_t e, const char* what);
+
+#define LG_HIP(call)                                                    \
+    do {                                                                \
+        hipError_t _e = (call);                                         \
+        if (_e != hipSuccess) return ::lg::hip_fail(_e, #call);         \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// per-shot Krylov control block, resident in device memory
+// ---------------------------------------------------------------------------
+struct ShotCtl {
+    double rz;        // (r, z) of the current iterate
+    double pq;        // (p, A p)
+    double alpha;     // CG step
+    double beta;      // CG direction update
+    double rr;        // ||r||^2
+    double bb;        // ||b||^2
+    double tol2;      // tol^2 ||b||^2
+    int32_t iters;    // completed iterations
+    int32_t active;   // 1 while the shot still iterates
+    int32_t status;   // lg_status of the shot
+    int32_t max_iter;
+};
+
+// The last block of a grid-wide reduction is found with one counter per shot
+// and per reduction; the counters live in one small device array.
+enum CounterSlot { CNT_STENCIL = 0, CNT_UPDATE = 1, CNT_REDUCED = 2, CNT_NUM = 4 };
+
+// ---------------------------------------------------------------------------
+// preconditioner block: z-tridiagonal systems per wavenumber
+// ---------------------------------------------------------------------------
+struct PrecBlock {
+    double kx = 0, kz = 0, d = 0;  // -kx Dxx - kz Dzz + d
+    double b = 0;                  // kz / dz^2 (off-diagonal magnitude)
+    int Ls = 0;                    // segment length (interior rows Ls-1 + 1 separator)
+    int P = 0;                     // number of segments (power of two)
+    int q = 0;                     // log2 P
+    int RW = 0;                    // row width of the reduced-system table
+    void* etab = nullptr;          // [Ls][nx-1] working type: Thomas factors e_i (row i)
+    void* utab = nullptr;          // [Ls][nx-1] working type: end response u_i (row i)
+    double* red = nullptr;         // [nx-1][RW]: Ar, Br, beta_l (q), half weights
+};
+
+struct lg_plan_impl;
+
+}  // namespace lg
+
+// ---------------------------------------------------------------------------
+// the opaque plan
+// ---------------------------------------------------------------------------
+struct lg_plan {
+    lg_kind kind;
+    lg_grid g;
+    lg_laguerre lag;
+    lg_precision prec;
+    int S = 1;                 // shots
+    int C = 1;                 // components
+    int nx1 = 0, nz1 = 0;      // interior extents
+    size_t npts = 0;           // nx1 * nz1
+    size_t nvec = 0;           // S * C * npts
+    int graph_iters = 8;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
+
+    // medium (device)
+    void* kap = nullptr;       // acoustic kappa nodes [(nz+1)(nx+1)], working type
+    void* lam = nullptr;       // elastic lambda nodes, working type
+    void* mu = nullptr;        // elastic mu nodes, working type
+    void* w = nullptr;         // interior rho h^2/4, working type
+    double* rho64 = nullptr;   // interior rho, FP64 (right-hand side recurrence)
+    double kappa_t = 0, rho_t = 0, lp2m_t = 0, mu_t = 0;   // midrange values
+
+    lg::PrecBlock blk[2];      // acoustic uses blk[0]; elastic blk[0]=B1, blk[1]=B2
+    void* tw = nullptr;        // FFT twiddles exp(-2 pi i j / (2 nx)), complex working type
+
+    // sources
+    int32_t* src_dev = nullptr;         // [S][2]
+    std::vector<int32_t> src_host;
+
+    // Krylov workspace
+    double* r = nullptr;       // FP64 residual
+    void* p = nullptr;         // working type
+    void* qv = nullptr;        // A p
+    void* rhat = nullptr;      // DST(r)
+    void* y = nullptr;         // Dichotomy output / spectral solution
+    double* E = nullptr;       // per-segment endpoint data [S*C][P][3][nx-1]
+    double* partial = nullptr; // per-block partial sums
+    size_t partial_stride = 0; // per shot
+    uint32_t* counters = nullptr;  // [CNT_NUM][S*C]
+    lg::ShotCtl* ctl = nullptr;    // [S*C]
+    lg::ShotCtl* ctl_host = nullptr;  // pinned mirror
+    double** xslot = nullptr;  // device slot holding the caller's x pointer
+
+    // HIP graph of graph_iters CG iterations
+    hipGraphExec_t cg_graph = nullptr;
+    int last_iters = 0;
+
+    // elastic GMRES workspace
+    double* gm_V = nullptr;    // (k+1) basis vectors, FP64
+    double* gm_w = nullptr;
+    double* gm_z = nullptr;
+    double* gm_x = nullptr;
+    double* gm_dots = nullptr;
+    int gm_k = 0;
+
+    size_t bytes_allocated = 0;
+};
+
+namespace lg {
+
+// element size of the working type
+inline size_t wsize(const lg_plan* p) { return p->prec == LG_FP64 ? 8 : 4; }
+
+// launchers (implemented in lg_acoustic.hip); all enqueue on plan->stream
+hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq);
+hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nfields);
+hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked);
+hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int mode);
+hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields);
+hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
+                              int max_iter);
+hipError_t launch_correct_idst(lg_plan* p, int init);
+hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,
+                      const double* fsrc_host, double* rhs);
+hipError_t launch_synth(lg_plan* p, int m, const double* R, const double* Wsnap, int nsnap,
+                        double* snap, int rec_row, double* rec);
+hipError_t launch_traces(lg_plan* p, const double* rec, const double* Wdev, int nt,
+                         double* traces);
+
+// PCG driver (lg_pcg.hip)
+lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts* o,
+                    lg_solve_info* info);
+void pcg_release(lg_plan* p);
+
+// GMRES driver (lg_elastic.hip)
+lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts* o,
+                      lg_solve_info* info);
+hipError_t launch_elastic_stencil(lg_plan* p, const void* x, void* y);
+
+}  // namespace lg

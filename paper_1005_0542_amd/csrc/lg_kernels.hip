@@ -1,0 +1,879 @@
+// gfx950 kernels of the Laguerre-harmonic preconditioned Krylov solve.
+//
+// Data layout: a field is (nz-1) rows of (nx-1) values, x fastest; fields of
+// all shots (and components) are stacked.  Spectral fields (after the DST
+// along x) keep the same layout with the wavenumber k in place of x, so the
+// z-systems of consecutive wavenumbers sit in consecutive addresses and every
+// sweep over z loads one coalesced row segment per step.
+//
+// Kernels (one pass of the preconditioned CG iteration is K1..K5):
+//   K1 stencil_kernel      q = A p, partial (p, q); last block: alpha
+//   K2 dst_kernel UPDATE   x += alpha p, r -= alpha q, ||r||^2, rhat = DST(r);
+//                          last block: convergence test
+//   K3 td_kernel           Dichotomy segments: local Thomas solves
+//   K4 rs_kernel           interface (reduced) systems by recursive halving
+//                          across the lanes of a wave; (r, z); last block: beta
+//   K5 dst_kernel CORRECT  segment correction, z = (2/nx) DST(zhat), p = z + beta p
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "lg_device.h"
+#include "lg_internal.h"
+
+namespace lg {
+
+// ===========================================================================
+// K1: 5-point operator (Sec. 2.3, eqs. poisson_diff_2 / scheme_op_r_z /
+// diff_approx1 in 2D Cartesian form, SPD sign):
+//   (A p)_{j,i} = [kE (p - pE) + kW (p - pW)] / dx^2 + [kS (p - pS) + kN (p - pN)] / dz^2
+//                 + w p,   face kappa = mean of the two node values.
+// Each thread marches down ST_RPT rows of one column, keeping the column's
+// p and kappa values in registers; x-neighbours come from the L1/L2.
+// ===========================================================================
+constexpr int ST_RPT = 8;
+
+template <typename T>
+struct StArgs {
+    const T* p;
+    T* q;
+    const T* kap;        // node kappa, (nz+1) x (nx+1)
+    const T* w;          // interior shift
+    int nx1, nz1;
+    T idx2, idz2;
+    // CG reduction (ctl == nullptr: plain operator application)
+    ShotCtl* ctl;
+    double* partial;
+    size_t pstride;
+    uint32_t* cnt;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
+    __shared__ double red[4];
+    const int field = blockIdx.z;
+    if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
+    const int nx1 = a.nx1, nz1 = a.nz1, NXN = nx1 + 2;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 1D block of 256 = 64 x 4
+    const int i = blockIdx.x * 64 + tx;
+    const int j0 = (blockIdx.y * 4 + ty) * ST_RPT;
+    const size_t fb = (size_t)field * nx1 * nz1;
+    const T* __restrict__ p = a.p + fb;
+    T* __restrict__ q = a.q + fb;
+    const T* __restrict__ kap = a.kap;
+    const T half = (T)0.5;
+    double pq = 0.0;
+    if (i < nx1 && j0 < nz1) {
+        const int I = i + 1;
+        T pN = (j0 > 0) ? p[(size_t)(j0 - 1) * nx1 + i] : (T)0;
+        T c = p[(size_t)j0 * nx1 + i];
+        T kN = kap[(size_t)j0 * NXN + I];            // node (I, J0-1) with J0 = j0+1
+        T k0 = kap[(size_t)(j0 + 1) * NXN + I];
+#pragma unroll
+        for (int rr = 0; rr < ST_RPT; ++rr) {
+            const int j = j0 + rr;
+            if (j >= nz1) break;
+            const int J = j + 1;
+            const T pS = (j + 1 < nz1) ? p[(size_t)(j + 1) * nx1 + i] : (T)0;
+            const T kS = kap[(size_t)(J + 1) * NXN + I];
+            const T pE = (i + 1 < nx1) ? p[(size_t)j * nx1 + i + 1] : (T)0;
+            const T pW = (i > 0) ? p[(size_t)j * nx1 + i - 1] : (T)0;
+            const T kE = kap[(size_t)J * NXN + I + 1];
+            const T kW = kap[(size_t)J * NXN + I - 1];
+            const T fE = half * (k0 + kE), fW = half * (k0 + kW);
+            const T fS = half * (k0 + kS), fN = half * (k0 + kN);
+            const T v = (fE * (c - pE) + fW * (c - pW)) * a.idx2 +
+                        (fS * (c - pS) + fN * (c - pN)) * a.idz2 +
+                        a.w[(size_t)j * nx1 + i] * c;
+            q[(size_t)j * nx1 + i] = v;
+            pq += (double)c * (double)v;
+            pN = c;
+            c = pS;
+            kN = k0;
+            k0 = kS;
+        }
+    }
+    if (a.ctl == nullptr) return;
+    const double s = block_sum(pq, red);
+    const uint32_t nb = gridDim.x * gridDim.y;
+    const uint32_t bid = blockIdx.y * gridDim.x + blockIdx.x;
+    double* part = a.partial + (size_t)field * a.pstride;
+    if (arrive_last(part + bid, s, a.cnt + field, nb)) {
+        const double tot = sum_partials(part, (int)nb, red);
+        if (threadIdx.x == 0) {
+            ShotCtl& c = a.ctl[field];
+            c.pq = tot;
+            if (!isfinite(tot)) {
+                c.status = LG_ERR_NONFINITE;
+                c.active = 0;
+            } else if (tot <= 0.0) {
+                c.status = LG_ERR_BREAKDOWN;
+                c.active = 0;
+            } else {
+                c.alpha = c.rz / tot;
+            }
+        }
+    }
+}
+
+// ===========================================================================
+// K2 / K5 and the plain transform: row-wise DST-I along x (Sec. 2.4,
+// variable separation).  Two rows (j0, j1) of one field are packed as the
+// real and imaginary parts of one complex sequence, odd-extended to length
+// M = 2 nx (w_0 = w_nx = 0, w_{M-i} = -w_i); its forward DFT is
+// V_k = -2i X_k(row j0) + 2 X_k(row j1), so the two DST-I results are
+// X(j0) = -Im V / 2, X(j1) = Re V / 2 for k = 1..nx-1.
+// ===========================================================================
+enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3 };
+
+template <typename T>
+struct DstArgs {
+    const T* in;           // DST_FWD / DST_INV input
+    T* out;                // FWD/INV output; UPDATE: rhat; CORRECT: p (in/out)
+    const cpx<T>* tw;      // exp(-2 pi i j / M), j < M
+    int nz1;               // rows per field
+    int bpf;               // blocks per field
+    // CG (UPDATE / CORRECT)
+    ShotCtl* ctl;
+    double* x;             // UPDATE init: caller x (stored into *xslot)
+    double** xslot;
+    double* r;
+    const double* b;       // UPDATE init: right-hand side
+    const T* p;            // UPDATE: search direction
+    const T* q;            // UPDATE: A p
+    double* partial;
+    size_t pstride;
+    uint32_t* cnt;
+    double tol2;           // tol^2 (init)
+    int max_iter;          // (init)
+    int init;
+    // CORRECT: Dichotomy segment correction
+    const T* y;
+    const T* utab;
+    int Ls, P;
+};
+
+template <typename T, int M, int R, int FPB, int MODE>
+__global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
+    constexpr int TPF = M / R;
+    constexpr int NX = M / 2;
+    constexpr int NX1 = NX - 1;
+    constexpr int LL = LdsLen<M>::value;
+    constexpr int NWAVE = (FPB * TPF + 63) / 64;
+    __shared__ cpx<T> lds[FPB * LL];
+    __shared__ double red[NWAVE];
+
+    const int fid = threadIdx.x / TPF;
+    const int t = threadIdx.x - fid * TPF;
+    const int field = blockIdx.x / a.bpf;
+    const int bif = blockIdx.x - field * a.bpf;
+    const int pair = bif * FPB + fid;
+    const int npairs = (a.nz1 + 1) >> 1;
+    const bool live = pair < npairs;
+    const int j0 = 2 * pair, j1 = j0 + 1;
+    const bool has1 = live && (j1 < a.nz1);
+
+    if constexpr (MODE == DST_UPDATE || MODE == DST_CORRECT) {
+        bool skip = a.ctl[field].active == 0;
+        if (MODE == DST_UPDATE && a.init) skip = false;
+        if (skip) return;   // uniform per block: blocks never span fields
+    }
+
+    cpx<T>* buf = lds + fid * LL;
+    const size_t fbase = (size_t)field * a.nz1 * NX1;
+    const size_t o0 = fbase + (size_t)j0 * NX1;
+    const size_t o1 = fbase + (size_t)j1 * NX1;
+    double rr = 0.0;
+
+    // ---- phase A: gather the two rows into the odd extension --------------
+    if (live) {
+        double* xp = nullptr;
+        double alpha = 0.0;
+        if constexpr (MODE == DST_UPDATE) {
+            if (a.init) {
+                xp = a.x;
+                if (blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
+            } else {
+                xp = *a.xslot;
+                alpha = a.ctl[field].alpha;
+            }
+        }
+        for (int i = t; i < NX1; i += TPF) {
+            T v0, v1 = (T)0;
+            if constexpr (MODE == DST_FWD || MODE == DST_INV) {
+                v0 = a.in[o0 + i];
+                if (has1) v1 = a.in[o1 + i];
+            } else if constexpr (MODE == DST_UPDATE) {
+                double r0, r1 = 0.0;
+                if (a.init) {
+                    r0 = a.b[o0 + i];
+                    a.r[o0 + i] = r0;
+                    xp[o0 + i] = 0.0;
+                    if (has1) {
+                        r1 = a.b[o1 + i];
+                        a.r[o1 + i] = r1;
+                        xp[o1 + i] = 0.0;
+                    }
+                } else {
+                    r0 = a.r[o0 + i] - alpha * (double)a.q[o0 + i];
+                    xp[o0 + i] = xp[o0 + i] + alpha * (double)a.p[o0 + i];
+                    a.r[o0 + i] = r0;
+                    if (has1) {
+                        r1 = a.r[o1 + i] - alpha * (double)a.q[o1 + i];
+                        xp[o1 + i] = xp[o1 + i] + alpha * (double)a.p[o1 + i];
+                        a.r[o1 + i] = r1;
+                    }
+                }
+                rr += r0 * r0 + r1 * r1;
+                v0 = (T)r0;
+                v1 = (T)r1;
+            } else {   // DST_CORRECT: zhat = y + xl u_i + xr u_{Ls-i} on segment rows
+                const int Ls = a.Ls, P = a.P;
+                const T* Y = a.y + fbase;
+                auto corr = [&](int j) -> T {
+                    T v = Y[(size_t)j * NX1 + i];
+                    const int jj = j + 1;
+                    const int rs = jj & (Ls - 1);
+                    if (rs != 0) {
+                        const int s = jj / Ls;
+                        const T xl = (s > 0) ? Y[(size_t)(s * Ls - 1) * NX1 + i] : (T)0;
+                        const T xr = (s < P - 1) ? Y[(size_t)((s + 1) * Ls - 1) * NX1 + i] : (T)0;
+                        v += xl * a.utab[(size_t)rs * NX1 + i] + xr * a.utab[(size_t)(Ls - rs) * NX1 + i];
+                    }
+                    return v;
+                };
+                v0 = corr(j0);
+                if (has1) v1 = corr(j1);
+            }
+            buf[lpad(1 + i)] = {v0, v1};
+            buf[lpad(M - 1 - i)] = {-v0, -v1};
+        }
+        if (t == 0) {
+            buf[lpad(0)] = {(T)0, (T)0};
+            buf[lpad(NX)] = {(T)0, (T)0};
+        }
+    } else {
+        for (int i = t; i < M; i += TPF) buf[lpad(i)] = {(T)0, (T)0};
+    }
+    __syncthreads();
+
+    fft_passes<T, M, R, 1>(buf, a.tw, t);
+
+    // ---- phase C: unpack ----------------------------------------------------
+    if (live) {
+        T beta = (T)0;
+        if constexpr (MODE == DST_CORRECT) beta = (T)a.ctl[field].beta;
+        for (int k = t; k < NX1; k += TPF) {
+            const cpx<T> V = buf[lpad(1 + k)];
+            T x0 = -V.y * (T)0.5, x1 = V.x * (T)0.5;
+            if constexpr (MODE == DST_FWD || MODE == DST_UPDATE) {
+                a.out[o0 + k] = x0;
+                if (has1) a.out[o1 + k] = x1;
+            } else if constexpr (MODE == DST_INV) {
+                const T sc = (T)(2.0 / NX);
+                a.out[o0 + k] = x0 * sc;
+                if (has1) a.out[o1 + k] = x1 * sc;
+            } else {   // CORRECT: p = z + beta p  (init: p = z)
+                const T sc = (T)(2.0 / NX);
+                x0 *= sc;
+                x1 *= sc;
+                if (a.init) {
+                    a.out[o0 + k] = x0;
+                    if (has1) a.out[o1 + k] = x1;
+                } else {
+                    a.out[o0 + k] = x0 + beta * a.out[o0 + k];
+                    if (has1) a.out[o1 + k] = x1 + beta * a.out[o1 + k];
+                }
+            }
+        }
+    }
+
+    if constexpr (MODE == DST_UPDATE) {
+        const double s = block_sum(rr, red);
+        double* part = a.partial + (size_t)field * a.pstride;
+        if (arrive_last(part + bif, s, a.cnt + field, (uint32_t)a.bpf)) {
+            const double tot = sum_partials(part, a.bpf, red);
+            if (threadIdx.x == 0) {
+                ShotCtl& c = a.ctl[field];
+                c.rr = tot;
+                if (a.init) {
+                    c.bb = tot;
+                    c.tol2 = a.tol2 * tot;
+                    c.iters = 0;
+                    c.max_iter = a.max_iter;
+                    c.alpha = 0.0;
+                    c.beta = 0.0;
+                    if (!isfinite(tot)) {
+                        c.status = LG_ERR_NONFINITE;
+                        c.active = 0;
+                    } else if (tot == 0.0) {
+                        c.status = LG_OK;
+                        c.active = 0;
+                    } else {
+                        c.status = LG_ERR_NOT_CONVERGED;
+                        c.active = 1;
+                    }
+                } else {
+                    const int it = c.iters + 1;
+                    c.iters = it;
+                    if (!isfinite(tot)) {
+                        c.status = LG_ERR_NONFINITE;
+                        c.active = 0;
+                    } else if (tot <= c.tol2) {
+                        c.status = LG_OK;
+                        c.active = 0;
+                    } else if (it >= c.max_iter) {
+                        c.status = LG_ERR_NOT_CONVERGED;
+                        c.active = 0;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ===========================================================================
+// K3: Dichotomy segments.  Each z-system (one wavenumber k) of length nz-1 is
+// split into P segments of Ls rows: Ls-1 interior rows and one separator row
+// (the last segment has none).  In the normalised system
+//   -s_{j-1} + theta_k s_j - s_{j+1} = rhat_j / b
+// every interior block is the same (Ls-1)x(Ls-1) Toeplitz matrix, so its
+// Thomas factors e_i = 1/(theta - e_{i-1}) are prepared once per plan and
+// shared by all segments, shots and iterations.  A lane owns one (k, segment):
+// forward sweep, back substitution with zero end values, store y.  It also
+// stores the two end values of y and g^T T^{-1} g = sum h_i d_i (h = L^{-1} g,
+// from the LDL^T form of the sweep), which the interface step needs.
+// ===========================================================================
+template <typename T>
+struct TdArgs {
+    const T* rhat;
+    T* y;
+    const T* etab;
+    double* E;       // [field][P][3][nx1]
+    int nx1, nz1, P;
+    T inv_b;
+    ShotCtl* ctl;    // nullptr: no masking
+};
+
+template <typename T, int LS>
+__global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + lane;
+    const int s = blockIdx.y * (blockDim.x >> 6) + wave;
+    const int field = blockIdx.z;
+    if (a.ctl != nullptr && a.ctl[field].active == 0) return;
+    if (k >= a.nx1 || s >= a.P) return;
+    const int nx1 = a.nx1;
+    const size_t fb = (size_t)field * a.nz1 * nx1;
+    const T* __restrict__ g = a.rhat + fb + (size_t)(s * LS) * nx1 + k;   // row s*LS (+i-1)
+    T* __restrict__ yo = a.y + fb + (size_t)(s * LS) * nx1 + k;
+    const T* __restrict__ e = a.etab + k;
+    constexpr int L = LS - 1;
+    T d[LS];
+    T prev = (T)0;
+    double d0 = 0.0;
+#pragma unroll
+    for (int i = 1; i <= L; ++i) {
+        const T h = g[(size_t)(i - 1) * nx1] * a.inv_b + prev;
+        prev = h * e[(size_t)i * nx1];
+        d[i] = prev;
+        d0 += (double)h * (double)prev;
+    }
+    T yv = d[L];
+    yo[(size_t)(L - 1) * nx1] = yv;
+    const T ylast = yv;
+#pragma unroll
+    for (int i = L - 1; i >= 1; --i) {
+        yv = d[i] + e[(size_t)i * nx1] * yv;
+        yo[(size_t)(i - 1) * nx1] = yv;
+    }
+    double* E = a.E + ((size_t)field * a.P + s) * 3 * nx1 + k;
+    E[0] = (double)yv;          // y_1
+    E[nx1] = (double)ylast;     // y_{Ls-1}
+    E[2 * (size_t)nx1] = d0;    // g^T T^{-1} g on the segment
+}
+
+// ===========================================================================
+// K4: interface systems.  With the segment solutions y^s and the end
+// responses u (T u = e_1, v = reversed u), the separator values x_s satisfy
+// a Toeplitz tridiagonal system of size P-1:
+//   Ar x_s - Br (x_{s-1} + x_{s+1}) = G_s = g_sep(s) + y^s_last + y^{s+1}_first,
+//   Ar = theta - 2 u_1, Br = u_{Ls-1}.
+// It is solved by the Dichotomy principle: at level l the unknowns split into
+// subdomains of 2^(q-l)-1 bounded by already-known separators; the middle
+// unknown of each is a weighted sum of the G in its subdomain (a row of the
+// subdomain's inverse, prepared once) plus the response to the two known
+// boundary values; the sums are segmented reductions across the lanes of the
+// wave (one lane per separator).  The wave also forms this system's share of
+// (rhat, zhat) = b (sum_s g^T T^{-1} g + sum_s x_s G_s), and the last block of
+// a field turns the total into (r, z) = (2/nx) (rhat, zhat) and beta.
+// mode 0: interface only; 1: CG start (rz); 2: CG iteration (beta, rz).
+// ===========================================================================
+template <typename T>
+struct RsArgs {
+    const T* rhat;
+    T* y;
+    const double* E;
+    const double* red;   // [nx1][RW]
+    int nx1, nz1, P, q, Ls, RW, bpf;
+    double inv_b, b, dot_scale;
+    int mode;
+    ShotCtl* ctl;
+    double* partial;
+    size_t pstride;
+    uint32_t* cnt;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int field = blockIdx.x / a.bpf;
+    const int bif = blockIdx.x - field * a.bpf;
+    const int k = bif * 4 + wave;
+    if (a.mode != 0 && a.ctl[field].active == 0) return;   // uniform per block
+    const bool valid = k < a.nx1;
+    const int P = a.P, q = a.q, Ls = a.Ls, nx1 = a.nx1;
+    const int sig = lane;
+    const size_t fb = (size_t)field * a.nz1 * nx1;
+    const double* Ef = a.E + (size_t)field * P * 3 * nx1;
+    const double* tab = a.red + (size_t)(valid ? k : 0) * a.RW;
+    const bool sepl = valid && sig < P - 1;
+    double G = 0.0, x = 0.0;
+    if (sepl) {
+        const int row = (sig + 1) * Ls - 1;
+        G = (double)a.rhat[fb + (size_t)row * nx1 + k] * a.inv_b + Ef[((size_t)sig * 3 + 1) * nx1 + k] +
+            Ef[((size_t)(sig + 1) * 3 + 0) * nx1 + k];
+    }
+    int woff = 2 + q;
+    for (int l = 0; l < q; ++l) {
+        const int size = P >> l;
+        const int pos = sig & (size - 1);
+        const bool member = sepl && (pos != size - 1);
+        const int widx = min(pos, size - 2 - pos);
+        double tv = member ? tab[woff + widx] * G : 0.0;
+        for (int off = 1; off < size; off <<= 1) tv += __shfl_xor(tv, off, 64);
+        const int base = sig - pos;
+        const int ll = base - 1, rl = base + size - 1;
+        const double xl_ = __shfl(x, ll < 0 ? 0 : ll, 64);
+        const double xr_ = __shfl(x, rl > 63 ? 63 : rl, 64);
+        const double xl = (ll < 0) ? 0.0 : xl_;
+        const double xr = (rl >= P - 1) ? 0.0 : xr_;
+        if (member && pos == (size >> 1) - 1) x = tv + tab[2 + l] * (xl + xr);
+        woff += size >> 1;
+    }
+    if (sepl) a.y[fb + (size_t)((sig + 1) * Ls - 1) * nx1 + k] = (T)x;
+    if (a.mode == 0) return;
+
+    double c = 0.0;
+    if (valid && sig < P) c += Ef[((size_t)sig * 3 + 2) * nx1 + k];
+    if (sepl) c += x * G;
+    c = wave_sum(c);
+    const double s = block_sum(lane == 0 ? c : 0.0, red);
+    double* part = a.partial + (size_t)field * a.pstride;
+    if (arrive_last(part + bif, s, a.cnt + field, (uint32_t)a.bpf)) {
+        const double tot = sum_partials(part, a.bpf, red);
+        if (threadIdx.x == 0) {
+            ShotCtl& cc = a.ctl[field];
+            const double rz = tot * a.b * a.dot_scale;
+            if (!isfinite(rz)) {
+                cc.status = LG_ERR_NONFINITE;
+                cc.active = 0;
+            } else if (a.mode == 1) {
+                cc.rz = rz;
+                cc.beta = 0.0;
+            } else {
+                cc.beta = rz / cc.rz;
+                cc.rz = rz;
+            }
+        }
+    }
+}
+
+// Standalone interface correction (the CG path fuses it into K5):
+// zhat = y + xl u_i + xr u_{Ls-i} on segment rows, in place.
+template <typename T>
+__global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, int nx1, int nz1,
+                                                      int Ls, int P, size_t total) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    const size_t npts = (size_t)nx1 * nz1;
+    const size_t f = e / npts;
+    const size_t pt = e - f * npts;
+    const int j = (int)(pt / nx1), k = (int)(pt - (size_t)j * nx1);
+    const int jj = j + 1;
+    const int rs = jj & (Ls - 1);
+    if (rs == 0) return;
+    const int s = jj / Ls;
+    T* Y = y + f * npts;
+    const T xl = (s > 0) ? Y[(size_t)(s * Ls - 1) * nx1 + k] : (T)0;
+    const T xr = (s < P - 1) ? Y[(size_t)((s + 1) * Ls - 1) * nx1 + k] : (T)0;
+    Y[pt] = Y[pt] + xl * utab[(size_t)rs * nx1 + k] + xr * utab[(size_t)(Ls - rs) * nx1 + k];
+}
+
+// ===========================================================================
+// Right-hand side of harmonic m (eq. laguerre_h, SPD sign):
+//   P_{m-1} = sqrt((m-1)/(m-1+a)) P_{m-2} + R_{m-1}
+//   Q_m     = sqrt(m/(m+a)) (Q_{m-1} + P_{m-1})
+//   rhs     = -h^2 rho Q_m           (the source is added by src_kernel)
+// ===========================================================================
+__global__ __launch_bounds__(256) void rhs_kernel(int m, const double* __restrict__ Rp,
+                                                  double* __restrict__ Ph, double* __restrict__ Qh,
+                                                  const double* __restrict__ rho, double hh,
+                                                  double rp, double rq, double* __restrict__ rhs,
+                                                  size_t npts, size_t total) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    if (m == 0) {
+        Ph[e] = 0.0;
+        Qh[e] = 0.0;
+        rhs[e] = 0.0;
+        return;
+    }
+    const double P = rp * Ph[e] + Rp[e];
+    const double Q = rq * (Qh[e] + P);
+    Ph[e] = P;
+    Qh[e] = Q;
+    rhs[e] = 0.0 - (hh * rho[e % npts]) * Q;
+}
+
+constexpr int SRC_CHUNK = 64;
+struct SrcArgs {
+    int n;
+    int32_t idx[SRC_CHUNK];     // element offset of the source node, per shot
+    double val[SRC_CHUNK];
+};
+
+__global__ void src_kernel(SrcArgs s, double* rhs) {
+    const int t = threadIdx.x;
+    if (t < s.n) rhs[s.idx[t]] += s.val[t];
+}
+
+// ===========================================================================
+// Synthesis (eq. series_lag): snapshots += W_s R_m; receiver-row coefficients.
+// ===========================================================================
+constexpr int MAX_SNAP = 8;
+struct SynArgs {
+    const double* R;
+    double* snap;
+    double* rec;
+    double W[MAX_SNAP];
+    int nsnap, m, n, rec_row0, nx1, nz1;
+    size_t npts, total;
+};
+
+__global__ __launch_bounds__(256) void synth_kernel(SynArgs a) {
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.total) return;
+    const double R = a.R[e];
+#pragma unroll
+    for (int s = 0; s < MAX_SNAP; ++s)
+        if (s < a.nsnap) a.snap[(size_t)s * a.total + e] += a.W[s] * R;
+    if (a.rec != nullptr) {
+        const size_t f = e / a.npts;
+        const size_t pt = e - f * a.npts;
+        const int j = (int)(pt / a.nx1);
+        if (j == a.rec_row0) {
+            const int i = (int)(pt - (size_t)j * a.nx1);
+            a.rec[(f * a.n + a.m) * a.nx1 + i] = R;
+        }
+    }
+}
+
+// traces[f][q][i] = sum_m W[q][m] rec[f][m][i]   (FP64; 8 outputs per thread)
+constexpr int TR_Q = 8;
+__global__ __launch_bounds__(256) void traces_kernel(const double* __restrict__ rec,
+                                                     const double* __restrict__ W, int n, int nt,
+                                                     int nx1, double* __restrict__ out) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int q0 = blockIdx.y * TR_Q;
+    const int f = blockIdx.z;
+    if (i >= nx1) return;
+    double acc[TR_Q];
+#pragma unroll
+    for (int u = 0; u < TR_Q; ++u) acc[u] = 0.0;
+    const double* rf = rec + (size_t)f * n * nx1 + i;
+    for (int m = 0; m < n; ++m) {
+        const double v = rf[(size_t)m * nx1];
+#pragma unroll
+        for (int u = 0; u < TR_Q; ++u)
+            if (q0 + u < nt) acc[u] += W[(size_t)(q0 + u) * n + m] * v;
+    }
+#pragma unroll
+    for (int u = 0; u < TR_Q; ++u)
+        if (q0 + u < nt) out[((size_t)f * nt + q0 + u) * nx1 + i] = acc[u];
+}
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+namespace {
+
+template <typename T>
+hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
+    StArgs<T> a;
+    a.p = x;
+    a.q = y;
+    a.kap = (const T*)p->kap;
+    a.w = (const T*)p->w;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
+    a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
+    a.ctl = reduce ? p->ctl : nullptr;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    a.cnt = p->counters + (size_t)CNT_STENCIL * p->S * p->C;
+    dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT), p->S * p->C);
+    hipLaunchKernelGGL(stencil_kernel<T>, grid, dim3(256), 0, p->stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, int M, int MODE>
+hipError_t dst_launch_M(lg_plan* pl, DstArgs<T>& a, int nfields) {
+    constexpr int R = M >= 16 ? 16 : M;
+    constexpr int TPF = M / R;
+    constexpr int FPB = TPF >= 256 ? 1 : 256 / TPF;
+    const int npairs = (a.nz1 + 1) / 2;
+    a.bpf = (npairs + FPB - 1) / FPB;
+    const dim3 grid(a.bpf * nfields);
+    hipLaunchKernelGGL((dst_kernel<T, M, R, FPB, MODE>), grid, dim3(FPB * TPF), 0, pl->stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t dst_dispatch(lg_plan* pl, DstArgs<T>& a, int nfields) {
+    switch (2 * pl->g.nx) {
+        case 4: return dst_launch_M<T, 4, MODE>(pl, a, nfields);
+        case 8: return dst_launch_M<T, 8, MODE>(pl, a, nfields);
+        case 16: return dst_launch_M<T, 16, MODE>(pl, a, nfields);
+        case 32: return dst_launch_M<T, 32, MODE>(pl, a, nfields);
+        case 64: return dst_launch_M<T, 64, MODE>(pl, a, nfields);
+        case 128: return dst_launch_M<T, 128, MODE>(pl, a, nfields);
+        case 256: return dst_launch_M<T, 256, MODE>(pl, a, nfields);
+        case 512: return dst_launch_M<T, 512, MODE>(pl, a, nfields);
+        case 1024: return dst_launch_M<T, 1024, MODE>(pl, a, nfields);
+        case 2048: return dst_launch_M<T, 2048, MODE>(pl, a, nfields);
+        case 4096: return dst_launch_M<T, 4096, MODE>(pl, a, nfields);
+        case 8192: return dst_launch_M<T, 8192, MODE>(pl, a, nfields);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+DstArgs<T> dst_args(lg_plan* p) {
+    DstArgs<T> a{};
+    a.tw = (const cpx<T>*)p->tw;
+    a.nz1 = p->nz1;
+    a.ctl = p->ctl;
+    a.xslot = p->xslot;
+    a.r = p->r;
+    a.p = (const T*)p->p;
+    a.q = (const T*)p->qv;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    a.cnt = p->counters + (size_t)CNT_UPDATE * p->S * p->C;
+    a.y = (const T*)p->y;
+    a.utab = (const T*)p->blk[0].utab;
+    a.Ls = p->blk[0].Ls;
+    a.P = p->blk[0].P;
+    return a;
+}
+
+template <typename T, int LS>
+hipError_t td_launch(lg_plan* p, TdArgs<T>& a, int nfields) {
+    const int wpb = std::min(4, a.P);
+    dim3 grid((a.nx1 + 63) / 64, (a.P + wpb - 1) / wpb, nfields);
+    hipLaunchKernelGGL((td_kernel<T, LS>), grid, dim3(64 * wpb), 0, p->stream, a);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t td_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, bool masked) {
+    const PrecBlock& B = p->blk[bi];
+    TdArgs<T> a;
+    a.rhat = rhat;
+    a.y = y;
+    a.etab = (const T*)B.etab;
+    a.E = p->E;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.P = B.P;
+    a.inv_b = (T)(1.0 / B.b);
+    a.ctl = masked ? p->ctl : nullptr;
+    switch (B.Ls) {
+        case 2: return td_launch<T, 2>(p, a, nfields);
+        case 4: return td_launch<T, 4>(p, a, nfields);
+        case 8: return td_launch<T, 8>(p, a, nfields);
+        case 16: return td_launch<T, 16>(p, a, nfields);
+        case 32: return td_launch<T, 32>(p, a, nfields);
+        case 64: return td_launch<T, 64>(p, a, nfields);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode) {
+    const PrecBlock& B = p->blk[bi];
+    RsArgs<T> a;
+    a.rhat = rhat;
+    a.y = y;
+    a.E = p->E;
+    a.red = B.red;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.P = B.P;
+    a.q = B.q;
+    a.Ls = B.Ls;
+    a.RW = B.RW;
+    a.bpf = (p->nx1 + 3) / 4;
+    a.inv_b = 1.0 / B.b;
+    a.b = B.b;
+    a.dot_scale = 2.0 / p->g.nx;
+    a.mode = mode;
+    a.ctl = p->ctl;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    a.cnt = p->counters + (size_t)CNT_REDUCED * p->S * p->C;
+    hipLaunchKernelGGL(rs_kernel<T>, dim3(a.bpf * nfields), dim3(256), 0, p->stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq) {
+    if (p->prec == LG_FP64) return stencil_T<double>(p, (const double*)x, (double*)y, reduce_pq);
+    return stencil_T<float>(p, (const float*)x, (float*)y, reduce_pq);
+}
+
+hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nfields) {
+    if (p->prec == LG_FP64) {
+        DstArgs<double> a = dst_args<double>(p);
+        a.in = (const double*)in;
+        a.out = (double*)out;
+        return inverse ? dst_dispatch<double, DST_INV>(p, a, nfields)
+                       : dst_dispatch<double, DST_FWD>(p, a, nfields);
+    }
+    DstArgs<float> a = dst_args<float>(p);
+    a.in = (const float*)in;
+    a.out = (float*)out;
+    return inverse ? dst_dispatch<float, DST_INV>(p, a, nfields)
+                   : dst_dispatch<float, DST_FWD>(p, a, nfields);
+}
+
+hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
+                              int max_iter) {
+    if (p->prec == LG_FP64) {
+        DstArgs<double> a = dst_args<double>(p);
+        a.out = (double*)p->rhat;
+        a.init = init;
+        a.b = b;
+        a.x = x;
+        a.tol2 = tol * tol;
+        a.max_iter = max_iter;
+        return dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
+    }
+    DstArgs<float> a = dst_args<float>(p);
+    a.out = (float*)p->rhat;
+    a.init = init;
+    a.b = b;
+    a.x = x;
+    a.tol2 = tol * tol;
+    a.max_iter = max_iter;
+    return dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
+}
+
+hipError_t launch_correct_idst(lg_plan* p, int init) {
+    if (p->prec == LG_FP64) {
+        DstArgs<double> a = dst_args<double>(p);
+        a.out = (double*)p->p;
+        a.init = init;
+        return dst_dispatch<double, DST_CORRECT>(p, a, p->S * p->C);
+    }
+    DstArgs<float> a = dst_args<float>(p);
+    a.out = (float*)p->p;
+    a.init = init;
+    return dst_dispatch<float, DST_CORRECT>(p, a, p->S * p->C);
+}
+
+hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked) {
+    if (p->prec == LG_FP64)
+        return td_T<double>(p, blk, (const double*)rhat, (double*)y, nfields, masked != 0);
+    return td_T<float>(p, blk, (const float*)rhat, (float*)y, nfields, masked != 0);
+}
+
+hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int mode) {
+    if (p->prec == LG_FP64) return rs_T<double>(p, blk, (const double*)rhat, (double*)y, nfields, mode);
+    return rs_T<float>(p, blk, (const float*)rhat, (float*)y, nfields, mode);
+}
+
+hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields) {
+    const PrecBlock& B = p->blk[blk];
+    const size_t total = (size_t)nfields * p->npts;
+    const dim3 grid((unsigned)((total + 255) / 256));
+    if (p->prec == LG_FP64)
+        hipLaunchKernelGGL(correct_kernel<double>, grid, dim3(256), 0, p->stream, (double*)y,
+                           (const double*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total);
+    else
+        hipLaunchKernelGGL(correct_kernel<float>, grid, dim3(256), 0, p->stream, (float*)y,
+                           (const float*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,
+                      const double* fsrc_host, double* rhs) {
+    const size_t total = p->nvec;
+    const double a = p->lag.alpha;
+    const double rp = (m >= 2) ? std::sqrt((m - 1.0) / (m - 1.0 + a)) : 0.0;
+    const double rq = (m >= 1) ? std::sqrt(m / (m + a)) : 0.0;
+    const double hh = p->lag.h * p->lag.h;
+    hipLaunchKernelGGL(rhs_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, p->stream, m,
+                       Rprev, Ph, Qh, p->rho64, hh, rp, rq, rhs, p->npts, total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const double inv = 1.0 / (p->g.dx * p->g.dz);
+    for (int s0 = 0; s0 < p->S; s0 += SRC_CHUNK) {
+        SrcArgs sa;
+        sa.n = std::min(SRC_CHUNK, p->S - s0);
+        for (int t = 0; t < sa.n; ++t) {
+            const int s = s0 + t;
+            const int i = p->src_host[2 * s], j = p->src_host[2 * s + 1];
+            const int comp = p->C - 1;   // acoustic: 0; elastic: z component
+            sa.idx[t] = (int32_t)(((size_t)s * p->C + comp) * p->npts + (size_t)(j - 1) * p->nx1 + (i - 1));
+            sa.val[t] = fsrc_host[s] * inv;
+        }
+        hipLaunchKernelGGL(src_kernel, dim3(1), dim3(SRC_CHUNK), 0, p->stream, sa, rhs);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_synth(lg_plan* p, int m, const double* R, const double* Wsnap, int nsnap,
+                        double* snap, int rec_row, double* rec) {
+    SynArgs a;
+    a.R = R;
+    a.snap = snap;
+    a.rec = rec;
+    for (int s = 0; s < MAX_SNAP; ++s) a.W[s] = (s < nsnap) ? Wsnap[s] : 0.0;
+    a.nsnap = nsnap;
+    a.m = m;
+    a.n = p->lag.n;
+    a.rec_row0 = rec_row - 1;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.npts = p->npts;
+    a.total = p->nvec;
+    hipLaunchKernelGGL(synth_kernel, dim3((unsigned)((a.total + 255) / 256)), dim3(256), 0, p->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_traces(lg_plan* p, const double* rec, const double* Wdev, int nt, double* traces) {
+    dim3 grid((p->nx1 + 255) / 256, (nt + TR_Q - 1) / TR_Q, p->S * p->C);
+    hipLaunchKernelGGL(traces_kernel, grid, dim3(256), 0, p->stream, rec, Wdev, p->lag.n, nt, p->nx1,
+                       traces);
+    return hipGetLastError();
+}
+
+}  // namespace lg

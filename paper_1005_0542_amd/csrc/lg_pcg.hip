@@ -1,0 +1,126 @@
+// Preconditioned CG driver (Sec. 2.3): all shots of the plan iterate together,
+// every scalar (alpha, beta, norms, convergence) stays on the device, and
+// converged shots drop out by masking.  Batches of iterations are captured in
+// a HIP graph once per plan and replayed; the host only reads the per-shot
+// "active" flags between batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "lg_internal.h"
+
+namespace lg {
+
+namespace {
+
+hipError_t enqueue_iteration(lg_plan* p) {
+    const int nf = p->S * p->C;
+    hipError_t e = launch_stencil(p, p->p, p->qv, true);                  // q = A p, alpha
+    if (e == hipSuccess) e = launch_update_fdst(p, 0, nullptr, nullptr, 0.0, 0);  // x, r, rhat
+    if (e == hipSuccess) e = launch_td(p, 0, p->rhat, p->y, nf, 1);        // segments
+    if (e == hipSuccess) e = launch_rs(p, 0, p->rhat, p->y, nf, 2);        // interfaces, beta
+    if (e == hipSuccess) e = launch_correct_idst(p, 0);                    // z, p = z + beta p
+    return e;
+}
+
+lg_status build_graph(lg_plan* p) {
+    if (p->cg_graph != nullptr) return LG_OK;
+    if (p->cap_stream == nullptr) LG_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    hipStream_t saved = p->stream;
+    p->stream = p->cap_stream;
+    hipError_t e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        p->stream = saved;
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    hipError_t le = hipSuccess;
+    for (int i = 0; i < p->graph_iters && le == hipSuccess; ++i) le = enqueue_iteration(p);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(p->cap_stream, &g);
+    p->stream = saved;
+    if (le != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return hip_fail(le, "kernel launch during capture");
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&p->cg_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        p->cg_graph = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return LG_OK;
+}
+
+int severity(int s) {
+    switch (s) {
+        case LG_OK: return 0;
+        case LG_ERR_NOT_CONVERGED: return 1;
+        case LG_ERR_BREAKDOWN: return 2;
+        case LG_ERR_NONFINITE: return 3;
+        default: return 4;
+    }
+}
+
+}  // namespace
+
+void pcg_release(lg_plan* p) {
+    if (p->cg_graph) (void)hipGraphExecDestroy(p->cg_graph);
+    p->cg_graph = nullptr;
+}
+
+lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts* o, lg_solve_info* info) {
+    const int nf = p->S * p->C;
+    const bool use_graph = p->graph_iters > 0;
+    const int chunk = use_graph ? p->graph_iters : 8;
+    if (use_graph) {
+        lg_status st = build_graph(p);
+        if (st != LG_OK) return st;
+    }
+    // start: x = 0, r = b, rhat = DST(b), z = B^{-1} r, p = z, rz = (r, z)
+    LG_HIP(launch_update_fdst(p, 1, b, x, o->tol, o->max_iter));
+    LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
+    LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
+    LG_HIP(launch_correct_idst(p, 1));
+
+    long launched = 0;
+    // Replay as many batches as the previous solve needed before the first
+    // check: consecutive harmonics take similar iteration counts.
+    long ahead = std::max(1L, (long)((p->last_iters + chunk - 1) / chunk));
+    const long cap = (long)o->max_iter + chunk;
+    while (true) {
+        for (long bt = 0; bt < ahead && launched < cap; ++bt) {
+            if (use_graph) {
+                LG_HIP(hipGraphLaunch(p->cg_graph, p->stream));
+            } else {
+                for (int i = 0; i < chunk; ++i) LG_HIP(enqueue_iteration(p));
+            }
+            launched += chunk;
+        }
+        LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
+                              p->stream));
+        LG_HIP(hipStreamSynchronize(p->stream));
+        bool any = false;
+        for (int s = 0; s < nf; ++s) any = any || (p->ctl_host[s].active != 0);
+        if (!any || launched >= cap) break;
+        ahead = 1;
+    }
+    int worst = LG_OK, maxit = 0;
+    for (int s = 0; s < nf; ++s) {
+        const ShotCtl& c = p->ctl_host[s];
+        int st = c.status;
+        if (c.active) st = LG_ERR_NOT_CONVERGED;   // only if the safety cap was hit
+        if (severity(st) > severity(worst)) worst = st;
+        maxit = std::max(maxit, (int)c.iters);
+        if (info) {
+            info[s].iters = c.iters;
+            info[s].status = st;
+            info[s].relres = (c.bb > 0.0) ? std::sqrt(c.rr / c.bb) : 0.0;
+        }
+    }
+    p->last_iters = maxit;
+    return (lg_status)worst;
+}
+
+}  // namespace lg

@@ -1,0 +1,85 @@
+"""Harmonic loop of the Laguerre method on the HIP library (product path).
+
+For harmonics m = 0, 1, ... (strictly in order, eq. laguerre_h):
+  1. ``lg_laguerre_rhs``        right-hand side from the running history sums;
+  2. ``lg_pcg_solve``           A R_m = rhs by preconditioned CG (all shots);
+  3. ``lg_laguerre_synthesize`` snapshots += W_m(t_s) R_m, receiver-row store.
+Traces are formed at the end with ``lg_trace_synthesize``.  Everything runs in
+the library's kernels; this module only allocates the buffers and sequences
+the calls.
+"""
+from __future__ import annotations
+
+from typing import List, Optional
+
+import numpy as np
+
+from . import api, inputs
+
+
+class AcousticRun:
+    """One workload on one GPU: medium, sources, buffers, plan."""
+
+    def __init__(self, w: inputs.Workload, precision: Optional[str] = None, shots: Optional[int] = None,
+                 n_harm: Optional[int] = None, segments: int = 0, graph_iters: int = 0,
+                 snapshots: bool = True, rec: bool = True, tol: Optional[float] = None,
+                 max_iter: int = 10000, medium=None):
+        import torch
+        self.torch = torch
+        self.w = w
+        self.precision = precision or w.precision
+        self.shots = shots or w.shots
+        self.n_harm = n_harm or w.n_harm
+        self.tol = w.tol if tol is None else tol
+        if self.precision == "fp64" and tol is None:
+            self.tol = min(self.tol, 1e-10)
+        self.max_iter = max_iter
+        N = w.n_cells
+        kappa, rho = medium if medium is not None else inputs.acoustic_medium_for(w)
+        self.kappa, self.rho = kappa, rho
+        self.plan = api.Plan("acoustic", N, N, w.d, w.d, w.alpha, w.h, self.n_harm,
+                             np.stack([kappa, rho]), precision=self.precision, nshots=self.shots,
+                             segments=segments, graph_iters=graph_iters)
+        if self.shots == w.shots:
+            src = inputs.sources_for(w)
+        else:
+            src = inputs.shot_positions(N, self.shots, w.shot_seed, w.src_row) if self.shots > 1 \
+                else np.array([w.src or (N // 2, w.src_row)], dtype=np.int32)
+        self.src = src
+        self.plan.set_sources(src)
+        self.f_m = api.source_coeffs(w.f0, w.t0, w.alpha, w.h, self.n_harm)
+        self.t_snap = inputs.snapshot_times(w)
+        self.W_snap = api.laguerre_weights(self.t_snap, w.alpha, w.h, self.n_harm)   # [4, n]
+        dev = "cuda"
+        shape = (self.shots, 1, N - 1, N - 1)
+        f64 = torch.float64
+        self.R = torch.zeros(shape, dtype=f64, device=dev)
+        self.Ph = torch.zeros(shape, dtype=f64, device=dev)
+        self.Qh = torch.zeros(shape, dtype=f64, device=dev)
+        self.rhs = torch.zeros(shape, dtype=f64, device=dev)
+        self.snap = torch.zeros((len(self.t_snap),) + shape, dtype=f64, device=dev) if snapshots else None
+        self.rec = torch.zeros((self.shots, 1, self.n_harm, N - 1), dtype=f64, device=dev) if rec else None
+        self.iters: List[List[int]] = []
+        self.status: List[int] = []
+        self.m = 0
+
+    def step(self) -> api.SolveResult:
+        """Advance one harmonic (rhs, solve, synthesis)."""
+        m = self.m
+        fs = np.full(self.shots, self.f_m[m])
+        self.plan.laguerre_rhs(m, self.R if m else None, self.Ph, self.Qh, fs, self.rhs)
+        res = self.plan.pcg_solve(self.rhs, self.R, tol=self.tol, max_iter=self.max_iter)
+        if self.snap is not None or self.rec is not None:
+            ws = self.W_snap[:, m] if self.snap is not None else []
+            self.plan.laguerre_synthesize(m, self.R, ws, self.snap, self.w.rec_row, self.rec)
+        self.iters.append(res.iters)
+        self.status.append(res.status)
+        self.m += 1
+        return res
+
+    def traces(self, t: np.ndarray):
+        W = api.laguerre_weights(t, self.w.alpha, self.w.h, self.n_harm)
+        out = self.torch.zeros((self.shots, 1, len(t), self.w.n_cells - 1), dtype=self.torch.float64,
+                               device="cuda")
+        self.plan.trace_synthesize(self.rec, W, out)
+        return out

@@ -1,0 +1,135 @@
+"""Host-only checks of the C ABI (no GPU needed).
+
+* the library loads and exports every function declared in include/laguerre.h;
+* argument validation returns LG_ERR_INVALID_ARG before any device work;
+* the host Laguerre helpers agree with the oracle.
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1005_0542_amd import _lib, api
+from oracle import laguerre as olag
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "laguerre.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lg_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    # the seven hot-path calls of the method are among them
+    for n in ("lg_laguerre_rhs", "lg_stencil_apply", "lg_precond_dst", "lg_precond_dichotomy_tdma",
+              "lg_pcg_solve", "lg_gmres_solve", "lg_laguerre_synthesize"):
+        assert n in names
+
+
+def test_status_strings():
+    lib = _lib.load()
+    for s in range(8):
+        assert lib.lg_status_string(s).decode()
+    assert lib.lg_status_string(0).decode() == "ok"
+
+
+def _create(kind=_lib.LG_ACOUSTIC, nx=16, nz=16, dx=5.0, dz=5.0, alpha=9, h=200.0, n=8,
+            prec=_lib.LG_FP64, shots=1, medium="ok", segments=0, graph_iters=0):
+    lib = _lib.load()
+    F = 2 if kind == _lib.LG_ACOUSTIC else 3
+    if isinstance(medium, str):
+        med = np.ones((F, nz + 1, nx + 1)) if nx > 0 and nz > 0 else np.ones(4)
+    else:
+        med = medium
+    med = np.ascontiguousarray(med, dtype=np.float64)
+    grid = _lib.Grid(nx, nz, dx, dz)
+    lag = _lib.Laguerre(alpha, h, n)
+    tun = _lib.Tuning(segments, graph_iters)
+    handle = ctypes.c_void_p()
+    st = lib.lg_plan_create(ctypes.byref(handle), kind, ctypes.byref(grid), ctypes.byref(lag), prec, shots,
+                            med.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(tun), None)
+    return st
+
+
+@pytest.mark.parametrize("kw", [
+    dict(nx=1), dict(nz=0), dict(dx=0.0), dict(dz=-1.0), dict(dx=float("nan")), dict(alpha=1),
+    dict(h=0.0), dict(h=float("inf")), dict(n=0), dict(shots=0), dict(kind=7), dict(prec=5),
+    dict(segments=3), dict(segments=128), dict(segments=16, nz=16), dict(graph_iters=-5),
+    dict(graph_iters=1000),
+])
+def test_plan_create_rejects_invalid_arguments(kw):
+    assert _create(**kw) == _lib.LG_ERR_INVALID_ARG
+
+
+def test_plan_create_rejects_nonfinite_medium():
+    med = np.ones((2, 17, 17))
+    med[1, 3, 4] = np.nan
+    assert _create(medium=med) == _lib.LG_ERR_INVALID_ARG
+
+
+def test_plan_create_unsupported_shapes():
+    assert _create(nx=24, nz=16) == _lib.LG_ERR_UNSUPPORTED
+    assert _create(nx=8192, nz=16) == _lib.LG_ERR_UNSUPPORTED
+
+
+def test_null_arguments_rejected():
+    lib = _lib.load()
+    assert lib.lg_plan_create(None, 0, None, None, 0, 1, None, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_plan_destroy(None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_stencil_apply(None, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_pcg_solve(None, None, None, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_gmres_solve(None, None, None, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_precond_dst(None, 0, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_precond_dichotomy_tdma(None, 0, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_laguerre_rhs(None, 0, None, None, None, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_laguerre_synthesize(None, 0, None, None, 0, None, 0, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_source_coeffs(0, 10.0, 0.1, 4.0, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert "NULL" in lib.lg_last_error().decode()
+
+
+@pytest.mark.parametrize("f0,alpha,h,n", [(15.0, 9, 200.0, 64), (25.0, 9, 400.0, 128), (20.0, 8, 300.0, 96)])
+def test_source_coeffs_match_oracle(f0, alpha, h, n):
+    t0 = 1.5 / f0
+    got = api.source_coeffs(f0, t0, alpha, h, n)
+    ref = olag.ricker_coeffs(f0, t0, h, alpha, n)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_gauss_sine_coeffs_match_oracle():
+    f0, t0, gam, alpha, h, n = 30.0, 0.2, 4.0, 9, 400.0, 100
+    got = api.source_coeffs(f0, t0, alpha, h, n, wavelet="gauss_sine", gamma=gam)
+    t_end = t0 + 8.0 * gam / (2 * math.pi * f0)
+    ref = olag.source_coeffs(olag.gauss_sine(f0, t0, gam), t_end, h, alpha, n)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("alpha,h,n,T", [(9, 200.0, 64, 0.4), (9, 600.0, 1024, 2.0), (8, 300.0, 256, 0.6)])
+def test_laguerre_weights_match_oracle(alpha, h, n, T):
+    t = np.linspace(0.0, T, 41)
+    got = api.laguerre_weights(t, alpha, h, n)
+    ref = olag.synthesis_weights(t, h, alpha, n)
+    scale = np.max(np.abs(ref), axis=1, keepdims=True) + 1e-300
+    assert np.max(np.abs(got - ref) / scale) < 1e-10
+
+
+def test_host_helpers_reject_bad_parameters():
+    lib = _lib.load()
+    out = np.zeros(4)
+    lag = _lib.Laguerre(1, 100.0, 4)
+    p = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert lib.lg_source_coeffs(0, 10.0, 0.1, 4.0, ctypes.byref(lag), p) == _lib.LG_ERR_INVALID_ARG
+    lag = _lib.Laguerre(9, 100.0, 4)
+    assert lib.lg_source_coeffs(0, -1.0, 0.1, 4.0, ctypes.byref(lag), p) == _lib.LG_ERR_INVALID_ARG
+    t = np.array([-1.0])
+    assert lib.lg_laguerre_weights(ctypes.byref(lag), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1,
+                                   p) == _lib.LG_ERR_INVALID_ARG
