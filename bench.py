@@ -1,0 +1,219 @@
+"""Benchmark of the Laguerre-harmonic PCG solve on one MI355X.
+
+One *step* is one harmonic of the Laguerre method over the whole shot batch:
+right-hand side (``lg_laguerre_rhs``), preconditioned CG to tolerance
+(``lg_pcg_solve``: operator, DST-I, Dichotomy solve, inverse DST per
+iteration) and synthesis (``lg_laguerre_synthesize``).  Harmonics are run in
+order from m = 0; the first ``--warmup`` are untimed (they also build the
+plan's HIP graph), the next ``--steps`` are timed between device
+synchronisations.
+
+Metric: PCG Mpoint-iters/s = sum over timed harmonics and shots of
+(interior points x CG iterations) / wall time / 1e6.  The headline workload is
+the mixed-precision 64-shot batch on a 2048^2 grid; the other precision/shot
+combinations of the metric are reported under "variants".
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PCG Mpoint-iters/s & HBM GB/s: FP64 plain vs mixed precision, 1 vs 64 shots"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_bytes(ws: int, shots: int, seg_len: int):
+    """Algorithmic HBM bytes per shot-point for each kernel of one CG iteration
+    (every array touched once per launch; medium arrays shared by all shots)."""
+    return {
+        "operator": 2 * ws + 2 * ws / shots,                  # p in, q out; kappa, w once per batch
+        "update_fdst": 32 + 3 * ws,                           # x, r in/out (f64); p, q in; rhat out
+        "dichotomy_segments": 2 * ws + 24.0 / seg_len,        # rhat in, y out; 3 f64 per segment
+        "interfaces": (2 * ws + 24.0) / seg_len,              # separator rows, segment data
+        "correct_idst": 3 * ws,                               # y in, p in/out
+    }
+
+
+def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0, profile=True):
+    import torch
+    from paper_1005_0542_amd import inputs
+    from paper_1005_0542_amd.driver import AcousticRun
+
+    w = inputs.WORKLOADS[name]
+    n_harm = warmup + steps
+    log(f"{name}: precision={precision} shots={shots} harmonics={n_harm}")
+    t0 = time.perf_counter()
+    run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2), segments=segments,
+                      graph_iters=graph_iters)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    npts = (w.n_cells - 1) ** 2
+    for _ in range(warmup):
+        run.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    iters = []
+    for _ in range(steps):
+        res = run.step()
+        iters.append(res.iters)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    pt_iters = float(npts) * float(np.sum(iters))
+    out = {
+        "workload": name, "precision": precision, "shots": shots,
+        "value": pt_iters / el / 1e6, "ms_per_step": 1e3 * el / steps,
+        "iters_per_harmonic": [int(max(i)) for i in iters],
+        "mean_iters": float(np.mean(iters)),
+        "setup_s": setup_s,
+        "status": [int(s) for s in run.status],
+    }
+    seg, seg_len = run.plan.layout()
+    out["segments"] = seg
+    ws = 8 if precision == "fp64" else 4
+    kb = kernel_bytes(ws, shots, seg_len)
+    per_iter_bytes = sum(kb.values()) * npts * shots
+    mean_it = max(out["mean_iters"], 1e-9)
+    t_iter = el / (steps * mean_it)
+    out["alg_bytes_per_point_iter"] = sum(kb.values())
+    out["whole_iteration_GBps"] = per_iter_bytes / t_iter / 1e9   # includes per-harmonic overheads
+    if profile:
+        b = run.rhs.clone()
+        x = torch.empty_like(b)
+        ms = run.plan.pcg_profile(b, x, iters=10)
+        names = list(kb.keys())
+        kern = {}
+        for k, nm in enumerate(names):
+            byts = kb[nm] * npts * shots
+            kern[nm] = {"avg_ms": ms[k], "alg_bytes": byts, "GBps": byts / (ms[k] * 1e-3) / 1e9}
+        out["kernels"] = kern
+        out["iteration_ms_profiled"] = float(sum(ms))
+        dom = max(names, key=lambda nm: kern[nm]["avg_ms"])
+        out["dominant"] = dom
+    out["_run"] = run
+    return out
+
+
+def cpu_baseline(name, k_lo=2, k_hi=12):
+    """The FP64 oracle's PCG (numpy/scipy) on one shot of the same workload:
+    per-iteration time from two fixed-iteration runs (tol = 0)."""
+    from paper_1005_0542_amd import inputs
+    from oracle import operator, precond, krylov
+
+    w = inputs.WORKLOADS[name]
+    kappa, rho = inputs.acoustic_medium_for(w)
+    N, d = w.n_cells, w.d
+    wv = operator.shift_coeff(rho, w.h)
+    B = precond.acoustic_preconditioner(kappa, rho, w.h, N, N, d, d)
+    b = np.zeros((N - 1, N - 1))
+    i, j = inputs.sources_for(w)[0]
+    b[j - 1, i - 1] = 1.0 / (d * d)
+    A = lambda y: operator.apply_A(y, kappa, wv, d, d)
+    times, cpus = [], []
+    for k in (k_lo, k_hi):
+        t = time.perf_counter()
+        c = time.process_time()
+        krylov.pcg(A, B.solve, b, 0.0, k)
+        times.append(time.perf_counter() - t)
+        cpus.append(time.process_time() - c)
+    dt = max(times[1] - times[0], 1e-9)
+    its = k_hi - k_lo
+    npts = (N - 1) ** 2
+    cores = max(1, int(round((cpus[1] - cpus[0]) / dt)))
+    return {
+        "value": npts * its / dt / 1e6, "unit": "Mpoint-iters/s", "cores": cores,
+        "kind": "oracle",
+        "sample": f"FP64 numpy oracle PCG, 1 shot of {name} ({N - 1}^2 points), "
+                  f"{its} iterations (difference of {k_hi}- and {k_lo}-iteration runs), "
+                  f"{os.cpu_count()} host cores visible",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="acoustic2048x64_mixed")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--segments", type=int, default=0)
+    ap.add_argument("--graph-iters", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(shots would shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_1005_0542_amd import inputs
+
+    w = inputs.WORKLOADS[args.workload]
+    head = run_variant(args.workload, w.precision, w.shots, args.steps, args.warmup,
+                       segments=args.segments, graph_iters=args.graph_iters)
+    head.pop("_run")
+    torch.cuda.empty_cache()
+    variants = {}
+    if not args.no_variants:
+        plan = [
+            ("acoustic1024", "fp64", 1, "fp64_1shot_1024"),
+            ("acoustic4096_mixed", "fp64", 1, "fp64_1shot_4096"),
+            ("acoustic4096_mixed", "mixed", 1, "mixed_1shot_4096"),
+            ("acoustic2048x64_mixed", "fp64", 64, "fp64_64shot_2048"),
+        ]
+        for name, prec, shots, key in plan:
+            v = run_variant(name, prec, shots, max(2, args.steps // 2), 1)
+            v.pop("_run")
+            variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "value", "ms_per_step",
+                                               "mean_iters", "whole_iteration_GBps", "dominant")}
+            variants[key]["kernels_GBps"] = {k: round(x["GBps"], 1) for k, x in v["kernels"].items()}
+            torch.cuda.empty_cache()
+        fp64_1 = variants["fp64_1shot_4096"]["value"]
+        variants["speedup_mixed64_vs_fp64_1shot_per_iteration"] = head["value"] / fp64_1
+
+    dom = head["dominant"]
+    kd = head["kernels"][dom]
+    achieved = kd["GBps"]
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "per_kernel_GBps": {k: round(x["GBps"], 1) for k, x in head["kernels"].items()},
+            "per_kernel_ms": {k: round(x["avg_ms"], 4) for k, x in head["kernels"].items()},
+            "whole_iteration_GBps": round(head["whole_iteration_GBps"], 1),
+            "alg_bytes_per_point_iter": round(head["alg_bytes_per_point_iter"], 2)}
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(args.workload)
+    line = {
+        "metric": METRIC, "value": round(head["value"], 1), "unit": "Mpoint-iters/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64" if w.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": f"{w.n_cells}x{w.n_cells}", "dx_m": w.d,
+                   "shots": w.shots, "precision": w.precision, "tol": w.tol, "alpha": w.alpha,
+                   "h": w.h, "harmonics_timed": f"{args.warmup}..{args.warmup + args.steps - 1}",
+                   "segments": head["segments"], "parallelism": "single GPU, shot batch"},
+        "iters_per_harmonic": head["iters_per_harmonic"],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "variants": variants,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

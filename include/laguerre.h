@@ -208,6 +208,18 @@ lg_status lg_laguerre_synthesize(lg_plan* plan, int32_t m, const double* R_m,
 lg_status lg_trace_synthesize(lg_plan* plan, const double* rec_coeff, const double* W_host,
                               int32_t nt, double* traces);
 
+/* Measurement helper (not part of the method): starts CG on b with tol = 0
+ * (so no shot converges) and runs `iters` (1..1000) eager iterations with HIP
+ * events on the plan stream around each of the five kernels of one
+ * iteration.  ms_host[0..4] receives the average duration in milliseconds of
+ *   0 operator q = A p (+ (p,q), alpha),
+ *   1 x/r update + forward DST of r (+ ||r||^2, convergence test),
+ *   2 Dichotomy segment solves,
+ *   3 interface systems (+ (r,z), beta),
+ *   4 segment correction + inverse DST + p update.
+ * x is overwritten with the iterate.  Acoustic plans only. */
+lg_status lg_pcg_profile(lg_plan* plan, const double* b, double* x, int32_t iters, float* ms_host);
+
 #ifdef __cplusplus
 }
 #endif

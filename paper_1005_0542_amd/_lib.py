@@ -67,6 +67,7 @@ _SIGNATURES = {
     "lg_laguerre_synthesize": [_PLAN, c_int32, c_void_p, POINTER(c_double), c_int32, c_void_p, c_int32,
                                c_void_p],
     "lg_trace_synthesize": [_PLAN, c_void_p, POINTER(c_double), c_int32, c_void_p],
+    "lg_pcg_profile": [_PLAN, c_void_p, c_void_p, c_int32, POINTER(ctypes.c_float)],
 }
 
 _lib = None

@@ -160,6 +160,15 @@ class Plan:
     def gmres_solve(self, b, x, tol: float = 1e-10, max_iter: int = 10000, restart: int = 10) -> SolveResult:
         return self._solve(self.lib.lg_gmres_solve, "lg_gmres_solve", b, x, tol, max_iter, restart)
 
+    def pcg_profile(self, b, x, iters: int = 10) -> List[float]:
+        """Average duration (ms) of the five kernels of one CG iteration."""
+        import torch
+        n = self._nvec()
+        ms = (ctypes.c_float * 5)()
+        check(self.lib.lg_pcg_profile(self.handle, self._ptr(b, torch.float64, "b", n),
+                                      self._ptr(x, torch.float64, "x", n), iters, ms), "lg_pcg_profile")
+        return [float(v) for v in ms]
+
     def laguerre_synthesize(self, m: int, R, W_snap: Sequence[float], snap, rec_row: int = 1, rec=None):
         import torch
         w = np.ascontiguousarray(np.asarray(W_snap, dtype=np.float64))

@@ -1,6 +1,5 @@
 // Device-side building blocks shared by the gfx950 kernels: complex helpers,
-// small in-register DFTs, the LDS Stockham FFT, wave/block reductions and the
-// "last block" grid reduction.
+// small in-register DFTs, the LDS Stockham FFT and wave/block reductions.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -149,41 +148,6 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
     double s = 0.0;
     for (int i = 0; i < nw; ++i) s += scratch[i];
     return s;
-}
-
-__device__ __forceinline__ double load_acquire_f64(const double* p) {
-    unsigned long long u = __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
-                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __longlong_as_double((long long)u);
-}
-
-// Publish this block's partial and report whether it is the last of `nblocks`
-// to arrive on counter `cnt`.  In the last block every thread has executed an
-// acquire fence, so the other blocks' partials are visible; the last block
-// also resets the counter for the next launch.
-__device__ __forceinline__ bool arrive_last(double* partial_slot, double value, uint32_t* cnt,
-                                            uint32_t nblocks) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __hip_atomic_store(reinterpret_cast<unsigned long long*>(partial_slot),
-                           (unsigned long long)__double_as_longlong(value), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-        __threadfence();
-        const uint32_t prev = atomicAdd(cnt, 1u);
-        last = (prev == nblocks - 1);
-        if (last) __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    const bool is_last = last != 0;
-    if (is_last) __threadfence();
-    return is_last;
-}
-
-// Sum `n` partials in a fixed order (deterministic) by the whole block.
-__device__ __forceinline__ double sum_partials(const double* part, int n, double* scratch) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) s += load_acquire_f64(part + i);
-    return block_sum(s, scratch);
 }
 
 }  // namespace lg

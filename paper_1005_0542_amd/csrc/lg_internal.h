@@ -42,10 +42,6 @@ struct ShotCtl {
     int32_t max_iter;
 };
 
-// The last block of a grid-wide reduction is found with one counter per shot
-// and per reduction; the counters live in one small device array.
-enum CounterSlot { CNT_STENCIL = 0, CNT_UPDATE = 1, CNT_REDUCED = 2, CNT_NUM = 4 };
-
 // ---------------------------------------------------------------------------
 // preconditioner block: z-tridiagonal systems per wavenumber
 // ---------------------------------------------------------------------------
@@ -107,7 +103,6 @@ struct lg_plan {
     double* E = nullptr;       // per-segment endpoint data [S*C][P][3][nx-1]
     double* partial = nullptr; // per-block partial sums
     size_t partial_stride = 0; // per shot
-    uint32_t* counters = nullptr;  // [CNT_NUM][S*C]
     lg::ShotCtl* ctl = nullptr;    // [S*C]
     lg::ShotCtl* ctl_host = nullptr;  // pinned mirror
     double** xslot = nullptr;  // device slot holding the caller's x pointer
@@ -152,6 +147,7 @@ hipError_t launch_traces(lg_plan* p, const double* rec, const double* Wdev, int 
 lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts* o,
                     lg_solve_info* info);
 void pcg_release(lg_plan* p);
+lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* ms);
 
 // GMRES driver (lg_elastic.hip)
 lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts* o,

@@ -46,7 +46,6 @@ struct StArgs {
     ShotCtl* ctl;
     double* partial;
     size_t pstride;
-    uint32_t* cnt;
 };
 
 template <typename T>
@@ -96,25 +95,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
     }
     if (a.ctl == nullptr) return;
     const double s = block_sum(pq, red);
-    const uint32_t nb = gridDim.x * gridDim.y;
-    const uint32_t bid = blockIdx.y * gridDim.x + blockIdx.x;
-    double* part = a.partial + (size_t)field * a.pstride;
-    if (arrive_last(part + bid, s, a.cnt + field, nb)) {
-        const double tot = sum_partials(part, (int)nb, red);
-        if (threadIdx.x == 0) {
-            ShotCtl& c = a.ctl[field];
-            c.pq = tot;
-            if (!isfinite(tot)) {
-                c.status = LG_ERR_NONFINITE;
-                c.active = 0;
-            } else if (tot <= 0.0) {
-                c.status = LG_ERR_BREAKDOWN;
-                c.active = 0;
-            } else {
-                c.alpha = c.rz / tot;
-            }
-        }
-    }
+    if (threadIdx.x == 0)
+        a.partial[(size_t)field * a.pstride + blockIdx.y * gridDim.x + blockIdx.x] = s;
 }
 
 // ===========================================================================
@@ -144,7 +126,6 @@ struct DstArgs {
     const T* q;            // UPDATE: A p
     double* partial;
     size_t pstride;
-    uint32_t* cnt;
     double tol2;           // tol^2 (init)
     int max_iter;          // (init)
     int init;
@@ -199,38 +180,84 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                 alpha = a.ctl[field].alpha;
             }
         }
-        for (int i = t; i < NX1; i += TPF) {
+        constexpr int NIT = (NX1 + TPF - 1) / TPF;
+        if constexpr (MODE == DST_UPDATE) {
+            double* __restrict__ X = xp;
+            double* __restrict__ Rr = a.r;
+            if (a.init) {
+                const double* __restrict__ Bv = a.b;
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int i = t + it * TPF;
+                    if (i < NX1) {
+                        const double r0 = Bv[o0 + i];
+                        const double r1 = has1 ? Bv[o1 + i] : 0.0;
+                        Rr[o0 + i] = r0;
+                        X[o0 + i] = 0.0;
+                        if (has1) {
+                            Rr[o1 + i] = r1;
+                            X[o1 + i] = 0.0;
+                        }
+                        rr += r0 * r0 + r1 * r1;
+                        buf[lpad(1 + i)] = {(T)r0, (T)r1};
+                        buf[lpad(M - 1 - i)] = {(T)-r0, (T)-r1};
+                    }
+                }
+            } else {
+                // all loads first (memory-level parallelism), then update and store
+                const T* __restrict__ Pv = a.p;
+                const T* __restrict__ Qv = a.q;
+                double x0[NIT], x1[NIT], r0[NIT], r1[NIT];
+                T p0[NIT], p1[NIT], q0[NIT], q1[NIT];
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int i = t + it * TPF;
+                    x1[it] = r1[it] = 0.0;
+                    p1[it] = q1[it] = (T)0;
+                    if (i < NX1) {
+                        x0[it] = X[o0 + i];
+                        r0[it] = Rr[o0 + i];
+                        p0[it] = Pv[o0 + i];
+                        q0[it] = Qv[o0 + i];
+                        if (has1) {
+                            x1[it] = X[o1 + i];
+                            r1[it] = Rr[o1 + i];
+                            p1[it] = Pv[o1 + i];
+                            q1[it] = Qv[o1 + i];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int i = t + it * TPF;
+                    if (i < NX1) {
+                        const double ra = r0[it] - alpha * (double)q0[it];
+                        const double rb = r1[it] - alpha * (double)q1[it];
+                        X[o0 + i] = x0[it] + alpha * (double)p0[it];
+                        Rr[o0 + i] = ra;
+                        if (has1) {
+                            X[o1 + i] = x1[it] + alpha * (double)p1[it];
+                            Rr[o1 + i] = rb;
+                        }
+                        rr += ra * ra + rb * rb;
+                        buf[lpad(1 + i)] = {(T)ra, (T)rb};
+                        buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = t + it * TPF;
+            if (i >= NX1) break;
             T v0, v1 = (T)0;
             if constexpr (MODE == DST_FWD || MODE == DST_INV) {
                 v0 = a.in[o0 + i];
                 if (has1) v1 = a.in[o1 + i];
-            } else if constexpr (MODE == DST_UPDATE) {
-                double r0, r1 = 0.0;
-                if (a.init) {
-                    r0 = a.b[o0 + i];
-                    a.r[o0 + i] = r0;
-                    xp[o0 + i] = 0.0;
-                    if (has1) {
-                        r1 = a.b[o1 + i];
-                        a.r[o1 + i] = r1;
-                        xp[o1 + i] = 0.0;
-                    }
-                } else {
-                    r0 = a.r[o0 + i] - alpha * (double)a.q[o0 + i];
-                    xp[o0 + i] = xp[o0 + i] + alpha * (double)a.p[o0 + i];
-                    a.r[o0 + i] = r0;
-                    if (has1) {
-                        r1 = a.r[o1 + i] - alpha * (double)a.q[o1 + i];
-                        xp[o1 + i] = xp[o1 + i] + alpha * (double)a.p[o1 + i];
-                        a.r[o1 + i] = r1;
-                    }
-                }
-                rr += r0 * r0 + r1 * r1;
-                v0 = (T)r0;
-                v1 = (T)r1;
             } else {   // DST_CORRECT: zhat = y + xl u_i + xr u_{Ls-i} on segment rows
                 const int Ls = a.Ls, P = a.P;
-                const T* Y = a.y + fbase;
+                const T* __restrict__ Y = a.y + fbase;
+                const T* __restrict__ U = a.utab;
                 auto corr = [&](int j) -> T {
                     T v = Y[(size_t)j * NX1 + i];
                     const int jj = j + 1;
@@ -239,7 +266,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                         const int s = jj / Ls;
                         const T xl = (s > 0) ? Y[(size_t)(s * Ls - 1) * NX1 + i] : (T)0;
                         const T xr = (s < P - 1) ? Y[(size_t)((s + 1) * Ls - 1) * NX1 + i] : (T)0;
-                        v += xl * a.utab[(size_t)rs * NX1 + i] + xr * a.utab[(size_t)(Ls - rs) * NX1 + i];
+                        v += xl * U[(size_t)rs * NX1 + i] + xr * U[(size_t)(Ls - rs) * NX1 + i];
                     }
                     return v;
                 };
@@ -248,6 +275,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
             }
             buf[lpad(1 + i)] = {v0, v1};
             buf[lpad(M - 1 - i)] = {-v0, -v1};
+        }
         }
         if (t == 0) {
             buf[lpad(0)] = {(T)0, (T)0};
@@ -291,45 +319,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
 
     if constexpr (MODE == DST_UPDATE) {
         const double s = block_sum(rr, red);
-        double* part = a.partial + (size_t)field * a.pstride;
-        if (arrive_last(part + bif, s, a.cnt + field, (uint32_t)a.bpf)) {
-            const double tot = sum_partials(part, a.bpf, red);
-            if (threadIdx.x == 0) {
-                ShotCtl& c = a.ctl[field];
-                c.rr = tot;
-                if (a.init) {
-                    c.bb = tot;
-                    c.tol2 = a.tol2 * tot;
-                    c.iters = 0;
-                    c.max_iter = a.max_iter;
-                    c.alpha = 0.0;
-                    c.beta = 0.0;
-                    if (!isfinite(tot)) {
-                        c.status = LG_ERR_NONFINITE;
-                        c.active = 0;
-                    } else if (tot == 0.0) {
-                        c.status = LG_OK;
-                        c.active = 0;
-                    } else {
-                        c.status = LG_ERR_NOT_CONVERGED;
-                        c.active = 1;
-                    }
-                } else {
-                    const int it = c.iters + 1;
-                    c.iters = it;
-                    if (!isfinite(tot)) {
-                        c.status = LG_ERR_NONFINITE;
-                        c.active = 0;
-                    } else if (tot <= c.tol2) {
-                        c.status = LG_OK;
-                        c.active = 0;
-                    } else if (it >= c.max_iter) {
-                        c.status = LG_ERR_NOT_CONVERGED;
-                        c.active = 0;
-                    }
-                }
-            }
-        }
+        if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + bif] = s;
     }
 }
 
@@ -416,77 +406,175 @@ struct RsArgs {
     T* y;
     const double* E;
     const double* red;   // [nx1][RW]
-    int nx1, nz1, P, q, Ls, RW, bpf;
-    double inv_b, b, dot_scale;
+    int nx1, nz1, P, q, Ls, RW;
+    double inv_b;
     int mode;
     ShotCtl* ctl;
     double* partial;
     size_t pstride;
-    uint32_t* cnt;
 };
 
+// One block per (64 consecutive wavenumbers, field).  Phase 1 loads the
+// interface right-hand sides G[s][k] with coalesced row reads into LDS;
+// phase 2 solves the 64 systems, each by one wave with one lane per
+// separator; phase 3 writes the separator values back row by row and forms
+// this block's share of (rhat, zhat) / b.
 template <typename T>
 __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
+    __shared__ double Gs[64 * 65];
+    __shared__ double Xs[64 * 65];
     __shared__ double red[4];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int field = blockIdx.x / a.bpf;
-    const int bif = blockIdx.x - field * a.bpf;
-    const int k = bif * 4 + wave;
+    const int field = blockIdx.y;
     if (a.mode != 0 && a.ctl[field].active == 0) return;   // uniform per block
-    const bool valid = k < a.nx1;
     const int P = a.P, q = a.q, Ls = a.Ls, nx1 = a.nx1;
-    const int sig = lane;
+    const int tid = threadIdx.x, kl = tid & 63, grp = tid >> 6;
+    const int k0 = blockIdx.x * 64;
+    const int k = k0 + kl;
+    const bool valid = k < nx1;
     const size_t fb = (size_t)field * a.nz1 * nx1;
     const double* Ef = a.E + (size_t)field * P * 3 * nx1;
-    const double* tab = a.red + (size_t)(valid ? k : 0) * a.RW;
-    const bool sepl = valid && sig < P - 1;
-    double G = 0.0, x = 0.0;
-    if (sepl) {
-        const int row = (sig + 1) * Ls - 1;
-        G = (double)a.rhat[fb + (size_t)row * nx1 + k] * a.inv_b + Ef[((size_t)sig * 3 + 1) * nx1 + k] +
-            Ef[((size_t)(sig + 1) * 3 + 0) * nx1 + k];
+    double d0 = 0.0;
+    for (int sg = grp; sg < P; sg += 4) {
+        if (valid) d0 += Ef[((size_t)sg * 3 + 2) * nx1 + k];
+        if (sg < P - 1) {
+            double g = 0.0;
+            if (valid)
+                g = (double)a.rhat[fb + (size_t)((sg + 1) * Ls - 1) * nx1 + k] * a.inv_b +
+                    Ef[((size_t)sg * 3 + 1) * nx1 + k] + Ef[((size_t)(sg + 1) * 3 + 0) * nx1 + k];
+            Gs[sg * 65 + kl] = g;
+        }
     }
-    int woff = 2 + q;
-    for (int l = 0; l < q; ++l) {
-        const int size = P >> l;
-        const int pos = sig & (size - 1);
-        const bool member = sepl && (pos != size - 1);
-        const int widx = min(pos, size - 2 - pos);
-        double tv = member ? tab[woff + widx] * G : 0.0;
-        for (int off = 1; off < size; off <<= 1) tv += __shfl_xor(tv, off, 64);
-        const int base = sig - pos;
-        const int ll = base - 1, rl = base + size - 1;
-        const double xl_ = __shfl(x, ll < 0 ? 0 : ll, 64);
-        const double xr_ = __shfl(x, rl > 63 ? 63 : rl, 64);
-        const double xl = (ll < 0) ? 0.0 : xl_;
-        const double xr = (rl >= P - 1) ? 0.0 : xr_;
-        if (member && pos == (size >> 1) - 1) x = tv + tab[2 + l] * (xl + xr);
-        woff += size >> 1;
-    }
-    if (sepl) a.y[fb + (size_t)((sig + 1) * Ls - 1) * nx1 + k] = (T)x;
-    if (a.mode == 0) return;
+    __syncthreads();
 
-    double c = 0.0;
-    if (valid && sig < P) c += Ef[((size_t)sig * 3 + 2) * nx1 + k];
-    if (sepl) c += x * G;
-    c = wave_sum(c);
-    const double s = block_sum(lane == 0 ? c : 0.0, red);
-    double* part = a.partial + (size_t)field * a.pstride;
-    if (arrive_last(part + bif, s, a.cnt + field, (uint32_t)a.bpf)) {
-        const double tot = sum_partials(part, a.bpf, red);
-        if (threadIdx.x == 0) {
-            ShotCtl& cc = a.ctl[field];
-            const double rz = tot * a.b * a.dot_scale;
-            if (!isfinite(rz)) {
-                cc.status = LG_ERR_NONFINITE;
-                cc.active = 0;
-            } else if (a.mode == 1) {
-                cc.rz = rz;
-                cc.beta = 0.0;
+    // phase 2: Dichotomy on the interface system, lanes = separators
+    const int lane = tid & 63, wave = tid >> 6;
+    const int sig = lane;
+    const bool sepl = sig < P - 1;
+    for (int kk = wave; kk < 64; kk += 4) {
+        if (k0 + kk >= nx1) break;                          // uniform per wave
+        const double* tab = a.red + (size_t)(k0 + kk) * a.RW;
+        const double G = sepl ? Gs[sig * 65 + kk] : 0.0;
+        double x = 0.0;
+        int woff = 2 + q;
+        for (int l = 0; l < q; ++l) {
+            const int size = P >> l;
+            const int pos = sig & (size - 1);
+            const bool member = sepl && (pos != size - 1);
+            const int widx = min(pos, size - 2 - pos);
+            double tv = member ? tab[woff + widx] * G : 0.0;
+            for (int off = 1; off < size; off <<= 1) tv += __shfl_xor(tv, off, 64);
+            const int base = sig - pos;
+            const int ll = base - 1, rl = base + size - 1;
+            const double xl_ = __shfl(x, ll < 0 ? 0 : ll, 64);
+            const double xr_ = __shfl(x, rl > 63 ? 63 : rl, 64);
+            const double xl = (ll < 0) ? 0.0 : xl_;
+            const double xr = (rl >= P - 1) ? 0.0 : xr_;
+            if (member && pos == (size >> 1) - 1) x = tv + tab[2 + l] * (xl + xr);
+            woff += size >> 1;
+        }
+        if (sepl) Xs[sig * 65 + kk] = x;
+    }
+    __syncthreads();
+
+    // phase 3: store separators, interface part of the inner product
+    double c = d0;
+    for (int sg = grp; sg < P - 1; sg += 4) {
+        const double x = Xs[sg * 65 + kl];
+        if (valid) {
+            a.y[fb + (size_t)((sg + 1) * Ls - 1) * nx1 + k] = (T)x;
+            c += x * Gs[sg * 65 + kl];
+        }
+    }
+    if (a.mode == 0) return;
+    const double s = block_sum(c, red);
+    if (tid == 0) a.partial[(size_t)field * a.pstride + blockIdx.x] = s;
+}
+
+// ===========================================================================
+// Grid-wide reductions of the CG scalars: one block per field sums the
+// per-block partials of the preceding kernel in a fixed order (so results
+// are bitwise reproducible) and updates the field's control block.
+// ===========================================================================
+enum FinKind { FIN_PQ = 0, FIN_RR = 1, FIN_RZ = 2 };
+
+struct FinArgs {
+    ShotCtl* ctl;
+    const double* partial;
+    size_t pstride;
+    int nparts;
+    int kind;
+    int init;         // FIN_RR: start of a solve; FIN_RZ: 1 start, 2 iteration
+    double tol2;
+    int max_iter;
+    double scale;     // FIN_RZ: b * 2/nx
+};
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
+    __shared__ double red[4];
+    const int field = blockIdx.x;
+    ShotCtl& c = a.ctl[field];
+    const bool start_rr = (a.kind == FIN_RR && a.init);
+    if (!start_rr && c.active == 0) return;                  // uniform per block
+    double s = 0.0;
+    const double* part = a.partial + (size_t)field * a.pstride;
+    for (int i = threadIdx.x; i < a.nparts; i += blockDim.x) s += part[i];
+    const double tot = block_sum(s, red);
+    if (threadIdx.x != 0) return;
+    if (a.kind == FIN_PQ) {
+        c.pq = tot;
+        if (!isfinite(tot)) {
+            c.status = LG_ERR_NONFINITE;
+            c.active = 0;
+        } else if (tot <= 0.0) {
+            c.status = LG_ERR_BREAKDOWN;
+            c.active = 0;
+        } else {
+            c.alpha = c.rz / tot;
+        }
+    } else if (a.kind == FIN_RR) {
+        c.rr = tot;
+        if (a.init) {
+            c.bb = tot;
+            c.tol2 = a.tol2 * tot;
+            c.iters = 0;
+            c.max_iter = a.max_iter;
+            c.alpha = 0.0;
+            c.beta = 0.0;
+            if (!isfinite(tot)) {
+                c.status = LG_ERR_NONFINITE;
+                c.active = 0;
+            } else if (tot == 0.0) {
+                c.status = LG_OK;
+                c.active = 0;
             } else {
-                cc.beta = rz / cc.rz;
-                cc.rz = rz;
+                c.status = LG_ERR_NOT_CONVERGED;
+                c.active = 1;
             }
+        } else {
+            const int it = c.iters + 1;
+            c.iters = it;
+            if (!isfinite(tot)) {
+                c.status = LG_ERR_NONFINITE;
+                c.active = 0;
+            } else if (tot <= c.tol2) {
+                c.status = LG_OK;
+                c.active = 0;
+            } else if (it >= c.max_iter) {
+                c.status = LG_ERR_NOT_CONVERGED;
+                c.active = 0;
+            }
+        }
+    } else {
+        const double rz = tot * a.scale;
+        if (!isfinite(rz)) {
+            c.status = LG_ERR_NONFINITE;
+            c.active = 0;
+        } else if (a.init == 1) {
+            c.rz = rz;
+            c.beta = 0.0;
+        } else {
+            c.beta = rz / c.rz;
+            c.rz = rz;
         }
     }
 }
@@ -610,6 +698,21 @@ __global__ __launch_bounds__(256) void traces_kernel(const double* __restrict__ 
 // ===========================================================================
 namespace {
 
+hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale) {
+    FinArgs f;
+    f.ctl = p->ctl;
+    f.partial = p->partial;
+    f.pstride = p->partial_stride;
+    f.nparts = nparts;
+    f.kind = kind;
+    f.init = init;
+    f.tol2 = tol2;
+    f.max_iter = max_iter;
+    f.scale = scale;
+    hipLaunchKernelGGL(finalize_kernel, dim3(p->S * p->C), dim3(256), 0, p->stream, f);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     StArgs<T> a;
@@ -624,10 +727,11 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.ctl = reduce ? p->ctl : nullptr;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
-    a.cnt = p->counters + (size_t)CNT_STENCIL * p->S * p->C;
     dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT), p->S * p->C);
     hipLaunchKernelGGL(stencil_kernel<T>, grid, dim3(256), 0, p->stream, a);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !reduce) return e;
+    return finalize(p, FIN_PQ, (int)(grid.x * grid.y), 0, 0.0, 0, 0.0);
 }
 
 template <typename T, int M, int MODE>
@@ -673,7 +777,6 @@ DstArgs<T> dst_args(lg_plan* p) {
     a.q = (const T*)p->qv;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
-    a.cnt = p->counters + (size_t)CNT_UPDATE * p->S * p->C;
     a.y = (const T*)p->y;
     a.utab = (const T*)p->blk[0].utab;
     a.Ls = p->blk[0].Ls;
@@ -727,17 +830,16 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode) 
     a.q = B.q;
     a.Ls = B.Ls;
     a.RW = B.RW;
-    a.bpf = (p->nx1 + 3) / 4;
     a.inv_b = 1.0 / B.b;
-    a.b = B.b;
-    a.dot_scale = 2.0 / p->g.nx;
     a.mode = mode;
     a.ctl = p->ctl;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
-    a.cnt = p->counters + (size_t)CNT_REDUCED * p->S * p->C;
-    hipLaunchKernelGGL(rs_kernel<T>, dim3(a.bpf * nfields), dim3(256), 0, p->stream, a);
-    return hipGetLastError();
+    const dim3 grid((p->nx1 + 63) / 64, nfields);
+    hipLaunchKernelGGL(rs_kernel<T>, grid, dim3(256), 0, p->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || mode == 0) return e;
+    return finalize(p, FIN_RZ, (int)grid.x, mode, 0.0, 0, B.b * 2.0 / p->g.nx);
 }
 
 }  // namespace
@@ -764,6 +866,8 @@ hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nf
 
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter) {
+    hipError_t e;
+    int bpf;
     if (p->prec == LG_FP64) {
         DstArgs<double> a = dst_args<double>(p);
         a.out = (double*)p->rhat;
@@ -772,16 +876,21 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         a.x = x;
         a.tol2 = tol * tol;
         a.max_iter = max_iter;
-        return dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
+        e = dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
+        bpf = a.bpf;
+    } else {
+        DstArgs<float> a = dst_args<float>(p);
+        a.out = (float*)p->rhat;
+        a.init = init;
+        a.b = b;
+        a.x = x;
+        a.tol2 = tol * tol;
+        a.max_iter = max_iter;
+        e = dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
+        bpf = a.bpf;
     }
-    DstArgs<float> a = dst_args<float>(p);
-    a.out = (float*)p->rhat;
-    a.init = init;
-    a.b = b;
-    a.x = x;
-    a.tol2 = tol * tol;
-    a.max_iter = max_iter;
-    return dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
+    if (e != hipSuccess) return e;
+    return finalize(p, FIN_RR, bpf, init, tol * tol, max_iter, 0.0);
 }
 
 hipError_t launch_correct_idst(lg_plan* p, int init) {

@@ -123,4 +123,39 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
     return (lg_status)worst;
 }
 
+lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* ms) {
+    const int nf = p->S * p->C;
+    LG_HIP(launch_update_fdst(p, 1, b, x, 0.0, iters + 1));
+    LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
+    LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
+    LG_HIP(launch_correct_idst(p, 1));
+    hipEvent_t ev[6] = {};
+    for (int i = 0; i < 6; ++i) LG_HIP(hipEventCreate(&ev[i]));
+    double acc[5] = {0, 0, 0, 0, 0};
+    hipError_t e = hipSuccess;
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+        e = hipEventRecord(ev[0], p->stream);
+        if (e == hipSuccess) e = launch_stencil(p, p->p, p->qv, true);
+        if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
+        if (e == hipSuccess) e = launch_update_fdst(p, 0, nullptr, nullptr, 0.0, 0);
+        if (e == hipSuccess) e = hipEventRecord(ev[2], p->stream);
+        if (e == hipSuccess) e = launch_td(p, 0, p->rhat, p->y, nf, 1);
+        if (e == hipSuccess) e = hipEventRecord(ev[3], p->stream);
+        if (e == hipSuccess) e = launch_rs(p, 0, p->rhat, p->y, nf, 2);
+        if (e == hipSuccess) e = hipEventRecord(ev[4], p->stream);
+        if (e == hipSuccess) e = launch_correct_idst(p, 0);
+        if (e == hipSuccess) e = hipEventRecord(ev[5], p->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
+        for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+            float t = 0.f;
+            e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
+            acc[k] += t;
+        }
+    }
+    for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    if (e != hipSuccess) return hip_fail(e, "lg_pcg_profile");
+    for (int k = 0; k < 5; ++k) ms[k] = (float)(acc[k] / iters);
+    return LG_OK;
+}
+
 }  // namespace lg

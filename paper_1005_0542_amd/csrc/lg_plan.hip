@@ -162,7 +162,7 @@ void free_plan(lg_plan* p) {
     if (!p) return;
     pcg_release(p);
     void* ptrs[] = {p->kap, p->lam, p->mu, p->w, p->rho64, p->tw, p->src_dev, p->r, p->p, p->qv,
-                    p->rhat, p->y, p->E, p->partial, p->counters, p->ctl, p->xslot, p->gm_V,
+                    p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red};
     for (void* q : ptrs)
@@ -425,13 +425,10 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     {
         const size_t sb = (size_t)((p->nx1 + 63) / 64) * ((p->nz1 + 31) / 32);
         const size_t db = (size_t)dst_blocks_per_field(grid->nx, p->nz1);
-        const size_t rb = (size_t)((p->nx1 + 3) / 4);
+        const size_t rb = (size_t)((p->nx1 + 63) / 64);
         p->partial_stride = std::max(sb, std::max(db, rb));
     }
     if ((st = dev_alloc(p, &p->partial, (size_t)SC * p->partial_stride * 8)) != LG_OK) return bail(st);
-    if ((st = dev_alloc(p, &p->counters, (size_t)CNT_NUM * SC * 4)) != LG_OK) return bail(st);
-    if ((he = hipMemset(p->counters, 0, (size_t)CNT_NUM * SC * 4)) != hipSuccess)
-        return bail(hip_fail(he, "hipMemset"));
     if ((st = dev_alloc(p, &p->ctl, (size_t)SC * sizeof(ShotCtl))) != LG_OK) return bail(st);
     if ((he = hipMemset(p->ctl, 0, (size_t)SC * sizeof(ShotCtl))) != hipSuccess)
         return bail(hip_fail(he, "hipMemset"));
@@ -695,4 +692,16 @@ extern "C" lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z) {
     }
     LG_HIP(launch_dst(plan, 1, plan->y, z, nf));
     return LG_OK;
+}
+
+extern "C" lg_status lg_pcg_profile(lg_plan* plan, const double* b, double* x, int32_t iters, float* ms_host) {
+    LG_CHECK(check_plan(plan));
+    LG_CHECK(check_vec(b, "b"));
+    LG_CHECK(check_vec(x, "x"));
+    LG_CHECK(check_vec(ms_host, "ms_host"));
+    if (b == x) return fail(LG_ERR_INVALID_ARG, "b and x must differ");
+    if (plan->kind != LG_ACOUSTIC) return fail(LG_ERR_INVALID_ARG, "profiling needs an acoustic plan");
+    if (iters < 1 || iters > 1000) return fail(LG_ERR_INVALID_ARG, "iters must be in 1..1000");
+    LG_HIP(hipSetDevice(plan->device));
+    return lg::pcg_profile(plan, b, x, iters, ms_host);
 }
