@@ -152,6 +152,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--graph-iters", type=int, default=0)
+    ap.add_argument("--profile-only", action="store_true",
+                    help="only the per-kernel profile of the workload (for hardware-counter runs)")
+    ap.add_argument("--precision", default=None, help="override the workload precision")
+    ap.add_argument("--shots", type=int, default=None, help="override the workload shot count")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="time a plain device copy of MIB MiB (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -162,7 +168,25 @@ def main():
     from paper_1005_0542_amd import inputs
 
     w = inputs.WORKLOADS[args.workload]
-    head = run_variant(args.workload, w.precision, w.shots, args.steps, args.warmup,
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+        return
+    prec = args.precision or w.precision
+    shots = args.shots or w.shots
+    if args.profile_only:
+        v = run_variant(args.workload, prec, shots, 1, 0, segments=args.segments,
+                        graph_iters=args.graph_iters)
+        v.pop("_run")
+        print(json.dumps({"workload": args.workload, "precision": prec, "shots": shots,
+                          "profile_iterations": 10, "kernels": v["kernels"]}))
+        return
+    head = run_variant(args.workload, prec, shots, args.steps, args.warmup,
                        segments=args.segments, graph_iters=args.graph_iters)
     head.pop("_run")
     torch.cuda.empty_cache()

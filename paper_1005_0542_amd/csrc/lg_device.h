@@ -86,44 +86,89 @@ struct LdsLen {
     static constexpr int value = M + M / 16;
 };
 
-// Stockham autosort FFT (forward, natural order in and out) of length M held
-// in LDS, executed by TPF = M/R threads of the block (t = 0..TPF-1), each
-// doing R/r radix-r butterflies per pass; r = R except for the last pass.
-// Every pass: read inputs -> barrier -> twiddle + DFT -> write -> barrier.
-// All threads of the block must call this (it contains __syncthreads).
+// Pass structure of a length-M Stockham FFT with radix-R passes: every pass
+// but the last has radix R; the last pass has radix R_LAST = M / NS_LAST.
+template <int M, int R>
+struct FftPlan {
+    static constexpr int ns_last() {
+        int ns = 1;
+        while (ns * R < M) ns *= R;
+        return ns;
+    }
+    static constexpr int NS_LAST = ns_last();
+    static constexpr int R_LAST = M / NS_LAST;
+    static constexpr int NB_LAST = R / R_LAST;   // last-pass butterflies per thread
+};
+
+// Twiddles w[u] = tw[u j] (u < r) of one butterfly from at most four table
+// loads (u = 1, 2, 4, 8); the others are products of at most three factors.
+template <typename T, int r>
+__device__ __forceinline__ void make_twiddles(const cpx<T>* __restrict__ tw, int j, cpx<T>* w) {
+    w[0] = {(T)1, (T)0};
+    if constexpr (r >= 2) w[1] = tw[j];
+    if constexpr (r >= 4) {
+        w[2] = tw[2 * j];
+        w[3] = cmul(w[2], w[1]);
+    }
+    if constexpr (r >= 8) {
+        w[4] = tw[4 * j];
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+    }
+    if constexpr (r >= 16) {
+        w[8] = tw[8 * j];
+#pragma unroll
+        for (int u = 9; u < 16; ++u) w[u] = cmul(w[8], w[u - 8]);
+    }
+}
+
+// Stockham passes (LDS -> LDS) of span Ns .. NS_LAST/R, radix R, one
+// butterfly per thread: read -> barrier -> twiddle + DFT -> write -> barrier
+// (no twiddles for the span-1 pass).  The last pass is fft_last.  All threads
+// of the block must call this.
 template <typename T, int M, int R, int Ns>
-__device__ __forceinline__ void fft_passes(cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw,
-                                           int t) {
-    if constexpr (Ns < M) {
-        constexpr int r = (M / Ns >= R) ? R : (M / Ns);
-        constexpr int NB = R / r;
-        constexpr int TPF = M / R;
+__device__ __forceinline__ void fft_mid(cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw, int t) {
+    if constexpr (Ns < FftPlan<M, R>::NS_LAST) {
         cpx<T> v[R];
 #pragma unroll
-        for (int qb = 0; qb < NB; ++qb) {
-            const int bi = t + qb * TPF;
-#pragma unroll
-            for (int u = 0; u < r; ++u) v[qb * r + u] = buf[lpad(bi + u * (M / r))];
-        }
+        for (int u = 0; u < R; ++u) v[u] = buf[lpad(t + u * (M / R))];
         __syncthreads();
+        const int k = t & (Ns - 1);
+        if constexpr (Ns > 1) {
+            cpx<T> w[R];
+            make_twiddles<T, R>(tw, k * (M / (Ns * R)), w);
 #pragma unroll
-        for (int qb = 0; qb < NB; ++qb) {
-            const int bi = t + qb * TPF;
-            const int k = bi & (Ns - 1);
-            if constexpr (Ns > 1) {
-#pragma unroll
-                for (int u = 1; u < r; ++u) {
-                    const cpx<T> w = tw[(u * k) * (M / (Ns * r))];
-                    v[qb * r + u] = cmul(v[qb * r + u], w);
-                }
-            }
-            dft<T, r>(&v[qb * r]);
-            const int base = (bi - k) * r + k;
-#pragma unroll
-            for (int u = 0; u < r; ++u) buf[lpad(base + u * Ns)] = v[qb * r + u];
+            for (int u = 1; u < R; ++u) v[u] = cmul(v[u], w[u]);
         }
+        dft<T, R>(v);
+        const int base = (t - k) * R + k;
+#pragma unroll
+        for (int u = 0; u < R; ++u) buf[lpad(base + u * Ns)] = v[u];
         __syncthreads();
-        fft_passes<T, M, R, Ns * r>(buf, tw, t);
+        fft_mid<T, M, R, Ns * R>(buf, tw, t);
+    }
+}
+
+// Last Stockham pass (span NS_LAST, radix R_LAST): reads LDS, leaves the
+// results in registers: v[qb*R_LAST + u] is output K = t + qb*(M/R) + u*NS_LAST.
+template <typename T, int M, int R>
+__device__ __forceinline__ void fft_last(const cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw,
+                                         int t, cpx<T>* v) {
+    using FP = FftPlan<M, R>;
+    constexpr int r = FP::R_LAST, NB = FP::NB_LAST, Ns = FP::NS_LAST, TPF = M / R;
+#pragma unroll
+    for (int qb = 0; qb < NB; ++qb)
+#pragma unroll
+        for (int u = 0; u < r; ++u) v[qb * r + u] = buf[lpad(t + qb * TPF + u * Ns)];
+#pragma unroll
+    for (int qb = 0; qb < NB; ++qb) {
+        const int k = t + qb * TPF;               // < Ns: the twiddle index is k itself
+        cpx<T> w[r];
+        make_twiddles<T, r>(tw, k, w);
+#pragma unroll
+        for (int u = 1; u < r; ++u) v[qb * r + u] = cmul(v[qb * r + u], w[u]);
+        dft<T, r>(&v[qb * r]);
     }
 }
 

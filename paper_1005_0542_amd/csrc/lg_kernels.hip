@@ -42,61 +42,76 @@ struct StArgs {
     const T* w;          // interior shift
     int nx1, nz1;
     T idx2, idz2;
+    int nfields, nsh;    // fields, fields per block (grid.z chunks)
     // CG reduction (ctl == nullptr: plain operator application)
     ShotCtl* ctl;
     double* partial;
     size_t pstride;
 };
 
+// The medium (kappa at the nodes the column touches, w) is loaded once into
+// registers and reused for a chunk of `nsh` shots; each shot's p column is
+// marched down the strip with its x-neighbours read from L1/L2.
 template <typename T>
 __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
     __shared__ double red[4];
-    const int field = blockIdx.z;
-    if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
     const int nx1 = a.nx1, nz1 = a.nz1, NXN = nx1 + 2;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 1D block of 256 = 64 x 4
-    const int i = blockIdx.x * 64 + tx;
+    const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 1D block of 256 = 64 x 4
+    const int i = blockIdx.x * 64 + lane;
     const int j0 = (blockIdx.y * 4 + ty) * ST_RPT;
-    const size_t fb = (size_t)field * nx1 * nz1;
-    const T* __restrict__ p = a.p + fb;
-    T* __restrict__ q = a.q + fb;
-    const T* __restrict__ kap = a.kap;
+    const bool live = (i < nx1) && (j0 < nz1);
+    const int I = i + 1;
     const T half = (T)0.5;
-    double pq = 0.0;
-    if (i < nx1 && j0 < nz1) {
-        const int I = i + 1;
-        T pN = (j0 > 0) ? p[(size_t)(j0 - 1) * nx1 + i] : (T)0;
-        T c = p[(size_t)j0 * nx1 + i];
-        T kN = kap[(size_t)j0 * NXN + I];            // node (I, J0-1) with J0 = j0+1
-        T k0 = kap[(size_t)(j0 + 1) * NXN + I];
+    // medium of this column strip: node kappa rows j0 .. j0+RPT+1 and the
+    // face coefficients / shift of rows j0 .. j0+RPT-1
+    T kc[ST_RPT + 2], fE[ST_RPT], fW[ST_RPT], wv[ST_RPT];
 #pragma unroll
-        for (int rr = 0; rr < ST_RPT; ++rr) {
-            const int j = j0 + rr;
-            if (j >= nz1) break;
-            const int J = j + 1;
-            const T pS = (j + 1 < nz1) ? p[(size_t)(j + 1) * nx1 + i] : (T)0;
-            const T kS = kap[(size_t)(J + 1) * NXN + I];
-            const T pE = (i + 1 < nx1) ? p[(size_t)j * nx1 + i + 1] : (T)0;
-            const T pW = (i > 0) ? p[(size_t)j * nx1 + i - 1] : (T)0;
-            const T kE = kap[(size_t)J * NXN + I + 1];
-            const T kW = kap[(size_t)J * NXN + I - 1];
-            const T fE = half * (k0 + kE), fW = half * (k0 + kW);
-            const T fS = half * (k0 + kS), fN = half * (k0 + kN);
-            const T v = (fE * (c - pE) + fW * (c - pW)) * a.idx2 +
-                        (fS * (c - pS) + fN * (c - pN)) * a.idz2 +
-                        a.w[(size_t)j * nx1 + i] * c;
-            q[(size_t)j * nx1 + i] = v;
-            pq += (double)c * (double)v;
-            pN = c;
-            c = pS;
-            kN = k0;
-            k0 = kS;
+    for (int r = 0; r < ST_RPT + 2; ++r) {
+        const int J = j0 + r;                       // node row (interior row j0+r-1)
+        kc[r] = (live && J <= nz1 + 1) ? a.kap[(size_t)J * NXN + I] : (T)0;
+    }
+#pragma unroll
+    for (int r = 0; r < ST_RPT; ++r) {
+        const int j = j0 + r, J = j + 1;
+        fE[r] = fW[r] = wv[r] = (T)0;
+        if (live && j < nz1) {
+            fE[r] = half * (kc[r + 1] + a.kap[(size_t)J * NXN + I + 1]);
+            fW[r] = half * (kc[r + 1] + a.kap[(size_t)J * NXN + I - 1]);
+            wv[r] = a.w[(size_t)j * nx1 + i];
         }
     }
-    if (a.ctl == nullptr) return;
-    const double s = block_sum(pq, red);
-    if (threadIdx.x == 0)
-        a.partial[(size_t)field * a.pstride + blockIdx.y * gridDim.x + blockIdx.x] = s;
+    const int s0 = blockIdx.z * a.nsh;
+    const int s1 = min(s0 + a.nsh, a.nfields);
+    for (int field = s0; field < s1; ++field) {
+        if (a.ctl != nullptr && a.ctl[field].active == 0) continue;   // uniform per block
+        const size_t fb = (size_t)field * nx1 * nz1;
+        const T* __restrict__ p = a.p + fb;
+        T* __restrict__ q = a.q + fb;
+        double pq = 0.0;
+        if (live) {
+            T pN = (j0 > 0) ? p[(size_t)(j0 - 1) * nx1 + i] : (T)0;
+            T c = p[(size_t)j0 * nx1 + i];
+#pragma unroll
+            for (int r = 0; r < ST_RPT; ++r) {
+                const int j = j0 + r;
+                if (j >= nz1) break;
+                const T pS = (j + 1 < nz1) ? p[(size_t)(j + 1) * nx1 + i] : (T)0;
+                const T pE = (i + 1 < nx1) ? p[(size_t)j * nx1 + i + 1] : (T)0;
+                const T pW = (i > 0) ? p[(size_t)j * nx1 + i - 1] : (T)0;
+                const T fS = half * (kc[r + 1] + kc[r + 2]), fN = half * (kc[r + 1] + kc[r]);
+                const T v = (fE[r] * (c - pE) + fW[r] * (c - pW)) * a.idx2 +
+                            (fS * (c - pS) + fN * (c - pN)) * a.idz2 + wv[r] * c;
+                q[(size_t)j * nx1 + i] = v;
+                pq += (double)c * (double)v;
+                pN = c;
+                c = pS;
+            }
+        }
+        if (a.ctl == nullptr) continue;
+        const double s = block_sum(pq, red);
+        if (threadIdx.x == 0)
+            a.partial[(size_t)field * a.pstride + blockIdx.y * gridDim.x + blockIdx.x] = s;
+    }
 }
 
 // ===========================================================================
@@ -135,13 +150,23 @@ struct DstArgs {
     int Ls, P;
 };
 
+// Phase A: each row element x_i (i = t + it TPF) is loaded once by its
+// thread, which writes it to LDS at both odd-extension positions 1+i and
+// M-1-i.  The Stockham passes then run LDS -> LDS, except the last pass,
+// which leaves its outputs in registers; they are stored straight to global
+// memory (coalesced: output K = t + qb M/R + u NS_LAST).
 template <typename T, int M, int R, int FPB, int MODE>
 __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
+    using FP = FftPlan<M, R>;
     constexpr int TPF = M / R;
     constexpr int NX = M / 2;
     constexpr int NX1 = NX - 1;
+    constexpr int RL = FP::R_LAST, NBL = FP::NB_LAST, NSL = FP::NS_LAST;
+    constexpr int NOUT = NBL * (RL / 2);       // first-half outputs per thread
     constexpr int LL = LdsLen<M>::value;
     constexpr int NWAVE = (FPB * TPF + 63) / 64;
+    constexpr int NIT = (NX1 + TPF - 1) / TPF;
+    constexpr int CH = NIT < 4 ? NIT : 4;
     __shared__ cpx<T> lds[FPB * LL];
     __shared__ double red[NWAVE];
 
@@ -166,77 +191,63 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     const size_t o0 = fbase + (size_t)j0 * NX1;
     const size_t o1 = fbase + (size_t)j1 * NX1;
     double rr = 0.0;
+    T pold0[MODE == DST_CORRECT ? NOUT : 1], pold1[MODE == DST_CORRECT ? NOUT : 1];
 
-    // ---- phase A: gather the two rows into the odd extension --------------
+    // ---- phase A: gather the two rows into the odd extension (LDS) ---------
     if (live) {
-        double* xp = nullptr;
-        double alpha = 0.0;
         if constexpr (MODE == DST_UPDATE) {
+            double* __restrict__ X;
+            double alpha = 0.0;
             if (a.init) {
-                xp = a.x;
+                X = a.x;
                 if (blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
             } else {
-                xp = *a.xslot;
+                X = *a.xslot;
                 alpha = a.ctl[field].alpha;
             }
-        }
-        constexpr int NIT = (NX1 + TPF - 1) / TPF;
-        if constexpr (MODE == DST_UPDATE) {
-            double* __restrict__ X = xp;
             double* __restrict__ Rr = a.r;
-            if (a.init) {
-                const double* __restrict__ Bv = a.b;
+            const T* __restrict__ Pv = a.p;
+            const T* __restrict__ Qv = a.q;
+            const double* __restrict__ Bv = a.b;
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const int i = t + it * TPF;
-                    if (i < NX1) {
-                        const double r0 = Bv[o0 + i];
-                        const double r1 = has1 ? Bv[o1 + i] : 0.0;
-                        Rr[o0 + i] = r0;
-                        X[o0 + i] = 0.0;
-                        if (has1) {
-                            Rr[o1 + i] = r1;
-                            X[o1 + i] = 0.0;
-                        }
-                        rr += r0 * r0 + r1 * r1;
-                        buf[lpad(1 + i)] = {(T)r0, (T)r1};
-                        buf[lpad(M - 1 - i)] = {(T)-r0, (T)-r1};
-                    }
-                }
-            } else {
-                // all loads first (memory-level parallelism), then update and store
-                const T* __restrict__ Pv = a.p;
-                const T* __restrict__ Qv = a.q;
-                double x0[NIT], x1[NIT], r0[NIT], r1[NIT];
-                T p0[NIT], p1[NIT], q0[NIT], q1[NIT];
+            for (int cb = 0; cb < NIT; cb += CH) {
+                // loads of a chunk first (memory-level parallelism), then update
+                // and store; chunks keep the register footprint moderate
+                double x0[CH], x1[CH], r0[CH], r1[CH];
+                T p0[CH], p1[CH], q0[CH], q1[CH];
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const int i = t + it * TPF;
-                    x1[it] = r1[it] = 0.0;
-                    p1[it] = q1[it] = (T)0;
-                    if (i < NX1) {
-                        x0[it] = X[o0 + i];
-                        r0[it] = Rr[o0 + i];
-                        p0[it] = Pv[o0 + i];
-                        q0[it] = Qv[o0 + i];
-                        if (has1) {
-                            x1[it] = X[o1 + i];
-                            r1[it] = Rr[o1 + i];
-                            p1[it] = Pv[o1 + i];
-                            q1[it] = Qv[o1 + i];
+                for (int u = 0; u < CH; ++u) {
+                    const int i = t + (cb + u) * TPF;
+                    x0[u] = r0[u] = x1[u] = r1[u] = 0.0;
+                    p0[u] = q0[u] = p1[u] = q1[u] = (T)0;
+                    if (cb + u < NIT && i < NX1) {
+                        if (a.init) {
+                            r0[u] = Bv[o0 + i];
+                            if (has1) r1[u] = Bv[o1 + i];
+                        } else {
+                            x0[u] = X[o0 + i];
+                            r0[u] = Rr[o0 + i];
+                            p0[u] = Pv[o0 + i];
+                            q0[u] = Qv[o0 + i];
+                            if (has1) {
+                                x1[u] = X[o1 + i];
+                                r1[u] = Rr[o1 + i];
+                                p1[u] = Pv[o1 + i];
+                                q1[u] = Qv[o1 + i];
+                            }
                         }
                     }
                 }
 #pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    const int i = t + it * TPF;
-                    if (i < NX1) {
-                        const double ra = r0[it] - alpha * (double)q0[it];
-                        const double rb = r1[it] - alpha * (double)q1[it];
-                        X[o0 + i] = x0[it] + alpha * (double)p0[it];
+                for (int u = 0; u < CH; ++u) {
+                    const int i = t + (cb + u) * TPF;
+                    if (cb + u < NIT && i < NX1) {
+                        const double ra = r0[u] - alpha * (double)q0[u];
+                        const double rb = r1[u] - alpha * (double)q1[u];
+                        X[o0 + i] = x0[u] + alpha * (double)p0[u];
                         Rr[o0 + i] = ra;
                         if (has1) {
-                            X[o1 + i] = x1[it] + alpha * (double)p1[it];
+                            X[o1 + i] = x1[u] + alpha * (double)p1[u];
                             Rr[o1 + i] = rb;
                         }
                         rr += ra * ra + rb * rb;
@@ -245,37 +256,80 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     }
                 }
             }
+        } else if constexpr (MODE == DST_CORRECT) {
+            // zhat = y + xl u_rs + xr u_{Ls-rs} on segment rows (separator rows as
+            // is); the segment geometry depends on the row only
+            const int Ls = a.Ls, P = a.P;
+            const T* __restrict__ Y = a.y + fbase;
+            const T* __restrict__ U = a.utab;
+            const int rs0 = (j0 + 1) & (Ls - 1), sg0 = (j0 + 1) / Ls;
+            const int rs1 = (j1 + 1) & (Ls - 1), sg1 = (j1 + 1) / Ls;
+            const bool c0 = rs0 != 0, c1 = has1 && rs1 != 0;
+            const int l0 = (c0 && sg0 > 0) ? sg0 * Ls - 1 : -1;
+            const int r0 = (c0 && sg0 < P - 1) ? (sg0 + 1) * Ls - 1 : -1;
+            const int l1 = (c1 && sg1 > 0) ? sg1 * Ls - 1 : -1;
+            const int r1 = (c1 && sg1 < P - 1) ? (sg1 + 1) * Ls - 1 : -1;
+#pragma unroll
+            for (int cb = 0; cb < NIT; cb += CH) {
+                T yv0[CH], yv1[CH], xl0[CH], xr0[CH], xl1[CH], xr1[CH];
+                T ua0[CH], ub0[CH], ua1[CH], ub1[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int i = t + (cb + u) * TPF;
+                    yv0[u] = yv1[u] = xl0[u] = xr0[u] = xl1[u] = xr1[u] = (T)0;
+                    ua0[u] = ub0[u] = ua1[u] = ub1[u] = (T)0;
+                    if (cb + u < NIT && i < NX1) {
+                        yv0[u] = Y[(size_t)j0 * NX1 + i];
+                        if (has1) yv1[u] = Y[(size_t)j1 * NX1 + i];
+                        if (l0 >= 0) xl0[u] = Y[(size_t)l0 * NX1 + i];
+                        if (r0 >= 0) xr0[u] = Y[(size_t)r0 * NX1 + i];
+                        if (l1 >= 0) xl1[u] = Y[(size_t)l1 * NX1 + i];
+                        if (r1 >= 0) xr1[u] = Y[(size_t)r1 * NX1 + i];
+                        if (c0) {
+                            ua0[u] = U[(size_t)rs0 * NX1 + i];
+                            ub0[u] = U[(size_t)(Ls - rs0) * NX1 + i];
+                        }
+                        if (c1) {
+                            ua1[u] = U[(size_t)rs1 * NX1 + i];
+                            ub1[u] = U[(size_t)(Ls - rs1) * NX1 + i];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    const int i = t + (cb + u) * TPF;
+                    if (cb + u < NIT && i < NX1) {
+                        const T v0 = c0 ? yv0[u] + xl0[u] * ua0[u] + xr0[u] * ub0[u] : yv0[u];
+                        const T v1 = c1 ? yv1[u] + xl1[u] * ua1[u] + xr1[u] * ub1[u] : yv1[u];
+                        buf[lpad(1 + i)] = {v0, v1};
+                        buf[lpad(M - 1 - i)] = {-v0, -v1};
+                    }
+                }
+            }
+            // p of the outputs this thread will write (read now, used after the FFT)
+#pragma unroll
+            for (int qb = 0; qb < NBL; ++qb)
+#pragma unroll
+                for (int u = 0; u < RL / 2; ++u) {
+                    const int K = t + qb * TPF + u * NSL;
+                    const int oi = qb * (RL / 2) + u;
+                    pold0[oi] = pold1[oi] = (T)0;
+                    if (!a.init && K >= 1 && K <= NX1) {
+                        pold0[oi] = a.out[o0 + K - 1];
+                        if (has1) pold1[oi] = a.out[o1 + K - 1];
+                    }
+                }
         } else {
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int i = t + it * TPF;
-            if (i >= NX1) break;
-            T v0, v1 = (T)0;
-            if constexpr (MODE == DST_FWD || MODE == DST_INV) {
-                v0 = a.in[o0 + i];
-                if (has1) v1 = a.in[o1 + i];
-            } else {   // DST_CORRECT: zhat = y + xl u_i + xr u_{Ls-i} on segment rows
-                const int Ls = a.Ls, P = a.P;
-                const T* __restrict__ Y = a.y + fbase;
-                const T* __restrict__ U = a.utab;
-                auto corr = [&](int j) -> T {
-                    T v = Y[(size_t)j * NX1 + i];
-                    const int jj = j + 1;
-                    const int rs = jj & (Ls - 1);
-                    if (rs != 0) {
-                        const int s = jj / Ls;
-                        const T xl = (s > 0) ? Y[(size_t)(s * Ls - 1) * NX1 + i] : (T)0;
-                        const T xr = (s < P - 1) ? Y[(size_t)((s + 1) * Ls - 1) * NX1 + i] : (T)0;
-                        v += xl * U[(size_t)rs * NX1 + i] + xr * U[(size_t)(Ls - rs) * NX1 + i];
-                    }
-                    return v;
-                };
-                v0 = corr(j0);
-                if (has1) v1 = corr(j1);
+            for (int it = 0; it < NIT; ++it) {
+                const int i = t + it * TPF;
+                if (i < NX1) {
+                    const T v0 = a.in[o0 + i];
+                    const T v1 = has1 ? a.in[o1 + i] : (T)0;
+                    buf[lpad(1 + i)] = {v0, v1};
+                    buf[lpad(M - 1 - i)] = {-v0, -v1};
+                }
             }
-            buf[lpad(1 + i)] = {v0, v1};
-            buf[lpad(M - 1 - i)] = {-v0, -v1};
-        }
         }
         if (t == 0) {
             buf[lpad(0)] = {(T)0, (T)0};
@@ -286,35 +340,45 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     }
     __syncthreads();
 
-    fft_passes<T, M, R, 1>(buf, a.tw, t);
+    // ---- transform ----------------------------------------------------------
+    cpx<T> v[R];
+    fft_mid<T, M, R, 1>(buf, a.tw, t);
+    fft_last<T, M, R>(buf, a.tw, t, v);
 
-    // ---- phase C: unpack ----------------------------------------------------
+    // ---- outputs: registers -> global (first half of the spectrum) ---------
     if (live) {
         T beta = (T)0;
         if constexpr (MODE == DST_CORRECT) beta = (T)a.ctl[field].beta;
-        for (int k = t; k < NX1; k += TPF) {
-            const cpx<T> V = buf[lpad(1 + k)];
-            T x0 = -V.y * (T)0.5, x1 = V.x * (T)0.5;
-            if constexpr (MODE == DST_FWD || MODE == DST_UPDATE) {
-                a.out[o0 + k] = x0;
-                if (has1) a.out[o1 + k] = x1;
-            } else if constexpr (MODE == DST_INV) {
-                const T sc = (T)(2.0 / NX);
-                a.out[o0 + k] = x0 * sc;
-                if (has1) a.out[o1 + k] = x1 * sc;
-            } else {   // CORRECT: p = z + beta p  (init: p = z)
-                const T sc = (T)(2.0 / NX);
-                x0 *= sc;
-                x1 *= sc;
-                if (a.init) {
-                    a.out[o0 + k] = x0;
-                    if (has1) a.out[o1 + k] = x1;
-                } else {
-                    a.out[o0 + k] = x0 + beta * a.out[o0 + k];
-                    if (has1) a.out[o1 + k] = x1 + beta * a.out[o1 + k];
+#pragma unroll
+        for (int qb = 0; qb < NBL; ++qb)
+#pragma unroll
+            for (int u = 0; u < RL / 2; ++u) {
+                const int K = t + qb * TPF + u * NSL;
+                if (K < 1 || K > NX1) continue;
+                const int col = K - 1;
+                const cpx<T> V = v[qb * RL + u];
+                T x0 = -V.y * (T)0.5, x1 = V.x * (T)0.5;
+                if constexpr (MODE == DST_FWD || MODE == DST_UPDATE) {
+                    a.out[o0 + col] = x0;
+                    if (has1) a.out[o1 + col] = x1;
+                } else if constexpr (MODE == DST_INV) {
+                    const T sc = (T)(2.0 / NX);
+                    a.out[o0 + col] = x0 * sc;
+                    if (has1) a.out[o1 + col] = x1 * sc;
+                } else {   // CORRECT: p = z + beta p  (init: p = z)
+                    const T sc = (T)(2.0 / NX);
+                    const int oi = qb * (RL / 2) + u;
+                    x0 *= sc;
+                    x1 *= sc;
+                    if (a.init) {
+                        a.out[o0 + col] = x0;
+                        if (has1) a.out[o1 + col] = x1;
+                    } else {
+                        a.out[o0 + col] = x0 + beta * pold0[oi];
+                        if (has1) a.out[o1 + col] = x1 + beta * pold1[oi];
+                    }
                 }
             }
-        }
     }
 
     if constexpr (MODE == DST_UPDATE) {
@@ -342,46 +406,62 @@ struct TdArgs {
     const T* etab;
     double* E;       // [field][P][3][nx1]
     int nx1, nz1, P;
+    int spw;         // segments per wave
     T inv_b;
     ShotCtl* ctl;    // nullptr: no masking
 };
 
+// Block = 4 waves over 64 consecutive wavenumbers (lane = k); each wave
+// solves `spw` consecutive segments.  The block's slice of the shared Thomas
+// factors (LS x 64) is staged once in LDS, so the sweeps read it from LDS
+// instead of streaming it from L2 for every segment.
 template <typename T, int LS>
 __global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
+    __shared__ T es[LS * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int k = blockIdx.x * 64 + lane;
-    const int s = blockIdx.y * (blockDim.x >> 6) + wave;
     const int field = blockIdx.z;
-    if (a.ctl != nullptr && a.ctl[field].active == 0) return;
-    if (k >= a.nx1 || s >= a.P) return;
+    if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
     const int nx1 = a.nx1;
-    const size_t fb = (size_t)field * a.nz1 * nx1;
-    const T* __restrict__ g = a.rhat + fb + (size_t)(s * LS) * nx1 + k;   // row s*LS (+i-1)
-    T* __restrict__ yo = a.y + fb + (size_t)(s * LS) * nx1 + k;
-    const T* __restrict__ e = a.etab + k;
+    {
+        const int kk = blockIdx.x * 64 + (threadIdx.x & 63);
+        for (int i = threadIdx.x >> 6; i < LS; i += 4)
+            es[i * 64 + (threadIdx.x & 63)] = (kk < nx1) ? a.etab[(size_t)i * nx1 + kk] : (T)0;
+    }
+    __syncthreads();
+    if (k >= nx1) return;
     constexpr int L = LS - 1;
-    T d[LS];
-    T prev = (T)0;
-    double d0 = 0.0;
+    const size_t fb = (size_t)field * a.nz1 * nx1;
+    const int s_begin = (blockIdx.y * 4 + wave) * a.spw;
+    const int s_end = min(s_begin + a.spw, a.P);
+    for (int s = s_begin; s < s_end; ++s) {
+        const T* __restrict__ g = a.rhat + fb + (size_t)(s * LS) * nx1 + k;   // row s*LS (+i-1)
+        T* __restrict__ yo = a.y + fb + (size_t)(s * LS) * nx1 + k;
+        T d[LS];
 #pragma unroll
-    for (int i = 1; i <= L; ++i) {
-        const T h = g[(size_t)(i - 1) * nx1] * a.inv_b + prev;
-        prev = h * e[(size_t)i * nx1];
-        d[i] = prev;
-        d0 += (double)h * (double)prev;
-    }
-    T yv = d[L];
-    yo[(size_t)(L - 1) * nx1] = yv;
-    const T ylast = yv;
+        for (int i = 1; i <= L; ++i) d[i] = g[(size_t)(i - 1) * nx1];
+        T prev = (T)0;
+        double d0 = 0.0;
 #pragma unroll
-    for (int i = L - 1; i >= 1; --i) {
-        yv = d[i] + e[(size_t)i * nx1] * yv;
-        yo[(size_t)(i - 1) * nx1] = yv;
+        for (int i = 1; i <= L; ++i) {
+            const T h = d[i] * a.inv_b + prev;
+            prev = h * es[i * 64 + lane];
+            d[i] = prev;
+            d0 += (double)h * (double)prev;
+        }
+        T yv = d[L];
+        yo[(size_t)(L - 1) * nx1] = yv;
+        const T ylast = yv;
+#pragma unroll
+        for (int i = L - 1; i >= 1; --i) {
+            yv = d[i] + es[i * 64 + lane] * yv;
+            yo[(size_t)(i - 1) * nx1] = yv;
+        }
+        double* E = a.E + ((size_t)field * a.P + s) * 3 * nx1 + k;
+        E[0] = (double)yv;          // y_1
+        E[nx1] = (double)ylast;     // y_{Ls-1}
+        E[2 * (size_t)nx1] = d0;    // g^T T^{-1} g on the segment
     }
-    double* E = a.E + ((size_t)field * a.P + s) * 3 * nx1 + k;
-    E[0] = (double)yv;          // y_1
-    E[nx1] = (double)ylast;     // y_{Ls-1}
-    E[2 * (size_t)nx1] = d0;    // g^T T^{-1} g on the segment
 }
 
 // ===========================================================================
@@ -419,29 +499,31 @@ struct RsArgs {
 // phase 2 solves the 64 systems, each by one wave with one lane per
 // separator; phase 3 writes the separator values back row by row and forms
 // this block's share of (rhat, zhat) / b.
-template <typename T>
+template <typename T, int KT>
 __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
-    __shared__ double Gs[64 * 65];
-    __shared__ double Xs[64 * 65];
+    constexpr int KS = KT + 1;             // padded LDS row
+    constexpr int NG = 256 / KT;           // thread groups over separators
+    __shared__ double Gs[64 * KS];
+    __shared__ double Xs[64 * KS];
     __shared__ double red[4];
     const int field = blockIdx.y;
     if (a.mode != 0 && a.ctl[field].active == 0) return;   // uniform per block
     const int P = a.P, q = a.q, Ls = a.Ls, nx1 = a.nx1;
-    const int tid = threadIdx.x, kl = tid & 63, grp = tid >> 6;
-    const int k0 = blockIdx.x * 64;
+    const int tid = threadIdx.x, kl = tid % KT, grp = tid / KT;
+    const int k0 = blockIdx.x * KT;
     const int k = k0 + kl;
     const bool valid = k < nx1;
     const size_t fb = (size_t)field * a.nz1 * nx1;
     const double* Ef = a.E + (size_t)field * P * 3 * nx1;
     double d0 = 0.0;
-    for (int sg = grp; sg < P; sg += 4) {
+    for (int sg = grp; sg < P; sg += NG) {
         if (valid) d0 += Ef[((size_t)sg * 3 + 2) * nx1 + k];
         if (sg < P - 1) {
             double g = 0.0;
             if (valid)
                 g = (double)a.rhat[fb + (size_t)((sg + 1) * Ls - 1) * nx1 + k] * a.inv_b +
                     Ef[((size_t)sg * 3 + 1) * nx1 + k] + Ef[((size_t)(sg + 1) * 3 + 0) * nx1 + k];
-            Gs[sg * 65 + kl] = g;
+            Gs[sg * KS + kl] = g;
         }
     }
     __syncthreads();
@@ -450,18 +532,35 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
     const int lane = tid & 63, wave = tid >> 6;
     const int sig = lane;
     const bool sepl = sig < P - 1;
-    for (int kk = wave; kk < 64; kk += 4) {
+    for (int kk = wave; kk < KT; kk += 4) {
         if (k0 + kk >= nx1) break;                          // uniform per wave
         const double* tab = a.red + (size_t)(k0 + kk) * a.RW;
-        const double G = sepl ? Gs[sig * 65 + kk] : 0.0;
+        const double G = sepl ? Gs[sig * KS + kk] : 0.0;
+        // this lane's weight at every level, loaded up front (independent loads)
+        double wl[6], bl[6];
+        {
+            int woff = 2 + q;
+#pragma unroll
+            for (int l = 0; l < 6; ++l) {
+                wl[l] = bl[l] = 0.0;
+                if (l < q) {
+                    const int size = P >> l;
+                    const int pos = sig & (size - 1);
+                    const int widx = min(pos, size - 2 - pos);
+                    if (sepl && pos != size - 1) wl[l] = tab[woff + widx];
+                    bl[l] = tab[2 + l];
+                    woff += size >> 1;
+                }
+            }
+        }
         double x = 0.0;
-        int woff = 2 + q;
-        for (int l = 0; l < q; ++l) {
+#pragma unroll
+        for (int l = 0; l < 6; ++l) {
+            if (l >= q) break;
             const int size = P >> l;
             const int pos = sig & (size - 1);
             const bool member = sepl && (pos != size - 1);
-            const int widx = min(pos, size - 2 - pos);
-            double tv = member ? tab[woff + widx] * G : 0.0;
+            double tv = member ? wl[l] * G : 0.0;
             for (int off = 1; off < size; off <<= 1) tv += __shfl_xor(tv, off, 64);
             const int base = sig - pos;
             const int ll = base - 1, rl = base + size - 1;
@@ -469,20 +568,19 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
             const double xr_ = __shfl(x, rl > 63 ? 63 : rl, 64);
             const double xl = (ll < 0) ? 0.0 : xl_;
             const double xr = (rl >= P - 1) ? 0.0 : xr_;
-            if (member && pos == (size >> 1) - 1) x = tv + tab[2 + l] * (xl + xr);
-            woff += size >> 1;
+            if (member && pos == (size >> 1) - 1) x = tv + bl[l] * (xl + xr);
         }
-        if (sepl) Xs[sig * 65 + kk] = x;
+        if (sepl) Xs[sig * KS + kk] = x;
     }
     __syncthreads();
 
     // phase 3: store separators, interface part of the inner product
     double c = d0;
-    for (int sg = grp; sg < P - 1; sg += 4) {
-        const double x = Xs[sg * 65 + kl];
+    for (int sg = grp; sg < P - 1; sg += NG) {
+        const double x = Xs[sg * KS + kl];
         if (valid) {
             a.y[fb + (size_t)((sg + 1) * Ls - 1) * nx1 + k] = (T)x;
-            c += x * Gs[sg * 65 + kl];
+            c += x * Gs[sg * KS + kl];
         }
     }
     if (a.mode == 0) return;
@@ -727,7 +825,10 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.ctl = reduce ? p->ctl : nullptr;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
-    dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT), p->S * p->C);
+    a.nfields = p->S * p->C;
+    a.nsh = std::min(a.nfields, 8);
+    dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT),
+              (a.nfields + a.nsh - 1) / a.nsh);
     hipLaunchKernelGGL(stencil_kernel<T>, grid, dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !reduce) return e;
@@ -786,9 +887,15 @@ DstArgs<T> dst_args(lg_plan* p) {
 
 template <typename T, int LS>
 hipError_t td_launch(lg_plan* p, TdArgs<T>& a, int nfields) {
-    const int wpb = std::min(4, a.P);
-    dim3 grid((a.nx1 + 63) / 64, (a.P + wpb - 1) / wpb, nfields);
-    hipLaunchKernelGGL((td_kernel<T, LS>), grid, dim3(64 * wpb), 0, p->stream, a);
+    // segments per wave: up to 4 while the grid keeps >= 2048 blocks
+    const int ktiles = (a.nx1 + 63) / 64;
+    int spw = 1;
+    while (spw < 4 && 4 * spw * 2 <= a.P &&
+           (long)ktiles * ((a.P + 8 * spw - 1) / (8 * spw)) * nfields >= 2048)
+        spw *= 2;
+    a.spw = spw;
+    dim3 grid(ktiles, (a.P + 4 * spw - 1) / (4 * spw), nfields);
+    hipLaunchKernelGGL((td_kernel<T, LS>), grid, dim3(256), 0, p->stream, a);
     return hipGetLastError();
 }
 
@@ -835,8 +942,14 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode) 
     a.ctl = p->ctl;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
-    const dim3 grid((p->nx1 + 63) / 64, nfields);
-    hipLaunchKernelGGL(rs_kernel<T>, grid, dim3(256), 0, p->stream, a);
+    // 64 wavenumbers per block when the grid stays large, else 16 (more blocks)
+    const bool wide = (long)((p->nx1 + 63) / 64) * nfields >= 1024;
+    const int KT = wide ? 64 : 16;
+    const dim3 grid((p->nx1 + KT - 1) / KT, nfields);
+    if (wide)
+        hipLaunchKernelGGL((rs_kernel<T, 64>), grid, dim3(256), 0, p->stream, a);
+    else
+        hipLaunchKernelGGL((rs_kernel<T, 16>), grid, dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == 0) return e;
     return finalize(p, FIN_RZ, (int)grid.x, mode, 0.0, 0, B.b * 2.0 / p->g.nx);

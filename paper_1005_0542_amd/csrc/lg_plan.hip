@@ -425,7 +425,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     {
         const size_t sb = (size_t)((p->nx1 + 63) / 64) * ((p->nz1 + 31) / 32);
         const size_t db = (size_t)dst_blocks_per_field(grid->nx, p->nz1);
-        const size_t rb = (size_t)((p->nx1 + 63) / 64);
+        const size_t rb = (size_t)((p->nx1 + 15) / 16);
         p->partial_stride = std::max(sb, std::max(db, rb));
     }
     if ((st = dev_alloc(p, &p->partial, (size_t)SC * p->partial_stride * 8)) != LG_OK) return bail(st);

@@ -130,7 +130,9 @@ def _oracle_pcg(kappa, rho, h, nx, nz, dx, dz, b, tol, max_iter):
     return krylov.pcg(lambda y: operator.apply_A(y, kappa, w, dx, dz), B.solve, b, tol, max_iter)
 
 
-@pytest.mark.parametrize("nx,nz,P,gi", [(64, 64, 4, 0), (64, 64, 1, -1), (128, 64, 8, 3), (32, 128, 8, 0)])
+@pytest.mark.parametrize("nx,nz,P,gi", [(64, 64, 4, 0), (64, 64, 1, -1), (128, 64, 8, 3), (32, 128, 8, 0),
+                                        (1024, 256, 0, 0), (4096, 64, 0, 0), (2048, 128, 0, 0),
+                                        (8, 4096, 64, 0)])
 def test_pcg_parity_fp64(nx, nz, P, gi):
     torch = torch_cuda()
     kappa, rho = heterogeneous(nx, nz)
@@ -215,7 +217,7 @@ def test_pcg_status_semantics():
     assert res2.iters[0] == ito
 
 
-@pytest.mark.parametrize("nx,nz", [(64, 64), (256, 128)])
+@pytest.mark.parametrize("nx,nz", [(64, 64), (256, 128), (4096, 64), (2048, 128)])
 def test_pcg_mixed_precision_error_reported(nx, nz):
     torch = torch_cuda()
     kappa, rho = heterogeneous(nx, nz, variable_density=False)
