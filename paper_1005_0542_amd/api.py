@@ -147,7 +147,7 @@ class Plan:
         import torch
         n = self._nvec()
         opts = _lib.SolveOpts(tol, max_iter, restart)
-        infos = (_lib.SolveInfo * (self.nshots * self.ncomp))()
+        infos = (_lib.SolveInfo * self.nshots)()
         st = fn(self.handle, self._ptr(b, torch.float64, "b", n), self._ptr(x, torch.float64, "x", n),
                 ctypes.byref(opts), infos)
         check(st, name, allowed=(_lib.LG_OK, _lib.LG_ERR_NOT_CONVERGED, _lib.LG_ERR_BREAKDOWN,

@@ -1,24 +1,486 @@
-// Elastic (Lame) operator and GMRES(k) driver.
+// Elastic (Lame) Laguerre-domain operator, block preconditioner apply, and the
+// restarted GMRES(k) driver (Sec. 2.2-2.4, eqs. elastic_problemQn, precond2).
+//
+// Operator (2D Cartesian reading of the paper's second-order scheme, SPD sign;
+// node-sampled lambda, mu; face values are means of node values; Dc is the
+// two-cell central difference):
+//   (C u)_x = -Dx+((l+2m) Dx- ux) - Dz+(m Dz- ux) - Dxc(l Dzc uz) - Dzc(m Dxc uz) + w ux
+//   (C u)_z = -Dx+(m Dx- uz) - Dz+((l+2m) Dz- uz) - Dzc(l Dxc ux) - Dxc(m Dzc ux) + w uz
+//
+// GMRES(k) is right-preconditioned by K = diag(B1, B2); the Arnoldi basis is
+// orthogonalised by classical Gram-Schmidt applied twice (all inner products
+// of one pass in a single sweep over the basis), every vector operation and
+// inner product runs on the device, and only the (k+1) x k Hessenberg matrix
+// with its Givens rotations lives on the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "lg_device.h"
 #include "lg_internal.h"
 
 namespace lg {
 
-hipError_t launch_elastic_stencil(lg_plan* p, const void* x, void* y) {
-    (void)p;
-    (void)x;
-    (void)y;
-    return hipErrorNotSupported;
+// ---------------------------------------------------------------------------
+// operator
+// ---------------------------------------------------------------------------
+template <typename T>
+struct ElArgs {
+    const T* u;     // [S][2][nz1][nx1]
+    T* y;
+    const T* lam;   // nodes (nz+1)(nx+1)
+    const T* mu;
+    const T* w;     // interior
+    int nx1, nz1, S;
+    T idx2, idz2, ixz;   // 1/dx^2, 1/dz^2, 1/(4 dx dz)
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void elastic_stencil_kernel(ElArgs<T> a) {
+    const size_t npts = (size_t)a.nx1 * a.nz1;
+    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= npts * a.S) return;
+    const size_t s = e / npts;
+    const size_t pt = e - s * npts;
+    const int j = (int)(pt / a.nx1), i = (int)(pt - (size_t)j * a.nx1);
+    const int nx1 = a.nx1, nz1 = a.nz1, NXN = nx1 + 2;
+    const int I = i + 1, J = j + 1;
+    const T* ux = a.u + s * 2 * npts;
+    const T* uz = ux + npts;
+    // interior value of a component at node (Ii, Jj), zero on the boundary
+    auto U = [&](const T* f, int Ii, int Jj) -> T {
+        if (Ii < 1 || Ii > nx1 || Jj < 1 || Jj > nz1) return (T)0;
+        return f[(size_t)(Jj - 1) * nx1 + (Ii - 1)];
+    };
+    auto L = [&](int Ii, int Jj) -> T { return a.lam[(size_t)Jj * NXN + Ii]; };
+    auto Mu = [&](int Ii, int Jj) -> T { return a.mu[(size_t)Jj * NXN + Ii]; };
+    const T h = (T)0.5;
+    const T l0 = L(I, J), m0 = Mu(I, J);
+    const T p0 = l0 + 2 * m0;
+    const T pE = h * (p0 + L(I + 1, J) + 2 * Mu(I + 1, J)), pW = h * (p0 + L(I - 1, J) + 2 * Mu(I - 1, J));
+    const T pS = h * (p0 + L(I, J + 1) + 2 * Mu(I, J + 1)), pN = h * (p0 + L(I, J - 1) + 2 * Mu(I, J - 1));
+    const T mE = h * (m0 + Mu(I + 1, J)), mW = h * (m0 + Mu(I - 1, J));
+    const T mS = h * (m0 + Mu(I, J + 1)), mN = h * (m0 + Mu(I, J - 1));
+    const T cx = U(ux, I, J), cz = U(uz, I, J);
+    // diagonal (flux) parts
+    T yx = (pE * (cx - U(ux, I + 1, J)) + pW * (cx - U(ux, I - 1, J))) * a.idx2 +
+           (mS * (cx - U(ux, I, J + 1)) + mN * (cx - U(ux, I, J - 1))) * a.idz2;
+    T yz = (mE * (cz - U(uz, I + 1, J)) + mW * (cz - U(uz, I - 1, J))) * a.idx2 +
+           (pS * (cz - U(uz, I, J + 1)) + pN * (cz - U(uz, I, J - 1))) * a.idz2;
+    // mixed parts, x-equation: -Dxc(l Dzc uz) - Dzc(m Dxc uz)
+    const T dxz_p = U(uz, I + 1, J + 1) - U(uz, I + 1, J - 1);   // Dzc uz at I+1 (x 2dz)
+    const T dxz_m = U(uz, I - 1, J + 1) - U(uz, I - 1, J - 1);   // Dzc uz at I-1
+    const T dzx_p = U(uz, I + 1, J + 1) - U(uz, I - 1, J + 1);   // Dxc uz at J+1 (x 2dx)
+    const T dzx_m = U(uz, I + 1, J - 1) - U(uz, I - 1, J - 1);   // Dxc uz at J-1
+    yx -= (L(I + 1, J) * dxz_p - L(I - 1, J) * dxz_m + Mu(I, J + 1) * dzx_p - Mu(I, J - 1) * dzx_m) * a.ixz;
+    const T exz_p = U(ux, I + 1, J + 1) - U(ux, I + 1, J - 1);   // Dzc ux at I+1
+    const T exz_m = U(ux, I - 1, J + 1) - U(ux, I - 1, J - 1);
+    const T ezx_p = U(ux, I + 1, J + 1) - U(ux, I - 1, J + 1);   // Dxc ux at J+1
+    const T ezx_m = U(ux, I + 1, J - 1) - U(ux, I - 1, J - 1);
+    // z-equation: -Dzc(l Dxc ux) - Dxc(m Dzc ux)
+    yz -= (L(I, J + 1) * ezx_p - L(I, J - 1) * ezx_m + Mu(I + 1, J) * exz_p - Mu(I - 1, J) * exz_m) * a.ixz;
+    const T wv = a.w[pt];
+    T* yo = a.y + s * 2 * npts;
+    yo[pt] = yx + wv * cx;
+    yo[npts + pt] = yz + wv * cz;
 }
 
+template <typename T>
+hipError_t el_stencil_T(lg_plan* p, const T* x, T* y) {
+    ElArgs<T> a;
+    a.u = x;
+    a.y = y;
+    a.lam = (const T*)p->lam;
+    a.mu = (const T*)p->mu;
+    a.w = (const T*)p->w;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.S = p->S;
+    a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
+    a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
+    a.ixz = (T)(1.0 / (4.0 * p->g.dx * p->g.dz));
+    const size_t total = p->npts * p->S;
+    hipLaunchKernelGGL(elastic_stencil_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       p->stream, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_elastic_stencil(lg_plan* p, const void* x, void* y) {
+    if (p->prec == LG_FP64) return el_stencil_T<double>(p, (const double*)x, (double*)y);
+    return el_stencil_T<float>(p, (const float*)x, (float*)y);
+}
+
+// K^{-1} = diag(B1^{-1}, B2^{-1}) on working-type vectors [S][2][..]; uses the
+// plan's spectral buffers rhat and y.
+hipError_t launch_elastic_precond(lg_plan* p, const void* r, void* z) {
+    const int S = p->S;
+    hipError_t e = launch_dst(p, 0, r, p->rhat, S * 2);
+    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
+        e = launch_td(p, c, p->rhat, p->y, S, 0, 2, c);
+        if (e == hipSuccess && p->blk[c].P > 1) e = launch_rs(p, c, p->rhat, p->y, S, 0, 2, c);
+        if (e == hipSuccess && p->blk[c].P > 1) e = launch_correct(p, c, p->y, S, 2, c);
+    }
+    if (e == hipSuccess) e = launch_dst(p, 1, p->y, z, S * 2);
+    return e;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES vector kernels (FP64), one shot = 2 npts contiguous values
+// ---------------------------------------------------------------------------
+constexpr int GM_MAXK = 32;            // largest restart length supported
+constexpr int GM_BLK = 256;
+constexpr int GM_CHUNK = 4096;         // elements per block per shot in reductions
+
+// partial[s][i][b] = sum over block b of the shot's chunk of V_i * w (i < m);
+// one sweep reads w and every V_i once.
+__global__ __launch_bounds__(GM_BLK) void gm_multidot_kernel(const double* __restrict__ V, size_t vstride,
+                                                             int m, const double* __restrict__ w, size_t n_s,
+                                                             const int* __restrict__ active,
+                                                             double* __restrict__ partial, int nblk) {
+    __shared__ double red[GM_BLK / 64];
+    const int s = blockIdx.y, b = blockIdx.x;
+    if (active[s] == 0) return;
+    const size_t base = (size_t)s * n_s;
+    const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
+    double acc[GM_MAXK + 1];
+#pragma unroll
+    for (int i = 0; i <= GM_MAXK; ++i) acc[i] = 0.0;
+    for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) {
+        const double wv = w[base + e];
+#pragma unroll
+        for (int i = 0; i <= GM_MAXK; ++i)
+            if (i < m) acc[i] += V[i * vstride + base + e] * wv;
+    }
+#pragma unroll
+    for (int i = 0; i <= GM_MAXK; ++i) {
+        if (i < m) {                       // uniform over the block
+            const double t = block_sum(acc[i], red);
+            if (threadIdx.x == 0) partial[((size_t)s * (GM_MAXK + 1) + i) * nblk + b] = t;
+        }
+    }
+}
+
+// out[s][i] = sum_b partial[s][i][b] (fixed order), i < m; plus add[s][i] if given
+__global__ __launch_bounds__(GM_BLK) void gm_reduce_kernel(const double* __restrict__ partial, int m, int nblk,
+                                                           const int* __restrict__ active,
+                                                           double* __restrict__ out, int out_stride) {
+    __shared__ double red[GM_BLK / 64];
+    const int s = blockIdx.x;
+    if (active[s] == 0) return;
+    for (int i = 0; i < m; ++i) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += GM_BLK) v += partial[((size_t)s * (GM_MAXK + 1) + i) * nblk + b];
+        v = block_sum(v, red);
+        if (threadIdx.x == 0) out[(size_t)s * out_stride + i] = v;
+    }
+}
+
+// w -= sum_{i<m} coef[s][i] V_i   (per-shot coefficients in device memory)
+__global__ __launch_bounds__(GM_BLK) void gm_subtract_kernel(const double* __restrict__ V, size_t vstride, int m,
+                                                             const double* __restrict__ coef, int coef_stride,
+                                                             double* __restrict__ w, size_t n_s, int S,
+                                                             const int* __restrict__ active) {
+    const size_t e = (size_t)blockIdx.x * GM_BLK + threadIdx.x;
+    if (e >= n_s * S) return;
+    const int s = (int)(e / n_s);
+    if (active[s] == 0) return;
+    double acc = w[e];
+    for (int i = 0; i < m; ++i) acc -= coef[(size_t)s * coef_stride + i] * V[i * vstride + e];
+    w[e] = acc;
+}
+
+// out = x * (1/sqrt(nrm2[s])) when nrm2 > 0
+__global__ __launch_bounds__(GM_BLK) void gm_normalize_kernel(const double* __restrict__ x,
+                                                              const double* __restrict__ nrm2, int nrm_stride,
+                                                              double* __restrict__ out, size_t n_s, int S,
+                                                              const int* __restrict__ active) {
+    const size_t e = (size_t)blockIdx.x * GM_BLK + threadIdx.x;
+    if (e >= n_s * S) return;
+    const int s = (int)(e / n_s);
+    if (active[s] == 0) return;
+    const double q = nrm2[(size_t)s * nrm_stride];
+    out[e] = q > 0.0 ? x[e] / sqrt(q) : 0.0;
+}
+
+// out = sum_{i<m} y[s][i] V_i
+__global__ __launch_bounds__(GM_BLK) void gm_combine_kernel(const double* __restrict__ V, size_t vstride, int m,
+                                                            const double* __restrict__ y, int y_stride,
+                                                            double* __restrict__ out, size_t n_s, int S,
+                                                            const int* __restrict__ active) {
+    const size_t e = (size_t)blockIdx.x * GM_BLK + threadIdx.x;
+    if (e >= n_s * S) return;
+    const int s = (int)(e / n_s);
+    if (active[s] == 0) return;
+    double acc = 0.0;
+    for (int i = 0; i < m; ++i) acc += y[(size_t)s * y_stride + i] * V[i * vstride + e];
+    out[e] = acc;
+}
+
+// out = a + sa * b   (masked per shot)
+__global__ __launch_bounds__(GM_BLK) void gm_axpy_kernel(const double* __restrict__ a, double sa,
+                                                         const double* __restrict__ b, double* __restrict__ out,
+                                                         size_t n_s, int S, const int* __restrict__ active) {
+    const size_t e = (size_t)blockIdx.x * GM_BLK + threadIdx.x;
+    if (e >= n_s * S) return;
+    const int s = (int)(e / n_s);
+    if (active[s] == 0) return;
+    out[e] = a[e] + sa * b[e];
+}
+
+namespace {
+
+struct GmState {
+    double* V = nullptr;       // [k+1][nvec]
+    double* w = nullptr;       // [nvec]
+    double* z = nullptr;       // [nvec]
+    double* partial = nullptr; // [S][MAXK+1][nblk]
+    double* dots = nullptr;    // [S][DS]
+    int* active = nullptr;     // [S]
+};
+
+constexpr int DS = 2 * (GM_MAXK + 1) + 2;   // h (k+1), h2 (k+1), norm^2, spare
+
+inline unsigned nblocks(size_t n) { return (unsigned)((n + GM_BLK - 1) / GM_BLK); }
+
+}  // namespace
+
 lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts* o, lg_solve_info* info) {
-    (void)p;
-    (void)b;
-    (void)x;
-    (void)o;
-    (void)info;
-    return fail(LG_ERR_UNSUPPORTED, "elastic GMRES not built yet");
+    if (p->prec != LG_FP64) return fail(LG_ERR_UNSUPPORTED, "GMRES is built for FP64 plans");
+    const int k = o->restart;
+    if (k > GM_MAXK) return fail(LG_ERR_UNSUPPORTED, "restart must be <= 32");
+    const int S = p->S;
+    const size_t n_s = 2 * p->npts, nvec = p->nvec;
+    const int nblk = (int)((n_s + GM_CHUNK - 1) / GM_CHUNK);
+    // workspace (grown on demand, owned by the plan)
+    if (p->gm_k < k) {
+        if (p->gm_V) (void)hipFree(p->gm_V);
+        p->gm_V = nullptr;
+        p->gm_k = 0;
+        LG_HIP(hipMalloc((void**)&p->gm_V, (size_t)(k + 1) * nvec * 8));
+        p->gm_k = k;
+    }
+    if (!p->gm_w) LG_HIP(hipMalloc((void**)&p->gm_w, nvec * 8));
+    if (!p->gm_z) LG_HIP(hipMalloc((void**)&p->gm_z, nvec * 8));
+    if (!p->gm_x) LG_HIP(hipMalloc((void**)&p->gm_x, ((size_t)S * (GM_MAXK + 1) * nblk + (size_t)S * DS) * 8 + S * 4 + 64));
+    GmState g;
+    g.V = p->gm_V;
+    g.w = p->gm_w;
+    g.z = p->gm_z;
+    g.partial = p->gm_x;
+    g.dots = g.partial + (size_t)S * (GM_MAXK + 1) * nblk;
+    g.active = (int*)(g.dots + (size_t)S * DS);
+    hipStream_t st = p->stream;
+    const unsigned nb = nblocks(nvec);
+
+    std::vector<int> act(S, 1), status(S, LG_ERR_NOT_CONVERGED), total(S, 0);
+    std::vector<double> bnorm(S, 0.0), est(S, 1.0), dots_h((size_t)S * DS);
+    auto push_active = [&]() -> hipError_t {
+        return hipMemcpyAsync(g.active, act.data(), S * sizeof(int), hipMemcpyHostToDevice, st);
+    };
+    auto dot_into = [&](const double* Vb, size_t vstride, int m, const double* wv, int slot) -> hipError_t {
+        hipLaunchKernelGGL(gm_multidot_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, Vb, vstride, m, wv, n_s,
+                           g.active, g.partial, nblk);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(gm_reduce_kernel, dim3(S), dim3(GM_BLK), 0, st, g.partial, m, nblk, g.active,
+                           g.dots + slot, DS);
+        return hipGetLastError();
+    };
+    auto fetch_dots = [&]() -> hipError_t {
+        hipError_t e = hipMemcpyAsync(dots_h.data(), g.dots, (size_t)S * DS * 8, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        return e;
+    };
+    auto fin = [&](lg_status s) {
+        int worst = LG_OK;
+        for (int i = 0; i < S; ++i) {
+            if (info) {
+                info[i].iters = total[i];
+                info[i].status = status[i];
+                info[i].relres = bnorm[i] > 0 ? est[i] : 0.0;
+            }
+            auto sev = [](int v) { return v == LG_OK ? 0 : v == LG_ERR_NOT_CONVERGED ? 1 : v == LG_ERR_BREAKDOWN ? 2 : 3; };
+            if (sev(status[i]) > sev(worst)) worst = status[i];
+        }
+        return s != LG_OK ? s : (lg_status)worst;
+    };
+
+    // ||b||, x = 0
+    LG_HIP(push_active());
+    LG_HIP(hipMemsetAsync(x, 0, nvec * 8, st));
+    LG_HIP(dot_into(b, 0, 1, b, 2 * (GM_MAXK + 1)));
+    LG_HIP(fetch_dots());
+    for (int s = 0; s < S; ++s) {
+        const double bb = dots_h[(size_t)s * DS + 2 * (GM_MAXK + 1)];
+        bnorm[s] = std::sqrt(bb);
+        if (!std::isfinite(bnorm[s])) {
+            status[s] = LG_ERR_NONFINITE;
+            act[s] = 0;
+            est[s] = NAN;
+        } else if (bnorm[s] == 0.0) {
+            status[s] = LG_OK;
+            act[s] = 0;
+            est[s] = 0.0;
+        }
+    }
+    const double tol = o->tol;
+    std::vector<double> H((size_t)S * (k + 1) * k), cs((size_t)S * k), sn((size_t)S * k), gv((size_t)S * (k + 1));
+    std::vector<double> yv((size_t)S * (GM_MAXK + 1));
+    std::vector<int> jused(S), cyc(S);
+    bool first = true;
+    for (int cycle = 0; cycle < 100000; ++cycle) {
+        bool any = false;
+        for (int s = 0; s < S; ++s) any = any || act[s];
+        if (!any) break;
+        LG_HIP(push_active());
+        // r = b - C x  (first cycle: r = b), into V_0; beta = ||r||
+        double* V0 = g.V;
+        if (first) {
+            LG_HIP(hipMemcpyAsync(V0, b, nvec * 8, hipMemcpyDeviceToDevice, st));
+        } else {
+            LG_HIP(launch_elastic_stencil(p, x, g.w));
+            hipLaunchKernelGGL(gm_axpy_kernel, dim3(nb), dim3(GM_BLK), 0, st, b, -1.0, g.w, V0, n_s, S, g.active);
+            LG_HIP(hipGetLastError());
+        }
+        first = false;
+        LG_HIP(dot_into(V0, 0, 1, V0, 2 * (GM_MAXK + 1)));
+        LG_HIP(fetch_dots());
+        for (int s = 0; s < S; ++s) {
+            cyc[s] = act[s];
+            jused[s] = 0;
+            if (!act[s]) continue;
+            const double beta = std::sqrt(dots_h[(size_t)s * DS + 2 * (GM_MAXK + 1)]);
+            if (!std::isfinite(beta)) {
+                status[s] = LG_ERR_NONFINITE;
+                act[s] = cyc[s] = 0;
+                est[s] = NAN;
+            } else if (beta <= tol * bnorm[s]) {
+                status[s] = LG_OK;
+                act[s] = cyc[s] = 0;
+                est[s] = beta / bnorm[s];
+            } else {
+                std::fill(gv.begin() + (size_t)s * (k + 1), gv.begin() + (size_t)(s + 1) * (k + 1), 0.0);
+                gv[(size_t)s * (k + 1)] = beta;
+            }
+        }
+        LG_HIP(push_active());
+        // V_0 = r / beta
+        hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, V0, g.dots + 2 * (GM_MAXK + 1), DS,
+                           V0, n_s, S, g.active);
+        LG_HIP(hipGetLastError());
+        std::vector<int> inner = act;   // shots still in this cycle's Arnoldi
+        for (int j = 0; j < k; ++j) {
+            bool anyin = false;
+            for (int s = 0; s < S; ++s) anyin = anyin || inner[s];
+            if (!anyin) break;
+            double* Vj = g.V + (size_t)j * nvec;
+            double* Vn = g.V + (size_t)(j + 1) * nvec;
+            // w = C K^{-1} v_j
+            LG_HIP(launch_elastic_precond(p, Vj, g.z));
+            LG_HIP(launch_elastic_stencil(p, g.z, g.w));
+            // classical Gram-Schmidt, twice
+            LG_HIP(dot_into(g.V, nvec, j + 1, g.w, 0));
+            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1, g.dots, DS, g.w,
+                               n_s, S, g.active);
+            LG_HIP(hipGetLastError());
+            LG_HIP(dot_into(g.V, nvec, j + 1, g.w, GM_MAXK + 1));
+            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1,
+                               g.dots + GM_MAXK + 1, DS, g.w, n_s, S, g.active);
+            LG_HIP(hipGetLastError());
+            LG_HIP(dot_into(g.w, 0, 1, g.w, 2 * (GM_MAXK + 1)));
+            hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.w, g.dots + 2 * (GM_MAXK + 1),
+                               DS, Vn, n_s, S, g.active);
+            LG_HIP(hipGetLastError());
+            LG_HIP(fetch_dots());
+            for (int s = 0; s < S; ++s) {
+                if (!inner[s]) continue;
+                const double* d = &dots_h[(size_t)s * DS];
+                double* Hs = &H[(size_t)s * (k + 1) * k];
+                auto Hc = [&](int r, int c) -> double& { return Hs[(size_t)r * k + c]; };
+                for (int i = 0; i <= j; ++i) Hc(i, j) = d[i] + d[GM_MAXK + 1 + i];
+                Hc(j + 1, j) = std::sqrt(d[2 * (GM_MAXK + 1)]);
+                double* csv = &cs[(size_t)s * k];
+                double* snv = &sn[(size_t)s * k];
+                double* gs = &gv[(size_t)s * (k + 1)];
+                for (int i = 0; i < j; ++i) {
+                    const double tmp = csv[i] * Hc(i, j) + snv[i] * Hc(i + 1, j);
+                    Hc(i + 1, j) = -snv[i] * Hc(i, j) + csv[i] * Hc(i + 1, j);
+                    Hc(i, j) = tmp;
+                }
+                const double hj1 = Hc(j + 1, j);
+                const double den = std::hypot(Hc(j, j), hj1);
+                total[s] += 1;
+                jused[s] = j + 1;
+                if (den == 0.0) {
+                    status[s] = LG_ERR_BREAKDOWN;
+                    act[s] = inner[s] = cyc[s] = 0;
+                    jused[s] = 0;
+                    continue;
+                }
+                csv[j] = Hc(j, j) / den;
+                snv[j] = hj1 / den;
+                Hc(j, j) = den;
+                Hc(j + 1, j) = 0.0;
+                gs[j + 1] = -snv[j] * gs[j];
+                gs[j] = csv[j] * gs[j];
+                est[s] = std::fabs(gs[j + 1]) / bnorm[s];
+                if (!std::isfinite(est[s])) {
+                    status[s] = LG_ERR_NONFINITE;
+                    act[s] = inner[s] = cyc[s] = 0;
+                    jused[s] = 0;
+                    continue;
+                }
+                if (est[s] <= tol || hj1 == 0.0) {
+                    status[s] = LG_OK;
+                    act[s] = 0;          // converged: finish after this cycle's update
+                    inner[s] = 0;
+                } else if (total[s] >= o->max_iter) {
+                    status[s] = LG_ERR_NOT_CONVERGED;
+                    act[s] = 0;
+                    inner[s] = 0;
+                }
+            }
+            // shots that stopped keep their basis; the kernels skip them from now on
+            std::vector<int> mask = inner;
+            LG_HIP(hipMemcpyAsync(g.active, mask.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+        }
+        // x += K^{-1} (V y) for every shot that ran an Arnoldi cycle
+        bool anyupd = false;
+        for (int s = 0; s < S; ++s) {
+            const int m = cyc[s] ? jused[s] : 0;
+            double* ys = &yv[(size_t)s * (GM_MAXK + 1)];
+            std::fill(ys, ys + GM_MAXK + 1, 0.0);
+            if (m == 0) continue;
+            anyupd = true;
+            const double* Hs = &H[(size_t)s * (k + 1) * k];
+            const double* gs = &gv[(size_t)s * (k + 1)];
+            for (int i = m - 1; i >= 0; --i) {
+                double acc = gs[i];
+                for (int c = i + 1; c < m; ++c) acc -= Hs[(size_t)i * k + c] * ys[c];
+                ys[i] = acc / Hs[(size_t)i * k + i];
+            }
+        }
+        if (!anyupd) continue;
+        std::vector<int> upd(S);
+        int mmax = 0;
+        for (int s = 0; s < S; ++s) {
+            upd[s] = (cyc[s] && jused[s] > 0) ? 1 : 0;
+            mmax = std::max(mmax, upd[s] ? jused[s] : 0);
+        }
+        LG_HIP(hipMemcpyAsync(g.dots, yv.data(), (size_t)S * (GM_MAXK + 1) * 8, hipMemcpyHostToDevice, st));
+        LG_HIP(hipMemcpyAsync(g.active, upd.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+        hipLaunchKernelGGL(gm_combine_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, mmax, g.dots, GM_MAXK + 1,
+                           g.w, n_s, S, g.active);
+        LG_HIP(hipGetLastError());
+        LG_HIP(launch_elastic_precond(p, g.w, g.z));
+        hipLaunchKernelGGL(gm_axpy_kernel, dim3(nb), dim3(GM_BLK), 0, st, x, 1.0, g.z, x, n_s, S, g.active);
+        LG_HIP(hipGetLastError());
+        LG_HIP(hipStreamSynchronize(st));
+    }
+    LG_HIP(hipStreamSynchronize(st));
+    return fin(LG_OK);
 }
 
 }  // namespace lg

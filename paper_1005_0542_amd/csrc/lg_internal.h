@@ -130,9 +130,13 @@ inline size_t wsize(const lg_plan* p) { return p->prec == LG_FP64 ? 8 : 4; }
 // launchers (implemented in lg_acoustic.hip); all enqueue on plan->stream
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq);
 hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nfields);
-hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked);
-hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int mode);
-hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields);
+// Dichotomy kernels over `nfields` fields; field f of the launch is buffer
+// field f * fstride + foff (acoustic: 1, 0; one elastic component: 2, c).
+hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked,
+                     int fstride = 1, int foff = 0);
+hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int mode,
+                     int fstride = 1, int foff = 0);
+hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride = 1, int foff = 0);
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter);
 hipError_t launch_correct_idst(lg_plan* p, int init);
@@ -153,5 +157,6 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
 lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts* o,
                       lg_solve_info* info);
 hipError_t launch_elastic_stencil(lg_plan* p, const void* x, void* y);
+hipError_t launch_elastic_precond(lg_plan* p, const void* r, void* z);
 
 }  // namespace lg

@@ -407,6 +407,7 @@ struct TdArgs {
     double* E;       // [field][P][3][nx1]
     int nx1, nz1, P;
     int spw;         // segments per wave
+    int fstride, foff;   // field = grid index * fstride + foff (component selection)
     T inv_b;
     ShotCtl* ctl;    // nullptr: no masking
 };
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
     __shared__ T es[LS * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int k = blockIdx.x * 64 + lane;
-    const int field = blockIdx.z;
+    const int field = blockIdx.z * a.fstride + a.foff;
     if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
     const int nx1 = a.nx1;
     {
@@ -487,6 +488,7 @@ struct RsArgs {
     const double* E;
     const double* red;   // [nx1][RW]
     int nx1, nz1, P, q, Ls, RW;
+    int fstride, foff;   // field = grid index * fstride + foff
     double inv_b;
     int mode;
     ShotCtl* ctl;
@@ -506,7 +508,7 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
     __shared__ double Gs[64 * KS];
     __shared__ double Xs[64 * KS];
     __shared__ double red[4];
-    const int field = blockIdx.y;
+    const int field = blockIdx.y * a.fstride + a.foff;
     if (a.mode != 0 && a.ctl[field].active == 0) return;   // uniform per block
     const int P = a.P, q = a.q, Ls = a.Ls, nx1 = a.nx1;
     const int tid = threadIdx.x, kl = tid % KT, grp = tid / KT;
@@ -681,12 +683,13 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
 // zhat = y + xl u_i + xr u_{Ls-i} on segment rows, in place.
 template <typename T>
 __global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, int nx1, int nz1,
-                                                      int Ls, int P, size_t total) {
+                                                      int Ls, int P, size_t total, int fstride,
+                                                      int foff) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     const size_t npts = (size_t)nx1 * nz1;
-    const size_t f = e / npts;
-    const size_t pt = e - f * npts;
+    const size_t f = (e / npts) * fstride + foff;
+    const size_t pt = e % npts;
     const int j = (int)(pt / nx1), k = (int)(pt - (size_t)j * nx1);
     const int jj = j + 1;
     const int rs = jj & (Ls - 1);
@@ -900,9 +903,12 @@ hipError_t td_launch(lg_plan* p, TdArgs<T>& a, int nfields) {
 }
 
 template <typename T>
-hipError_t td_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, bool masked) {
+hipError_t td_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, bool masked, int fstride,
+                int foff) {
     const PrecBlock& B = p->blk[bi];
     TdArgs<T> a;
+    a.fstride = fstride;
+    a.foff = foff;
     a.rhat = rhat;
     a.y = y;
     a.etab = (const T*)B.etab;
@@ -924,9 +930,12 @@ hipError_t td_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, bool maske
 }
 
 template <typename T>
-hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode) {
+hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, int fstride,
+                int foff) {
     const PrecBlock& B = p->blk[bi];
     RsArgs<T> a;
+    a.fstride = fstride;
+    a.foff = foff;
     a.rhat = rhat;
     a.y = y;
     a.E = p->E;
@@ -1019,27 +1028,30 @@ hipError_t launch_correct_idst(lg_plan* p, int init) {
     return dst_dispatch<float, DST_CORRECT>(p, a, p->S * p->C);
 }
 
-hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked) {
+hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked,
+                     int fstride, int foff) {
     if (p->prec == LG_FP64)
-        return td_T<double>(p, blk, (const double*)rhat, (double*)y, nfields, masked != 0);
-    return td_T<float>(p, blk, (const float*)rhat, (float*)y, nfields, masked != 0);
+        return td_T<double>(p, blk, (const double*)rhat, (double*)y, nfields, masked != 0, fstride, foff);
+    return td_T<float>(p, blk, (const float*)rhat, (float*)y, nfields, masked != 0, fstride, foff);
 }
 
-hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int mode) {
-    if (p->prec == LG_FP64) return rs_T<double>(p, blk, (const double*)rhat, (double*)y, nfields, mode);
-    return rs_T<float>(p, blk, (const float*)rhat, (float*)y, nfields, mode);
+hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int mode, int fstride,
+                     int foff) {
+    if (p->prec == LG_FP64)
+        return rs_T<double>(p, blk, (const double*)rhat, (double*)y, nfields, mode, fstride, foff);
+    return rs_T<float>(p, blk, (const float*)rhat, (float*)y, nfields, mode, fstride, foff);
 }
 
-hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields) {
+hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride, int foff) {
     const PrecBlock& B = p->blk[blk];
     const size_t total = (size_t)nfields * p->npts;
     const dim3 grid((unsigned)((total + 255) / 256));
     if (p->prec == LG_FP64)
         hipLaunchKernelGGL(correct_kernel<double>, grid, dim3(256), 0, p->stream, (double*)y,
-                           (const double*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total);
+                           (const double*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff);
     else
         hipLaunchKernelGGL(correct_kernel<float>, grid, dim3(256), 0, p->stream, (float*)y,
-                           (const float*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total);
+                           (const float*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff);
     return hipGetLastError();
 }
 

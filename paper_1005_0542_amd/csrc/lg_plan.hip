@@ -681,8 +681,11 @@ extern "C" lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z) {
     LG_CHECK(check_vec(r, "r"));
     LG_CHECK(check_vec(z, "z"));
     if (r == z) return fail(LG_ERR_INVALID_ARG, "r and z must differ");
-    if (plan->kind != LG_ACOUSTIC) return fail(LG_ERR_UNSUPPORTED, "elastic composite apply not built yet");
     LG_HIP(hipSetDevice(plan->device));
+    if (plan->kind == LG_ELASTIC) {
+        LG_HIP(launch_elastic_precond(plan, r, z));
+        return LG_OK;
+    }
     const int nf = plan->S;
     LG_HIP(launch_dst(plan, 0, r, plan->rhat, nf));
     LG_HIP(launch_td(plan, 0, plan->rhat, plan->y, nf, 0));

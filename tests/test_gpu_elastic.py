@@ -1,0 +1,150 @@
+"""GPU parity of the elastic path (operator C, block preconditioner K, GMRES(k))
+against the FP64 oracle.  The elastic finite-volume scheme itself is not
+printed in the paper, so these cases check the HIP path against the oracle's
+reading of it (the oracle is pinned by dense brute force and symmetry)."""
+import numpy as np
+import pytest
+
+from oracle import elastic, krylov, harmonics, laguerre, precond
+from oracle import OK, NONFINITE
+from paper_1005_0542_amd import api, inputs
+
+from _gpu import log, rel, to_dev, to_np, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _medium(nx, nz, d, seed=1):
+    n = max(nx, nz)
+    vp = inputs.perturbed_layered_velocity(n, d, 2000.0, 4500.0, seed)[: nz + 1, : nx + 1]
+    rho = inputs.perturbed_layered_velocity(n, d, 2000.0, 2600.0, seed + 1)[: nz + 1, : nx + 1]
+    return inputs.elastic_coeffs(vp, rho)
+
+
+def _plan(nx, nz, d, lam, mu, rho, h=300.0, shots=1, precision="fp64", segments=0, n=8, alpha=8):
+    return api.Plan("elastic", nx, nz, d, d, alpha, h, n, np.stack([lam, mu, rho]), precision=precision,
+                    nshots=shots, segments=segments)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("nx,nz,shots", [(16, 16, 1), (64, 32, 2), (8, 128, 1)])
+def test_elastic_operator_parity(prec, nx, nz, shots):
+    torch = torch_cuda()
+    d, h = 5.0, 300.0
+    lam, mu, rho = _medium(nx, nz, d)
+    plan = _plan(nx, nz, d, lam, mu, rho, h=h, shots=shots, precision=prec)
+    u = np.random.default_rng(nx + nz).standard_normal((shots, 2, nz - 1, nx - 1))
+    log(f"elastic operator {prec} {nx}x{nz} shots={shots}")
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    ud = to_dev(u, dt)
+    yd = torch.empty_like(ud)
+    plan.stencil_apply(ud, yd)
+    w = rho[1:-1, 1:-1] * h * h / 4
+    ur = to_np(ud)
+    for s in range(shots):
+        ref = elastic.apply_C(ur[s], lam, mu, w, d, d)
+        assert rel(to_np(yd)[s], ref) < (1e-13 if prec == "fp64" else 2e-5)
+
+
+@pytest.mark.parametrize("nx,nz,P", [(16, 16, 2), (64, 64, 4), (32, 256, 16)])
+def test_elastic_preconditioner_parity(nx, nz, P):
+    torch = torch_cuda()
+    d, h = 5.0, 300.0
+    lam, mu, rho = _medium(nx, nz, d)
+    plan = _plan(nx, nz, d, lam, mu, rho, h=h, shots=2, segments=P)
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, h, nx, nz, d, d)
+    r = np.random.default_rng(P).standard_normal((2, 2, nz - 1, nx - 1))
+    log(f"elastic K^-1 {nx}x{nz} P={P}")
+    rd = to_dev(r, torch.float64)
+    zd = torch.empty_like(rd)
+    plan.precond_apply(rd, zd)
+    for s in range(2):
+        ref = elastic.apply_Kinv(r[s], B1, B2)
+        assert rel(to_np(zd)[s], ref) < 1e-12
+    # the two tridiagonal blocks on their own (one component per shot)
+    for blk, B in ((1, B1), (2, B2)):
+        rh = to_dev(r[:, 0], torch.float64)
+        sh = torch.empty_like(rh)
+        plan.precond_dichotomy_tdma(blk, rh, sh)
+        for s in range(2):
+            assert rel(to_np(sh)[s], B.tridiag_solve(r[s, 0])) < 1e-12
+
+
+@pytest.mark.parametrize("nx,nz,k", [(32, 32, 10), (64, 64, 10), (64, 32, 4)])
+def test_gmres_parity_fp64(nx, nz, k):
+    torch = torch_cuda()
+    d, h = 5.0, 300.0
+    lam, mu, rho = _medium(nx, nz, d)
+    plan = _plan(nx, nz, d, lam, mu, rho, h=h, shots=1)
+    w = rho[1:-1, 1:-1] * h * h / 4
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, h, nx, nz, d, d)
+    b = np.random.default_rng(nx * k).standard_normal((2, nz - 1, nx - 1))
+    xo, ito, rro, sto = krylov.gmres(lambda u: elastic.apply_C(u, lam, mu, w, d, d),
+                                     lambda u: elastic.apply_Kinv(u, B1, B2), b, 1e-10, k)
+    log(f"gmres fp64 {nx}x{nz} k={k}")
+    bd = to_dev(b[None], torch.float64)
+    xd = torch.empty_like(bd)
+    res = plan.gmres_solve(bd, xd, tol=1e-10, max_iter=5000, restart=k)
+    assert sto == OK and res.statuses == [OK]
+    assert abs(res.iters[0] - ito) <= 1, (res.iters, ito)
+    assert rel(to_np(xd)[0], xo) < 1e-8
+    # the true residual meets the tolerance (up to the estimate's slack)
+    r = b - elastic.apply_C(to_np(xd)[0], lam, mu, w, d, d)
+    assert np.linalg.norm(r) <= 10 * 1e-10 * np.linalg.norm(b)
+
+
+def test_gmres_status_and_batched_shots():
+    torch = torch_cuda()
+    nx = nz = 16
+    d, h = 5.0, 300.0
+    lam, mu, rho = _medium(nx, nz, d)
+    plan = _plan(nx, nz, d, lam, mu, rho, h=h, shots=3)
+    b = np.random.default_rng(7).standard_normal((3, 2, nz - 1, nx - 1))
+    b[0] = 0.0
+    b[2, 1, 3, 3] = np.nan
+    log("gmres status: zero / normal / nan")
+    bd = to_dev(b, torch.float64)
+    xd = torch.full_like(bd, 3.0)
+    res = plan.gmres_solve(bd, xd, tol=1e-10, max_iter=2000, restart=10)
+    assert res.statuses[0] == OK and res.iters[0] == 0 and not to_np(xd)[0].any()
+    assert res.statuses[1] == OK
+    assert res.statuses[2] == NONFINITE
+    # shot 1 of the batch equals a single-shot solve of the same system
+    plan1 = _plan(nx, nz, d, lam, mu, rho, h=h, shots=1)
+    x1 = torch.empty_like(bd[1:2])
+    r1 = plan1.gmres_solve(bd[1:2].contiguous(), x1, tol=1e-10, max_iter=2000, restart=10)
+    assert r1.iters[0] == res.iters[1]
+    assert rel(to_np(x1)[0], to_np(xd)[1]) < 1e-13
+
+
+def test_elastic_harmonic_chain_parity():
+    """A few harmonics of the elastic problem with a vertical point force."""
+    torch = torch_cuda()
+    nx = nz = 32
+    d, h, alpha, nh = 5.0, 300.0, 8, 6
+    lam, mu, rho = _medium(nx, nz, d)
+    plan = _plan(nx, nz, d, lam, mu, rho, h=h, shots=1, n=nh, alpha=alpha)
+    src = np.array([[16, 6]], dtype=np.int32)
+    plan.set_sources(src)
+    f = api.source_coeffs(20.0, 1.5 / 20.0, alpha, h, nh)
+    shape = (1, 2, nz - 1, nx - 1)
+    R = torch.zeros(shape, dtype=torch.float64, device="cuda")
+    Ph, Qh, rhs = (torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3))
+    w = rho[1:-1, 1:-1] * h * h / 4
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, h, nx, nz, d, d)
+    sums = harmonics.RunningSums((2, nz - 1, nx - 1), alpha)
+    Rprev = None
+    for m in range(nh):
+        log(f"elastic harmonic {m}")
+        plan.laguerre_rhs(m, R if m else None, Ph, Qh, [f[m]], rhs)
+        res = plan.gmres_solve(rhs, R, tol=1e-11, max_iter=5000, restart=10)
+        assert res.statuses == [OK]
+        srcf = np.zeros((2, nz - 1, nx - 1))
+        srcf[1] = harmonics.source_field((nz - 1, nx - 1), src[0], f[m], d, d)
+        Q = sums.step(m, Rprev)
+        phi = srcf - h * h * rho[1:-1, 1:-1][None] * Q
+        assert rel(to_np(rhs)[0], phi) < 1e-12
+        xo, ito, rro, sto = krylov.gmres(lambda u: elastic.apply_C(u, lam, mu, w, d, d),
+                                         lambda u: elastic.apply_Kinv(u, B1, B2), phi, 1e-11, 10)
+        assert rel(to_np(R)[0], xo) < 1e-8
+        Rprev = to_np(R)[0]
