@@ -48,17 +48,39 @@ def kernel_bytes(ws: int, shots: int, seg_len: int):
     }
 
 
-def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0, profile=True):
+def tuned_params(name, precision, shots, enabled=True):
+    """Tile/segment parameters from the autotuner (its JSON cache, or a fresh
+    search on this device when the cache has no entry for the problem)."""
+    if not enabled:
+        return {}
+    from paper_1005_0542_amd import inputs, tune
+    w = inputs.WORKLOADS[name]
+    kappa, rho = inputs.acoustic_medium_for(w)
+    t0 = time.perf_counter()
+    best = tune.tune_acoustic(w.n_cells, w.n_cells, w.d, w.d, w.alpha, w.h, np.stack([kappa, rho]),
+                              precision, shots)
+    log(f"{name} {precision} x{shots}: tuned {best} ({time.perf_counter() - t0:.1f} s)")
+    return best
+
+
+def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0, profile=True,
+                tuned=None):
     import torch
     from paper_1005_0542_amd import inputs
     from paper_1005_0542_amd.driver import AcousticRun
 
     w = inputs.WORKLOADS[name]
     n_harm = warmup + steps
-    log(f"{name}: precision={precision} shots={shots} harmonics={n_harm}")
+    tuned = dict(tuned or {})
+    if segments:
+        tuned["segments"] = segments
+    if graph_iters:
+        tuned["graph_iters"] = graph_iters
+    log(f"{name}: precision={precision} shots={shots} harmonics={n_harm} params={tuned}")
     t0 = time.perf_counter()
-    run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2), segments=segments,
-                      graph_iters=graph_iters)
+    run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2),
+                      segments=tuned.get("segments", 0), graph_iters=tuned.get("graph_iters", 0),
+                      op_shots=tuned.get("op_shots", 0), seg_per_wave=tuned.get("seg_per_wave", 0))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     npts = (w.n_cells - 1) ** 2
@@ -158,6 +180,7 @@ def main():
     ap.add_argument("--shots", type=int, default=None, help="override the workload shot count")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="time a plain device copy of MIB MiB (counter calibration) and exit")
+    ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuned tiles")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -181,13 +204,15 @@ def main():
     shots = args.shots or w.shots
     if args.profile_only:
         v = run_variant(args.workload, prec, shots, 1, 0, segments=args.segments,
-                        graph_iters=args.graph_iters)
+                        graph_iters=args.graph_iters,
+                        tuned=tuned_params(args.workload, prec, shots, not args.no_tune))
         v.pop("_run")
         print(json.dumps({"workload": args.workload, "precision": prec, "shots": shots,
                           "profile_iterations": 10, "kernels": v["kernels"]}))
         return
+    head_tuned = tuned_params(args.workload, prec, shots, not args.no_tune)
     head = run_variant(args.workload, prec, shots, args.steps, args.warmup,
-                       segments=args.segments, graph_iters=args.graph_iters)
+                       segments=args.segments, graph_iters=args.graph_iters, tuned=head_tuned)
     head.pop("_run")
     torch.cuda.empty_cache()
     variants = {}
@@ -199,7 +224,8 @@ def main():
             ("acoustic2048x64_mixed", "fp64", 64, "fp64_64shot_2048"),
         ]
         for name, prec, shots, key in plan:
-            v = run_variant(name, prec, shots, max(2, args.steps // 2), 1)
+            v = run_variant(name, prec, shots, max(2, args.steps // 2), 1,
+                            tuned=tuned_params(name, prec, shots, not args.no_tune))
             v.pop("_run")
             variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "value", "ms_per_step",
                                                "mean_iters", "whole_iteration_GBps", "dominant")}
@@ -230,7 +256,8 @@ def main():
         "config": {"workload": args.workload, "grid": f"{w.n_cells}x{w.n_cells}", "dx_m": w.d,
                    "shots": w.shots, "precision": w.precision, "tol": w.tol, "alpha": w.alpha,
                    "h": w.h, "harmonics_timed": f"{args.warmup}..{args.warmup + args.steps - 1}",
-                   "segments": head["segments"], "parallelism": "single GPU, shot batch"},
+                   "segments": head["segments"], "tuned": head_tuned,
+                   "parallelism": "single GPU, shot batch"},
         "iters_per_harmonic": head["iters_per_harmonic"],
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -79,11 +79,21 @@ typedef struct { double tol; int32_t max_iter; int32_t restart; } lg_solve_opts;
 typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
 
 /* Optional tuning (zero fields = library default).
- *  segments     number P of Dichotomy segments per z-system (power of two,
- *               1..64, with nz/P in {2,4,...,64}).
- *  graph_iters  Krylov iterations captured per HIP graph (0: default 8,
- *               -1: no graph, plain stream launches). */
-typedef struct { int32_t segments; int32_t graph_iters; int32_t reserved[6]; } lg_tuning;
+ *  segments      number P of Dichotomy segments per z-system (power of two,
+ *                1..64, with nz/P in {2,4,...,64}).
+ *  graph_iters   Krylov iterations captured per HIP graph (0: default 8,
+ *                -1: no graph, plain stream launches).
+ *  op_shots      shots per block of the operator kernel, which reuses the
+ *                medium held in registers across them (1..64; default 8).
+ *  seg_per_wave  Dichotomy segments solved by one wave (1, 2 or 4; default:
+ *                chosen from the grid size). */
+typedef struct {
+    int32_t segments;
+    int32_t graph_iters;
+    int32_t op_shots;
+    int32_t seg_per_wave;
+    int32_t reserved[4];
+} lg_tuning;
 
 typedef struct lg_plan lg_plan;
 

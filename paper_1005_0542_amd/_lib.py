@@ -42,7 +42,8 @@ class SolveInfo(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("segments", c_int32), ("graph_iters", c_int32), ("reserved", c_int32 * 6)]
+    _fields_ = [("segments", c_int32), ("graph_iters", c_int32), ("op_shots", c_int32),
+                ("seg_per_wave", c_int32), ("reserved", c_int32 * 4)]
 
 
 _PLAN = c_void_p

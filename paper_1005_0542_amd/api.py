@@ -58,7 +58,8 @@ class Plan:
 
     def __init__(self, kind: str, nx: int, nz: int, dx: float, dz: float, alpha: int, h: float,
                  n: int, medium: np.ndarray, precision: str = "fp64", nshots: int = 1,
-                 segments: int = 0, graph_iters: int = 0, stream=None):
+                 segments: int = 0, graph_iters: int = 0, op_shots: int = 0, seg_per_wave: int = 0,
+                 stream=None):
         import torch
         self.lib = _lib.load()
         self.kind = kind
@@ -69,7 +70,7 @@ class Plan:
         med = np.ascontiguousarray(np.asarray(medium, dtype=np.float64))
         grid = _lib.Grid(nx, nz, dx, dz)
         lag = _lib.Laguerre(alpha, h, n)
-        tun = _lib.Tuning(segments, graph_iters)
+        tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -75,6 +75,8 @@ struct lg_plan {
     size_t npts = 0;           // nx1 * nz1
     size_t nvec = 0;           // S * C * npts
     int graph_iters = 8;
+    int op_shots = 8;          // operator kernel: shots per block
+    int td_spw = 0;            // Dichotomy segments per wave (0: automatic)
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
@@ -84,6 +86,8 @@ struct lg_plan {
     void* lam = nullptr;       // elastic lambda nodes, working type
     void* mu = nullptr;        // elastic mu nodes, working type
     void* w = nullptr;         // interior rho h^2/4, working type
+    double* kap64 = nullptr;   // FP64 copies for the true residual of mixed plans
+    double* w64 = nullptr;
     double* rho64 = nullptr;   // interior rho, FP64 (right-hand side recurrence)
     double kappa_t = 0, rho_t = 0, lp2m_t = 0, mu_t = 0;   // midrange values
 
@@ -129,6 +133,8 @@ inline size_t wsize(const lg_plan* p) { return p->prec == LG_FP64 ? 8 : 4; }
 
 // launchers (implemented in lg_acoustic.hip); all enqueue on plan->stream
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq);
+// r = b - A x with the FP64 operator (x, b, r FP64; all fields)
+hipError_t launch_true_residual(lg_plan* p, const double* x, const double* b, double* r);
 hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nfields);
 // Dichotomy kernels over `nfields` fields; field f of the launch is buffer
 // field f * fstride + foff (acoustic: 1, 0; one elastic component: 2, c).

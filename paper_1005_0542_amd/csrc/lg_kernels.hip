@@ -43,6 +43,7 @@ struct StArgs {
     int nx1, nz1;
     T idx2, idz2;
     int nfields, nsh;    // fields, fields per block (grid.z chunks)
+    const T* bsub;       // non-null: store bsub - A p instead of A p (true residual)
     // CG reduction (ctl == nullptr: plain operator application)
     ShotCtl* ctl;
     double* partial;
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
                 const T fS = half * (kc[r + 1] + kc[r + 2]), fN = half * (kc[r + 1] + kc[r]);
                 const T v = (fE[r] * (c - pE) + fW[r] * (c - pW)) * a.idx2 +
                             (fS * (c - pS) + fN * (c - pN)) * a.idz2 + wv[r] * c;
-                q[(size_t)j * nx1 + i] = v;
+                q[(size_t)j * nx1 + i] = (a.bsub != nullptr) ? a.bsub[fb + (size_t)j * nx1 + i] - v : v;
                 pq += (double)c * (double)v;
                 pN = c;
                 c = pS;
@@ -198,9 +199,11 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
         if constexpr (MODE == DST_UPDATE) {
             double* __restrict__ X;
             double alpha = 0.0;
-            if (a.init) {
+            if (a.init == 1) {
                 X = a.x;
                 if (blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
+            } else if (a.init == 2) {
+                X = nullptr;                 // x is not touched on a restart
             } else {
                 X = *a.xslot;
                 alpha = a.ctl[field].alpha;
@@ -221,7 +224,10 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     x0[u] = r0[u] = x1[u] = r1[u] = 0.0;
                     p0[u] = q0[u] = p1[u] = q1[u] = (T)0;
                     if (cb + u < NIT && i < NX1) {
-                        if (a.init) {
+                        if (a.init == 2) {           // restart: r holds b - A x already
+                            r0[u] = Rr[o0 + i];
+                            if (has1) r1[u] = Rr[o1 + i];
+                        } else if (a.init) {
                             r0[u] = Bv[o0 + i];
                             if (has1) r1[u] = Bv[o1 + i];
                         } else {
@@ -244,11 +250,13 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     if (cb + u < NIT && i < NX1) {
                         const double ra = r0[u] - alpha * (double)q0[u];
                         const double rb = r1[u] - alpha * (double)q1[u];
-                        X[o0 + i] = x0[u] + alpha * (double)p0[u];
-                        Rr[o0 + i] = ra;
-                        if (has1) {
-                            X[o1 + i] = x1[u] + alpha * (double)p1[u];
-                            Rr[o1 + i] = rb;
+                        if (a.init != 2) {
+                            X[o0 + i] = x0[u] + alpha * (double)p0[u];
+                            Rr[o0 + i] = ra;
+                            if (has1) {
+                                X[o1 + i] = x1[u] + alpha * (double)p1[u];
+                                Rr[o1 + i] = rb;
+                            }
                         }
                         rr += ra * ra + rb * rb;
                         buf[lpad(1 + i)] = {(T)ra, (T)rb};
@@ -633,7 +641,24 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         }
     } else if (a.kind == FIN_RR) {
         c.rr = tot;
-        if (a.init) {
+        if (a.init == 2) {                   // restart from the true residual
+            if (c.status != LG_OK) return;   // only shots that met the tolerance are re-checked
+            c.alpha = 0.0;
+            c.beta = 0.0;
+            if (!isfinite(tot)) {
+                c.status = LG_ERR_NONFINITE;
+                c.active = 0;
+            } else if (tot <= c.tol2) {
+                c.status = LG_OK;
+                c.active = 0;
+            } else if (c.iters >= c.max_iter) {
+                c.status = LG_ERR_NOT_CONVERGED;
+                c.active = 0;
+            } else {
+                c.status = LG_ERR_NOT_CONVERGED;
+                c.active = 1;
+            }
+        } else if (a.init) {
             c.bb = tot;
             c.tol2 = a.tol2 * tot;
             c.iters = 0;
@@ -826,10 +851,11 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
     a.ctl = reduce ? p->ctl : nullptr;
+    a.bsub = nullptr;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
     a.nfields = p->S * p->C;
-    a.nsh = std::min(a.nfields, 8);
+    a.nsh = std::min(a.nfields, p->op_shots);
     dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT),
               (a.nfields + a.nsh - 1) / a.nsh);
     hipLaunchKernelGGL(stencil_kernel<T>, grid, dim3(256), 0, p->stream, a);
@@ -893,9 +919,13 @@ hipError_t td_launch(lg_plan* p, TdArgs<T>& a, int nfields) {
     // segments per wave: up to 4 while the grid keeps >= 2048 blocks
     const int ktiles = (a.nx1 + 63) / 64;
     int spw = 1;
-    while (spw < 4 && 4 * spw * 2 <= a.P &&
-           (long)ktiles * ((a.P + 8 * spw - 1) / (8 * spw)) * nfields >= 2048)
-        spw *= 2;
+    if (p->td_spw > 0) {
+        spw = p->td_spw;
+    } else {
+        while (spw < 4 && 4 * spw * 2 <= a.P &&
+               (long)ktiles * ((a.P + 8 * spw - 1) / (8 * spw)) * nfields >= 2048)
+            spw *= 2;
+    }
     a.spw = spw;
     dim3 grid(ktiles, (a.P + 4 * spw - 1) / (4 * spw), nfields);
     hipLaunchKernelGGL((td_kernel<T, LS>), grid, dim3(256), 0, p->stream, a);
@@ -965,6 +995,27 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, 
 }
 
 }  // namespace
+
+hipError_t launch_true_residual(lg_plan* p, const double* x, const double* b, double* r) {
+    StArgs<double> a;
+    a.p = x;
+    a.q = r;
+    a.kap = (p->prec == LG_FP64) ? (const double*)p->kap : p->kap64;
+    a.w = (p->prec == LG_FP64) ? (const double*)p->w : p->w64;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.idx2 = 1.0 / (p->g.dx * p->g.dx);
+    a.idz2 = 1.0 / (p->g.dz * p->g.dz);
+    a.ctl = nullptr;
+    a.bsub = b;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    a.nfields = p->S * p->C;
+    a.nsh = std::min(a.nfields, 8);
+    dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT), (a.nfields + a.nsh - 1) / a.nsh);
+    hipLaunchKernelGGL(stencil_kernel<double>, grid, dim3(256), 0, p->stream, a);
+    return hipGetLastError();
+}
 
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq) {
     if (p->prec == LG_FP64) return stencil_T<double>(p, (const double*)x, (double*)y, reduce_pq);

@@ -84,27 +84,54 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
     LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
     LG_HIP(launch_correct_idst(p, 1));
 
-    long launched = 0;
-    // Replay as many batches as the previous solve needed before the first
-    // check: consecutive harmonics take similar iteration counts.
-    long ahead = std::max(1L, (long)((p->last_iters + chunk - 1) / chunk));
-    const long cap = (long)o->max_iter + chunk;
-    while (true) {
-        for (long bt = 0; bt < ahead && launched < cap; ++bt) {
-            if (use_graph) {
-                LG_HIP(hipGraphLaunch(p->cg_graph, p->stream));
-            } else {
-                for (int i = 0; i < chunk; ++i) LG_HIP(enqueue_iteration(p));
+    // Replay batches of captured iterations until every shot has stopped.
+    // Consecutive harmonics take similar iteration counts, so as many batches
+    // as the previous solve needed are queued before the first check.
+    auto iterate = [&](long& launched) -> lg_status {
+        long ahead = std::max(1L, (long)((p->last_iters + chunk - 1) / chunk));
+        const long cap = (long)o->max_iter + chunk;
+        while (true) {
+            for (long bt = 0; bt < ahead && launched < cap; ++bt) {
+                if (use_graph) {
+                    LG_HIP(hipGraphLaunch(p->cg_graph, p->stream));
+                } else {
+                    for (int i = 0; i < chunk; ++i) LG_HIP(enqueue_iteration(p));
+                }
+                launched += chunk;
             }
-            launched += chunk;
+            LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
+                                  p->stream));
+            LG_HIP(hipStreamSynchronize(p->stream));
+            bool any = false;
+            for (int s = 0; s < nf; ++s) any = any || (p->ctl_host[s].active != 0);
+            if (!any || launched >= cap) break;
+            ahead = 1;
         }
-        LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
-                              p->stream));
-        LG_HIP(hipStreamSynchronize(p->stream));
-        bool any = false;
-        for (int s = 0; s < nf; ++s) any = any || (p->ctl_host[s].active != 0);
-        if (!any || launched >= cap) break;
-        ahead = 1;
+        return LG_OK;
+    };
+    long launched = 0;
+    lg_status st = iterate(launched);
+    if (st != LG_OK) return st;
+    // Mixed precision: the recursive residual converges on the FP32 operator;
+    // check the FP64 true residual b - A x and, where it misses the tolerance,
+    // restart CG from it (iterative refinement with an FP64 residual).
+    if (p->prec == LG_MIXED) {
+        for (int rep = 0; rep < 4; ++rep) {
+            LG_HIP(launch_true_residual(p, x, b, p->r));
+            LG_HIP(launch_update_fdst(p, 2, nullptr, nullptr, o->tol, o->max_iter));
+            LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
+            LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
+            LG_HIP(launch_correct_idst(p, 1));
+            LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
+                                  p->stream));
+            LG_HIP(hipStreamSynchronize(p->stream));
+            bool any = false;
+            for (int s = 0; s < nf; ++s) any = any || (p->ctl_host[s].active != 0);
+            if (!any) break;
+            launched = 0;
+            st = iterate(launched);
+            if (st != LG_OK) return st;
+        }
     }
     int worst = LG_OK, maxit = 0;
     for (int s = 0; s < nf; ++s) {

@@ -161,7 +161,7 @@ lg_status prepare_block(lg_plan* pl, PrecBlock& B, double kx, double kz, double 
 void free_plan(lg_plan* p) {
     if (!p) return;
     pcg_release(p);
-    void* ptrs[] = {p->kap, p->lam, p->mu, p->w, p->rho64, p->tw, p->src_dev, p->r, p->p, p->qv,
+    void* ptrs[] = {p->kap, p->lam, p->mu, p->w, p->rho64, p->kap64, p->w64, p->tw, p->src_dev, p->r, p->p, p->qv,
                     p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red};
@@ -311,12 +311,17 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (nshots < 1) return fail(LG_ERR_INVALID_ARG, "nshots must be >= 1");
     if (!is_pow2(grid->nx) || !is_pow2(grid->nz) || grid->nx > 4096 || grid->nz > 4096)
         return fail(LG_ERR_UNSUPPORTED, "nx and nz must be powers of two <= 4096");
-    int P = 0, gi = 8;
+    int P = 0, gi = 8, osh = 8, spw = 0;
     if (tuning != nullptr) {
         P = tuning->segments;
         if (tuning->graph_iters != 0) gi = tuning->graph_iters;
+        if (tuning->op_shots != 0) osh = tuning->op_shots;
+        spw = tuning->seg_per_wave;
     }
     if (gi < -1 || gi == 0 || gi > 64) return fail(LG_ERR_INVALID_ARG, "graph_iters must be -1 or 1..64");
+    if (osh < 1 || osh > 64) return fail(LG_ERR_INVALID_ARG, "op_shots must be in 1..64");
+    if (spw != 0 && spw != 1 && spw != 2 && spw != 4)
+        return fail(LG_ERR_INVALID_ARG, "seg_per_wave must be 0, 1, 2 or 4");
     if (P == 0) P = std::max(1, std::min(64, grid->nz / 16));
     if (!is_pow2(P) || P > 64 || grid->nz % P != 0 || grid->nz / P < 2 || grid->nz / P > 64)
         return fail(LG_ERR_INVALID_ARG, "segments must be a power of two <= 64 with nz/segments in 2..64");
@@ -341,6 +346,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->npts = (size_t)p->nx1 * p->nz1;
     p->nvec = (size_t)p->S * p->C * p->npts;
     p->graph_iters = gi;
+    p->op_shots = osh;
+    p->td_spw = spw;
     p->device = dev;
     p->stream = (hipStream_t)hip_stream;
 
@@ -369,6 +376,14 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (kind == LG_ACOUSTIC) {
         std::vector<double> kap(medium_host, medium_host + nn);
         if ((st = upload_working(p, &p->kap, kap)) != LG_OK) return bail(st);
+        if (prec == LG_MIXED) {   // FP64 medium for the true residual of the refinement
+            if ((st = dev_alloc(p, &p->kap64, nn * 8)) != LG_OK) return bail(st);
+            if ((st = dev_alloc(p, &p->w64, p->npts * 8)) != LG_OK) return bail(st);
+            if ((he = hipMemcpy(p->kap64, kap.data(), nn * 8, hipMemcpyHostToDevice)) != hipSuccess)
+                return bail(hip_fail(he, "hipMemcpy"));
+            if ((he = hipMemcpy(p->w64, w_int.data(), p->npts * 8, hipMemcpyHostToDevice)) != hipSuccess)
+                return bail(hip_fail(he, "hipMemcpy"));
+        }
         p->kappa_t = midrange(medium_host, nn);
         p->rho_t = midrange(rho_node, nn);
         if (!(p->kappa_t > 0.0) || !(p->rho_t >= 0.0))

@@ -23,7 +23,7 @@ class AcousticRun:
     def __init__(self, w: inputs.Workload, precision: Optional[str] = None, shots: Optional[int] = None,
                  n_harm: Optional[int] = None, segments: int = 0, graph_iters: int = 0,
                  snapshots: bool = True, rec: bool = True, tol: Optional[float] = None,
-                 max_iter: int = 10000, medium=None):
+                 max_iter: int = 10000, medium=None, op_shots: int = 0, seg_per_wave: int = 0):
         import torch
         self.torch = torch
         self.w = w
@@ -39,7 +39,8 @@ class AcousticRun:
         self.kappa, self.rho = kappa, rho
         self.plan = api.Plan("acoustic", N, N, w.d, w.d, w.alpha, w.h, self.n_harm,
                              np.stack([kappa, rho]), precision=self.precision, nshots=self.shots,
-                             segments=segments, graph_iters=graph_iters)
+                             segments=segments, graph_iters=graph_iters, op_shots=op_shots,
+                             seg_per_wave=seg_per_wave)
         if self.shots == w.shots:
             src = inputs.sources_for(w)
         else:
@@ -76,6 +77,28 @@ class AcousticRun:
         self.status.append(res.status)
         self.m += 1
         return res
+
+    # -- checkpoint / resume ----------------------------------------------------
+    def state_dict(self) -> dict:
+        """Complete harmonic-loop state: the next harmonic m, the last solution
+        R_{m-1}, the running history sums, the snapshot accumulators and the
+        receiver coefficients (device tensors are copied to the host)."""
+        out = {"m": self.m, "iters": [list(i) for i in self.iters], "status": list(self.status),
+               "R": self.R.cpu(), "Ph": self.Ph.cpu(), "Qh": self.Qh.cpu()}
+        if self.snap is not None:
+            out["snap"] = self.snap.cpu()
+        if self.rec is not None:
+            out["rec"] = self.rec.cpu()
+        return out
+
+    def load_state_dict(self, st: dict) -> None:
+        self.m = int(st["m"])
+        self.iters = [list(i) for i in st["iters"]]
+        self.status = list(st["status"])
+        for name in ("R", "Ph", "Qh", "snap", "rec"):
+            t = getattr(self, name)
+            if t is not None and name in st:
+                t.copy_(st[name].to(t.device))
 
     def traces(self, t: np.ndarray):
         W = api.laguerre_weights(t, self.w.alpha, self.w.h, self.n_harm)

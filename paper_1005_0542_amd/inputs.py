@@ -85,11 +85,11 @@ WORKLOADS: Dict[str, Workload] = {
     "acoustic4096_mixed": Workload(
         name="acoustic4096_mixed", kind="acoustic", n_cells=4096, d=2.5,
         medium="layered_perturbed", f0=30.0, alpha=9, h=600.0, n_harm=1024, T=2.0,
-        precision="mixed", tol=1e-7, shots=1, src=(2048, 8)),
+        precision="mixed", tol=1e-9, shots=1, src=(2048, 8)),
     "acoustic2048x64_mixed": Workload(
         name="acoustic2048x64_mixed", kind="acoustic", n_cells=2048, d=5.0,
         medium="layered_perturbed", f0=25.0, alpha=9, h=400.0, n_harm=512, T=1.0,
-        precision="mixed", tol=1e-7, shots=64),
+        precision="mixed", tol=1e-9, shots=64),
 }
 
 

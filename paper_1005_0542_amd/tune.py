@@ -1,0 +1,113 @@
+"""Autotuner for the plan's tile and segment parameters.
+
+For a given workload (grid, precision, shot count) it measures, on the device
+and medium actually used, one CG iteration (the five iteration kernels timed
+with HIP events by ``lg_pcg_profile``) for every candidate of
+
+* ``segments``      Dichotomy segments P per z-system (segment length nz/P),
+* ``op_shots``      shots per block of the operator kernel,
+* ``seg_per_wave``  Dichotomy segments solved by one wave,
+
+then times short solves for ``graph_iters`` (iterations per HIP graph), and
+keeps the fastest.  Results are cached in a JSON file keyed by the device
+architecture and the problem shape (``LG_TUNE_CACHE`` overrides the path).
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import api
+
+# The cache ships with the package (entries written by this tuner on the target
+# device); LG_TUNE_CACHE points it elsewhere.
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def segment_candidates(nz: int) -> List[int]:
+    """Powers of two P <= 64 with segment length nz/P in 2..64."""
+    out = []
+    P = 1
+    while P <= 64:
+        if nz % P == 0 and 2 <= nz // P <= 64:
+            out.append(P)
+        P *= 2
+    return out
+
+
+def _key(arch: str, kind: str, nx: int, nz: int, precision: str, shots: int) -> str:
+    return f"{arch}|{kind}|{nx}x{nz}|{precision}|{shots}"
+
+
+def _load(path: str) -> Dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, data: Dict) -> None:
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def tune_acoustic(nx: int, nz: int, dx: float, dz: float, alpha: int, h: float, medium: np.ndarray,
+                  precision: str, shots: int, rhs=None, cache: Optional[str] = None,
+                  profile_iters: int = 6, verbose: bool = False) -> Dict[str, int]:
+    """Best ``{segments, op_shots, seg_per_wave, graph_iters}`` for this problem."""
+    import torch
+    path = cache or os.environ.get("LG_TUNE_CACHE", DEFAULT_CACHE)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = _key(arch, "acoustic", nx, nz, precision, shots)
+    db = _load(path)
+    if key in db:
+        return dict(db[key]["best"])
+    shape = (shots, 1, nz - 1, nx - 1)
+    if rhs is None:
+        rhs = torch.zeros(shape, dtype=torch.float64, device="cuda")
+        rhs[:, 0, min(7, nz - 2), nx // 2] = 1.0
+    x = torch.empty(shape, dtype=torch.float64, device="cuda")
+    op_c = sorted({min(shots, c) for c in (1, 4, 8, 16)})
+    spw_c = [1, 2, 4]
+    trials = []
+    for P, osh, spw in itertools.product(segment_candidates(nz), op_c, spw_c):
+        if spw > 1 and 4 * spw > P:
+            continue
+        plan = api.Plan("acoustic", nx, nz, dx, dz, alpha, h, 2, medium, precision=precision, nshots=shots,
+                        segments=P, op_shots=osh, seg_per_wave=spw)
+        plan.pcg_profile(rhs, x, iters=2)                       # warm-up
+        ms = sum(plan.pcg_profile(rhs, x, iters=profile_iters))
+        trials.append({"segments": P, "op_shots": osh, "seg_per_wave": spw, "iteration_ms": ms})
+        if verbose:
+            print(f"[tune] P={P} op_shots={osh} seg_per_wave={spw}: {ms:.4f} ms/iteration", flush=True)
+        plan.destroy()
+    best = min(trials, key=lambda t: t["iteration_ms"])
+    # iterations per captured graph: time short solves with the best tiles
+    gtrials = []
+    for gi in (4, 8, 16):
+        plan = api.Plan("acoustic", nx, nz, dx, dz, alpha, h, 2, medium, precision=precision, nshots=shots,
+                        segments=best["segments"], op_shots=best["op_shots"],
+                        seg_per_wave=best["seg_per_wave"], graph_iters=gi)
+        plan.pcg_solve(rhs, x, tol=1e-8, max_iter=200)           # builds the graph
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            plan.pcg_solve(rhs, x, tol=1e-8, max_iter=200)
+        torch.cuda.synchronize()
+        gtrials.append({"graph_iters": gi, "solve_ms": 1e3 * (time.perf_counter() - t) / 3})
+        plan.destroy()
+    gbest = min(gtrials, key=lambda t: t["solve_ms"])
+    out = {k: best[k] for k in ("segments", "op_shots", "seg_per_wave")}
+    out["graph_iters"] = gbest["graph_iters"]
+    db[key] = {"best": out, "trials": trials, "graph_trials": gtrials}
+    _store(path, db)
+    return out
