@@ -36,12 +36,19 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(ws: int, shots: int, seg_len: int):
+def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True):
     """Algorithmic HBM bytes per shot-point for each kernel of one CG iteration
-    (every array touched once per launch; medium arrays shared by all shots)."""
+    (every array touched once per launch; medium arrays shared by all shots).
+    fused: the update recomputes A p, so the operator kernel stores no q."""
+    if fused:
+        op = ws + 2 * ws / shots                              # p in; kappa, w once per batch
+        upd = 32 + 2 * ws + 2 * ws / shots                    # x, r in/out (f64); p in; rhat out; medium
+    else:
+        op = 2 * ws + 2 * ws / shots                          # p in, q out; kappa, w once per batch
+        upd = 32 + 3 * ws                                     # x, r in/out (f64); p, q in; rhat out
     return {
-        "operator": 2 * ws + 2 * ws / shots,                  # p in, q out; kappa, w once per batch
-        "update_fdst": 32 + 3 * ws,                           # x, r in/out (f64); p, q in; rhat out
+        "operator": op,
+        "update_fdst": upd,
         "dichotomy_segments": 2 * ws + 24.0 / seg_len,        # rhat in, y out; 3 f64 per segment
         "interfaces": (2 * ws + 24.0) / seg_len,              # separator rows, segment data
         "correct_idst": 3 * ws,                               # y in, p in/out
@@ -80,7 +87,8 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     t0 = time.perf_counter()
     run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2),
                       segments=tuned.get("segments", 0), graph_iters=tuned.get("graph_iters", 0),
-                      op_shots=tuned.get("op_shots", 0), seg_per_wave=tuned.get("seg_per_wave", 0))
+                      op_shots=tuned.get("op_shots", 0), seg_per_wave=tuned.get("seg_per_wave", 0),
+                      op_fusion=tuned.get("op_fusion", 0))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     npts = (w.n_cells - 1) ** 2
@@ -106,7 +114,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     seg, seg_len = run.plan.layout()
     out["segments"] = seg
     ws = 8 if precision == "fp64" else 4
-    kb = kernel_bytes(ws, shots, seg_len)
+    kb = kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
     per_iter_bytes = sum(kb.values()) * npts * shots
     mean_it = max(out["mean_iters"], 1e-9)
     t_iter = el / (steps * mean_it)
@@ -127,6 +135,40 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
         out["dominant"] = dom
     out["_run"] = run
     return out
+
+
+def profile_variant(name, precision, shots, iters, tuned, segments=0, overrides=None):
+    """Only the per-kernel profile (no harmonic solves): the plan, the first
+    harmonic's right-hand side, then ``iters`` eager CG iterations with every
+    shot active, each of the five kernels timed with HIP events on the plan's
+    stream.  A kernel trace of this mode holds exactly those launches (plus
+    one start-up launch of the update, Dichotomy and correction kernels)."""
+    import torch
+    from paper_1005_0542_amd import inputs
+    from paper_1005_0542_amd.driver import AcousticRun
+
+    w = inputs.WORKLOADS[name]
+    tuned = dict(tuned or {})
+    tuned.update(overrides or {})
+    if segments:
+        tuned["segments"] = segments
+    log(f"{name}: profile precision={precision} shots={shots} iterations={iters} params={tuned}")
+    run = AcousticRun(w, precision=precision, shots=shots, n_harm=2, snapshots=False, rec=False,
+                      segments=tuned.get("segments", 0), op_shots=tuned.get("op_shots", 0),
+                      seg_per_wave=tuned.get("seg_per_wave", 0), op_fusion=tuned.get("op_fusion", 0))
+    fs = np.full(shots, run.f_m[0])
+    run.plan.laguerre_rhs(0, None, run.Ph, run.Qh, fs, run.rhs)
+    x = torch.empty_like(run.rhs)
+    run.plan.pcg_profile(run.rhs, x, iters=max(2, iters // 4))      # clocks up, caches warm
+    ms = run.plan.pcg_profile(run.rhs, x, iters=iters)
+    torch.cuda.synchronize()
+    seg, seg_len = run.plan.layout()
+    npts = (w.n_cells - 1) ** 2
+    kb = kernel_bytes(8 if precision == "fp64" else 4, shots, seg_len, tuned.get("op_fusion", 0) != 2)
+    kern = {nm: {"avg_ms": ms[k], "alg_bytes": kb[nm] * npts * shots,
+                 "GBps": kb[nm] * npts * shots / (ms[k] * 1e-3) / 1e9} for k, nm in enumerate(kb)}
+    return {"workload": name, "precision": precision, "shots": shots, "segments": seg,
+            "tuned": tuned, "profile_iterations": iters, "kernels": kern}
 
 
 def cpu_baseline(name, k_lo=2, k_hi=12):
@@ -176,11 +218,16 @@ def main():
     ap.add_argument("--graph-iters", type=int, default=0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-kernel profile of the workload (for hardware-counter runs)")
+    ap.add_argument("--profile-iters", type=int, default=10,
+                    help="CG iterations timed per kernel by --profile-only")
     ap.add_argument("--precision", default=None, help="override the workload precision")
     ap.add_argument("--shots", type=int, default=None, help="override the workload shot count")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="time a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuned tiles")
+    ap.add_argument("--op-shots", type=int, default=0, help="override (profile-only)")
+    ap.add_argument("--seg-per-wave", type=int, default=0, help="override (profile-only)")
+    ap.add_argument("--op-fusion", type=int, default=0, help="override (profile-only): 1 fused, 2 stored q")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -203,12 +250,10 @@ def main():
     prec = args.precision or w.precision
     shots = args.shots or w.shots
     if args.profile_only:
-        v = run_variant(args.workload, prec, shots, 1, 0, segments=args.segments,
-                        graph_iters=args.graph_iters,
-                        tuned=tuned_params(args.workload, prec, shots, not args.no_tune))
-        v.pop("_run")
-        print(json.dumps({"workload": args.workload, "precision": prec, "shots": shots,
-                          "profile_iterations": 10, "kernels": v["kernels"]}))
+        ov = {k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion") if getattr(args, k)}
+        v = profile_variant(args.workload, prec, shots, args.profile_iters,
+                            tuned_params(args.workload, prec, shots, not args.no_tune), args.segments, ov)
+        print(json.dumps(v))
         return
     head_tuned = tuned_params(args.workload, prec, shots, not args.no_tune)
     head = run_variant(args.workload, prec, shots, args.steps, args.warmup,

@@ -86,13 +86,19 @@ typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
  *  op_shots      shots per block of the operator kernel, which reuses the
  *                medium held in registers across them (1..64; default 8).
  *  seg_per_wave  Dichotomy segments solved by one wave (1, 2 or 4; default:
- *                chosen from the grid size). */
+ *                chosen from the grid size).
+ *  op_fusion     where the update x += alpha p, r -= alpha A p takes A p from
+ *                (acoustic CG): 0 or 1 = recomputed inside the update kernel
+ *                from p and the medium, so the operator kernel only forms
+ *                (p, A p) (default); 2 = stored by the operator kernel and read
+ *                back.  Both give bitwise the same iterates. */
 typedef struct {
     int32_t segments;
     int32_t graph_iters;
     int32_t op_shots;
     int32_t seg_per_wave;
-    int32_t reserved[4];
+    int32_t op_fusion;
+    int32_t reserved[3];
 } lg_tuning;
 
 typedef struct lg_plan lg_plan;

@@ -43,7 +43,7 @@ class SolveInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("segments", c_int32), ("graph_iters", c_int32), ("op_shots", c_int32),
-                ("seg_per_wave", c_int32), ("reserved", c_int32 * 4)]
+                ("seg_per_wave", c_int32), ("op_fusion", c_int32), ("reserved", c_int32 * 3)]
 
 
 _PLAN = c_void_p

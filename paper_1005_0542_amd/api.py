@@ -59,6 +59,7 @@ class Plan:
     def __init__(self, kind: str, nx: int, nz: int, dx: float, dz: float, alpha: int, h: float,
                  n: int, medium: np.ndarray, precision: str = "fp64", nshots: int = 1,
                  segments: int = 0, graph_iters: int = 0, op_shots: int = 0, seg_per_wave: int = 0,
+                 op_fusion: int = 0,
                  stream=None):
         import torch
         self.lib = _lib.load()
@@ -70,7 +71,7 @@ class Plan:
         med = np.ascontiguousarray(np.asarray(medium, dtype=np.float64))
         grid = _lib.Grid(nx, nz, dx, dz)
         lag = _lib.Laguerre(alpha, h, n)
-        tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave)
+        tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream

@@ -175,6 +175,70 @@ __device__ __forceinline__ void fft_last(const cpx<T>* __restrict__ buf, const c
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+// L2: hardware block b runs on XCD b % 8.  xcd_linear maps b to a logical
+// index so that every XCD works through one contiguous range of logical
+// indices (a bijection of [0, n)); kernels order their tiles so that tiles
+// sharing cache lines (halo rows and columns, medium rows) are neighbours in
+// that order and therefore meet in the same L2.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int xcd_linear(int b, int n) {
+    const int q = n / NUM_XCD, r = n - q * NUM_XCD;
+    const int x = b % NUM_XCD, i = b / NUM_XCD;
+    return x * q + min(x, r) + i;
+}
+
+// Raw buffer addressing.  A resource covers nbytes from a wave-uniform base;
+// a load at a byte offset outside [0, nbytes) returns 0 and a store there is
+// dropped (the hardware range check).  Out-of-grid neighbours (the Dirichlet
+// zero) and padding lanes therefore need no branch, and every load of a
+// strip is issued back to back.
+constexpr uint32_t BUF_OOB = 0xFFFFFFF0u;     // an offset beyond any resource
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ rsrc_t buf_rsrc(const void* base, uint32_t nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)nbytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bload(rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ float bload<float>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ void bstore<float>(float v, rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(double v, rsrc_t r, uint32_t off) {
+    using u2 = __attribute__((ext_vector_type(2))) uint32_t;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)off, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ T fmad(T a, T b, T c);
+template <>
+__device__ __forceinline__ float fmad<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <>
+__device__ __forceinline__ double fmad<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// The 5-point operator at one node (Sec. 2.3, SPD sign):
+//   [fE (c - pE) + fW (c - pW)] / dx^2 + [fS (c - pS) + fN (c - pN)] / dz^2 + w c
+// with explicit fused multiply-adds, so every kernel that evaluates it (the
+// operator, the fused CG update) produces bitwise the same value.
+template <typename T>
+__device__ __forceinline__ T stencil_point(T c, T pE, T pW, T pS, T pN, T fE, T fW, T fS, T fN, T w,
+                                           T idx2, T idz2) {
+    const T sx = fmad(fE, c - pE, fW * (c - pW));
+    const T sz = fmad(fS, c - pS, fN * (c - pN));
+    return fmad(sx, idx2, fmad(sz, idz2, w * c));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

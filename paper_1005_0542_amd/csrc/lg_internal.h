@@ -77,6 +77,7 @@ struct lg_plan {
     int graph_iters = 8;
     int op_shots = 8;          // operator kernel: shots per block
     int td_spw = 0;            // Dichotomy segments per wave (0: automatic)
+    bool fuse_op = true;       // CG update recomputes A p (no stored q)
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture

@@ -33,16 +33,18 @@ namespace lg {
 // p and kappa values in registers; x-neighbours come from the L1/L2.
 // ===========================================================================
 constexpr int ST_RPT = 8;
+constexpr int ST_MAXSH = 64;     // fields per block (op_shots) at most
 
 template <typename T>
 struct StArgs {
     const T* p;
-    T* q;
+    T* q;                // nullptr: no store (dot only)
     const T* kap;        // node kappa, (nz+1) x (nx+1)
     const T* w;          // interior shift
     int nx1, nz1;
     T idx2, idz2;
-    int nfields, nsh;    // fields, fields per block (grid.z chunks)
+    int nfields, nsh;    // fields, fields per block (shot chunks)
+    int gx, gy;          // column tiles, row strips (1D grid of gx*gy*chunks blocks)
     const T* bsub;       // non-null: store bsub - A p instead of A p (true residual)
     // CG reduction (ctl == nullptr: plain operator application)
     ShotCtl* ctl;
@@ -51,67 +53,108 @@ struct StArgs {
 };
 
 // The medium (kappa at the nodes the column touches, w) is loaded once into
-// registers and reused for a chunk of `nsh` shots; each shot's p column is
-// marched down the strip with its x-neighbours read from L1/L2.
+// registers and reused for a chunk of `nsh` shots.  For each shot all p loads
+// of the strip are buffer loads issued together (out-of-grid neighbours read
+// as the Dirichlet zero through the range check), q is written by buffer
+// stores (rows past the grid are dropped), and the (p, A p) partial is
+// reduced per wave without barriers; one block barrier at the end combines
+// the waves of every shot.
 template <typename T>
 __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
-    __shared__ double red[4];
+    __shared__ double red[ST_MAXSH][4];
     const int nx1 = a.nx1, nz1 = a.nz1, NXN = nx1 + 2;
     const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 1D block of 256 = 64 x 4
-    const int i = blockIdx.x * 64 + lane;
-    const int j0 = (blockIdx.y * 4 + ty) * ST_RPT;
-    const bool live = (i < nx1) && (j0 < nz1);
-    const int I = i + 1;
+    // tiles in x-fastest order, contiguous per XCD: the column neighbours of a
+    // tile (sharing its boundary cache lines) run next to it in the same L2
+    const int L = xcd_linear(blockIdx.x, gridDim.x);
+    const int bx = L % a.gx, by = (L / a.gx) % a.gy, bz = L / (a.gx * a.gy);
+    const int i = bx * 64 + lane;
+    const int j0 = (by * 4 + ty) * ST_RPT;
+    const bool live = i < nx1;
+    const int ic = min(i, nx1 - 1);                 // clamped column (dead lanes)
+    const int I = ic + 1;
     const T half = (T)0.5;
     // medium of this column strip: node kappa rows j0 .. j0+RPT+1 and the
-    // face coefficients / shift of rows j0 .. j0+RPT-1
+    // face coefficients / shift of rows j0 .. j0+RPT-1 (clamped indices)
     T kc[ST_RPT + 2], fE[ST_RPT], fW[ST_RPT], wv[ST_RPT];
 #pragma unroll
     for (int r = 0; r < ST_RPT + 2; ++r) {
-        const int J = j0 + r;                       // node row (interior row j0+r-1)
-        kc[r] = (live && J <= nz1 + 1) ? a.kap[(size_t)J * NXN + I] : (T)0;
+        const int J = min(j0 + r, nz1 + 1);         // node row (interior row j0+r-1)
+        kc[r] = a.kap[(size_t)J * NXN + I];
     }
 #pragma unroll
     for (int r = 0; r < ST_RPT; ++r) {
-        const int j = j0 + r, J = j + 1;
-        fE[r] = fW[r] = wv[r] = (T)0;
-        if (live && j < nz1) {
-            fE[r] = half * (kc[r + 1] + a.kap[(size_t)J * NXN + I + 1]);
-            fW[r] = half * (kc[r + 1] + a.kap[(size_t)J * NXN + I - 1]);
-            wv[r] = a.w[(size_t)j * nx1 + i];
-        }
+        const int j = min(j0 + r, nz1 - 1), J = j + 1;
+        fE[r] = half * (kc[r + 1] + a.kap[(size_t)J * NXN + I + 1]);
+        fW[r] = half * (kc[r + 1] + a.kap[(size_t)J * NXN + I - 1]);
+        wv[r] = a.w[(size_t)j * nx1 + ic];
     }
-    const int s0 = blockIdx.z * a.nsh;
-    const int s1 = min(s0 + a.nsh, a.nfields);
-    for (int field = s0; field < s1; ++field) {
-        if (a.ctl != nullptr && a.ctl[field].active == 0) continue;   // uniform per block
-        const size_t fb = (size_t)field * nx1 * nz1;
-        const T* __restrict__ p = a.p + fb;
-        T* __restrict__ q = a.q + fb;
-        double pq = 0.0;
-        if (live) {
-            T pN = (j0 > 0) ? p[(size_t)(j0 - 1) * nx1 + i] : (T)0;
-            T c = p[(size_t)j0 * nx1 + i];
+    // byte offsets within one field: rows j0-1 .. j0+RPT at column i, and the
+    // x-neighbours of rows j0 .. j0+RPT-1; outside the grid: BUF_OOB
+    constexpr uint32_t SZ = sizeof(T);
+    uint32_t oc[ST_RPT + 2], oe[ST_RPT], ow[ST_RPT];
 #pragma unroll
-            for (int r = 0; r < ST_RPT; ++r) {
-                const int j = j0 + r;
-                if (j >= nz1) break;
-                const T pS = (j + 1 < nz1) ? p[(size_t)(j + 1) * nx1 + i] : (T)0;
-                const T pE = (i + 1 < nx1) ? p[(size_t)j * nx1 + i + 1] : (T)0;
-                const T pW = (i > 0) ? p[(size_t)j * nx1 + i - 1] : (T)0;
-                const T fS = half * (kc[r + 1] + kc[r + 2]), fN = half * (kc[r + 1] + kc[r]);
-                const T v = (fE[r] * (c - pE) + fW[r] * (c - pW)) * a.idx2 +
-                            (fS * (c - pS) + fN * (c - pN)) * a.idz2 + wv[r] * c;
-                q[(size_t)j * nx1 + i] = (a.bsub != nullptr) ? a.bsub[fb + (size_t)j * nx1 + i] - v : v;
-                pq += (double)c * (double)v;
-                pN = c;
-                c = pS;
-            }
+    for (int r = 0; r < ST_RPT + 2; ++r) {
+        const int j = j0 - 1 + r;
+        oc[r] = (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + i) * SZ : BUF_OOB;
+    }
+#pragma unroll
+    for (int r = 0; r < ST_RPT; ++r) {
+        const uint32_t c = oc[r + 1];
+        oe[r] = (c != BUF_OOB && i + 1 < nx1) ? c + SZ : BUF_OOB;
+        ow[r] = (c != BUF_OOB && i > 0) ? c - SZ : BUF_OOB;
+    }
+    const uint32_t fbytes = (uint32_t)nx1 * (uint32_t)nz1 * SZ;
+    const int s0 = bz * a.nsh;
+    const int ns = min(a.nsh, a.nfields - s0);
+    __shared__ int act[ST_MAXSH];               // the chunk's active flags, read once
+    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr) ? a.ctl[s0 + threadIdx.x].active : 1;
+    __syncthreads();
+    for (int k = 0; k < ns; ++k) {
+        const int field = s0 + k;
+        if (act[k] == 0) continue;              // uniform per block
+        const size_t fb = (size_t)field * nx1 * nz1;
+        const rsrc_t rp = buf_rsrc(a.p + fb, fbytes);
+        T pv[ST_RPT + 2], pe[ST_RPT], pw[ST_RPT];
+#pragma unroll
+        for (int r = 0; r < ST_RPT + 2; ++r) pv[r] = bload<T>(rp, oc[r]);
+#pragma unroll
+        for (int r = 0; r < ST_RPT; ++r) {
+            pe[r] = bload<T>(rp, oe[r]);
+            pw[r] = bload<T>(rp, ow[r]);
+        }
+        T bs[ST_RPT];
+        if (a.bsub != nullptr) {
+            const rsrc_t rb = buf_rsrc(a.bsub + fb, fbytes);
+#pragma unroll
+            for (int r = 0; r < ST_RPT; ++r) bs[r] = bload<T>(rb, oc[r + 1]);
+        }
+        double pq = 0.0;
+        T v[ST_RPT];
+#pragma unroll
+        for (int r = 0; r < ST_RPT; ++r) {
+            const T fS = half * (kc[r + 1] + kc[r + 2]), fN = half * (kc[r + 1] + kc[r]);
+            const T c = pv[r + 1];                  // 0 outside the grid, so no dot term
+            v[r] = stencil_point(c, pe[r], pw[r], pv[r + 2], pv[r], fE[r], fW[r], fS, fN, wv[r],
+                                 a.idx2, a.idz2);
+            pq += (double)c * (double)v[r];
+        }
+        if (a.q != nullptr) {
+            const rsrc_t rq = buf_rsrc(a.q + fb, fbytes);
+#pragma unroll
+            for (int r = 0; r < ST_RPT; ++r)
+                bstore<T>(a.bsub != nullptr ? bs[r] - v[r] : v[r], rq, oc[r + 1]);
         }
         if (a.ctl == nullptr) continue;
-        const double s = block_sum(pq, red);
-        if (threadIdx.x == 0)
-            a.partial[(size_t)field * a.pstride + blockIdx.y * gridDim.x + blockIdx.x] = s;
+        pq = wave_sum(pq);
+        if (lane == 0) red[k][ty] = pq;
+    }
+    if (a.ctl == nullptr) return;
+    __syncthreads();
+    if (threadIdx.x < ns && act[threadIdx.x] != 0) {
+        const int k = threadIdx.x;
+        const double s = ((red[k][0] + red[k][1]) + red[k][2]) + red[k][3];
+        a.partial[(size_t)(s0 + k) * a.pstride + by * a.gx + bx] = s;
     }
 }
 
@@ -123,7 +166,11 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
 // V_k = -2i X_k(row j0) + 2 X_k(row j1), so the two DST-I results are
 // X(j0) = -Im V / 2, X(j1) = Re V / 2 for k = 1..nx-1.
 // ===========================================================================
-enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3 };
+constexpr int DST_GROUP = 4;
+
+// DST_UPDATE_OP is DST_UPDATE with A p recomputed from p and the medium
+// instead of read from a stored q.
+enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3, DST_UPDATE_OP = 4 };
 
 template <typename T>
 struct DstArgs {
@@ -140,6 +187,9 @@ struct DstArgs {
     const double* b;       // UPDATE init: right-hand side
     const T* p;            // UPDATE: search direction
     const T* q;            // UPDATE: A p
+    const T* kap;          // UPDATE_OP: node kappa, (nz+1) x (nx+1)
+    const T* wsh;          // UPDATE_OP: interior shift
+    T idx2, idz2;          // UPDATE_OP: 1/dx^2, 1/dz^2
     double* partial;
     size_t pstride;
     double tol2;           // tol^2 (init)
@@ -150,6 +200,38 @@ struct DstArgs {
     const T* utab;
     int Ls, P;
 };
+
+// A p on the rows j0 and j0 + 1 of a row pair at column i, with the operator
+// kernel's face coefficients and stencil_point, so the values are bitwise
+// those of the operator kernel.  rP covers the field's p; c0, c1: p at
+// (j0, i) and (j0 + 1, i).  ok0 / ok1: the element / its second row exist
+// (otherwise every p read is 0 and the result is 0).
+template <typename T>
+__device__ __forceinline__ void apply_pair(rsrc_t rP, const T* __restrict__ kap, const T* __restrict__ wsh,
+                                           int nx1, int nz1, int i, int j0, bool ok0, bool ok1, T c0, T c1,
+                                           T idx2, T idz2, T& q0, T& q1) {
+    constexpr uint32_t SZ = sizeof(T);
+    const int NXN = nx1 + 2, I = i + 1, J0 = j0 + 1;
+    const uint32_t e = (uint32_t)(j0 * nx1 + i);
+    const T half = (T)0.5;
+    const T pN0 = bload<T>(rP, (ok0 && j0 > 0) ? (e - nx1) * SZ : BUF_OOB);
+    const T p0E = bload<T>(rP, (ok0 && i + 1 < nx1) ? (e + 1) * SZ : BUF_OOB);
+    const T p0W = bload<T>(rP, (ok0 && i > 0) ? (e - 1) * SZ : BUF_OOB);
+    const T pS1 = bload<T>(rP, (ok1 && j0 + 2 < nz1) ? (e + 2 * nx1) * SZ : BUF_OOB);
+    const T p1E = bload<T>(rP, (ok1 && i + 1 < nx1) ? (e + nx1 + 1) * SZ : BUF_OOB);
+    const T p1W = bload<T>(rP, (ok1 && i > 0) ? (e + nx1 - 1) * SZ : BUF_OOB);
+    const T* k0 = kap + (size_t)J0 * NXN + I;
+    const T k00 = k0[0], k0E = k0[1], k0W = k0[-1], k0N = k0[-NXN];
+    const T k10 = k0[NXN];                                    // node row J0 + 1 <= nz1 + 1
+    const T* k1 = kap + (size_t)min(J0 + 1, nz1) * NXN + I;   // second row (clamped)
+    const T k1E = k1[1], k1W = k1[-1], k1S = k1[NXN];
+    const int j1c = min(j0 + 1, nz1 - 1);
+    q0 = stencil_point(c0, p0E, p0W, c1, pN0, half * (k00 + k0E), half * (k00 + k0W), half * (k00 + k10),
+                       half * (k00 + k0N), wsh[(size_t)j0 * nx1 + i], idx2, idz2);
+    const T v1 = stencil_point(c1, p1E, p1W, pS1, c0, half * (k10 + k1E), half * (k10 + k1W),
+                               half * (k10 + k1S), half * (k10 + k00), wsh[(size_t)j1c * nx1 + i], idx2, idz2);
+    q1 = ok1 ? v1 : (T)0;
+}
 
 // Phase A: each row element x_i (i = t + it TPF) is loaded once by its
 // thread, which writes it to LDS at both odd-extension positions 1+i and
@@ -167,23 +249,37 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     constexpr int LL = LdsLen<M>::value;
     constexpr int NWAVE = (FPB * TPF + 63) / 64;
     constexpr int NIT = (NX1 + TPF - 1) / TPF;
-    constexpr int CH = NIT < 4 ? NIT : 4;
+    constexpr int CHMAX = (MODE == DST_UPDATE_OP && sizeof(T) == 8) ? 2 : 4;
+    constexpr int CH = NIT < CHMAX ? NIT : CHMAX;
+    constexpr bool UPD = MODE == DST_UPDATE || MODE == DST_UPDATE_OP;
     __shared__ cpx<T> lds[FPB * LL];
     __shared__ double red[NWAVE];
 
     const int fid = threadIdx.x / TPF;
     const int t = threadIdx.x - fid * TPF;
-    const int field = blockIdx.x / a.bpf;
-    const int bif = blockIdx.x - field * a.bpf;
+    // Logical order (contiguous per XCD): groups of DST_GROUP consecutive
+    // blocks of one field, all fields of a group before the next group.  The
+    // blocks of one group share halo rows (fused update: p rows j0-1, j1+1),
+    // and all fields of a group read the same medium rows.
+    int field, bif;
+    {
+        const int nf = gridDim.x / a.bpf;
+        const int L = xcd_linear(blockIdx.x, gridDim.x);
+        const int g = L / (DST_GROUP * nf);
+        const int sz = min(DST_GROUP, a.bpf - g * DST_GROUP);
+        const int rem = L - g * DST_GROUP * nf;
+        field = rem / sz;
+        bif = g * DST_GROUP + (rem - field * sz);
+    }
     const int pair = bif * FPB + fid;
     const int npairs = (a.nz1 + 1) >> 1;
     const bool live = pair < npairs;
     const int j0 = 2 * pair, j1 = j0 + 1;
     const bool has1 = live && (j1 < a.nz1);
 
-    if constexpr (MODE == DST_UPDATE || MODE == DST_CORRECT) {
+    if constexpr (UPD || MODE == DST_CORRECT) {
         bool skip = a.ctl[field].active == 0;
-        if (MODE == DST_UPDATE && a.init) skip = false;
+        if (UPD && a.init) skip = false;
         if (skip) return;   // uniform per block: blocks never span fields
     }
 
@@ -195,70 +291,68 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     T pold0[MODE == DST_CORRECT ? NOUT : 1], pold1[MODE == DST_CORRECT ? NOUT : 1];
 
     // ---- phase A: gather the two rows into the odd extension (LDS) ---------
+    // All loads are buffer loads at per-element byte offsets (BUF_OOB for the
+    // missing second row of an odd row count and for i >= nx-1, which read 0);
+    // a resource of size 0 turns a whole array off (loads 0, stores dropped),
+    // so the start and restart variants of the update run the same code.
+    constexpr uint32_t SZ = sizeof(T);
+    const uint32_t nfe = (uint32_t)a.nz1 * (uint32_t)NX1;     // elements per field
     if (live) {
-        if constexpr (MODE == DST_UPDATE) {
-            double* __restrict__ X;
+        if constexpr (UPD) {
+            const int init = a.init;
+            double* X = nullptr;
             double alpha = 0.0;
-            if (a.init == 1) {
+            if (init == 1) {
                 X = a.x;
                 if (blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
-            } else if (a.init == 2) {
-                X = nullptr;                 // x is not touched on a restart
-            } else {
+            } else if (init == 0) {
                 X = *a.xslot;
                 alpha = a.ctl[field].alpha;
-            }
-            double* __restrict__ Rr = a.r;
-            const T* __restrict__ Pv = a.p;
-            const T* __restrict__ Qv = a.q;
-            const double* __restrict__ Bv = a.b;
+            }                                // init 2 (restart): x is not touched
+            const rsrc_t rX = buf_rsrc(X != nullptr ? X + fbase : a.r, init == 0 ? nfe * 8u : 0u);
+            const rsrc_t rXs = buf_rsrc(X != nullptr ? X + fbase : a.r, init == 2 ? 0u : nfe * 8u);
+            const rsrc_t rR = buf_rsrc(init == 1 ? a.b + fbase : a.r + fbase, nfe * 8u);
+            const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 2 ? 0u : nfe * 8u);
+            const rsrc_t rP = buf_rsrc(a.p + fbase, init == 0 ? nfe * SZ : 0u);
+            const rsrc_t rQ = buf_rsrc(a.q + fbase, (init == 0 && MODE == DST_UPDATE) ? nfe * SZ : 0u);
 #pragma unroll
             for (int cb = 0; cb < NIT; cb += CH) {
                 // loads of a chunk first (memory-level parallelism), then update
                 // and store; chunks keep the register footprint moderate
                 double x0[CH], x1[CH], r0[CH], r1[CH];
                 T p0[CH], p1[CH], q0[CH], q1[CH];
+                uint32_t e0[CH], e1[CH];
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     const int i = t + (cb + u) * TPF;
-                    x0[u] = r0[u] = x1[u] = r1[u] = 0.0;
-                    p0[u] = q0[u] = p1[u] = q1[u] = (T)0;
-                    if (cb + u < NIT && i < NX1) {
-                        if (a.init == 2) {           // restart: r holds b - A x already
-                            r0[u] = Rr[o0 + i];
-                            if (has1) r1[u] = Rr[o1 + i];
-                        } else if (a.init) {
-                            r0[u] = Bv[o0 + i];
-                            if (has1) r1[u] = Bv[o1 + i];
-                        } else {
-                            x0[u] = X[o0 + i];
-                            r0[u] = Rr[o0 + i];
-                            p0[u] = Pv[o0 + i];
-                            q0[u] = Qv[o0 + i];
-                            if (has1) {
-                                x1[u] = X[o1 + i];
-                                r1[u] = Rr[o1 + i];
-                                p1[u] = Pv[o1 + i];
-                                q1[u] = Qv[o1 + i];
-                            }
-                        }
+                    const bool in = (cb + u < NIT) && i < NX1;
+                    e0[u] = in ? (uint32_t)(j0 * NX1 + i) : BUF_OOB / 8u;
+                    e1[u] = (in && has1) ? (uint32_t)(j1 * NX1 + i) : BUF_OOB / 8u;
+                    x0[u] = bload<double>(rX, e0[u] * 8u);
+                    r0[u] = bload<double>(rR, e0[u] * 8u);
+                    p0[u] = bload<T>(rP, e0[u] * SZ);
+                    x1[u] = bload<double>(rX, e1[u] * 8u);
+                    r1[u] = bload<double>(rR, e1[u] * 8u);
+                    p1[u] = bload<T>(rP, e1[u] * SZ);
+                    if constexpr (MODE == DST_UPDATE_OP) {
+                        apply_pair<T>(rP, a.kap, a.wsh, NX1, a.nz1, min(i, NX1 - 1), j0, in, in && has1, p0[u],
+                                      p1[u], a.idx2, a.idz2, q0[u], q1[u]);
+                    } else {
+                        q0[u] = bload<T>(rQ, e0[u] * SZ);
+                        q1[u] = bload<T>(rQ, e1[u] * SZ);
                     }
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     const int i = t + (cb + u) * TPF;
+                    const double ra = r0[u] - alpha * (double)q0[u];
+                    const double rb = r1[u] - alpha * (double)q1[u];
+                    bstore<double>(x0[u] + alpha * (double)p0[u], rXs, e0[u] * 8u);
+                    bstore<double>(ra, rRs, e0[u] * 8u);
+                    bstore<double>(x1[u] + alpha * (double)p1[u], rXs, e1[u] * 8u);
+                    bstore<double>(rb, rRs, e1[u] * 8u);
+                    rr += ra * ra + rb * rb;
                     if (cb + u < NIT && i < NX1) {
-                        const double ra = r0[u] - alpha * (double)q0[u];
-                        const double rb = r1[u] - alpha * (double)q1[u];
-                        if (a.init != 2) {
-                            X[o0 + i] = x0[u] + alpha * (double)p0[u];
-                            Rr[o0 + i] = ra;
-                            if (has1) {
-                                X[o1 + i] = x1[u] + alpha * (double)p1[u];
-                                Rr[o1 + i] = rb;
-                            }
-                        }
-                        rr += ra * ra + rb * rb;
                         buf[lpad(1 + i)] = {(T)ra, (T)rb};
                         buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
                     }
@@ -266,17 +360,22 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
             }
         } else if constexpr (MODE == DST_CORRECT) {
             // zhat = y + xl u_rs + xr u_{Ls-rs} on segment rows (separator rows as
-            // is); the segment geometry depends on the row only
+            // is); the segment geometry depends on the row only.  Absent terms
+            // (separator rows, the first / last segment) read 0.
             const int Ls = a.Ls, P = a.P;
-            const T* __restrict__ Y = a.y + fbase;
-            const T* __restrict__ U = a.utab;
+            const rsrc_t rY = buf_rsrc(a.y + fbase, nfe * SZ);
+            const rsrc_t rU = buf_rsrc(a.utab, (uint32_t)Ls * (uint32_t)NX1 * SZ);
             const int rs0 = (j0 + 1) & (Ls - 1), sg0 = (j0 + 1) / Ls;
             const int rs1 = (j1 + 1) & (Ls - 1), sg1 = (j1 + 1) / Ls;
             const bool c0 = rs0 != 0, c1 = has1 && rs1 != 0;
+            // row indices (-1: absent) of the y rows and u-table rows
             const int l0 = (c0 && sg0 > 0) ? sg0 * Ls - 1 : -1;
             const int r0 = (c0 && sg0 < P - 1) ? (sg0 + 1) * Ls - 1 : -1;
             const int l1 = (c1 && sg1 > 0) ? sg1 * Ls - 1 : -1;
             const int r1 = (c1 && sg1 < P - 1) ? (sg1 + 1) * Ls - 1 : -1;
+            const int ua0r = c0 ? rs0 : -1, ub0r = c0 ? Ls - rs0 : -1;
+            const int ua1r = c1 ? rs1 : -1, ub1r = c1 ? Ls - rs1 : -1;
+            const int y1r = has1 ? j1 : -1;
 #pragma unroll
             for (int cb = 0; cb < NIT; cb += CH) {
                 T yv0[CH], yv1[CH], xl0[CH], xr0[CH], xl1[CH], xr1[CH];
@@ -284,24 +383,20 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     const int i = t + (cb + u) * TPF;
-                    yv0[u] = yv1[u] = xl0[u] = xr0[u] = xl1[u] = xr1[u] = (T)0;
-                    ua0[u] = ub0[u] = ua1[u] = ub1[u] = (T)0;
-                    if (cb + u < NIT && i < NX1) {
-                        yv0[u] = Y[(size_t)j0 * NX1 + i];
-                        if (has1) yv1[u] = Y[(size_t)j1 * NX1 + i];
-                        if (l0 >= 0) xl0[u] = Y[(size_t)l0 * NX1 + i];
-                        if (r0 >= 0) xr0[u] = Y[(size_t)r0 * NX1 + i];
-                        if (l1 >= 0) xl1[u] = Y[(size_t)l1 * NX1 + i];
-                        if (r1 >= 0) xr1[u] = Y[(size_t)r1 * NX1 + i];
-                        if (c0) {
-                            ua0[u] = U[(size_t)rs0 * NX1 + i];
-                            ub0[u] = U[(size_t)(Ls - rs0) * NX1 + i];
-                        }
-                        if (c1) {
-                            ua1[u] = U[(size_t)rs1 * NX1 + i];
-                            ub1[u] = U[(size_t)(Ls - rs1) * NX1 + i];
-                        }
-                    }
+                    const bool in = (cb + u < NIT) && i < NX1;
+                    auto off = [&](int row) -> uint32_t {
+                        return (in && row >= 0) ? (uint32_t)(row * NX1 + i) * SZ : BUF_OOB;
+                    };
+                    yv0[u] = bload<T>(rY, off(j0));
+                    yv1[u] = bload<T>(rY, off(y1r));
+                    xl0[u] = bload<T>(rY, off(l0));
+                    xr0[u] = bload<T>(rY, off(r0));
+                    xl1[u] = bload<T>(rY, off(l1));
+                    xr1[u] = bload<T>(rY, off(r1));
+                    ua0[u] = bload<T>(rU, off(ua0r));
+                    ub0[u] = bload<T>(rU, off(ub0r));
+                    ua1[u] = bload<T>(rU, off(ua1r));
+                    ub1[u] = bload<T>(rU, off(ub1r));
                 }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
@@ -315,25 +410,26 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                 }
             }
             // p of the outputs this thread will write (read now, used after the FFT)
+            const rsrc_t rPo = buf_rsrc(a.out + fbase, a.init ? 0u : nfe * SZ);
 #pragma unroll
             for (int qb = 0; qb < NBL; ++qb)
 #pragma unroll
                 for (int u = 0; u < RL / 2; ++u) {
                     const int K = t + qb * TPF + u * NSL;
                     const int oi = qb * (RL / 2) + u;
-                    pold0[oi] = pold1[oi] = (T)0;
-                    if (!a.init && K >= 1 && K <= NX1) {
-                        pold0[oi] = a.out[o0 + K - 1];
-                        if (has1) pold1[oi] = a.out[o1 + K - 1];
-                    }
+                    const bool ok = K >= 1 && K <= NX1;
+                    pold0[oi] = bload<T>(rPo, ok ? (uint32_t)(j0 * NX1 + K - 1) * SZ : BUF_OOB);
+                    pold1[oi] = bload<T>(rPo, (ok && has1) ? (uint32_t)(j1 * NX1 + K - 1) * SZ : BUF_OOB);
                 }
         } else {
+            const rsrc_t rI = buf_rsrc(a.in + fbase, nfe * SZ);
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int i = t + it * TPF;
-                if (i < NX1) {
-                    const T v0 = a.in[o0 + i];
-                    const T v1 = has1 ? a.in[o1 + i] : (T)0;
+                const bool in = i < NX1;
+                const T v0 = bload<T>(rI, in ? (uint32_t)(j0 * NX1 + i) * SZ : BUF_OOB);
+                const T v1 = bload<T>(rI, (in && has1) ? (uint32_t)(j1 * NX1 + i) * SZ : BUF_OOB);
+                if (in) {
                     buf[lpad(1 + i)] = {v0, v1};
                     buf[lpad(M - 1 - i)] = {-v0, -v1};
                 }
@@ -366,7 +462,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                 const int col = K - 1;
                 const cpx<T> V = v[qb * RL + u];
                 T x0 = -V.y * (T)0.5, x1 = V.x * (T)0.5;
-                if constexpr (MODE == DST_FWD || MODE == DST_UPDATE) {
+                if constexpr (MODE == DST_FWD || UPD) {
                     a.out[o0 + col] = x0;
                     if (has1) a.out[o1 + col] = x1;
                 } else if constexpr (MODE == DST_INV) {
@@ -389,7 +485,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
             }
     }
 
-    if constexpr (MODE == DST_UPDATE) {
+    if constexpr (UPD) {
         const double s = block_sum(rr, red);
         if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + bif] = s;
     }
@@ -415,6 +511,7 @@ struct TdArgs {
     double* E;       // [field][P][3][nx1]
     int nx1, nz1, P;
     int spw;         // segments per wave
+    int ktiles, sgroups;   // 1D grid of ktiles * sgroups * fields blocks
     int fstride, foff;   // field = grid index * fstride + foff (component selection)
     T inv_b;
     ShotCtl* ctl;    // nullptr: no masking
@@ -428,12 +525,16 @@ template <typename T, int LS>
 __global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
     __shared__ T es[LS * 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int k = blockIdx.x * 64 + lane;
-    const int field = blockIdx.z * a.fstride + a.foff;
+    // wavenumber tiles fastest, contiguous per XCD: neighbouring tiles share
+    // the cache lines at their edges (rows are not line aligned)
+    const int lb = xcd_linear(blockIdx.x, gridDim.x);
+    const int bx = lb % a.ktiles, by = (lb / a.ktiles) % a.sgroups, bz = lb / (a.ktiles * a.sgroups);
+    const int k = bx * 64 + lane;
+    const int field = bz * a.fstride + a.foff;
     if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
     const int nx1 = a.nx1;
     {
-        const int kk = blockIdx.x * 64 + (threadIdx.x & 63);
+        const int kk = bx * 64 + (threadIdx.x & 63);
         for (int i = threadIdx.x >> 6; i < LS; i += 4)
             es[i * 64 + (threadIdx.x & 63)] = (kk < nx1) ? a.etab[(size_t)i * nx1 + kk] : (T)0;
     }
@@ -441,7 +542,7 @@ __global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
     if (k >= nx1) return;
     constexpr int L = LS - 1;
     const size_t fb = (size_t)field * a.nz1 * nx1;
-    const int s_begin = (blockIdx.y * 4 + wave) * a.spw;
+    const int s_begin = (by * 4 + wave) * a.spw;
     const int s_end = min(s_begin + a.spw, a.P);
     for (int s = s_begin; s < s_end; ++s) {
         const T* __restrict__ g = a.rhat + fb + (size_t)(s * LS) * nx1 + k;   // row s*LS (+i-1)
@@ -841,6 +942,8 @@ hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int
 
 template <typename T>
 hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
+    // y == nullptr with reduce: only the (p, A p) partials (the update kernel
+    // recomputes A p itself)
     StArgs<T> a;
     a.p = x;
     a.q = y;
@@ -856,12 +959,13 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.pstride = p->partial_stride;
     a.nfields = p->S * p->C;
     a.nsh = std::min(a.nfields, p->op_shots);
-    dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT),
-              (a.nfields + a.nsh - 1) / a.nsh);
+    a.gx = (p->nx1 + 63) / 64;
+    a.gy = (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT);
+    const dim3 grid(a.gx * a.gy * ((a.nfields + a.nsh - 1) / a.nsh));
     hipLaunchKernelGGL(stencil_kernel<T>, grid, dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !reduce) return e;
-    return finalize(p, FIN_PQ, (int)(grid.x * grid.y), 0, 0.0, 0, 0.0);
+    return finalize(p, FIN_PQ, a.gx * a.gy, 0, 0.0, 0, 0.0);
 }
 
 template <typename T, int M, int MODE>
@@ -908,6 +1012,10 @@ DstArgs<T> dst_args(lg_plan* p) {
     a.partial = p->partial;
     a.pstride = p->partial_stride;
     a.y = (const T*)p->y;
+    a.kap = (const T*)p->kap;
+    a.wsh = (const T*)p->w;
+    a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
+    a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
     a.utab = (const T*)p->blk[0].utab;
     a.Ls = p->blk[0].Ls;
     a.P = p->blk[0].P;
@@ -927,7 +1035,9 @@ hipError_t td_launch(lg_plan* p, TdArgs<T>& a, int nfields) {
             spw *= 2;
     }
     a.spw = spw;
-    dim3 grid(ktiles, (a.P + 4 * spw - 1) / (4 * spw), nfields);
+    a.ktiles = ktiles;
+    a.sgroups = (a.P + 4 * spw - 1) / (4 * spw);
+    const dim3 grid(ktiles * a.sgroups * nfields);
     hipLaunchKernelGGL((td_kernel<T, LS>), grid, dim3(256), 0, p->stream, a);
     return hipGetLastError();
 }
@@ -1012,7 +1122,9 @@ hipError_t launch_true_residual(lg_plan* p, const double* x, const double* b, do
     a.pstride = p->partial_stride;
     a.nfields = p->S * p->C;
     a.nsh = std::min(a.nfields, 8);
-    dim3 grid((p->nx1 + 63) / 64, (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT), (a.nfields + a.nsh - 1) / a.nsh);
+    a.gx = (p->nx1 + 63) / 64;
+    a.gy = (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT);
+    const dim3 grid(a.gx * a.gy * ((a.nfields + a.nsh - 1) / a.nsh));
     hipLaunchKernelGGL(stencil_kernel<double>, grid, dim3(256), 0, p->stream, a);
     return hipGetLastError();
 }
@@ -1049,7 +1161,8 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         a.x = x;
         a.tol2 = tol * tol;
         a.max_iter = max_iter;
-        e = dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
+        e = (p->fuse_op && init == 0) ? dst_dispatch<double, DST_UPDATE_OP>(p, a, p->S * p->C)
+                                      : dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
         bpf = a.bpf;
     } else {
         DstArgs<float> a = dst_args<float>(p);
@@ -1059,7 +1172,8 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         a.x = x;
         a.tol2 = tol * tol;
         a.max_iter = max_iter;
-        e = dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
+        e = (p->fuse_op && init == 0) ? dst_dispatch<float, DST_UPDATE_OP>(p, a, p->S * p->C)
+                                      : dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;

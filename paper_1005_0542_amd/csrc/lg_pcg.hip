@@ -16,7 +16,9 @@ namespace {
 
 hipError_t enqueue_iteration(lg_plan* p) {
     const int nf = p->S * p->C;
-    hipError_t e = launch_stencil(p, p->p, p->qv, true);                  // q = A p, alpha
+    // (p, A p) and alpha; q = A p is stored only when the update does not
+    // recompute it
+    hipError_t e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);
     if (e == hipSuccess) e = launch_update_fdst(p, 0, nullptr, nullptr, 0.0, 0);  // x, r, rhat
     if (e == hipSuccess) e = launch_td(p, 0, p->rhat, p->y, nf, 1);        // segments
     if (e == hipSuccess) e = launch_rs(p, 0, p->rhat, p->y, nf, 2);        // interfaces, beta
@@ -162,7 +164,7 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
     hipError_t e = hipSuccess;
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
         e = hipEventRecord(ev[0], p->stream);
-        if (e == hipSuccess) e = launch_stencil(p, p->p, p->qv, true);
+        if (e == hipSuccess) e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);
         if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
         if (e == hipSuccess) e = launch_update_fdst(p, 0, nullptr, nullptr, 0.0, 0);
         if (e == hipSuccess) e = hipEventRecord(ev[2], p->stream);

@@ -311,13 +311,15 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (nshots < 1) return fail(LG_ERR_INVALID_ARG, "nshots must be >= 1");
     if (!is_pow2(grid->nx) || !is_pow2(grid->nz) || grid->nx > 4096 || grid->nz > 4096)
         return fail(LG_ERR_UNSUPPORTED, "nx and nz must be powers of two <= 4096");
-    int P = 0, gi = 8, osh = 8, spw = 0;
+    int P = 0, gi = 8, osh = 8, spw = 0, fus = 1;
     if (tuning != nullptr) {
         P = tuning->segments;
         if (tuning->graph_iters != 0) gi = tuning->graph_iters;
         if (tuning->op_shots != 0) osh = tuning->op_shots;
         spw = tuning->seg_per_wave;
+        if (tuning->op_fusion != 0) fus = tuning->op_fusion;
     }
+    if (fus != 1 && fus != 2) return fail(LG_ERR_INVALID_ARG, "op_fusion must be 0, 1 or 2");
     if (gi < -1 || gi == 0 || gi > 64) return fail(LG_ERR_INVALID_ARG, "graph_iters must be -1 or 1..64");
     if (osh < 1 || osh > 64) return fail(LG_ERR_INVALID_ARG, "op_shots must be in 1..64");
     if (spw != 0 && spw != 1 && spw != 2 && spw != 4)
@@ -348,6 +350,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->graph_iters = gi;
     p->op_shots = osh;
     p->td_spw = spw;
+    p->fuse_op = (fus == 1);
     p->device = dev;
     p->stream = (hipStream_t)hip_stream;
 

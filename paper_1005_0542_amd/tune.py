@@ -7,6 +7,7 @@ with HIP events by ``lg_pcg_profile``) for every candidate of
 * ``segments``      Dichotomy segments P per z-system (segment length nz/P),
 * ``op_shots``      shots per block of the operator kernel,
 * ``seg_per_wave``  Dichotomy segments solved by one wave,
+* ``op_fusion``     A p recomputed in the update kernel (1) or stored (2),
 
 then times short solves for ``graph_iters`` (iterations per HIP graph), and
 keeps the fastest.  Results are cached in a JSON file keyed by the device
@@ -60,6 +61,14 @@ def _store(path: str, data: Dict) -> None:
     os.replace(tmp, path)
 
 
+def lookup(nx: int, nz: int, precision: str, shots: int, kind: str = "acoustic",
+           arch: str = "gfx950", cache: Optional[str] = None) -> Dict[str, int]:
+    """The cached best parameters for a problem ({} when it was never tuned)."""
+    path = cache or os.environ.get("LG_TUNE_CACHE", DEFAULT_CACHE)
+    ent = _load(path).get(_key(arch, kind, nx, nz, precision, shots))
+    return dict(ent["best"]) if ent else {}
+
+
 def tune_acoustic(nx: int, nz: int, dx: float, dz: float, alpha: int, h: float, medium: np.ndarray,
                   precision: str, shots: int, rhs=None, cache: Optional[str] = None,
                   profile_iters: int = 6, verbose: bool = False) -> Dict[str, int]:
@@ -79,16 +88,18 @@ def tune_acoustic(nx: int, nz: int, dx: float, dz: float, alpha: int, h: float, 
     op_c = sorted({min(shots, c) for c in (1, 4, 8, 16)})
     spw_c = [1, 2, 4]
     trials = []
-    for P, osh, spw in itertools.product(segment_candidates(nz), op_c, spw_c):
+    for P, osh, spw, fus in itertools.product(segment_candidates(nz), op_c, spw_c, (1, 2)):
         if spw > 1 and 4 * spw > P:
             continue
         plan = api.Plan("acoustic", nx, nz, dx, dz, alpha, h, 2, medium, precision=precision, nshots=shots,
-                        segments=P, op_shots=osh, seg_per_wave=spw)
+                        segments=P, op_shots=osh, seg_per_wave=spw, op_fusion=fus)
         plan.pcg_profile(rhs, x, iters=2)                       # warm-up
         ms = sum(plan.pcg_profile(rhs, x, iters=profile_iters))
-        trials.append({"segments": P, "op_shots": osh, "seg_per_wave": spw, "iteration_ms": ms})
+        trials.append({"segments": P, "op_shots": osh, "seg_per_wave": spw, "op_fusion": fus,
+                       "iteration_ms": ms})
         if verbose:
-            print(f"[tune] P={P} op_shots={osh} seg_per_wave={spw}: {ms:.4f} ms/iteration", flush=True)
+            print(f"[tune] P={P} op_shots={osh} seg_per_wave={spw} op_fusion={fus}: {ms:.4f} ms/iteration",
+                  flush=True)
         plan.destroy()
     best = min(trials, key=lambda t: t["iteration_ms"])
     # iterations per captured graph: time short solves with the best tiles
@@ -96,7 +107,7 @@ def tune_acoustic(nx: int, nz: int, dx: float, dz: float, alpha: int, h: float, 
     for gi in (4, 8, 16):
         plan = api.Plan("acoustic", nx, nz, dx, dz, alpha, h, 2, medium, precision=precision, nshots=shots,
                         segments=best["segments"], op_shots=best["op_shots"],
-                        seg_per_wave=best["seg_per_wave"], graph_iters=gi)
+                        seg_per_wave=best["seg_per_wave"], op_fusion=best["op_fusion"], graph_iters=gi)
         plan.pcg_solve(rhs, x, tol=1e-8, max_iter=200)           # builds the graph
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -106,7 +117,7 @@ def tune_acoustic(nx: int, nz: int, dx: float, dz: float, alpha: int, h: float, 
         gtrials.append({"graph_iters": gi, "solve_ms": 1e3 * (time.perf_counter() - t) / 3})
         plan.destroy()
     gbest = min(gtrials, key=lambda t: t["solve_ms"])
-    out = {k: best[k] for k in ("segments", "op_shots", "seg_per_wave")}
+    out = {k: best[k] for k in ("segments", "op_shots", "seg_per_wave", "op_fusion")}
     out["graph_iters"] = gbest["graph_iters"]
     db[key] = {"best": out, "trials": trials, "graph_trials": gtrials}
     _store(path, db)

@@ -127,6 +127,7 @@ def test_elastic_harmonic_chain_parity():
     src = np.array([[16, 6]], dtype=np.int32)
     plan.set_sources(src)
     f = api.source_coeffs(20.0, 1.5 / 20.0, alpha, h, nh)
+    fo = laguerre.ricker_coeffs(20.0, 1.5 / 20.0, h, alpha, nh)      # the oracle's own coefficients
     shape = (1, 2, nz - 1, nx - 1)
     R = torch.zeros(shape, dtype=torch.float64, device="cuda")
     Ph, Qh, rhs = (torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(3))
@@ -140,7 +141,7 @@ def test_elastic_harmonic_chain_parity():
         res = plan.gmres_solve(rhs, R, tol=1e-11, max_iter=5000, restart=10)
         assert res.statuses == [OK]
         srcf = np.zeros((2, nz - 1, nx - 1))
-        srcf[1] = harmonics.source_field((nz - 1, nx - 1), src[0], f[m], d, d)
+        srcf[1] = harmonics.source_field((nz - 1, nx - 1), src[0], fo[m], d, d)
         Q = sums.step(m, Rprev)
         phi = srcf - h * h * rho[1:-1, 1:-1][None] * Q
         assert rel(to_np(rhs)[0], phi) < 1e-12

@@ -21,7 +21,8 @@ def _oracle_run(run, n, tol=1e-10, keep_all=True):
     B = precond.acoustic_preconditioner(kappa, rho, w.h, N, N, d, d)
     solve = lambda phi: krylov.pcg(lambda y: operator.apply_A(y, kappa, wv, d, d), B.solve, phi, tol, 10000)
     W = laguerre.synthesis_weights(inputs.snapshot_times(w), w.h, w.alpha, n)
-    return harmonics.harmonic_loop(n, solve, rho[1:-1, 1:-1], w.h, w.alpha, run.f_m, run.src[0], d, d,
+    f_m = laguerre.ricker_coeffs(w.f0, w.t0, w.h, w.alpha, n)      # the oracle's own coefficients
+    return harmonics.harmonic_loop(n, solve, rho[1:-1, 1:-1], w.h, w.alpha, f_m, run.src[0], d, d,
                                    snap_w=W, rec_row=w.rec_row, keep_all=keep_all)
 
 
