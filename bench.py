@@ -71,7 +71,7 @@ def tuned_params(name, precision, shots, enabled=True):
 
 
 def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0, profile=True,
-                tuned=None):
+                tuned=None, profile_iters=20):
     import torch
     from paper_1005_0542_amd import inputs
     from paper_1005_0542_amd.driver import AcousticRun
@@ -121,9 +121,11 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     out["alg_bytes_per_point_iter"] = sum(kb.values())
     out["whole_iteration_GBps"] = per_iter_bytes / t_iter / 1e9   # includes per-harmonic overheads
     if profile:
+        # per-kernel durations on the same plan and stream, with the last timed
+        # harmonic's right-hand side and every shot active
         b = run.rhs.clone()
         x = torch.empty_like(b)
-        ms = run.plan.pcg_profile(b, x, iters=10)
+        ms = run.plan.pcg_profile(b, x, iters=profile_iters)
         names = list(kb.keys())
         kern = {}
         for k, nm in enumerate(names):
@@ -135,40 +137,6 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
         out["dominant"] = dom
     out["_run"] = run
     return out
-
-
-def profile_variant(name, precision, shots, iters, tuned, segments=0, overrides=None):
-    """Only the per-kernel profile (no harmonic solves): the plan, the first
-    harmonic's right-hand side, then ``iters`` eager CG iterations with every
-    shot active, each of the five kernels timed with HIP events on the plan's
-    stream.  A kernel trace of this mode holds exactly those launches (plus
-    one start-up launch of the update, Dichotomy and correction kernels)."""
-    import torch
-    from paper_1005_0542_amd import inputs
-    from paper_1005_0542_amd.driver import AcousticRun
-
-    w = inputs.WORKLOADS[name]
-    tuned = dict(tuned or {})
-    tuned.update(overrides or {})
-    if segments:
-        tuned["segments"] = segments
-    log(f"{name}: profile precision={precision} shots={shots} iterations={iters} params={tuned}")
-    run = AcousticRun(w, precision=precision, shots=shots, n_harm=2, snapshots=False, rec=False,
-                      segments=tuned.get("segments", 0), op_shots=tuned.get("op_shots", 0),
-                      seg_per_wave=tuned.get("seg_per_wave", 0), op_fusion=tuned.get("op_fusion", 0))
-    fs = np.full(shots, run.f_m[0])
-    run.plan.laguerre_rhs(0, None, run.Ph, run.Qh, fs, run.rhs)
-    x = torch.empty_like(run.rhs)
-    run.plan.pcg_profile(run.rhs, x, iters=max(2, iters // 4))      # clocks up, caches warm
-    ms = run.plan.pcg_profile(run.rhs, x, iters=iters)
-    torch.cuda.synchronize()
-    seg, seg_len = run.plan.layout()
-    npts = (w.n_cells - 1) ** 2
-    kb = kernel_bytes(8 if precision == "fp64" else 4, shots, seg_len, tuned.get("op_fusion", 0) != 2)
-    kern = {nm: {"avg_ms": ms[k], "alg_bytes": kb[nm] * npts * shots,
-                 "GBps": kb[nm] * npts * shots / (ms[k] * 1e-3) / 1e9} for k, nm in enumerate(kb)}
-    return {"workload": name, "precision": precision, "shots": shots, "segments": seg,
-            "tuned": tuned, "profile_iterations": iters, "kernels": kern}
 
 
 def cpu_baseline(name, k_lo=2, k_hi=12):
@@ -250,10 +218,17 @@ def main():
     prec = args.precision or w.precision
     shots = args.shots or w.shots
     if args.profile_only:
-        ov = {k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion") if getattr(args, k)}
-        v = profile_variant(args.workload, prec, shots, args.profile_iters,
-                            tuned_params(args.workload, prec, shots, not args.no_tune), args.segments, ov)
-        print(json.dumps(v))
+        # the benchmark's own path on two harmonics (one untimed), then the
+        # per-kernel profile: a kernel trace of this mode ends with exactly
+        # --profile-iters launches of each iteration kernel with all shots active
+        tp = tuned_params(args.workload, prec, shots, not args.no_tune)
+        tp.update({k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion") if getattr(args, k)})
+        v = run_variant(args.workload, prec, shots, 1, 1, segments=args.segments, graph_iters=args.graph_iters,
+                        tuned=tp, profile_iters=args.profile_iters)
+        v.pop("_run")
+        print(json.dumps({k: v[k] for k in ("workload", "precision", "shots", "segments", "kernels",
+                                            "iteration_ms_profiled")} | {"tuned": tp,
+                                                                         "profile_iterations": args.profile_iters}))
         return
     head_tuned = tuned_params(args.workload, prec, shots, not args.no_tune)
     head = run_variant(args.workload, prec, shots, args.steps, args.warmup,

@@ -605,37 +605,55 @@ struct RsArgs {
     size_t pstride;
 };
 
-// One block per (64 consecutive wavenumbers, field).  Phase 1 loads the
-// interface right-hand sides G[s][k] with coalesced row reads into LDS;
-// phase 2 solves the 64 systems, each by one wave with one lane per
-// separator; phase 3 writes the separator values back row by row and forms
-// this block's share of (rhat, zhat) / b.
-template <typename T, int KT>
+// One block per (KT consecutive wavenumbers, field).  Phase 1 loads, with
+// every load issued up front, the interface right-hand sides G[s][k] (row
+// reads of the separator rows and of the segment data E) and the block's
+// slice of the interface weight table into LDS; phase 2 solves the KT
+// systems, each by one wave with one lane per separator, and overwrites G by
+// the separator values; phase 3 writes them back row by row and forms this
+// block's share of (rhat, zhat) / b.  PM >= P bounds the phase-1 unroll.
+template <typename T, int KT, int PM>
 __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
     constexpr int KS = KT + 1;             // padded LDS row
     constexpr int NG = 256 / KT;           // thread groups over separators
-    __shared__ double Gs[64 * KS];
-    __shared__ double Xs[64 * KS];
+    constexpr int NIT1 = (PM + NG - 1) / NG;
+    extern __shared__ double rs_lds[];
     __shared__ double red[4];
-    const int field = blockIdx.y * a.fstride + a.foff;
+    const int P = a.P, q = a.q, Ls = a.Ls, nx1 = a.nx1, RW = a.RW;
+    double* Gs = rs_lds;                   // [P-1][KS]
+    double* Ws = rs_lds + (P - 1) * KS;    // [KT][RW]
+    const int nkt = (nx1 + KT - 1) / KT;
+    const int lb = xcd_linear(blockIdx.x, gridDim.x);
+    const int bx = lb % nkt, bf = lb / nkt;
+    const int field = bf * a.fstride + a.foff;
     if (a.mode != 0 && a.ctl[field].active == 0) return;   // uniform per block
-    const int P = a.P, q = a.q, Ls = a.Ls, nx1 = a.nx1;
     const int tid = threadIdx.x, kl = tid % KT, grp = tid / KT;
-    const int k0 = blockIdx.x * KT;
+    const int k0 = bx * KT;
     const int k = k0 + kl;
     const bool valid = k < nx1;
+    constexpr uint32_t SZ = sizeof(T);
     const size_t fb = (size_t)field * a.nz1 * nx1;
-    const double* Ef = a.E + (size_t)field * P * 3 * nx1;
+    const rsrc_t rR = buf_rsrc(a.rhat + fb, (uint32_t)a.nz1 * (uint32_t)nx1 * SZ);
+    const rsrc_t rE = buf_rsrc(a.E + (size_t)field * P * 3 * nx1, (uint32_t)P * 3u * (uint32_t)nx1 * 8u);
+    const rsrc_t rW = buf_rsrc(a.red, (uint32_t)nx1 * (uint32_t)RW * 8u);
+    // weight table rows k0 .. k0+KT-1 are contiguous
+    for (int e = tid; e < KT * RW; e += 256)
+        Ws[e] = bload<double>(rW, (uint32_t)(k0 * RW + e) * 8u);
     double d0 = 0.0;
-    for (int sg = grp; sg < P; sg += NG) {
-        if (valid) d0 += Ef[((size_t)sg * 3 + 2) * nx1 + k];
-        if (sg < P - 1) {
-            double g = 0.0;
-            if (valid)
-                g = (double)a.rhat[fb + (size_t)((sg + 1) * Ls - 1) * nx1 + k] * a.inv_b +
-                    Ef[((size_t)sg * 3 + 1) * nx1 + k] + Ef[((size_t)(sg + 1) * 3 + 0) * nx1 + k];
-            Gs[sg * KS + kl] = g;
-        }
+    double gv[NIT1];
+#pragma unroll
+    for (int it = 0; it < NIT1; ++it) {
+        const int sg = grp + it * NG;
+        const bool okd = valid && sg < P, okg = valid && sg < P - 1;
+        d0 += bload<double>(rE, okd ? (uint32_t)((sg * 3 + 2) * nx1 + k) * 8u : BUF_OOB);
+        gv[it] = (double)bload<T>(rR, okg ? (uint32_t)(((sg + 1) * Ls - 1) * nx1 + k) * SZ : BUF_OOB) * a.inv_b +
+                 bload<double>(rE, okg ? (uint32_t)((sg * 3 + 1) * nx1 + k) * 8u : BUF_OOB) +
+                 bload<double>(rE, okg ? (uint32_t)(((sg + 1) * 3 + 0) * nx1 + k) * 8u : BUF_OOB);
+    }
+#pragma unroll
+    for (int it = 0; it < NIT1; ++it) {
+        const int sg = grp + it * NG;
+        if (sg < P - 1) Gs[sg * KS + kl] = gv[it];
     }
     __syncthreads();
 
@@ -643,35 +661,21 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
     const int lane = tid & 63, wave = tid >> 6;
     const int sig = lane;
     const bool sepl = sig < P - 1;
+    double c = d0;
     for (int kk = wave; kk < KT; kk += 4) {
         if (k0 + kk >= nx1) break;                          // uniform per wave
-        const double* tab = a.red + (size_t)(k0 + kk) * a.RW;
+        const double* tab = Ws + kk * RW;
         const double G = sepl ? Gs[sig * KS + kk] : 0.0;
-        // this lane's weight at every level, loaded up front (independent loads)
-        double wl[6], bl[6];
-        {
-            int woff = 2 + q;
-#pragma unroll
-            for (int l = 0; l < 6; ++l) {
-                wl[l] = bl[l] = 0.0;
-                if (l < q) {
-                    const int size = P >> l;
-                    const int pos = sig & (size - 1);
-                    const int widx = min(pos, size - 2 - pos);
-                    if (sepl && pos != size - 1) wl[l] = tab[woff + widx];
-                    bl[l] = tab[2 + l];
-                    woff += size >> 1;
-                }
-            }
-        }
         double x = 0.0;
+        int woff = 2 + q;
 #pragma unroll
         for (int l = 0; l < 6; ++l) {
             if (l >= q) break;
             const int size = P >> l;
             const int pos = sig & (size - 1);
             const bool member = sepl && (pos != size - 1);
-            double tv = member ? wl[l] * G : 0.0;
+            const int widx = min(pos, size - 2 - pos);
+            double tv = member ? tab[woff + (widx < 0 ? 0 : widx)] * G : 0.0;
             for (int off = 1; off < size; off <<= 1) tv += __shfl_xor(tv, off, 64);
             const int base = sig - pos;
             const int ll = base - 1, rl = base + size - 1;
@@ -679,24 +683,23 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
             const double xr_ = __shfl(x, rl > 63 ? 63 : rl, 64);
             const double xl = (ll < 0) ? 0.0 : xl_;
             const double xr = (rl >= P - 1) ? 0.0 : xr_;
-            if (member && pos == (size >> 1) - 1) x = tv + bl[l] * (xl + xr);
+            if (member && pos == (size >> 1) - 1) x = tv + tab[2 + l] * (xl + xr);
+            woff += size >> 1;
         }
-        if (sepl) Xs[sig * KS + kk] = x;
+        if (sepl) {
+            c += x * G;
+            Gs[sig * KS + kk] = x;
+        }
     }
     __syncthreads();
 
-    // phase 3: store separators, interface part of the inner product
-    double c = d0;
-    for (int sg = grp; sg < P - 1; sg += NG) {
-        const double x = Xs[sg * KS + kl];
-        if (valid) {
-            a.y[fb + (size_t)((sg + 1) * Ls - 1) * nx1 + k] = (T)x;
-            c += x * Gs[sg * KS + kl];
-        }
-    }
+    // phase 3: store the separator values
+    const rsrc_t rY = buf_rsrc(a.y + fb, (uint32_t)a.nz1 * (uint32_t)nx1 * SZ);
+    for (int sg = grp; sg < P - 1; sg += NG)
+        bstore<T>((T)Gs[sg * KS + kl], rY, valid ? (uint32_t)(((sg + 1) * Ls - 1) * nx1 + k) * SZ : BUF_OOB);
     if (a.mode == 0) return;
     const double s = block_sum(c, red);
-    if (tid == 0) a.partial[(size_t)field * a.pstride + blockIdx.x] = s;
+    if (tid == 0) a.partial[(size_t)field * a.pstride + bx] = s;
 }
 
 // ===========================================================================
@@ -1091,17 +1094,30 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, 
     a.ctl = p->ctl;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
-    // 64 wavenumbers per block when the grid stays large, else 16 (more blocks)
+    // 64 wavenumbers per block when the grid stays large (32 when the LDS
+    // tables would pass 48 KB), else 16 (more blocks)
+    auto lds_bytes = [&](int kt) {
+        return ((size_t)(B.P - 1) * (kt + 1) + (size_t)kt * B.RW) * sizeof(double);
+    };
     const bool wide = (long)((p->nx1 + 63) / 64) * nfields >= 1024;
-    const int KT = wide ? 64 : 16;
-    const dim3 grid((p->nx1 + KT - 1) / KT, nfields);
-    if (wide)
-        hipLaunchKernelGGL((rs_kernel<T, 64>), grid, dim3(256), 0, p->stream, a);
-    else
-        hipLaunchKernelGGL((rs_kernel<T, 16>), grid, dim3(256), 0, p->stream, a);
+    const int KT = !wide ? 16 : (lds_bytes(64) <= 48 * 1024 ? 64 : 32);
+    const int nkt = (p->nx1 + KT - 1) / KT;
+    const dim3 grid(nkt * nfields);
+    const size_t lds = lds_bytes(KT);
+    auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), lds, p->stream, a); };
+    if (KT == 64) {
+        if (B.P <= 8) go(rs_kernel<T, 64, 8>);
+        else if (B.P <= 16) go(rs_kernel<T, 64, 16>);
+        else go(rs_kernel<T, 64, 32>);
+    } else if (KT == 32) {
+        go(rs_kernel<T, 32, 64>);
+    } else {
+        if (B.P <= 16) go(rs_kernel<T, 16, 16>);
+        else go(rs_kernel<T, 16, 64>);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == 0) return e;
-    return finalize(p, FIN_RZ, (int)grid.x, mode, 0.0, 0, B.b * 2.0 / p->g.nx);
+    return finalize(p, FIN_RZ, nkt, mode, 0.0, 0, B.b * 2.0 / p->g.nx);
 }
 
 }  // namespace
