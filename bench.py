@@ -55,6 +55,61 @@ def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True):
     }
 
 
+def copy_probe(mib: int = 2048, reps: int = 10):
+    """Device-to-device copy bandwidth on this GPU (read + write bytes per
+    second), the practical streaming ceiling the kernels are compared with."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    e.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * n * 8 / (ms * 1e-3) / 1e9
+
+
+def library_source_sha256() -> str:
+    """Hash of the library sources (kernels, host code, C header)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_1005_0542_amd", "csrc", "*")))
+    files.append(os.path.join(ROOT, "include", "laguerre.h"))
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary of this workload (FETCH_SIZE / WRITE_SIZE scaled by a plain-copy
+    calibration), or None when there is none or the library has changed since
+    the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"pcg_kernels_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("library_source_sha256") != library_source_sha256():
+        return None
+    v = fields.get(f"traffic_bytes_per_launch[{kernel}]")
+    return float(v) if v is not None else None
+
+
 def tuned_params(name, precision, shots, enabled=True):
     """Tile/segment parameters from the autotuner (its JSON cache, or a fresh
     search on this device when the cache has no entry for the problem)."""
@@ -186,7 +241,7 @@ def main():
     ap.add_argument("--graph-iters", type=int, default=0)
     ap.add_argument("--profile-only", action="store_true",
                     help="only the per-kernel profile of the workload (for hardware-counter runs)")
-    ap.add_argument("--profile-iters", type=int, default=10,
+    ap.add_argument("--profile-iters", type=int, default=20,
                     help="CG iterations timed per kernel by --profile-only")
     ap.add_argument("--precision", default=None, help="override the workload precision")
     ap.add_argument("--shots", type=int, default=None, help="override the workload shot count")
@@ -223,8 +278,8 @@ def main():
         # --profile-iters launches of each iteration kernel with all shots active
         tp = tuned_params(args.workload, prec, shots, not args.no_tune)
         tp.update({k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion") if getattr(args, k)})
-        v = run_variant(args.workload, prec, shots, 1, 1, segments=args.segments, graph_iters=args.graph_iters,
-                        tuned=tp, profile_iters=args.profile_iters)
+        v = run_variant(args.workload, prec, shots, args.steps, args.warmup, segments=args.segments,
+                        graph_iters=args.graph_iters, tuned=tp, profile_iters=args.profile_iters)
         v.pop("_run")
         print(json.dumps({k: v[k] for k in ("workload", "precision", "shots", "segments", "kernels",
                                             "iteration_ms_profiled")} | {"tuned": tp,
@@ -232,7 +287,8 @@ def main():
         return
     head_tuned = tuned_params(args.workload, prec, shots, not args.no_tune)
     head = run_variant(args.workload, prec, shots, args.steps, args.warmup,
-                       segments=args.segments, graph_iters=args.graph_iters, tuned=head_tuned)
+                       segments=args.segments, graph_iters=args.graph_iters, tuned=head_tuned,
+                       profile_iters=args.profile_iters)
     head.pop("_run")
     torch.cuda.empty_cache()
     variants = {}
@@ -245,7 +301,8 @@ def main():
         ]
         for name, prec, shots, key in plan:
             v = run_variant(name, prec, shots, max(2, args.steps // 2), 1,
-                            tuned=tuned_params(name, prec, shots, not args.no_tune))
+                            tuned=tuned_params(name, prec, shots, not args.no_tune),
+                            profile_iters=args.profile_iters)
             v.pop("_run")
             variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "value", "ms_per_step",
                                                "mean_iters", "whole_iteration_GBps", "dominant")}
@@ -257,11 +314,18 @@ def main():
     dom = head["dominant"]
     kd = head["kernels"][dom]
     achieved = kd["GBps"]
+    traffic = counter_traffic(dom, args.workload)
+    copy_gbps = copy_probe()
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "alg_bytes_per_launch": round(kd["alg_bytes"]),
             "per_kernel_GBps": {k: round(x["GBps"], 1) for k, x in head["kernels"].items()},
             "per_kernel_ms": {k: round(x["avg_ms"], 4) for k, x in head["kernels"].items()},
             "whole_iteration_GBps": round(head["whole_iteration_GBps"], 1),
+            "copy_probe_GBps": round(copy_gbps, 1),
+            "frac_of_copy_probe": round(achieved / copy_gbps, 4),
             "alg_bytes_per_point_iter": round(head["alg_bytes_per_point_iter"], 2)}
     cpu = None
     if not args.no_cpu_baseline:
@@ -279,6 +343,7 @@ def main():
                    "segments": head["segments"], "tuned": head_tuned,
                    "parallelism": "single GPU, shot batch"},
         "iters_per_harmonic": head["iters_per_harmonic"],
+        "setup_s": round(head["setup_s"], 3),
         "roofline": roof,
         "cpu_baseline": cpu,
         "variants": variants,

@@ -166,8 +166,6 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
 // V_k = -2i X_k(row j0) + 2 X_k(row j1), so the two DST-I results are
 // X(j0) = -Im V / 2, X(j1) = Re V / 2 for k = 1..nx-1.
 // ===========================================================================
-constexpr int DST_GROUP = 4;
-
 // DST_UPDATE_OP is DST_UPDATE with A p recomputed from p and the medium
 // instead of read from a stored q.
 enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3, DST_UPDATE_OP = 4 };
@@ -257,20 +255,12 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
 
     const int fid = threadIdx.x / TPF;
     const int t = threadIdx.x - fid * TPF;
-    // Logical order (contiguous per XCD): groups of DST_GROUP consecutive
-    // blocks of one field, all fields of a group before the next group.  The
-    // blocks of one group share halo rows (fused update: p rows j0-1, j1+1),
-    // and all fields of a group read the same medium rows.
-    int field, bif;
-    {
-        const int nf = gridDim.x / a.bpf;
-        const int L = xcd_linear(blockIdx.x, gridDim.x);
-        const int g = L / (DST_GROUP * nf);
-        const int sz = min(DST_GROUP, a.bpf - g * DST_GROUP);
-        const int rem = L - g * DST_GROUP * nf;
-        field = rem / sz;
-        bif = g * DST_GROUP + (rem - field * sz);
-    }
+    // Field-major order: the blocks in flight at any time cover a few
+    // consecutive row pairs of one or two fields, which keeps the pages they
+    // touch few (measured faster than orders that spread the blocks in flight
+    // over many fields for medium or halo reuse in one L2).
+    const int field = blockIdx.x / a.bpf;
+    const int bif = blockIdx.x - field * a.bpf;
     const int pair = bif * FPB + fid;
     const int npairs = (a.nz1 + 1) >> 1;
     const bool live = pair < npairs;
