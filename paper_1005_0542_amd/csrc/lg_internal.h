@@ -134,8 +134,6 @@ inline size_t wsize(const lg_plan* p) { return p->prec == LG_FP64 ? 8 : 4; }
 
 // launchers (implemented in lg_acoustic.hip); all enqueue on plan->stream
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq);
-// r = b - A x with the FP64 operator (x, b, r FP64; all fields)
-hipError_t launch_true_residual(lg_plan* p, const double* x, const double* b, double* r);
 hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nfields);
 // Dichotomy kernels over `nfields` fields; field f of the launch is buffer
 // field f * fstride + foff (acoustic: 1, 0; one elastic component: 2, c).
@@ -144,6 +142,9 @@ hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields
 hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int mode,
                      int fstride = 1, int foff = 0);
 hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride = 1, int foff = 0);
+// CG update + forward DST.  init 0: iteration (x += alpha p, r -= alpha A p);
+// 1: start (x = 0, r = b); 2: restart from the stored r; 3 (mixed): restart
+// from the FP64 true residual r = b - A x formed in the same pass.
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter);
 hipError_t launch_correct_idst(lg_plan* p, int init);

@@ -45,7 +45,6 @@ struct StArgs {
     T idx2, idz2;
     int nfields, nsh;    // fields, fields per block (shot chunks)
     int gx, gy;          // column tiles, row strips (1D grid of gx*gy*chunks blocks)
-    const T* bsub;       // non-null: store bsub - A p instead of A p (true residual)
     // CG reduction (ctl == nullptr: plain operator application)
     ShotCtl* ctl;
     double* partial;
@@ -123,12 +122,6 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
             pe[r] = bload<T>(rp, oe[r]);
             pw[r] = bload<T>(rp, ow[r]);
         }
-        T bs[ST_RPT];
-        if (a.bsub != nullptr) {
-            const rsrc_t rb = buf_rsrc(a.bsub + fb, fbytes);
-#pragma unroll
-            for (int r = 0; r < ST_RPT; ++r) bs[r] = bload<T>(rb, oc[r + 1]);
-        }
         double pq = 0.0;
         T v[ST_RPT];
 #pragma unroll
@@ -143,7 +136,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
             const rsrc_t rq = buf_rsrc(a.q + fb, fbytes);
 #pragma unroll
             for (int r = 0; r < ST_RPT; ++r)
-                bstore<T>(a.bsub != nullptr ? bs[r] - v[r] : v[r], rq, oc[r + 1]);
+                bstore<T>(v[r], rq, oc[r + 1]);
         }
         if (a.ctl == nullptr) continue;
         pq = wave_sum(pq);
@@ -167,8 +160,10 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
 // X(j0) = -Im V / 2, X(j1) = Re V / 2 for k = 1..nx-1.
 // ===========================================================================
 // DST_UPDATE_OP is DST_UPDATE with A p recomputed from p and the medium
-// instead of read from a stored q.
-enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3, DST_UPDATE_OP = 4 };
+// instead of read from a stored q.  DST_RESTART (mixed precision) forms the
+// FP64 true residual r = b - A x from x, b and the FP64 medium, stores it and
+// transforms it: the restart of CG from the true residual in one pass.
+enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3, DST_UPDATE_OP = 4, DST_RESTART = 5 };
 
 template <typename T>
 struct DstArgs {
@@ -188,6 +183,9 @@ struct DstArgs {
     const T* kap;          // UPDATE_OP: node kappa, (nz+1) x (nx+1)
     const T* wsh;          // UPDATE_OP: interior shift
     T idx2, idz2;          // UPDATE_OP: 1/dx^2, 1/dz^2
+    const double* kap64;   // RESTART: FP64 node kappa and shift
+    const double* w64;
+    double idx2d, idz2d;
     double* partial;
     size_t pstride;
     double tol2;           // tol^2 (init)
@@ -249,7 +247,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     constexpr int NIT = (NX1 + TPF - 1) / TPF;
     constexpr int CHMAX = (MODE == DST_UPDATE_OP && sizeof(T) == 8) ? 2 : 4;
     constexpr int CH = NIT < CHMAX ? NIT : CHMAX;
-    constexpr bool UPD = MODE == DST_UPDATE || MODE == DST_UPDATE_OP;
+    constexpr bool UPD = MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART;
     __shared__ cpx<T> lds[FPB * LL];
     __shared__ double red[NWAVE];
 
@@ -288,7 +286,45 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     constexpr uint32_t SZ = sizeof(T);
     const uint32_t nfe = (uint32_t)a.nz1 * (uint32_t)NX1;     // elements per field
     if (live) {
-        if constexpr (UPD) {
+        if constexpr (MODE == DST_RESTART) {
+            // r = b - A x in FP64 with the operator kernel's arithmetic (bitwise
+            // the separate true-residual pass), stored, then transformed in FP32
+            const rsrc_t rX = buf_rsrc(a.x + fbase, nfe * 8u);
+            const rsrc_t rB = buf_rsrc(a.b + fbase, nfe * 8u);
+            const rsrc_t rRs = buf_rsrc(a.r + fbase, nfe * 8u);
+            constexpr int CR = NIT < 2 ? NIT : 2;
+#pragma unroll
+            for (int cb = 0; cb < NIT; cb += CR) {
+                double x0[CR], x1[CR], b0[CR], b1[CR], q0[CR], q1[CR];
+                uint32_t e0[CR], e1[CR];
+#pragma unroll
+                for (int u = 0; u < CR; ++u) {
+                    const int i = t + (cb + u) * TPF;
+                    const bool in = (cb + u < NIT) && i < NX1;
+                    e0[u] = in ? (uint32_t)(j0 * NX1 + i) : BUF_OOB / 8u;
+                    e1[u] = (in && has1) ? (uint32_t)(j1 * NX1 + i) : BUF_OOB / 8u;
+                    x0[u] = bload<double>(rX, e0[u] * 8u);
+                    x1[u] = bload<double>(rX, e1[u] * 8u);
+                    b0[u] = bload<double>(rB, e0[u] * 8u);
+                    b1[u] = bload<double>(rB, e1[u] * 8u);
+                    apply_pair<double>(rX, a.kap64, a.w64, NX1, a.nz1, min(i, NX1 - 1), j0, in, in && has1,
+                                       x0[u], x1[u], a.idx2d, a.idz2d, q0[u], q1[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < CR; ++u) {
+                    const int i = t + (cb + u) * TPF;
+                    const double ra = b0[u] - q0[u];
+                    const double rb = b1[u] - q1[u];
+                    bstore<double>(ra, rRs, e0[u] * 8u);
+                    bstore<double>(rb, rRs, e1[u] * 8u);
+                    rr += ra * ra + rb * rb;
+                    if (cb + u < NIT && i < NX1) {
+                        buf[lpad(1 + i)] = {(T)ra, (T)rb};
+                        buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
+                    }
+                }
+            }
+        } else if constexpr (UPD) {
             const int init = a.init;
             double* X = nullptr;
             double alpha = 0.0;
@@ -947,7 +983,6 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
     a.ctl = reduce ? p->ctl : nullptr;
-    a.bsub = nullptr;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
     a.nfields = p->S * p->C;
@@ -1009,6 +1044,10 @@ DstArgs<T> dst_args(lg_plan* p) {
     a.wsh = (const T*)p->w;
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
+    a.kap64 = p->kap64;
+    a.w64 = p->w64;
+    a.idx2d = 1.0 / (p->g.dx * p->g.dx);
+    a.idz2d = 1.0 / (p->g.dz * p->g.dz);
     a.utab = (const T*)p->blk[0].utab;
     a.Ls = p->blk[0].Ls;
     a.P = p->blk[0].P;
@@ -1112,29 +1151,6 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, 
 
 }  // namespace
 
-hipError_t launch_true_residual(lg_plan* p, const double* x, const double* b, double* r) {
-    StArgs<double> a;
-    a.p = x;
-    a.q = r;
-    a.kap = (p->prec == LG_FP64) ? (const double*)p->kap : p->kap64;
-    a.w = (p->prec == LG_FP64) ? (const double*)p->w : p->w64;
-    a.nx1 = p->nx1;
-    a.nz1 = p->nz1;
-    a.idx2 = 1.0 / (p->g.dx * p->g.dx);
-    a.idz2 = 1.0 / (p->g.dz * p->g.dz);
-    a.ctl = nullptr;
-    a.bsub = b;
-    a.partial = p->partial;
-    a.pstride = p->partial_stride;
-    a.nfields = p->S * p->C;
-    a.nsh = std::min(a.nfields, 8);
-    a.gx = (p->nx1 + 63) / 64;
-    a.gy = (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT);
-    const dim3 grid(a.gx * a.gy * ((a.nfields + a.nsh - 1) / a.nsh));
-    hipLaunchKernelGGL(stencil_kernel<double>, grid, dim3(256), 0, p->stream, a);
-    return hipGetLastError();
-}
-
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq) {
     if (p->prec == LG_FP64) return stencil_T<double>(p, (const double*)x, (double*)y, reduce_pq);
     return stencil_T<float>(p, (const float*)x, (float*)y, reduce_pq);
@@ -1178,12 +1194,16 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         a.x = x;
         a.tol2 = tol * tol;
         a.max_iter = max_iter;
-        e = (p->fuse_op && init == 0) ? dst_dispatch<float, DST_UPDATE_OP>(p, a, p->S * p->C)
-                                      : dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
+        if (init == 3)
+            e = dst_dispatch<float, DST_RESTART>(p, a, p->S * p->C);
+        else if (p->fuse_op && init == 0)
+            e = dst_dispatch<float, DST_UPDATE_OP>(p, a, p->S * p->C);
+        else
+            e = dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;
-    return finalize(p, FIN_RR, bpf, init, tol * tol, max_iter, 0.0);
+    return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, tol * tol, max_iter, 0.0);
 }
 
 hipError_t launch_correct_idst(lg_plan* p, int init) {
