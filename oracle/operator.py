@@ -13,6 +13,12 @@ that it is symmetric positive definite (the paper's ``A = A* > 0``)::
 
 Face coefficients are the arithmetic mean of the two node values of kappa,
 ``y`` is zero on every boundary node, unknowns are the interior nodes.
+
+Free surface (``free_top=True``): the paper's condition du/dz = 0 at z = 0
+(Sec. 2.1, eq. boundary_cond), in the form its staggered mesh gives it
+(Sec. 2.3: the first unknown lies half a cell below the surface): no flux
+crosses the face above the first unknown row, i.e. that face coefficient is
+zero.  The other three sides stay Dirichlet.
 """
 from __future__ import annotations
 
@@ -24,7 +30,8 @@ def shift_coeff(rho: np.ndarray, h: float) -> np.ndarray:
     return rho[1:-1, 1:-1] * (h * h / 4.0)
 
 
-def apply_A(y: np.ndarray, kappa: np.ndarray, w: np.ndarray, dx: float, dz: float) -> np.ndarray:
+def apply_A(y: np.ndarray, kappa: np.ndarray, w: np.ndarray, dx: float, dz: float,
+            free_top: bool = False) -> np.ndarray:
     """``A y`` for interior values ``y`` of shape ``(Nz-1, Nx-1)`` (or a leading
     batch axis).  ``kappa`` is the node array ``(Nz+1, Nx+1)``, ``w`` interior."""
     y = np.asarray(y, dtype=np.float64)
@@ -32,13 +39,16 @@ def apply_A(y: np.ndarray, kappa: np.ndarray, w: np.ndarray, dx: float, dz: floa
     Y = np.pad(y, pad)                       # zero Dirichlet ring
     kx = 0.5 * (kappa[1:-1, :-1] + kappa[1:-1, 1:])   # faces i+1/2, rows 1..Nz-1
     kz = 0.5 * (kappa[:-1, 1:-1] + kappa[1:, 1:-1])   # faces j+1/2, cols 1..Nx-1
+    if free_top:
+        kz = kz.copy()
+        kz[0, :] = 0.0                                # no flux through the surface face
     c = Y[..., 1:-1, 1:-1]
     ax = (kx[:, 1:] * (c - Y[..., 1:-1, 2:]) + kx[:, :-1] * (c - Y[..., 1:-1, :-2])) / (dx * dx)
     az = (kz[1:, :] * (c - Y[..., 2:, 1:-1]) + kz[:-1, :] * (c - Y[..., :-2, 1:-1])) / (dz * dz)
     return ax + az + w * c
 
 
-def assemble_A(kappa: np.ndarray, w: np.ndarray, dx: float, dz: float) -> np.ndarray:
+def assemble_A(kappa: np.ndarray, w: np.ndarray, dx: float, dz: float, free_top: bool = False) -> np.ndarray:
     """Dense matrix of A by explicit loops over the stencil (small grids only).
 
     Written independently of :func:`apply_A` so that the two can check each
@@ -55,6 +65,8 @@ def assemble_A(kappa: np.ndarray, w: np.ndarray, dx: float, dz: float) -> np.nda
             kW = 0.5 * (kappa[J, I] + kappa[J, I - 1])
             kS = 0.5 * (kappa[J, I] + kappa[J + 1, I])
             kN = 0.5 * (kappa[J, I] + kappa[J - 1, I])
+            if free_top and j == 0:
+                kN = 0.0
             M[row, row] = (kE + kW) / dx ** 2 + (kS + kN) / dz ** 2 + w[j, i]
             if i + 1 < nx1:
                 M[row, row + 1] = -kE / dx ** 2

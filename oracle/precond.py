@@ -76,7 +76,9 @@ class Laplace:
     the elastic blocks use different x and z coefficients (eq. precond2).
     """
 
-    def __init__(self, nx: int, nz: int, dx: float, dz: float, kx: float, kz: float, d: float):
+    def __init__(self, nx: int, nz: int, dx: float, dz: float, kx: float, kz: float, d: float,
+                 free_top: bool = False):
+        self.free_top = bool(free_top)
         self.nx, self.nz, self.dx, self.dz = nx, nz, dx, dz
         self.kx, self.kz, self.d = float(kx), float(kz), float(d)
         k = np.arange(1, nx)
@@ -91,6 +93,9 @@ class Laplace:
         lower = np.full(nz1, self.off)[:, None]
         upper = lower
         diag = np.broadcast_to(self.diag[None, :], (nz1, self.nx - 1))
+        if self.free_top:                       # no z-flux above the first row
+            diag = diag.copy()
+            diag[0, :] -= self.kz / self.dz ** 2
         if rhat.ndim == 2:
             return thomas(lower, diag, upper, rhat)
         return np.stack([thomas(lower, diag, upper, r) for r in rhat])
@@ -106,13 +111,16 @@ class Laplace:
         pad = [(0, 0)] * (y.ndim - 2) + [(1, 1), (1, 1)]
         Y = np.pad(y, pad)
         c = Y[..., 1:-1, 1:-1]
+        if self.free_top:                       # mirror row: the top face carries no flux
+            Y[..., 0, 1:-1] = Y[..., 1, 1:-1]
         dxx = (Y[..., 1:-1, 2:] - 2 * c + Y[..., 1:-1, :-2]) / self.dx ** 2
         dzz = (Y[..., 2:, 1:-1] - 2 * c + Y[..., :-2, 1:-1]) / self.dz ** 2
         return -self.kx * dxx - self.kz * dzz + self.d * c
 
 
 def acoustic_preconditioner(kappa: np.ndarray, rho: np.ndarray, h: float,
-                            nx: int, nz: int, dx: float, dz: float) -> Laplace:
-    """B of eq. precond1: ``kappa~`` on both axes and ``d = rho~ h^2/4``."""
+                            nx: int, nz: int, dx: float, dz: float, free_top: bool = False) -> Laplace:
+    """B of eq. precond1: ``kappa~`` on both axes and ``d = rho~ h^2/4``; with
+    a free surface B keeps the operator's flux-free top face."""
     kt, rt = midrange(kappa), midrange(rho)
-    return Laplace(nx, nz, dx, dz, kt, kt, rt * h * h / 4.0)
+    return Laplace(nx, nz, dx, dz, kt, kt, rt * h * h / 4.0, free_top=free_top)

@@ -402,3 +402,74 @@ def test_elastic_block_preconditioner_is_diagonal_block_in_homogeneous_medium():
     cz = elastic.apply_C(np.stack([z, u]), lam, mu, w, d, d)[1]
     assert np.max(np.abs(B1.apply(u) - cx)) < 1e-12 * np.max(np.abs(cx))
     assert np.max(np.abs(B2.apply(u) - cz)) < 1e-12 * np.max(np.abs(cz))
+
+
+# ---------------------------------------------------------------------------
+# Free surface (Sec. 2.1, eq. boundary_cond: du/dz = 0 at z = 0)
+# ---------------------------------------------------------------------------
+
+def test_free_surface_operator_dense_symmetric_positive():
+    nx, nz, dx, dz, h = 10, 9, 4.0, 6.0, 300.0
+    kappa, rho = _small_medium(nx, nz)
+    w = operator.shift_coeff(rho, h)
+    M = operator.assemble_A(kappa, w, dx, dz, free_top=True)
+    y = np.random.default_rng(31).standard_normal((nz - 1, nx - 1))
+    Ay = operator.apply_A(y, kappa, w, dx, dz, free_top=True)
+    assert np.max(np.abs(M @ y.ravel() - Ay.ravel())) < 1e-13 * np.max(np.abs(Ay))
+    assert np.allclose(M, M.T, rtol=0, atol=1e-15 * np.max(np.abs(M)))
+    assert np.linalg.eigvalsh(M).min() > 0
+    # only the first row's north face differs from the Dirichlet operator
+    D = operator.assemble_A(kappa, w, dx, dz) - M
+    kN = 0.5 * (kappa[1, 1:-1] + kappa[0, 1:-1]) / dz ** 2
+    assert np.allclose(np.diag(D)[: nx - 1], kN, rtol=1e-14, atol=0)
+    assert np.max(np.abs(np.diag(D)[nx - 1:])) == 0 and np.max(np.abs(D - np.diag(np.diag(D)))) == 0
+
+
+def test_free_surface_equals_mirrored_dirichlet_problem():
+    """Method of images: the free-surface solution equals the upper-half-
+    mirrored Dirichlet problem (medium and source reflected about the surface
+    face) restricted to the original rows.  The doubled problem is solved by a
+    dense solve of the independently assembled Dirichlet operator."""
+    nx, nz, dx, dz, h = 12, 10, 5.0, 5.0, 250.0
+    kappa, rho = _small_medium(nx, nz)
+    nz1 = nz - 1
+    k2 = np.concatenate([kappa[nz:0:-1], kappa[1:]])       # node rows of the doubled domain
+    r2 = np.concatenate([rho[nz:0:-1], rho[1:]])
+    assert k2.shape[0] == 2 * nz
+    b = np.zeros((nz1, nx - 1))
+    b[2, 5] = 1.0
+    b[6, 3] = -0.5
+    b2 = np.concatenate([b[::-1], b])                      # mirrored sources, same sign
+    M2 = operator.assemble_A(k2, operator.shift_coeff(r2, h), dx, dz)
+    u2 = np.linalg.solve(M2, b2.ravel()).reshape(2 * nz1, nx - 1)
+    w = operator.shift_coeff(rho, h)
+    B = precond.acoustic_preconditioner(kappa, rho, h, nx, nz, dx, dz, free_top=True)
+    x, it, rr, st = krylov.pcg(lambda y: operator.apply_A(y, kappa, w, dx, dz, free_top=True), B.solve,
+                               b, 1e-14, 500)
+    assert st == OK
+    assert np.max(np.abs(x - u2[nz1:])) < 1e-12 * np.max(np.abs(u2))
+    assert np.max(np.abs(u2[nz1:] - u2[:nz1][::-1])) < 1e-12 * np.max(np.abs(u2))
+
+
+def test_free_surface_laplace_inverse_and_one_iteration():
+    nx, nz, dx, dz, h = 16, 8, 4.0, 6.0, 300.0
+    B = precond.Laplace(nx, nz, dx, dz, 1.7, 1.7, 0.3, free_top=True)
+    n = (nx - 1) * (nz - 1)
+    M = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n); e[c] = 1
+        M[:, c] = B.apply(e.reshape(nz - 1, nx - 1)).ravel()
+    # B.apply is the constant-medium free-surface operator
+    Ma = operator.assemble_A(np.full((nz + 1, nx + 1), 1.7), np.full((nz - 1, nx - 1), 0.3), dx, dz,
+                             free_top=True)
+    assert np.max(np.abs(M - Ma)) < 1e-13 * np.max(np.abs(Ma))
+    r = np.random.default_rng(33).standard_normal((nz - 1, nx - 1))
+    assert np.max(np.abs(B.solve(r).ravel() - np.linalg.solve(M, r.ravel()))) < 1e-12
+    # constant medium: B = A, so PCG converges in one iteration
+    kappa = np.full((nz + 1, nx + 1), 1.0)
+    rho = np.full((nz + 1, nx + 1), 1.0 / 2200.0 ** 2)
+    w = operator.shift_coeff(rho, h)
+    Bc = precond.acoustic_preconditioner(kappa, rho, h, nx, nz, dx, dz, free_top=True)
+    x, it, rr, st = krylov.pcg(lambda y: operator.apply_A(y, kappa, w, dx, dz, free_top=True), Bc.solve,
+                               r, 1e-10, 50)
+    assert st == OK and it == 1 and rr < 1e-13
