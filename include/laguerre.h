@@ -64,8 +64,17 @@ typedef enum { LG_FP64 = 0, LG_MIXED = 1 } lg_precision;
 typedef enum { LG_ACOUSTIC = 0, LG_ELASTIC = 1 } lg_kind;
 typedef enum { LG_RICKER = 0, LG_GAUSS_SINE = 1 } lg_wavelet;
 
-/* Grid: nx, nz cells (powers of two, 2..4096), spacings dx, dz > 0 (metres). */
-typedef struct { int32_t nx, nz; double dx, dz; } lg_grid;
+/* Boundary at z = 0 (the top).  LG_TOP_DIRICHLET: zero values on the top
+ * node row, like the other three sides.  LG_TOP_FREE: the free surface
+ * du/dz = 0 at z = 0 of Sec. 2.1 (eq. boundary_cond), in the form of the
+ * paper's staggered mesh (Sec. 2.3), where the first unknown lies half a cell
+ * below the surface: no flux crosses the face above the first unknown row
+ * (acoustic plans only).  The preconditioner keeps the same face. */
+typedef enum { LG_TOP_DIRICHLET = 0, LG_TOP_FREE = 1 } lg_top_bc;
+
+/* Grid: nx, nz cells (powers of two, 2..4096), spacings dx, dz > 0 (metres),
+ * top boundary (lg_top_bc). */
+typedef struct { int32_t nx, nz; double dx, dz; int32_t top_bc; int32_t reserved; } lg_grid;
 
 /* Laguerre transform (Sec. 2.1): order alpha >= 2, scale h > 0 (1/s), n >= 1
  * harmonics. */

@@ -59,7 +59,7 @@ class Plan:
     def __init__(self, kind: str, nx: int, nz: int, dx: float, dz: float, alpha: int, h: float,
                  n: int, medium: np.ndarray, precision: str = "fp64", nshots: int = 1,
                  segments: int = 0, graph_iters: int = 0, op_shots: int = 0, seg_per_wave: int = 0,
-                 op_fusion: int = 0,
+                 op_fusion: int = 0, top: str = "dirichlet",
                  stream=None):
         import torch
         self.lib = _lib.load()
@@ -69,7 +69,10 @@ class Plan:
         self.precision = precision
         self.wdtype = torch.float64 if precision == "fp64" else torch.float32
         med = np.ascontiguousarray(np.asarray(medium, dtype=np.float64))
-        grid = _lib.Grid(nx, nz, dx, dz)
+        if top not in ("dirichlet", "free"):
+            raise ValueError("top must be 'dirichlet' or 'free'")
+        self.top = top
+        grid = _lib.Grid(nx, nz, dx, dz, _lib.LG_TOP_FREE if top == "free" else _lib.LG_TOP_DIRICHLET, 0)
         lag = _lib.Laguerre(alpha, h, n)
         tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion)
         if stream is None:

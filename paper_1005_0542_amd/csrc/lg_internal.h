@@ -78,6 +78,13 @@ struct lg_plan {
     int op_shots = 8;          // operator kernel: shots per block
     int td_spw = 0;            // Dichotomy segments per wave (0: automatic)
     bool fuse_op = true;       // CG update recomputes A p (no stored q)
+    // Free surface (top face flux-free): the z-systems become T - e1 e1^T,
+    // solved as the Dirichlet Dichotomy result plus a rank-one
+    // (Sherman-Morrison) term coef_k g_k with g_k = T_k^{-1} e1.
+    bool free_top = false;
+    void* sm_g = nullptr;      // [nz-1][nx-1] working type: g_k(j)
+    double* sm_t = nullptr;    // [2][nx-1]: 1 / (1 - g_k(0)), u_{Ls-1}(k)
+    double* sm_c = nullptr;    // [fields][nx-1]: coef_k of the current solve
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture

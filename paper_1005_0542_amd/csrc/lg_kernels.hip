@@ -45,6 +45,7 @@ struct StArgs {
     T idx2, idz2;
     int nfields, nsh;    // fields, fields per block (shot chunks)
     int gx, gy;          // column tiles, row strips (1D grid of gx*gy*chunks blocks)
+    int free_top;        // free surface: no flux through the face above row 0
     // CG reduction (ctl == nullptr: plain operator application)
     ShotCtl* ctl;
     double* partial;
@@ -126,7 +127,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
         T v[ST_RPT];
 #pragma unroll
         for (int r = 0; r < ST_RPT; ++r) {
-            const T fS = half * (kc[r + 1] + kc[r + 2]), fN = half * (kc[r + 1] + kc[r]);
+            const T fS = half * (kc[r + 1] + kc[r + 2]);
+            const T fN = (a.free_top && j0 + r == 0) ? (T)0 : half * (kc[r + 1] + kc[r]);
             const T c = pv[r + 1];                  // 0 outside the grid, so no dot term
             v[r] = stencil_point(c, pe[r], pw[r], pv[r + 2], pv[r], fE[r], fW[r], fS, fN, wv[r],
                                  a.idx2, a.idz2);
@@ -186,6 +188,9 @@ struct DstArgs {
     const double* kap64;   // RESTART: FP64 node kappa and shift
     const double* w64;
     double idx2d, idz2d;
+    int free_top;          // free surface (operator face; CORRECT: rank-one term)
+    const T* smg;          // CORRECT (free surface): g_k rows
+    const double* smc;     // CORRECT (free surface): coef_k per field
     double* partial;
     size_t pstride;
     double tol2;           // tol^2 (init)
@@ -205,7 +210,7 @@ struct DstArgs {
 template <typename T>
 __device__ __forceinline__ void apply_pair(rsrc_t rP, const T* __restrict__ kap, const T* __restrict__ wsh,
                                            int nx1, int nz1, int i, int j0, bool ok0, bool ok1, T c0, T c1,
-                                           T idx2, T idz2, T& q0, T& q1) {
+                                           T idx2, T idz2, bool free_top, T& q0, T& q1) {
     constexpr uint32_t SZ = sizeof(T);
     const int NXN = nx1 + 2, I = i + 1, J0 = j0 + 1;
     const uint32_t e = (uint32_t)(j0 * nx1 + i);
@@ -222,8 +227,9 @@ __device__ __forceinline__ void apply_pair(rsrc_t rP, const T* __restrict__ kap,
     const T* k1 = kap + (size_t)min(J0 + 1, nz1) * NXN + I;   // second row (clamped)
     const T k1E = k1[1], k1W = k1[-1], k1S = k1[NXN];
     const int j1c = min(j0 + 1, nz1 - 1);
+    const T fN0 = (free_top && j0 == 0) ? (T)0 : half * (k00 + k0N);   // free surface: no flux above row 0
     q0 = stencil_point(c0, p0E, p0W, c1, pN0, half * (k00 + k0E), half * (k00 + k0W), half * (k00 + k10),
-                       half * (k00 + k0N), wsh[(size_t)j0 * nx1 + i], idx2, idz2);
+                       fN0, wsh[(size_t)j0 * nx1 + i], idx2, idz2);
     const T v1 = stencil_point(c1, p1E, p1W, pS1, c0, half * (k10 + k1E), half * (k10 + k1W),
                                half * (k10 + k1S), half * (k10 + k00), wsh[(size_t)j1c * nx1 + i], idx2, idz2);
     q1 = ok1 ? v1 : (T)0;
@@ -308,7 +314,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     b0[u] = bload<double>(rB, e0[u] * 8u);
                     b1[u] = bload<double>(rB, e1[u] * 8u);
                     apply_pair<double>(rX, a.kap64, a.w64, NX1, a.nz1, min(i, NX1 - 1), j0, in, in && has1,
-                                       x0[u], x1[u], a.idx2d, a.idz2d, q0[u], q1[u]);
+                                       x0[u], x1[u], a.idx2d, a.idz2d, a.free_top != 0, q0[u], q1[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < CR; ++u) {
@@ -362,7 +368,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     p1[u] = bload<T>(rP, e1[u] * SZ);
                     if constexpr (MODE == DST_UPDATE_OP) {
                         apply_pair<T>(rP, a.kap, a.wsh, NX1, a.nz1, min(i, NX1 - 1), j0, in, in && has1, p0[u],
-                                      p1[u], a.idx2, a.idz2, q0[u], q1[u]);
+                                      p1[u], a.idx2, a.idz2, a.free_top != 0, q0[u], q1[u]);
                     } else {
                         q0[u] = bload<T>(rQ, e0[u] * SZ);
                         q1[u] = bload<T>(rQ, e1[u] * SZ);
@@ -424,14 +430,36 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     ua1[u] = bload<T>(rU, off(ua1r));
                     ub1[u] = bload<T>(rU, off(ub1r));
                 }
+                T v0[CH], v1[CH];
+#pragma unroll
+                for (int u = 0; u < CH; ++u) {
+                    v0[u] = c0 ? yv0[u] + xl0[u] * ua0[u] + xr0[u] * ub0[u] : yv0[u];
+                    v1[u] = c1 ? yv1[u] + xl1[u] * ua1[u] + xr1[u] * ub1[u] : yv1[u];
+                }
+                if (a.free_top) {                  // + coef_k g_k(j): the free-surface rank-one term
+                    const rsrc_t rG = buf_rsrc(a.smg, nfe * SZ);
+                    const rsrc_t rC = buf_rsrc(a.smc + (size_t)field * NX1, (uint32_t)NX1 * 8u);
+                    T cf[CH], g0[CH], g1[CH];
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        const int i = t + (cb + u) * TPF;
+                        const bool in = (cb + u < NIT) && i < NX1;
+                        cf[u] = (T)bload<double>(rC, in ? (uint32_t)i * 8u : BUF_OOB);
+                        g0[u] = bload<T>(rG, in ? (uint32_t)(j0 * NX1 + i) * SZ : BUF_OOB);
+                        g1[u] = bload<T>(rG, (in && has1) ? (uint32_t)(j1 * NX1 + i) * SZ : BUF_OOB);
+                    }
+#pragma unroll
+                    for (int u = 0; u < CH; ++u) {
+                        v0[u] += cf[u] * g0[u];
+                        v1[u] += cf[u] * g1[u];
+                    }
+                }
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     const int i = t + (cb + u) * TPF;
                     if (cb + u < NIT && i < NX1) {
-                        const T v0 = c0 ? yv0[u] + xl0[u] * ua0[u] + xr0[u] * ub0[u] : yv0[u];
-                        const T v1 = c1 ? yv1[u] + xl1[u] * ua1[u] + xr1[u] * ub1[u] : yv1[u];
-                        buf[lpad(1 + i)] = {v0, v1};
-                        buf[lpad(M - 1 - i)] = {-v0, -v1};
+                        buf[lpad(1 + i)] = {v0[u], v1[u]};
+                        buf[lpad(M - 1 - i)] = {-v0[u], -v1[u]};
                     }
                 }
             }
@@ -629,6 +657,9 @@ struct RsArgs {
     ShotCtl* ctl;
     double* partial;
     size_t pstride;
+    int free_top;          // free surface: form coef_k of the rank-one term
+    const double* smt;     // 1 / (1 - g_k(0))
+    double* smc;           // out: coef_k per field
 };
 
 // One block per (KT consecutive wavenumbers, field).  Phase 1 loads, with
@@ -715,6 +746,17 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
         if (sepl) {
             c += x * G;
             Gs[sig * KS + kk] = x;
+        }
+        if (a.free_top && sig == 0) {
+            // first row of the Dirichlet solution: zhat_0 = y_0 + x_0 u_{Ls-1}
+            // (u_{Ls-1} = Br; x = 0 when there is no separator); the rank-one
+            // term adds coef g with coef = zhat_0 / (1 - g_0), and
+            // (rhat, g) = b zhat_0 adds coef zhat_0 to (rhat, zhat) / b
+            const int kg = k0 + kk;
+            const double zh0 = bload<double>(rE, (uint32_t)kg * 8u) + x * tab[1];
+            const double cf = zh0 * a.smt[kg];
+            a.smc[(size_t)field * nx1 + kg] = cf;
+            c += cf * zh0;
         }
     }
     __syncthreads();
@@ -837,9 +879,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
 // Standalone interface correction (the CG path fuses it into K5):
 // zhat = y + xl u_i + xr u_{Ls-i} on segment rows, in place.
 template <typename T>
+// phase 0: segment rows (the separator rows are read, not written); with a
+// free surface (smg != nullptr) also + coef_k g_k(j).  phase 1 (free surface
+// only, after phase 0): the separator rows' rank-one term.
 __global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, int nx1, int nz1,
                                                       int Ls, int P, size_t total, int fstride,
-                                                      int foff) {
+                                                      int foff, const T* smg, const double* smc, int phase) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
     const size_t npts = (size_t)nx1 * nz1;
@@ -848,12 +893,17 @@ __global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, int n
     const int j = (int)(pt / nx1), k = (int)(pt - (size_t)j * nx1);
     const int jj = j + 1;
     const int rs = jj & (Ls - 1);
+    T* Y = y + f * npts;
+    const T sm = (smg != nullptr) ? (T)smc[f * nx1 + k] * smg[pt] : (T)0;
+    if (phase == 1) {
+        if (rs == 0) Y[pt] = Y[pt] + sm;
+        return;
+    }
     if (rs == 0) return;
     const int s = jj / Ls;
-    T* Y = y + f * npts;
     const T xl = (s > 0) ? Y[(size_t)(s * Ls - 1) * nx1 + k] : (T)0;
     const T xr = (s < P - 1) ? Y[(size_t)((s + 1) * Ls - 1) * nx1 + k] : (T)0;
-    Y[pt] = Y[pt] + xl * utab[(size_t)rs * nx1 + k] + xr * utab[(size_t)(Ls - rs) * nx1 + k];
+    Y[pt] = Y[pt] + xl * utab[(size_t)rs * nx1 + k] + xr * utab[(size_t)(Ls - rs) * nx1 + k] + sm;
 }
 
 // ===========================================================================
@@ -983,6 +1033,7 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
     a.ctl = reduce ? p->ctl : nullptr;
+    a.free_top = p->free_top ? 1 : 0;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
     a.nfields = p->S * p->C;
@@ -1044,8 +1095,11 @@ DstArgs<T> dst_args(lg_plan* p) {
     a.wsh = (const T*)p->w;
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
-    a.kap64 = p->kap64;
-    a.w64 = p->w64;
+    a.kap64 = (p->prec == LG_FP64) ? (const double*)p->kap : p->kap64;
+    a.w64 = (p->prec == LG_FP64) ? (const double*)p->w : p->w64;
+    a.free_top = p->free_top ? 1 : 0;
+    a.smg = (const T*)p->sm_g;
+    a.smc = p->sm_c;
     a.idx2d = 1.0 / (p->g.dx * p->g.dx);
     a.idz2d = 1.0 / (p->g.dz * p->g.dz);
     a.utab = (const T*)p->blk[0].utab;
@@ -1123,6 +1177,9 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, 
     a.ctl = p->ctl;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
+    a.free_top = (p->free_top && bi == 0) ? 1 : 0;
+    a.smt = p->sm_t;
+    a.smc = p->sm_c;
     // 64 wavenumbers per block when the grid stays large (32 when the LDS
     // tables would pass 48 KB), else 16 (more blocks)
     auto lds_bytes = [&](int kt) {
@@ -1237,13 +1294,20 @@ hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride
     const PrecBlock& B = p->blk[blk];
     const size_t total = (size_t)nfields * p->npts;
     const dim3 grid((unsigned)((total + 255) / 256));
-    if (p->prec == LG_FP64)
-        hipLaunchKernelGGL(correct_kernel<double>, grid, dim3(256), 0, p->stream, (double*)y,
-                           (const double*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff);
-    else
-        hipLaunchKernelGGL(correct_kernel<float>, grid, dim3(256), 0, p->stream, (float*)y,
-                           (const float*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff);
-    return hipGetLastError();
+    const bool sm = p->free_top && blk == 0;
+    for (int phase = 0; phase < (sm ? 2 : 1); ++phase) {
+        if (p->prec == LG_FP64)
+            hipLaunchKernelGGL(correct_kernel<double>, grid, dim3(256), 0, p->stream, (double*)y,
+                               (const double*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff,
+                               sm ? (const double*)p->sm_g : nullptr, p->sm_c, phase);
+        else
+            hipLaunchKernelGGL(correct_kernel<float>, grid, dim3(256), 0, p->stream, (float*)y,
+                               (const float*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff,
+                               sm ? (const float*)p->sm_g : nullptr, p->sm_c, phase);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,

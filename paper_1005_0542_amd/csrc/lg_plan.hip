@@ -91,6 +91,34 @@ void toeplitz_unit_solve(long double diag, long double c, int n, int col, std::v
     for (int i = n - 2; i >= 0; --i) x[i] = dp[i] - cp[i] * x[i + 1];
 }
 
+// Free-surface tables: per wavenumber, the normalised Dirichlet z-system is
+// T_k = tridiag(-1, theta_k, -1) of size nz-1 and the flux-free top face
+// makes it T_k - e1 e1^T.  Sherman-Morrison: (T - e1 e1^T)^{-1} r =
+// T^{-1} r + g (e1^T T^{-1} r) / (1 - g_0), g = T^{-1} e1.  g (all rows) and
+// 1 / (1 - g_0) are prepared here in long double.
+lg_status prepare_free_surface(lg_plan* pl, const PrecBlock& B) {
+    const int nx = pl->g.nx, nx1 = pl->nx1, nz1 = pl->nz1;
+    const long double dx = pl->g.dx, dz = pl->g.dz;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double> g((size_t)nz1 * nx1), t(nx1);
+    std::vector<long double> col;
+    for (int kk = 0; kk < nx1; ++kk) {
+        const long double s = std::sin(pi * (kk + 1) / (2.0L * nx));
+        const long double mu = 4.0L / (dx * dx) * s * s;
+        const long double diag = 2.0L * B.kz / (dz * dz) + (long double)B.kx * mu + (long double)B.d;
+        const long double theta = diag / ((long double)B.kz / (dz * dz));
+        toeplitz_unit_solve(theta, 1.0L, nz1, 0, col);
+        for (int j = 0; j < nz1; ++j) g[(size_t)j * nx1 + kk] = (double)col[j];
+        t[kk] = (double)(1.0L / (1.0L - col[0]));
+    }
+    lg_status st = upload_working(pl, &pl->sm_g, g);
+    if (st != LG_OK) return st;
+    st = dev_alloc(pl, &pl->sm_t, (size_t)nx1 * 8);
+    if (st != LG_OK) return st;
+    LG_HIP(hipMemcpy(pl->sm_t, t.data(), (size_t)nx1 * 8, hipMemcpyHostToDevice));
+    return dev_alloc(pl, &pl->sm_c, (size_t)pl->S * pl->C * nx1 * 8);
+}
+
 // Prepare the Dichotomy tables of one preconditioner block (done once).
 lg_status prepare_block(lg_plan* pl, PrecBlock& B, double kx, double kz, double d, int P) {
     const int nx = pl->g.nx, nz = pl->g.nz, nx1 = pl->nx1;
@@ -164,7 +192,8 @@ void free_plan(lg_plan* p) {
     void* ptrs[] = {p->kap, p->lam, p->mu, p->w, p->rho64, p->kap64, p->w64, p->tw, p->src_dev, p->r, p->p, p->qv,
                     p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
-                    p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red};
+                    p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
+                    p->sm_c};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -311,6 +340,10 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (nshots < 1) return fail(LG_ERR_INVALID_ARG, "nshots must be >= 1");
     if (!is_pow2(grid->nx) || !is_pow2(grid->nz) || grid->nx > 4096 || grid->nz > 4096)
         return fail(LG_ERR_UNSUPPORTED, "nx and nz must be powers of two <= 4096");
+    if (grid->top_bc != LG_TOP_DIRICHLET && grid->top_bc != LG_TOP_FREE)
+        return fail(LG_ERR_INVALID_ARG, "top_bc must be LG_TOP_DIRICHLET or LG_TOP_FREE");
+    if (grid->top_bc == LG_TOP_FREE && kind != LG_ACOUSTIC)
+        return fail(LG_ERR_UNSUPPORTED, "the free surface is implemented for acoustic plans");
     int P = 0, gi = 8, osh = 8, spw = 0, fus = 1;
     if (tuning != nullptr) {
         P = tuning->segments;
@@ -351,6 +384,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->op_shots = osh;
     p->td_spw = spw;
     p->fuse_op = (fus == 1);
+    p->free_top = (grid->top_bc == LG_TOP_FREE);
     p->device = dev;
     p->stream = (hipStream_t)hip_stream;
 
@@ -394,6 +428,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
                              "midrange kappa must be > 0 and midrange rho >= 0 (SPD preconditioner)"));
         if ((st = prepare_block(p, p->blk[0], p->kappa_t, p->kappa_t, p->rho_t * hh4, P)) != LG_OK)
             return bail(st);
+        if (p->free_top && (st = prepare_free_surface(p, p->blk[0])) != LG_OK) return bail(st);
     } else {
         const double* lam = medium_host;
         const double* mu = medium_host + nn;
@@ -620,7 +655,7 @@ lg_status lg_precond_dichotomy_tdma(lg_plan* plan, int32_t block, const void* rh
     LG_HIP(hipSetDevice(plan->device));
     const int nf = plan->S;   // acoustic: S fields; elastic: one component per shot
     LG_HIP(launch_td(plan, bi, rhs_hat, sol_hat, nf, 0));
-    if (plan->blk[bi].P > 1) {
+    if (plan->blk[bi].P > 1 || plan->free_top) {
         LG_HIP(launch_rs(plan, bi, rhs_hat, sol_hat, nf, 0));
         LG_HIP(launch_correct(plan, bi, sol_hat, nf));
     }
@@ -707,7 +742,7 @@ extern "C" lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z) {
     const int nf = plan->S;
     LG_HIP(launch_dst(plan, 0, r, plan->rhat, nf));
     LG_HIP(launch_td(plan, 0, plan->rhat, plan->y, nf, 0));
-    if (plan->blk[0].P > 1) {
+    if (plan->blk[0].P > 1 || plan->free_top) {
         LG_HIP(launch_rs(plan, 0, plan->rhat, plan->y, nf, 0));
         LG_HIP(launch_correct(plan, 0, plan->y, nf));
     }

@@ -24,7 +24,7 @@ class AcousticRun:
                  n_harm: Optional[int] = None, segments: int = 0, graph_iters: int = 0,
                  snapshots: bool = True, rec: bool = True, tol: Optional[float] = None,
                  max_iter: int = 10000, medium=None, op_shots: int = 0, seg_per_wave: int = 0,
-                 op_fusion: int = 0):
+                 op_fusion: int = 0, top: str = "dirichlet"):
         import torch
         self.torch = torch
         self.w = w
@@ -41,7 +41,7 @@ class AcousticRun:
         self.plan = api.Plan("acoustic", N, N, w.d, w.d, w.alpha, w.h, self.n_harm,
                              np.stack([kappa, rho]), precision=self.precision, nshots=self.shots,
                              segments=segments, graph_iters=graph_iters, op_shots=op_shots,
-                             seg_per_wave=seg_per_wave, op_fusion=op_fusion)
+                             seg_per_wave=seg_per_wave, op_fusion=op_fusion, top=top)
         if self.shots == w.shots:
             src = inputs.sources_for(w)
         else:
