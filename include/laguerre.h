@@ -81,8 +81,10 @@ typedef struct { int32_t nx, nz; double dx, dz; int32_t top_bc; int32_t reserved
 typedef struct { int32_t alpha; double h; int32_t n; } lg_laguerre;
 
 /* Krylov options: stop when ||r||_2 <= tol ||b||_2 (tol >= 0); max_iter >= 1
- * (CG iterations, or GMRES inner iterations); restart = GMRES k >= 1. */
-typedef struct { double tol; int32_t max_iter; int32_t restart; } lg_solve_opts;
+ * (CG iterations, or GMRES inner iterations); restart = GMRES k >= 1.
+ * x0_given (PCG only): 0 = start from x0 = 0; 1 = x holds the initial guess
+ * on entry (the previous harmonic, say). */
+typedef struct { double tol; int32_t max_iter; int32_t restart; int32_t x0_given; int32_t reserved; } lg_solve_opts;
 
 /* Per-shot solver report. */
 typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
@@ -204,15 +206,16 @@ lg_status lg_precond_dichotomy_tdma(lg_plan* plan, int32_t block, const void* rh
 lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z);
 
 /* Preconditioned CG (Sec. 2.3) for A x = b, every shot independently, from
- * x0 = 0, stopping per shot when ||r||_2 <= tol ||b||_2 on the recursively
- * updated residual.  A zero b gives x = 0, iters = 0.  Converged shots drop
- * out by masking.  b, x: FP64 vectors.  info_host: [S] (may be NULL).
- * Returns the worst per-shot status. */
+ * x0 = 0 (or from x on entry when opts->x0_given: r0 = b - A x0 in FP64, and
+ * 0 iterations when it already meets the tolerance), stopping per shot when
+ * ||r||_2 <= tol ||b||_2 on the recursively updated residual.  A zero b gives
+ * x = 0, iters = 0.  Converged shots drop out by masking.  b, x: FP64
+ * vectors.  info_host: [S] (may be NULL).  Returns the worst per-shot status. */
 lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve_opts* opts,
                        lg_solve_info* info_host);
 
 /* Right-preconditioned restarted GMRES(k) (Sec. 2.3) for the elastic C x = b,
- * K = diag(B1, B2) (eq. precond2), from x0 = 0; stops when the Givens
+ * K = diag(B1, B2) (eq. precond2), from x0 = 0 (x0_given must be 0); stops when the Givens
  * estimate of ||b - Cx|| <= tol ||b||.  b, x: FP64 vectors ([S][2][..]). */
 lg_status lg_gmres_solve(lg_plan* plan, const double* b, double* x, const lg_solve_opts* opts,
                          lg_solve_info* info_host);

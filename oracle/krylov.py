@@ -28,11 +28,13 @@ def _dot(a: np.ndarray, b: np.ndarray) -> float:
 
 
 def pcg(apply_A: Op, apply_Minv: Op, b: np.ndarray, tol: float,
-        max_iter: int) -> Tuple[np.ndarray, int, float, int]:
-    """Preconditioned CG from ``x0 = 0``.  Returns ``(x, iters, relres, status)``.
+        max_iter: int, x0: np.ndarray = None) -> Tuple[np.ndarray, int, float, int]:
+    """Preconditioned CG from ``x0`` (default 0).  Returns ``(x, iters, relres, status)``.
 
     ``iters`` counts operator applications; the residual is updated
-    recursively (``r -= alpha A p``) and tested right after each update.
+    recursively (``r -= alpha A p``) and tested right after each update.  A
+    given ``x0`` starts from ``r = b - A x0``, which is tested first (0
+    iterations when it already meets the tolerance); ``b = 0`` gives ``x = 0``.
     """
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b)
@@ -41,11 +43,20 @@ def pcg(apply_A: Op, apply_Minv: Op, b: np.ndarray, tol: float,
         return x, 0, float("nan"), NONFINITE
     if bnorm == 0.0:
         return x, 0, 0.0, OK
-    r = b.copy()
+    if x0 is None:
+        r = b.copy()
+        rnorm = bnorm
+    else:
+        x = np.array(x0, dtype=np.float64)
+        r = b - apply_A(x)
+        rnorm = math.sqrt(_dot(r, r))
+        if not math.isfinite(rnorm):
+            return x, 0, float("nan"), NONFINITE
+        if rnorm <= tol * bnorm:
+            return x, 0, rnorm / bnorm, OK
     z = apply_Minv(r)
     p = z.copy()
     rz = _dot(r, z)
-    rnorm = bnorm
     for it in range(1, max_iter + 1):
         q = apply_A(p)
         pq = _dot(p, q)

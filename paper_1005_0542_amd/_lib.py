@@ -36,7 +36,8 @@ class Laguerre(ctypes.Structure):
 
 
 class SolveOpts(ctypes.Structure):
-    _fields_ = [("tol", c_double), ("max_iter", c_int32), ("restart", c_int32)]
+    _fields_ = [("tol", c_double), ("max_iter", c_int32), ("restart", c_int32), ("x0_given", c_int32),
+                ("reserved", c_int32)]
 
 
 class SolveInfo(ctypes.Structure):

@@ -148,10 +148,10 @@ class Plan:
         check(self.lib.lg_precond_apply(self.handle, self._ptr(r, self.wdtype, "r", n),
                                         self._ptr(z, self.wdtype, "z", n)), "lg_precond_apply")
 
-    def _solve(self, fn, name, b, x, tol, max_iter, restart):
+    def _solve(self, fn, name, b, x, tol, max_iter, restart, x0_given=False):
         import torch
         n = self._nvec()
-        opts = _lib.SolveOpts(tol, max_iter, restart)
+        opts = _lib.SolveOpts(tol, max_iter, restart, 1 if x0_given else 0, 0)
         infos = (_lib.SolveInfo * self.nshots)()
         st = fn(self.handle, self._ptr(b, torch.float64, "b", n), self._ptr(x, torch.float64, "x", n),
                 ctypes.byref(opts), infos)
@@ -159,8 +159,9 @@ class Plan:
                                  _lib.LG_ERR_NONFINITE))
         return SolveResult(st, list(infos))
 
-    def pcg_solve(self, b, x, tol: float = 1e-10, max_iter: int = 10000) -> SolveResult:
-        return self._solve(self.lib.lg_pcg_solve, "lg_pcg_solve", b, x, tol, max_iter, 1)
+    def pcg_solve(self, b, x, tol: float = 1e-10, max_iter: int = 10000, x0_given: bool = False) -> SolveResult:
+        """x0_given: start from the values in x (otherwise from 0)."""
+        return self._solve(self.lib.lg_pcg_solve, "lg_pcg_solve", b, x, tol, max_iter, 1, x0_given)
 
     def gmres_solve(self, b, x, tol: float = 1e-10, max_iter: int = 10000, restart: int = 10) -> SolveResult:
         return self._solve(self.lib.lg_gmres_solve, "lg_gmres_solve", b, x, tol, max_iter, restart)

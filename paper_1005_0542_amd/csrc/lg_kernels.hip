@@ -281,7 +281,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     const size_t fbase = (size_t)field * a.nz1 * NX1;
     const size_t o0 = fbase + (size_t)j0 * NX1;
     const size_t o1 = fbase + (size_t)j1 * NX1;
-    double rr = 0.0;
+    double rr = 0.0, bb = 0.0;
     T pold0[MODE == DST_CORRECT ? NOUT : 1], pold1[MODE == DST_CORRECT ? NOUT : 1];
 
     // ---- phase A: gather the two rows into the odd extension (LDS) ---------
@@ -295,9 +295,11 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
         if constexpr (MODE == DST_RESTART) {
             // r = b - A x in FP64 with the operator kernel's arithmetic (bitwise
             // the separate true-residual pass), stored, then transformed in FP32
+            // init 4 (start from a given x) also forms ||b||^2
             const rsrc_t rX = buf_rsrc(a.x + fbase, nfe * 8u);
             const rsrc_t rB = buf_rsrc(a.b + fbase, nfe * 8u);
             const rsrc_t rRs = buf_rsrc(a.r + fbase, nfe * 8u);
+            if (a.init == 4 && blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
             constexpr int CR = NIT < 2 ? NIT : 2;
 #pragma unroll
             for (int cb = 0; cb < NIT; cb += CR) {
@@ -324,6 +326,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     bstore<double>(ra, rRs, e0[u] * 8u);
                     bstore<double>(rb, rRs, e1[u] * 8u);
                     rr += ra * ra + rb * rb;
+                    bb += b0[u] * b0[u] + b1[u] * b1[u];
                     if (cb + u < NIT && i < NX1) {
                         buf[lpad(1 + i)] = {(T)ra, (T)rb};
                         buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
@@ -542,6 +545,10 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
     if constexpr (UPD) {
         const double s = block_sum(rr, red);
         if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + bif] = s;
+        if (MODE == DST_RESTART && a.init == 4) {
+            const double sb = block_sum(bb, red);
+            if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + a.bpf + bif] = sb;
+        }
     }
 }
 
@@ -799,6 +806,12 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     const double* part = a.partial + (size_t)field * a.pstride;
     for (int i = threadIdx.x; i < a.nparts; i += blockDim.x) s += part[i];
     const double tot = block_sum(s, red);
+    double bbt = 0.0;                                        // FIN_RR init 4: ||b||^2 after the rr set
+    if (a.kind == FIN_RR && a.init == 4) {
+        double sb = 0.0;
+        for (int i = threadIdx.x; i < a.nparts; i += blockDim.x) sb += part[a.nparts + i];
+        bbt = block_sum(sb, red);
+    }
     if (threadIdx.x != 0) return;
     if (a.kind == FIN_PQ) {
         c.pq = tot;
@@ -813,8 +826,27 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         }
     } else if (a.kind == FIN_RR) {
         c.rr = tot;
-        if (a.init == 2) {                   // restart from the true residual
-            if (c.status != LG_OK) return;   // only shots that met the tolerance are re-checked
+        if (a.init == 4) {                   // start from a given x: r = b - A x, ||b||^2 second
+            c.bb = bbt;
+            c.tol2 = a.tol2 * bbt;
+            c.iters = 0;
+            c.max_iter = a.max_iter;
+            c.alpha = 0.0;
+            c.beta = 0.0;
+            if (!isfinite(tot) || !isfinite(bbt)) {
+                c.status = LG_ERR_NONFINITE;
+                c.active = 0;
+            } else if (bbt == 0.0 || tot <= c.tol2) {
+                c.status = LG_OK;            // b = 0: the host sets x = 0
+                c.active = 0;
+            } else {
+                c.status = LG_ERR_NOT_CONVERGED;
+                c.active = 1;
+            }
+        } else if (a.init == 2) {            // restart from the true residual
+            // only shots that met the tolerance are re-checked (b = 0 is final:
+            // its solution is 0, set by the host for a given x)
+            if (c.status != LG_OK || c.bb == 0.0) return;
             c.alpha = 0.0;
             c.beta = 0.0;
             if (!isfinite(tot)) {
@@ -1240,8 +1272,12 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         a.x = x;
         a.tol2 = tol * tol;
         a.max_iter = max_iter;
-        e = (p->fuse_op && init == 0) ? dst_dispatch<double, DST_UPDATE_OP>(p, a, p->S * p->C)
-                                      : dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
+        if (init >= 3)
+            e = dst_dispatch<double, DST_RESTART>(p, a, p->S * p->C);
+        else if (p->fuse_op && init == 0)
+            e = dst_dispatch<double, DST_UPDATE_OP>(p, a, p->S * p->C);
+        else
+            e = dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
         bpf = a.bpf;
     } else {
         DstArgs<float> a = dst_args<float>(p);
@@ -1251,7 +1287,7 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         a.x = x;
         a.tol2 = tol * tol;
         a.max_iter = max_iter;
-        if (init == 3)
+        if (init >= 3)
             e = dst_dispatch<float, DST_RESTART>(p, a, p->S * p->C);
         else if (p->fuse_op && init == 0)
             e = dst_dispatch<float, DST_UPDATE_OP>(p, a, p->S * p->C);
@@ -1260,7 +1296,7 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;
-    return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, tol * tol, max_iter, 0.0);
+    return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, tol * tol, max_iter, 0.0);   // init 4: given x
 }
 
 hipError_t launch_correct_idst(lg_plan* p, int init) {

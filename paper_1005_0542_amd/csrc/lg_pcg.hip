@@ -80,8 +80,9 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
         lg_status st = build_graph(p);
         if (st != LG_OK) return st;
     }
-    // start: x = 0, r = b, rhat = DST(b), z = B^{-1} r, p = z, rz = (r, z)
-    LG_HIP(launch_update_fdst(p, 1, b, x, o->tol, o->max_iter));
+    // start: x = 0, r = b (or, from a given x, r = b - A x in FP64), rhat = DST(r),
+    // z = B^{-1} r, p = z, rz = (r, z)
+    LG_HIP(launch_update_fdst(p, o->x0_given ? 4 : 1, b, x, o->tol, o->max_iter));
     LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
     LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
     LG_HIP(launch_correct_idst(p, 1));
@@ -133,6 +134,11 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
             st = iterate(launched);
             if (st != LG_OK) return st;
         }
+    }
+    if (o->x0_given) {                    // b = 0 from a given x: the solution is 0
+        for (int s = 0; s < nf; ++s)
+            if (p->ctl_host[s].bb == 0.0 && p->ctl_host[s].status == LG_OK)
+                LG_HIP(hipMemsetAsync(x + (size_t)s * p->npts, 0, p->npts * sizeof(double), p->stream));
     }
     int worst = LG_OK, maxit = 0;
     for (int s = 0; s < nf; ++s) {

@@ -479,7 +479,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         const size_t sb = (size_t)((p->nx1 + 63) / 64) * ((p->nz1 + 31) / 32);
         const size_t db = (size_t)dst_blocks_per_field(grid->nx, p->nz1);
         const size_t rb = (size_t)((p->nx1 + 15) / 16);
-        p->partial_stride = std::max(sb, std::max(db, rb));
+        // the transform kernel's start from a given x writes two partial sets
+        p->partial_stride = std::max(sb, std::max(2 * db, rb));
     }
     if ((st = dev_alloc(p, &p->partial, (size_t)SC * p->partial_stride * 8)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, &p->ctl, (size_t)SC * sizeof(ShotCtl))) != LG_OK) return bail(st);
@@ -708,6 +709,7 @@ lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve
     if (plan->kind != LG_ACOUSTIC) return fail(LG_ERR_INVALID_ARG, "PCG needs an acoustic plan");
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) return fail(LG_ERR_INVALID_ARG, "tol must be >= 0");
     if (opts->max_iter < 1) return fail(LG_ERR_INVALID_ARG, "max_iter must be >= 1");
+    if (opts->x0_given != 0 && opts->x0_given != 1) return fail(LG_ERR_INVALID_ARG, "x0_given must be 0 or 1");
     LG_HIP(hipSetDevice(plan->device));
     return lg::pcg_solve(plan, b, x, opts, info_host);
 }
@@ -723,6 +725,7 @@ lg_status lg_gmres_solve(lg_plan* plan, const double* b, double* x, const lg_sol
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) return fail(LG_ERR_INVALID_ARG, "tol must be >= 0");
     if (opts->max_iter < 1) return fail(LG_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (opts->restart < 1) return fail(LG_ERR_INVALID_ARG, "restart must be >= 1");
+    if (opts->x0_given != 0) return fail(LG_ERR_UNSUPPORTED, "GMRES starts from x0 = 0 (x0_given must be 0)");
     LG_HIP(hipSetDevice(plan->device));
     return lg::gmres_solve(plan, b, x, opts, info_host);
 }

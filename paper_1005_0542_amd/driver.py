@@ -24,7 +24,7 @@ class AcousticRun:
                  n_harm: Optional[int] = None, segments: int = 0, graph_iters: int = 0,
                  snapshots: bool = True, rec: bool = True, tol: Optional[float] = None,
                  max_iter: int = 10000, medium=None, op_shots: int = 0, seg_per_wave: int = 0,
-                 op_fusion: int = 0, top: str = "dirichlet"):
+                 op_fusion: int = 0, top: str = "dirichlet", warm_start: bool = False):
         import torch
         self.torch = torch
         self.w = w
@@ -35,6 +35,7 @@ class AcousticRun:
         if self.precision == "fp64" and tol is None:
             self.tol = min(self.tol, 1e-10)
         self.max_iter = max_iter
+        self.warm_start = warm_start      # start each solve from the previous harmonic
         N = w.n_cells
         kappa, rho = medium if medium is not None else inputs.acoustic_medium_for(w)
         self.kappa, self.rho = kappa, rho
@@ -70,7 +71,8 @@ class AcousticRun:
         m = self.m
         fs = np.full(self.shots, self.f_m[m])
         self.plan.laguerre_rhs(m, self.R if m else None, self.Ph, self.Qh, fs, self.rhs)
-        res = self.plan.pcg_solve(self.rhs, self.R, tol=self.tol, max_iter=self.max_iter)
+        res = self.plan.pcg_solve(self.rhs, self.R, tol=self.tol, max_iter=self.max_iter,
+                                  x0_given=self.warm_start and m > 0)
         if self.snap is not None or self.rec is not None:
             ws = self.W_snap[:, m] if self.snap is not None else []
             self.plan.laguerre_synthesize(m, self.R, ws, self.snap, self.w.rec_row, self.rec)

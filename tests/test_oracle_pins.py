@@ -473,3 +473,31 @@ def test_free_surface_laplace_inverse_and_one_iteration():
     x, it, rr, st = krylov.pcg(lambda y: operator.apply_A(y, kappa, w, dx, dz, free_top=True), Bc.solve,
                                r, 1e-10, 50)
     assert st == OK and it == 1 and rr < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# PCG from a given initial guess
+# ---------------------------------------------------------------------------
+
+def test_pcg_initial_guess():
+    nx, nz, dx, dz, h = 16, 16, 10.0, 10.0, 200.0
+    kappa, rho = _small_medium(nx, nz)
+    A, Minv, w = _acoustic_setup(nx, nz, kappa, rho, dx, dz, h)
+    b = np.random.default_rng(41).standard_normal((nz - 1, nx - 1))
+    M = operator.assemble_A(kappa, w, dx, dz)
+    xs = np.linalg.solve(M, b.ravel()).reshape(b.shape)
+    # x0 = 0 is the default path, bit for bit
+    x_a, it_a, _, _ = krylov.pcg(A, Minv, b, 1e-10, 500)
+    x_b, it_b, _, _ = krylov.pcg(A, Minv, b, 1e-10, 500, x0=np.zeros_like(b))
+    assert it_a == it_b and np.array_equal(x_a, x_b)
+    # the exact solution needs no iteration
+    x_c, it_c, rr_c, st_c = krylov.pcg(A, Minv, b, 1e-10, 500, x0=xs)
+    assert st_c == OK and it_c == 0 and np.array_equal(x_c, xs)
+    # any start converges to the dense solution
+    x0 = np.random.default_rng(42).standard_normal(b.shape)
+    x_d, it_d, rr_d, st_d = krylov.pcg(A, Minv, b, 1e-12, 500, x0=x0)
+    assert st_d == OK and it_d > 0
+    assert np.max(np.abs(x_d - xs)) < 1e-9 * np.max(np.abs(xs))
+    # b = 0 gives x = 0 whatever the start
+    x_e, it_e, _, st_e = krylov.pcg(A, Minv, np.zeros_like(b), 1e-10, 500, x0=x0)
+    assert st_e == OK and it_e == 0 and not x_e.any()
