@@ -126,7 +126,7 @@ def tuned_params(name, precision, shots, enabled=True):
 
 
 def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0, profile=True,
-                tuned=None, profile_iters=20):
+                tuned=None, profile_iters=20, top="dirichlet"):
     import torch
     from paper_1005_0542_amd import inputs
     from paper_1005_0542_amd.driver import AcousticRun
@@ -143,7 +143,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2),
                       segments=tuned.get("segments", 0), graph_iters=tuned.get("graph_iters", 0),
                       op_shots=tuned.get("op_shots", 0), seg_per_wave=tuned.get("seg_per_wave", 0),
-                      op_fusion=tuned.get("op_fusion", 0))
+                      op_fusion=tuned.get("op_fusion", 0), top=top)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     npts = (w.n_cells - 1) ** 2
@@ -159,7 +159,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     el = time.perf_counter() - t1
     pt_iters = float(npts) * float(np.sum(iters))
     out = {
-        "workload": name, "precision": precision, "shots": shots,
+        "workload": name, "precision": precision, "shots": shots, "top": top,
         "value": pt_iters / el / 1e6, "ms_per_step": 1e3 * el / steps,
         "iters_per_harmonic": [int(max(i)) for i in iters],
         "mean_iters": float(np.mean(iters)),
@@ -294,17 +294,19 @@ def main():
     variants = {}
     if not args.no_variants:
         plan = [
-            ("acoustic1024", "fp64", 1, "fp64_1shot_1024"),
-            ("acoustic4096_mixed", "fp64", 1, "fp64_1shot_4096"),
-            ("acoustic4096_mixed", "mixed", 1, "mixed_1shot_4096"),
-            ("acoustic2048x64_mixed", "fp64", 64, "fp64_64shot_2048"),
+            ("acoustic1024", "fp64", 1, "fp64_1shot_1024", "dirichlet"),
+            ("acoustic4096_mixed", "fp64", 1, "fp64_1shot_4096", "dirichlet"),
+            ("acoustic4096_mixed", "mixed", 1, "mixed_1shot_4096", "dirichlet"),
+            ("acoustic2048x64_mixed", "fp64", 64, "fp64_64shot_2048", "dirichlet"),
+            # the same batch with the free-surface top boundary (rank-one corrected Dichotomy)
+            ("acoustic2048x64_mixed", "mixed", 64, "mixed_64shot_2048_free_surface", "free"),
         ]
-        for name, prec, shots, key in plan:
+        for name, prec, shots, key, top in plan:
             v = run_variant(name, prec, shots, max(2, args.steps // 2), 1,
                             tuned=tuned_params(name, prec, shots, not args.no_tune),
-                            profile_iters=args.profile_iters)
+                            profile_iters=args.profile_iters, top=top)
             v.pop("_run")
-            variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "value", "ms_per_step",
+            variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "top", "value", "ms_per_step",
                                                "mean_iters", "whole_iteration_GBps", "dominant")}
             variants[key]["kernels_GBps"] = {k: round(x["GBps"], 1) for k, x in v["kernels"].items()}
             torch.cuda.empty_cache()
