@@ -103,3 +103,27 @@ def test_warm_started_harmonic_chain_fp64():
         assert sto == OK and res.iters[0] == ito, (m, res.iters, ito)
         assert rel(run.R.cpu().numpy()[0, 0], xo) < 1e-12
         Rp = xo
+
+
+def test_initial_guess_option_errors():
+    import ctypes
+    from paper_1005_0542_amd import _lib
+    torch = torch_cuda()
+    nx = nz = 16
+    kappa, rho = heterogeneous(nx, nz)
+    plan = acoustic_plan(nx, nz, 10.0, 10.0, kappa, rho)
+    b = torch.ones((1, 1, nz - 1, nx - 1), dtype=torch.float64, device="cuda")
+    x = torch.zeros_like(b)
+    lib = _lib.load()
+    opts = _lib.SolveOpts(1e-8, 100, 1, 2, 0)
+    log("x0_given = 2 rejected")
+    assert lib.lg_pcg_solve(plan.handle, ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                            ctypes.byref(opts), None) == _lib.LG_ERR_INVALID_ARG
+    lam = np.full((nz + 1, nx + 1), 2e9)
+    el = api.Plan("elastic", nx, nz, 5.0, 5.0, 8, 300.0, 4, np.stack([lam, lam / 2, np.full_like(lam, 2000.0)]))
+    b2 = torch.ones((1, 2, nz - 1, nx - 1), dtype=torch.float64, device="cuda")
+    x2 = torch.zeros_like(b2)
+    opts = _lib.SolveOpts(1e-8, 100, 10, 1, 0)
+    log("GMRES with a given x0 rejected")
+    assert lib.lg_gmres_solve(el.handle, ctypes.c_void_p(b2.data_ptr()), ctypes.c_void_p(x2.data_ptr()),
+                              ctypes.byref(opts), None) == _lib.LG_ERR_UNSUPPORTED
