@@ -194,6 +194,33 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     return out
 
 
+def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10):
+    """Elastic harmonics (GMRES(k) per harmonic) timed like the acoustic ones;
+    reported with the time of one GMRES(k) cycle (k inner iterations), the
+    unit of the paper's Table 2."""
+    import torch
+    from paper_1005_0542_amd import inputs
+    from paper_1005_0542_amd.driver import ElasticRun
+
+    w = inputs.WORKLOADS[name]
+    log(f"{name}: GMRES({restart}) harmonics={warmup + steps}")
+    run = ElasticRun(w, n_harm=warmup + steps, restart=restart)
+    for _ in range(warmup):
+        run.step()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    its = []
+    for _ in range(steps):
+        its.append(run.step().iters[0])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t
+    npts = 2 * (w.n_cells - 1) ** 2
+    return {"workload": name, "precision": "fp64", "shots": 1, "restart": restart,
+            "value": npts * sum(its) / el / 1e6, "unit": "Mpoint-iters/s (GMRES inner iterations, 2 components)",
+            "ms_per_step": 1e3 * el / steps, "inner_iters_per_harmonic": its,
+            "ms_per_gmres_cycle": 1e3 * el / (sum(its) / restart)}
+
+
 def cpu_baseline(name, k_lo=2, k_hi=12):
     """The FP64 oracle's PCG (numpy/scipy) on one shot of the same workload:
     per-iteration time from two fixed-iteration runs (tol = 0)."""
@@ -310,6 +337,8 @@ def main():
                                                "mean_iters", "whole_iteration_GBps", "dominant")}
             variants[key]["kernels_GBps"] = {k: round(x["GBps"], 1) for k, x in v["kernels"].items()}
             torch.cuda.empty_cache()
+        variants["elastic_gmres10_1024"] = run_elastic()
+        torch.cuda.empty_cache()
         fp64_1 = variants["fp64_1shot_4096"]["value"]
         variants["speedup_mixed64_vs_fp64_1shot_per_iteration"] = head["value"] / fp64_1
 

@@ -109,3 +109,55 @@ class AcousticRun:
                                device="cuda")
         self.plan.trace_synthesize(self.rec, W, out)
         return out
+
+
+class ElasticRun:
+    """The elastic harmonic loop on one GPU (eq. elastic_problemQn): for each
+    harmonic the right-hand side from the running sums of both displacement
+    components, right-preconditioned GMRES(k) with K = diag(B1, B2), and the
+    synthesis.  Vectors are [shots][2][nz-1][nx-1] (u_x, u_z)."""
+
+    def __init__(self, w: inputs.Workload, shots: Optional[int] = None, n_harm: Optional[int] = None,
+                 restart: int = 10, tol: Optional[float] = None, max_iter: int = 10000, snapshots: bool = True,
+                 rec: bool = True, segments: int = 0):
+        import torch
+        self.torch = torch
+        self.w = w
+        self.shots = shots or w.shots
+        self.n_harm = n_harm or w.n_harm
+        self.restart = restart
+        self.tol = w.tol if tol is None else tol
+        self.max_iter = max_iter
+        N = w.n_cells
+        lam, mu, rho = inputs.elastic_medium_for(w)
+        self.lam, self.mu, self.rho = lam, mu, rho
+        self.plan = api.Plan("elastic", N, N, w.d, w.d, w.alpha, w.h, self.n_harm, np.stack([lam, mu, rho]),
+                             precision="fp64", nshots=self.shots, segments=segments)
+        src = inputs.sources_for(w) if self.shots == w.shots else \
+            inputs.shot_positions(N, self.shots, w.shot_seed, w.src_row)
+        self.src = src
+        self.plan.set_sources(src)
+        self.f_m = api.source_coeffs(w.f0, w.t0, w.alpha, w.h, self.n_harm)
+        self.t_snap = inputs.snapshot_times(w)
+        self.W_snap = api.laguerre_weights(self.t_snap, w.alpha, w.h, self.n_harm)
+        shape = (self.shots, 2, N - 1, N - 1)
+        f64 = torch.float64
+        self.R, self.Ph, self.Qh, self.rhs = (torch.zeros(shape, dtype=f64, device="cuda") for _ in range(4))
+        self.snap = torch.zeros((len(self.t_snap),) + shape, dtype=f64, device="cuda") if snapshots else None
+        self.rec = torch.zeros((self.shots, 2, self.n_harm, N - 1), dtype=f64, device="cuda") if rec else None
+        self.iters: List[List[int]] = []
+        self.status: List[int] = []
+        self.m = 0
+
+    def step(self) -> api.SolveResult:
+        m = self.m
+        fs = np.full(self.shots, self.f_m[m])
+        self.plan.laguerre_rhs(m, self.R if m else None, self.Ph, self.Qh, fs, self.rhs)
+        res = self.plan.gmres_solve(self.rhs, self.R, tol=self.tol, max_iter=self.max_iter, restart=self.restart)
+        if self.snap is not None or self.rec is not None:
+            ws = self.W_snap[:, m] if self.snap is not None else []
+            self.plan.laguerre_synthesize(m, self.R, ws, self.snap, self.w.rec_row, self.rec)
+        self.iters.append(res.iters)
+        self.status.append(res.status)
+        self.m += 1
+        return res

@@ -149,3 +149,34 @@ def test_elastic_harmonic_chain_parity():
                                          lambda u: elastic.apply_Kinv(u, B1, B2), phi, 1e-11, 10)
         assert rel(to_np(R)[0], xo) < 1e-8
         Rprev = to_np(R)[0]
+
+
+def test_elastic_run_driver_matches_oracle_chain():
+    """The elastic harmonic-loop driver (RHS from the running sums of both
+    components, GMRES(10), synthesis) over four harmonics of a 64^2 version of
+    the 1024^2 elastic workload."""
+    from paper_1005_0542_amd.driver import ElasticRun
+    torch = torch_cuda()
+    w = inputs.Workload(**{**inputs.WORKLOADS["elastic1024"].__dict__, "n_cells": 64, "d": 20.0,
+                           "src": (32, 8)})
+    nh = 4
+    run = ElasticRun(w, n_harm=nh, tol=1e-11)
+    lam, mu, rho = run.lam, run.mu, run.rho
+    N, d = w.n_cells, w.d
+    wv = rho[1:-1, 1:-1] * w.h * w.h / 4
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, w.h, N, N, d, d)
+    fo = laguerre.ricker_coeffs(w.f0, w.t0, w.h, w.alpha, nh)
+    sums = harmonics.RunningSums((2, N - 1, N - 1), w.alpha)
+    Rp = None
+    for m in range(nh):
+        log(f"ElasticRun harmonic {m}")
+        res = run.step()
+        assert res.statuses == [OK]
+        srcf = np.zeros((2, N - 1, N - 1))
+        srcf[1] = harmonics.source_field((N - 1, N - 1), run.src[0], fo[m], d, d)
+        phi = srcf - w.h * w.h * rho[1:-1, 1:-1][None] * sums.step(m, Rp)
+        xo, ito, _, sto = krylov.gmres(lambda u: elastic.apply_C(u, lam, mu, wv, d, d),
+                                       lambda u: elastic.apply_Kinv(u, B1, B2), phi, 1e-11, 10)
+        assert sto == OK and abs(res.iters[0] - ito) <= 1
+        assert rel(to_np(run.R)[0], xo) < 1e-8
+        Rp = xo
