@@ -144,11 +144,12 @@ def test_elastic_harmonic_chain_parity():
         srcf[1] = harmonics.source_field((nz - 1, nx - 1), src[0], fo[m], d, d)
         Q = sums.step(m, Rprev)
         phi = srcf - h * h * rho[1:-1, 1:-1][None] * Q
-        assert rel(to_np(rhs)[0], phi) < 1e-12
+        # the oracle runs its own chain: the two differ by the GMRES tolerance
+        assert rel(to_np(rhs)[0], phi) < (1e-12 if m == 0 else 1e-8)
         xo, ito, rro, sto = krylov.gmres(lambda u: elastic.apply_C(u, lam, mu, w, d, d),
                                          lambda u: elastic.apply_Kinv(u, B1, B2), phi, 1e-11, 10)
         assert rel(to_np(R)[0], xo) < 1e-8
-        Rprev = to_np(R)[0]
+        Rprev = xo
 
 
 def test_elastic_run_driver_matches_oracle_chain():
