@@ -401,19 +401,21 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
             const rsrc_t rY = buf_rsrc(a.y + fbase, nfe * SZ);
             const rsrc_t rU = buf_rsrc(a.utab, (uint32_t)Ls * (uint32_t)NX1 * SZ);
             const int rs0 = (j0 + 1) & (Ls - 1), sg0 = (j0 + 1) / Ls;
-            const int rs1 = (j1 + 1) & (Ls - 1), sg1 = (j1 + 1) / Ls;
+            const int rs1 = (j1 + 1) & (Ls - 1);
             const bool c0 = rs0 != 0, c1 = has1 && rs1 != 0;
-            // row indices (-1: absent) of the y rows and u-table rows
+            // row indices (-1: absent) of the y rows and u-table rows.  Separator
+            // rows s Ls - 1 are odd (Ls is a power of two >= 2) and j0 is even,
+            // so j0 is never a separator and, whenever row j1 needs the
+            // correction, it lies in j0's segment: one pair of separator values
+            // serves both rows.
             const int l0 = (c0 && sg0 > 0) ? sg0 * Ls - 1 : -1;
             const int r0 = (c0 && sg0 < P - 1) ? (sg0 + 1) * Ls - 1 : -1;
-            const int l1 = (c1 && sg1 > 0) ? sg1 * Ls - 1 : -1;
-            const int r1 = (c1 && sg1 < P - 1) ? (sg1 + 1) * Ls - 1 : -1;
             const int ua0r = c0 ? rs0 : -1, ub0r = c0 ? Ls - rs0 : -1;
             const int ua1r = c1 ? rs1 : -1, ub1r = c1 ? Ls - rs1 : -1;
             const int y1r = has1 ? j1 : -1;
 #pragma unroll
             for (int cb = 0; cb < NIT; cb += CH) {
-                T yv0[CH], yv1[CH], xl0[CH], xr0[CH], xl1[CH], xr1[CH];
+                T yv0[CH], yv1[CH], xl0[CH], xr0[CH];
                 T ua0[CH], ub0[CH], ua1[CH], ub1[CH];
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
@@ -426,8 +428,6 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
                     yv1[u] = bload<T>(rY, off(y1r));
                     xl0[u] = bload<T>(rY, off(l0));
                     xr0[u] = bload<T>(rY, off(r0));
-                    xl1[u] = bload<T>(rY, off(l1));
-                    xr1[u] = bload<T>(rY, off(r1));
                     ua0[u] = bload<T>(rU, off(ua0r));
                     ub0[u] = bload<T>(rU, off(ub0r));
                     ua1[u] = bload<T>(rU, off(ua1r));
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
 #pragma unroll
                 for (int u = 0; u < CH; ++u) {
                     v0[u] = c0 ? yv0[u] + xl0[u] * ua0[u] + xr0[u] * ub0[u] : yv0[u];
-                    v1[u] = c1 ? yv1[u] + xl1[u] * ua1[u] + xr1[u] * ub1[u] : yv1[u];
+                    v1[u] = c1 ? yv1[u] + xl0[u] * ua1[u] + xr0[u] * ub1[u] : yv1[u];
                 }
                 if (a.free_top) {                  // + coef_k g_k(j): the free-surface rank-one term
                     const rsrc_t rG = buf_rsrc(a.smg, nfe * SZ);
