@@ -501,3 +501,111 @@ def test_pcg_initial_guess():
     # b = 0 gives x = 0 whatever the start
     x_e, it_e, _, st_e = krylov.pcg(A, Minv, np.zeros_like(b), 1e-10, 500, x0=x0)
     assert st_e == OK and it_e == 0 and not x_e.any()
+
+
+# ---------------------------------------------------------------------------
+# 2.5D axisymmetric problem (Sec. 2.1, 2.3, eq. precond1)
+# ---------------------------------------------------------------------------
+from oracle import cylindrical as cyl
+
+
+def _cyl_medium(nr, nz, seed=7):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.5, 2.0, (nr, nz)), rng.uniform(1e-7, 5e-7, (nr, nz))
+
+
+def test_cylindrical_operator_dense_symmetric_positive():
+    nr, nz, hr, hz, h = 9, 12, 4.0, 6.0, 300.0
+    kappa, rho = _cyl_medium(nr, nz)
+    a1, a2, w = cyl.coefficients(kappa, rho, h, hr)
+    M = cyl.assemble_A(a1, a2, w, hr, hz)
+    y = np.random.default_rng(3).standard_normal((nr - 1, nz))
+    Ay = cyl.apply_A(y, a1, a2, w, hr, hz)
+    assert np.max(np.abs(M @ y.ravel() - Ay.ravel())) < 1e-13 * np.max(np.abs(Ay))
+    assert np.allclose(M, M.T, rtol=0, atol=1e-15 * np.max(np.abs(M)))
+    assert np.linalg.eigvalsh(M).min() > 0
+    # the first row has no face towards r = 0, the ends no z-flux: with kappa = 1
+    # the row sums of the r- and z-parts vanish except on the Dirichlet side
+    a1u, a2u, _ = cyl.coefficients(np.ones((nr, nz)), np.zeros((nr, nz)), h, hr)
+    Mu = cyl.assemble_A(a1u, a2u, np.zeros((nr - 1, nz)), hr, hz)
+    rs = Mu.sum(axis=1).reshape(nr - 1, nz)
+    assert np.max(np.abs(rs[:-1])) < 1e-15 and np.all(rs[-1] > 0)
+
+
+def test_dct2_forms_agree_and_invert():
+    import scipy.fft
+    for n in (1, 2, 8, 64):
+        x = np.random.default_rng(n).standard_normal((3, n))
+        c = cyl.dct2_direct(x)
+        assert np.max(np.abs(cyl.dct2(x) - c)) < 1e-12 * max(1.0, np.max(np.abs(c)))
+        assert np.max(np.abs(0.5 * scipy.fft.dct(x, type=2, axis=-1) - c)) < 1e-12 * max(1.0, np.max(np.abs(c)))
+        assert np.max(np.abs(cyl.idct2(c) - x)) < 1e-12
+
+
+def test_dct2_diagonalizes_the_neumann_second_difference():
+    n, hz = 16, 2.5
+    D = np.zeros((n, n))
+    for k in range(n):
+        if k > 0:
+            D[k, k] += 1; D[k, k - 1] -= 1
+        if k < n - 1:
+            D[k, k] += 1; D[k, k + 1] -= 1
+    D /= hz * hz
+    lam = cyl.neumann_eigenvalues(n, hz)
+    for q in range(n):
+        v = np.cos(np.pi * q * (2 * np.arange(n) + 1) / (2 * n))
+        assert np.max(np.abs(D @ v - lam[q] * v)) < 1e-12
+
+
+def test_cylindrical_preconditioner_inverse_and_one_iteration():
+    nr, nz, hr, hz, h = 8, 16, 5.0, 3.0, 250.0
+    B = cyl.CylindricalPreconditioner(nr, nz, hr, hz, 1.3, 2e-7, h)
+    n = (nr - 1) * nz
+    M = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n); e[c] = 1
+        M[:, c] = B.apply(e.reshape(nr - 1, nz)).ravel()
+    # B.apply is the constant-medium operator
+    a1, a2, w = cyl.coefficients(np.full((nr, nz), 1.3), np.full((nr, nz), 2e-7), h, hr)
+    Ma = cyl.assemble_A(a1, a2, w, hr, hz)
+    assert np.max(np.abs(M - Ma)) < 1e-13 * np.max(np.abs(Ma))
+    r = np.random.default_rng(13).standard_normal((nr - 1, nz))
+    z = B.solve(r)
+    assert np.max(np.abs(z.ravel() - np.linalg.solve(M, r.ravel()))) < 1e-11 * np.max(np.abs(z))
+    # constant medium: B = A, one PCG iteration
+    x, it, rr, st = krylov.pcg(lambda y: cyl.apply_A(y, a1, a2, w, hr, hz), B.solve, r, 1e-10, 50)
+    assert st == OK and it == 1 and rr < 1e-12
+
+
+def test_cylindrical_pcg_matches_dense_solve():
+    nr, nz, hr, hz, h = 16, 16, 10.0, 10.0, 200.0
+    kappa, rho = _cyl_medium(nr, nz, seed=11)
+    a1, a2, w = cyl.coefficients(kappa, rho, h, hr)
+    B = cyl.preconditioner(kappa, rho, h, hr, hz)
+    b = np.random.default_rng(17).standard_normal((nr - 1, nz))
+    x, it, rr, st = krylov.pcg(lambda y: cyl.apply_A(y, a1, a2, w, hr, hz), B.solve, b, 1e-13, 500)
+    xs = np.linalg.solve(cyl.assemble_A(a1, a2, w, hr, hz), b.ravel()).reshape(b.shape)
+    assert st == OK and np.max(np.abs(x - xs)) < 1e-10 * np.max(np.abs(xs))
+
+
+def test_cylindrical_radial_operator_converges_to_bessel_eigenvalue():
+    """With kappa = 1 and one z-column, A v = lam diag(r) v discretizes
+    -(1/r)(r v')' with v'(0) = 0 (the r = 0 condition of the first row) and
+    v(l1) = 0: its smallest eigenvalue tends to (j_{0,1}/l1)^2, j_{0,1} the
+    first zero of the Bessel function J0, with second-order error.  This pins
+    the face weights rbar and the symmetry row independently of the code."""
+    import scipy.linalg
+    import scipy.special
+    l1 = 1.0
+    j01 = scipy.special.jn_zeros(0, 1)[0]
+    errs = []
+    for nr in (16, 32, 64, 128):
+        hr = l1 / (nr - 0.5)
+        a1, a2, w = cyl.coefficients(np.ones((nr, 1)), np.zeros((nr, 1)), 0.0, hr)
+        K = cyl.assemble_A(a1, a2, w, hr, 1.0)
+        R = np.diag(cyl.radii(nr, hr))
+        lam = scipy.linalg.eigh(K, R, eigvals_only=True)[0]
+        errs.append(abs(lam - (j01 / l1) ** 2))
+    assert errs[-1] < 1e-3 * (j01 / l1) ** 2
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.0 < e0 / e1 < 5.0          # second order
