@@ -55,6 +55,19 @@ def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True):
     }
 
 
+def cyl_kernel_bytes(shots: int):
+    """The same for the FP64 axisymmetric iteration (Sec. 2.3): q = A p is
+    stored; the r-systems read rhat and write zhat once (their forward-sweep
+    intermediate round trip through memory is not counted); the Thomas
+    factors (upper factors, inverse pivots) are shared by all shots."""
+    return {
+        "operator": 16 + 24.0 / shots,                        # p in, q out; a1, a2, w once per batch
+        "update_fdct": 56,                                    # x, r, p, q in; x, r, rhat out
+        "r_systems": 16 + 16.0 / shots,                       # rhat in, zhat out; factors once per batch
+        "correct_idct": 24,                                   # zhat in, p in/out
+    }
+
+
 def copy_probe(mib: int = 2048, reps: int = 10):
     """Device-to-device copy bandwidth on this GPU (read + write bytes per
     second), the practical streaming ceiling the kernels are compared with."""
@@ -126,7 +139,7 @@ def tuned_params(name, precision, shots, enabled=True):
 
 
 def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0, profile=True,
-                tuned=None, profile_iters=20, top="dirichlet"):
+                tuned=None, profile_iters=20, top="dirichlet", geometry="cartesian"):
     import torch
     from paper_1005_0542_amd import inputs
     from paper_1005_0542_amd.driver import AcousticRun
@@ -143,10 +156,11 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2),
                       segments=tuned.get("segments", 0), graph_iters=tuned.get("graph_iters", 0),
                       op_shots=tuned.get("op_shots", 0), seg_per_wave=tuned.get("seg_per_wave", 0),
-                      op_fusion=tuned.get("op_fusion", 0), top=top)
+                      op_fusion=tuned.get("op_fusion", 0), top=top, geometry=geometry)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    npts = (w.n_cells - 1) ** 2
+    cyl = geometry == "cylindrical"
+    npts = (w.n_cells - 1) * (w.n_cells if cyl else w.n_cells - 1)
     for _ in range(warmup):
         run.step()
     torch.cuda.synchronize()
@@ -159,7 +173,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     el = time.perf_counter() - t1
     pt_iters = float(npts) * float(np.sum(iters))
     out = {
-        "workload": name, "precision": precision, "shots": shots, "top": top,
+        "workload": name, "precision": precision, "shots": shots, "top": top, "geometry": geometry,
         "value": pt_iters / el / 1e6, "ms_per_step": 1e3 * el / steps,
         "iters_per_harmonic": [int(max(i)) for i in iters],
         "mean_iters": float(np.mean(iters)),
@@ -169,7 +183,8 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     seg, seg_len = run.plan.layout()
     out["segments"] = seg
     ws = 8 if precision == "fp64" else 4
-    kb = kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
+    kb = cyl_kernel_bytes(shots) if cyl else kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
+    slots = [0, 1, 2, 4] if cyl else [0, 1, 2, 3, 4]          # the profile helper's kernel slots
     per_iter_bytes = sum(kb.values()) * npts * shots
     mean_it = max(out["mean_iters"], 1e-9)
     t_iter = el / (steps * mean_it)
@@ -183,11 +198,11 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
         ms = run.plan.pcg_profile(b, x, iters=profile_iters)
         names = list(kb.keys())
         kern = {}
-        for k, nm in enumerate(names):
+        for k, nm in zip(slots, names):
             byts = kb[nm] * npts * shots
             kern[nm] = {"avg_ms": ms[k], "alg_bytes": byts, "GBps": byts / (ms[k] * 1e-3) / 1e9}
         out["kernels"] = kern
-        out["iteration_ms_profiled"] = float(sum(ms))
+        out["iteration_ms_profiled"] = float(sum(ms[k] for k in slots))
         dom = max(names, key=lambda nm: kern[nm]["avg_ms"])
         out["dominant"] = dom
     out["_run"] = run
@@ -278,6 +293,8 @@ def main():
     ap.add_argument("--op-shots", type=int, default=0, help="override (profile-only)")
     ap.add_argument("--seg-per-wave", type=int, default=0, help="override (profile-only)")
     ap.add_argument("--op-fusion", type=int, default=0, help="override (profile-only): 1 fused, 2 stored q")
+    ap.add_argument("--geometry", default="cartesian", choices=("cartesian", "cylindrical"),
+                    help="profile-only: the 2D Cartesian or the 2.5D axisymmetric problem (FP64)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -303,12 +320,13 @@ def main():
         # the benchmark's own path on two harmonics (one untimed), then the
         # per-kernel profile: a kernel trace of this mode ends with exactly
         # --profile-iters launches of each iteration kernel with all shots active
-        tp = tuned_params(args.workload, prec, shots, not args.no_tune)
+        geo = args.geometry
+        tp = tuned_params(args.workload, prec, shots, not args.no_tune and geo == "cartesian")
         tp.update({k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion") if getattr(args, k)})
         v = run_variant(args.workload, prec, shots, args.steps, args.warmup, segments=args.segments,
-                        graph_iters=args.graph_iters, tuned=tp, profile_iters=args.profile_iters)
+                        graph_iters=args.graph_iters, tuned=tp, profile_iters=args.profile_iters, geometry=geo)
         v.pop("_run")
-        print(json.dumps({k: v[k] for k in ("workload", "precision", "shots", "segments", "kernels",
+        print(json.dumps({k: v[k] for k in ("workload", "precision", "shots", "geometry", "segments", "kernels",
                                             "iteration_ms_profiled")} | {"tuned": tp,
                                                                          "profile_iterations": args.profile_iters}))
         return
@@ -327,14 +345,18 @@ def main():
             ("acoustic2048x64_mixed", "fp64", 64, "fp64_64shot_2048", "dirichlet"),
             # the same batch with the free-surface top boundary (rank-one corrected Dichotomy)
             ("acoustic2048x64_mixed", "mixed", 64, "mixed_64shot_2048_free_surface", "free"),
+            # the paper's 2.5D axisymmetric problem, N_r x N_z = 2048 x 2048, sources on the axis
+            ("acoustic2048x64_mixed", "fp64", 64, "fp64_64shot_2048_axisymmetric", "cylindrical"),
         ]
         for name, prec, shots, key, top in plan:
+            geo = "cylindrical" if top == "cylindrical" else "cartesian"
             v = run_variant(name, prec, shots, max(2, args.steps // 2), 1,
-                            tuned=tuned_params(name, prec, shots, not args.no_tune),
-                            profile_iters=args.profile_iters, top=top)
+                            tuned=tuned_params(name, prec, shots, not args.no_tune and geo == "cartesian"),
+                            profile_iters=args.profile_iters, top="dirichlet" if geo != "cartesian" else top,
+                            geometry=geo)
             v.pop("_run")
-            variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "top", "value", "ms_per_step",
-                                               "mean_iters", "whole_iteration_GBps", "dominant")}
+            variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "top", "geometry", "value",
+                                               "ms_per_step", "mean_iters", "whole_iteration_GBps", "dominant")}
             variants[key]["kernels_GBps"] = {k: round(x["GBps"], 1) for k, x in v["kernels"].items()}
             torch.cuda.empty_cache()
         variants["elastic_gmres10_1024"] = run_elastic()

@@ -72,9 +72,19 @@ typedef enum { LG_RICKER = 0, LG_GAUSS_SINE = 1 } lg_wavelet;
  * (acoustic plans only).  The preconditioner keeps the same face. */
 typedef enum { LG_TOP_DIRICHLET = 0, LG_TOP_FREE = 1 } lg_top_bc;
 
+/* Geometry.  LG_CARTESIAN: the 2D Cartesian problem, Dirichlet sides (top:
+ * lg_top_bc); fields [nz-1][nx-1].  LG_CYLINDRICAL: the paper's 2.5D
+ * axisymmetric acoustic problem (Sec. 2.1, 2.3, eqs. poisson_diff_2,
+ * scheme_op_r_z, diff_approx1, precond1) on its mesh r_i = (i-1/2) dz, i =
+ * 1..nz, z_k = (k-1/2) dx, k = 1..nx: the unknowns are i = 1..nz-1 (y = 0 on
+ * the side r = l1, row i = nz), with the symmetry condition at r = 0 and no
+ * flux through the two z-ends; fields [nz-1][nx] (z fastest), medium node
+ * arrays [F][nz][nx]; FP64 acoustic plans only (top_bc is not used). */
+typedef enum { LG_CARTESIAN = 0, LG_CYLINDRICAL = 1 } lg_geometry;
+
 /* Grid: nx, nz cells (powers of two, 2..4096), spacings dx, dz > 0 (metres),
- * top boundary (lg_top_bc). */
-typedef struct { int32_t nx, nz; double dx, dz; int32_t top_bc; int32_t reserved; } lg_grid;
+ * top boundary (lg_top_bc), geometry (lg_geometry). */
+typedef struct { int32_t nx, nz; double dx, dz; int32_t top_bc; int32_t geometry; } lg_grid;
 
 /* Laguerre transform (Sec. 2.1): order alpha >= 2, scale h > 0 (1/s), n >= 1
  * harmonics. */
@@ -245,6 +255,9 @@ lg_status lg_trace_synthesize(lg_plan* plan, const double* rec_coeff, const doub
  *   2 Dichotomy segment solves,
  *   3 interface systems (+ (r,z), beta),
  *   4 segment correction + inverse DST + p update.
+ * Axisymmetric plans (LG_CYLINDRICAL) report 0 operator, 1 update + forward
+ * cosine transform, 2 the r-systems (+ (r,z), beta), 3 zero (no interface
+ * stage), 4 inverse cosine transform + p update.
  * x is overwritten with the iterate.  Acoustic plans only. */
 lg_status lg_pcg_profile(lg_plan* plan, const double* b, double* x, int32_t iters, float* ms_host);
 

@@ -23,12 +23,13 @@ LG_ERR_UNSUPPORTED = 7
 LG_FP64, LG_MIXED = 0, 1
 LG_ACOUSTIC, LG_ELASTIC = 0, 1
 LG_TOP_DIRICHLET, LG_TOP_FREE = 0, 1
+LG_CARTESIAN, LG_CYLINDRICAL = 0, 1
 LG_RICKER, LG_GAUSS_SINE = 0, 1
 
 
 class Grid(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("nz", c_int32), ("dx", c_double), ("dz", c_double),
-                ("top_bc", c_int32), ("reserved", c_int32)]
+                ("top_bc", c_int32), ("geometry", c_int32)]
 
 
 class Laguerre(ctypes.Structure):

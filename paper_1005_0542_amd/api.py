@@ -59,7 +59,7 @@ class Plan:
     def __init__(self, kind: str, nx: int, nz: int, dx: float, dz: float, alpha: int, h: float,
                  n: int, medium: np.ndarray, precision: str = "fp64", nshots: int = 1,
                  segments: int = 0, graph_iters: int = 0, op_shots: int = 0, seg_per_wave: int = 0,
-                 op_fusion: int = 0, top: str = "dirichlet",
+                 op_fusion: int = 0, top: str = "dirichlet", geometry: str = "cartesian",
                  stream=None):
         import torch
         self.lib = _lib.load()
@@ -72,7 +72,11 @@ class Plan:
         if top not in ("dirichlet", "free"):
             raise ValueError("top must be 'dirichlet' or 'free'")
         self.top = top
-        grid = _lib.Grid(nx, nz, dx, dz, _lib.LG_TOP_FREE if top == "free" else _lib.LG_TOP_DIRICHLET, 0)
+        if geometry not in ("cartesian", "cylindrical"):
+            raise ValueError("geometry must be 'cartesian' or 'cylindrical'")
+        self.geometry = geometry
+        grid = _lib.Grid(nx, nz, dx, dz, _lib.LG_TOP_FREE if top == "free" else _lib.LG_TOP_DIRICHLET,
+                         _lib.LG_CYLINDRICAL if geometry == "cylindrical" else _lib.LG_CARTESIAN)
         lag = _lib.Laguerre(alpha, h, n)
         tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion)
         if stream is None:
@@ -91,6 +95,8 @@ class Plan:
     # -- helpers --------------------------------------------------------------
     def vec_shape(self, comps: Optional[int] = None):
         c = self.ncomp if comps is None else comps
+        if self.geometry == "cylindrical":          # [Nr-1][Nz], z fastest
+            return (self.nshots, c, self.nz - 1, self.nx)
         return (self.nshots, c, self.nz - 1, self.nx - 1)
 
     def _ptr(self, t, dtype, name, numel=None):

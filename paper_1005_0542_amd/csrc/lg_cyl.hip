@@ -1,0 +1,551 @@
+// The paper's 2.5D axisymmetric acoustic problem (Sec. 2.1, 2.3, eqs.
+// poisson_diff_2, scheme_op_r_z, diff_approx1, precond1) on gfx950.
+//
+// Mesh r_i = (i - 1/2) h_r, z_k = (k - 1/2) h_z.  A field holds the unknown
+// rows i = 1..Nr-1 (row j = i-1) of Nz values each, z fastest; y = 0 on the
+// row i = Nr.  The plan's nx1 is Nz (row length) and nz1 is Nr - 1.
+//
+// Operator (SPD sign): r-faces carry a1 = rbar kappa (0 on the face r = 0:
+// the symmetry row), z-faces a2 = r kappa (none at the two z-ends: no flux),
+// shift w = r rho h^2/4.  Preconditioner B (eq. precond1, midrange
+// coefficients): the cosine transform (DCT-II) along z diagonalises the
+// no-flux z-part; each z-wavenumber leaves one symmetric tridiagonal system
+// along r whose coefficients vary with r.  Its Thomas factors are prepared
+// once per plan and the systems are solved one lane per wavenumber.
+//
+// Kernels of one CG iteration:
+//   cyl_stencil_kernel        q = A p, (p, Ap) partials
+//   cyl_dct_kernel<UPDATE>    x += alpha p, r -= alpha q, ||r||^2, rhat = DCT r
+//   cyl_thomas_kernel         zhat = B_k^{-1} rhat per wavenumber, (r, z) partials
+//   cyl_dct_kernel<CORRECT>   z = DCT^{-1} zhat, p = z + beta p
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "lg_device.h"
+#include "lg_internal.h"
+
+namespace lg {
+
+// ===========================================================================
+// operator
+// ===========================================================================
+constexpr int CY_RPT = 8;   // operator: rows per thread
+constexpr int CY_TU = 8;    // r-systems: rows per load chunk
+
+template <typename T>
+struct CylStArgs {
+    const T* p;
+    T* q;
+    const T* a1;         // [nz1][nx1]: a1 / h_r^2 on the face between rows j and j+1
+    const T* a2;         // [nz1][nx1+1]: a2 / h_z^2 on the face left of column k (0 at both ends)
+    const T* w;          // [nz1][nx1]
+    int nx1, nz1;
+    int gx, gy;          // column tiles, row strips; 1D grid of gx*gy*fields blocks
+    ShotCtl* ctl;        // nullptr: plain application
+    double* partial;
+    size_t pstride;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
+    __shared__ double red[4];
+    const int nx1 = a.nx1, nz1 = a.nz1;
+    const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int L = xcd_linear(blockIdx.x, gridDim.x);
+    const int bx = L % a.gx, by = (L / a.gx) % a.gy, field = L / (a.gx * a.gy);
+    if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
+    const int k = bx * 64 + lane;
+    const int j0 = (by * 4 + ty) * CY_RPT;
+    const bool live = k < nx1;
+    constexpr uint32_t SZ = sizeof(T);
+    const uint32_t nf = (uint32_t)nx1 * (uint32_t)nz1;
+    const size_t fo = (size_t)field * nf;
+    const rsrc_t rp = buf_rsrc(a.p + fo, nf * SZ);
+    const rsrc_t r1 = buf_rsrc(a.a1, nf * SZ);
+    const rsrc_t r2 = buf_rsrc(a.a2, (uint32_t)nz1 * (uint32_t)(nx1 + 1) * SZ);
+    const rsrc_t rw = buf_rsrc(a.w, nf * SZ);
+    // rows j0-1 .. j0+RPT of p (0 outside: the r = 0 face has no coefficient,
+    // the row past the last unknown is the Dirichlet side)
+    T pv[CY_RPT + 2], pe[CY_RPT], pw[CY_RPT], f1[CY_RPT + 1], fl[CY_RPT], fr[CY_RPT], wv[CY_RPT];
+#pragma unroll
+    for (int r = 0; r < CY_RPT + 2; ++r) {
+        const int j = j0 - 1 + r;
+        pv[r] = bload<T>(rp, (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
+    }
+#pragma unroll
+    for (int r = 0; r < CY_RPT + 1; ++r) {       // faces j0-1|j0 .. j0+RPT-1|j0+RPT
+        const int j = j0 - 1 + r;
+        f1[r] = bload<T>(r1, (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
+    }
+#pragma unroll
+    for (int r = 0; r < CY_RPT; ++r) {
+        const int j = j0 + r;
+        const bool ok = live && j < nz1;
+        const uint32_t e = (uint32_t)(j * nx1 + k);
+        pe[r] = bload<T>(rp, (ok && k + 1 < nx1) ? (e + 1) * SZ : BUF_OOB);
+        pw[r] = bload<T>(rp, (ok && k > 0) ? (e - 1) * SZ : BUF_OOB);
+        const uint32_t e2 = (uint32_t)(j * (nx1 + 1) + k);
+        fl[r] = bload<T>(r2, ok ? e2 * SZ : BUF_OOB);
+        fr[r] = bload<T>(r2, ok ? (e2 + 1) * SZ : BUF_OOB);
+        wv[r] = bload<T>(rw, ok ? e * SZ : BUF_OOB);
+    }
+    double pq = 0.0;
+    const rsrc_t rq = buf_rsrc((a.q != nullptr ? a.q : const_cast<T*>(a.p)) + fo, a.q != nullptr ? nf * SZ : 0u);
+#pragma unroll
+    for (int r = 0; r < CY_RPT; ++r) {
+        const int j = j0 + r;
+        const T c = pv[r + 1];
+        const T v = fmad(f1[r + 1], c - pv[r + 2], f1[r] * (c - pv[r])) +
+                    fmad(fr[r], c - pe[r], fl[r] * (c - pw[r])) + wv[r] * c;
+        bstore<T>(v, rq, (live && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
+        pq += (double)c * (double)v;
+    }
+    if (a.ctl == nullptr) return;
+    const double s = block_sum(pq, red);
+    if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + by * a.gx + bx] = s;
+}
+
+// ===========================================================================
+// cosine transform along z (rows).  Two rows (j0, j1) are packed as one
+// complex sequence of length Nz, extended half-sample symmetrically to
+// M = 2 Nz; with V its DFT, exp(-i pi k / M) V_k / 2 = C_k(j0) + i C_k(j1)
+// (C_k = sum_n x_n cos(pi k (2n+1) / M)).  The inverse x_n = C_0/Nz +
+// (2/Nz) sum_{k>0} C_k cos(pi k (2n+1) / M) of a packed pair is the
+// conjugate of the DFT of conj(U), U_k = D_k e^{i pi k/M}/Nz,
+// U_{M-k} = D_k e^{-i pi k/M}/Nz (k > 0), U_0 = D_0/Nz, U_{Nz} = 0.
+// ===========================================================================
+enum CylMode { CY_FWD = 0, CY_INV = 1, CY_UPDATE = 2, CY_CORRECT = 3 };
+
+template <typename T>
+struct CylDctArgs {
+    const T* in;
+    T* out;
+    const cpx<T>* tw;      // exp(-2 pi i j / M)
+    const cpx<T>* ctw;     // exp(-i pi k / M), k < Nz
+    int nz1;
+    int bpf;
+    ShotCtl* ctl;
+    double* x;
+    double** xslot;
+    double* r;
+    const double* b;
+    const T* p;
+    const T* q;
+    double* partial;
+    size_t pstride;
+    int init;
+};
+
+template <typename T, int M, int R, int FPB, int MODE>
+__global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
+    using FP = FftPlan<M, R>;
+    constexpr int TPF = M / R;
+    constexpr int N = M / 2;                   // row length Nz
+    constexpr int RL = FP::R_LAST, NBL = FP::NB_LAST, NSL = FP::NS_LAST;
+    constexpr int NOUT = NBL * (RL / 2);
+    constexpr int LL = LdsLen<M>::value;
+    constexpr int NWAVE = (FPB * TPF + 63) / 64;
+    constexpr int NIT = (N + TPF - 1) / TPF;
+    constexpr bool INVERSE = MODE == CY_INV || MODE == CY_CORRECT;
+    __shared__ cpx<T> lds[FPB * LL];
+    __shared__ double red[NWAVE];
+
+    const int fid = threadIdx.x / TPF;
+    const int t = threadIdx.x - fid * TPF;
+    const int field = blockIdx.x / a.bpf;
+    const int bif = blockIdx.x - field * a.bpf;
+    const int pair = bif * FPB + fid;
+    const int npairs = (a.nz1 + 1) >> 1;
+    const bool live = pair < npairs;
+    const int j0 = 2 * pair, j1 = j0 + 1;
+    const bool has1 = live && (j1 < a.nz1);
+    if constexpr (MODE == CY_UPDATE || MODE == CY_CORRECT) {
+        if (!a.init && a.ctl[field].active == 0) return;   // uniform per block
+    }
+    cpx<T>* buf = lds + fid * LL;
+    constexpr uint32_t SZ = sizeof(T);
+    const uint32_t nfe = (uint32_t)a.nz1 * (uint32_t)N;
+    const size_t fbase = (size_t)field * nfe;
+    double rr = 0.0;
+    T pold0[MODE == CY_CORRECT ? NOUT : 1], pold1[MODE == CY_CORRECT ? NOUT : 1];
+
+    if (live) {
+        if constexpr (!INVERSE) {
+            // rows of the input (or, UPDATE, the updated residual) -> symmetric extension
+            T v0[NIT], v1[NIT];
+            if constexpr (MODE == CY_UPDATE) {
+                const int init = a.init;
+                double* X = init ? a.x : *a.xslot;
+                if (init && blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
+                const double alpha = init ? 0.0 : a.ctl[field].alpha;
+                const rsrc_t rX = buf_rsrc(X + fbase, init ? 0u : nfe * 8u);
+                const rsrc_t rXs = buf_rsrc(X + fbase, nfe * 8u);
+                const rsrc_t rR = buf_rsrc(init ? a.b + fbase : a.r + fbase, nfe * 8u);
+                const rsrc_t rRs = buf_rsrc(a.r + fbase, nfe * 8u);
+                const rsrc_t rP = buf_rsrc(a.p + fbase, init ? 0u : nfe * SZ);
+                const rsrc_t rQ = buf_rsrc(a.q + fbase, init ? 0u : nfe * SZ);
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int n = t + it * TPF;
+                    const bool in = n < N;
+                    const uint32_t e0 = in ? (uint32_t)(j0 * N + n) : BUF_OOB / 8u;
+                    const uint32_t e1 = (in && has1) ? (uint32_t)(j1 * N + n) : BUF_OOB / 8u;
+                    const double x0 = bload<double>(rX, e0 * 8u), x1 = bload<double>(rX, e1 * 8u);
+                    const double r0 = bload<double>(rR, e0 * 8u), r1 = bload<double>(rR, e1 * 8u);
+                    const T p0 = bload<T>(rP, e0 * SZ), p1 = bload<T>(rP, e1 * SZ);
+                    const T q0 = bload<T>(rQ, e0 * SZ), q1 = bload<T>(rQ, e1 * SZ);
+                    const double ra = r0 - alpha * (double)q0, rb = r1 - alpha * (double)q1;
+                    bstore<double>(x0 + alpha * (double)p0, rXs, e0 * 8u);
+                    bstore<double>(x1 + alpha * (double)p1, rXs, e1 * 8u);
+                    bstore<double>(ra, rRs, e0 * 8u);
+                    bstore<double>(rb, rRs, e1 * 8u);
+                    rr += ra * ra + rb * rb;
+                    v0[it] = (T)ra;
+                    v1[it] = (T)rb;
+                }
+            } else {
+                const rsrc_t rI = buf_rsrc(a.in + fbase, nfe * SZ);
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    const int n = t + it * TPF;
+                    const bool in = n < N;
+                    v0[it] = bload<T>(rI, in ? (uint32_t)(j0 * N + n) * SZ : BUF_OOB);
+                    v1[it] = bload<T>(rI, (in && has1) ? (uint32_t)(j1 * N + n) * SZ : BUF_OOB);
+                }
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int n = t + it * TPF;
+                if (n < N) {
+                    buf[lpad(n)] = {v0[it], v1[it]};
+                    buf[lpad(M - 1 - n)] = {v0[it], v1[it]};
+                }
+            }
+        } else {
+            // spectral rows D_k -> conj(U) at k and M-k
+            const rsrc_t rI = buf_rsrc(a.in + fbase, nfe * SZ);
+            const T inv_n = (T)(1.0 / N);
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int k = t + it * TPF;
+                const bool in = k < N;
+                const T d0 = bload<T>(rI, in ? (uint32_t)(j0 * N + k) * SZ : BUF_OOB);
+                const T d1 = bload<T>(rI, (in && has1) ? (uint32_t)(j1 * N + k) * SZ : BUF_OOB);
+                if (in) {
+                    const cpx<T> cd = {d0 * inv_n, -d1 * inv_n};         // conj(D) / Nz
+                    if (k == 0) {
+                        buf[lpad(0)] = cd;
+                    } else {
+                        const cpx<T> e = a.ctw[k];                          // exp(-i pi k / M)
+                        buf[lpad(k)] = cmul(cd, e);
+                        buf[lpad(M - k)] = cmul(cd, cpx<T>{e.x, -e.y});
+                    }
+                }
+            }
+            if (t == 0) buf[lpad(N)] = {(T)0, (T)0};
+            if constexpr (MODE == CY_CORRECT) {
+                const rsrc_t rPo = buf_rsrc(a.out + fbase, a.init ? 0u : nfe * SZ);
+#pragma unroll
+                for (int qb = 0; qb < NBL; ++qb)
+#pragma unroll
+                    for (int u = 0; u < RL / 2; ++u) {
+                        const int K = t + qb * TPF + u * NSL;
+                        const int oi = qb * (RL / 2) + u;
+                        pold0[oi] = bload<T>(rPo, (uint32_t)(j0 * N + K) * SZ);
+                        pold1[oi] = bload<T>(rPo, has1 ? (uint32_t)(j1 * N + K) * SZ : BUF_OOB);
+                    }
+            }
+        }
+    } else {
+        for (int i = t; i < M; i += TPF) buf[lpad(i)] = {(T)0, (T)0};
+    }
+    __syncthreads();
+
+    cpx<T> v[R];
+    fft_mid<T, M, R, 1>(buf, a.tw, t);
+    fft_last<T, M, R>(buf, a.tw, t, v);
+
+    if (live) {
+        T beta = (T)0;
+        if constexpr (MODE == CY_CORRECT) beta = (T)a.ctl[field].beta;
+        const size_t o0 = fbase + (size_t)j0 * N, o1 = fbase + (size_t)j1 * N;
+#pragma unroll
+        for (int qb = 0; qb < NBL; ++qb)
+#pragma unroll
+            for (int u = 0; u < RL / 2; ++u) {
+                const int K = t + qb * TPF + u * NSL;       // 0 <= K < Nz
+                const cpx<T> V = v[qb * RL + u];
+                T x0, x1;
+                if constexpr (!INVERSE) {
+                    const cpx<T> c = cmul(a.ctw[K], V);
+                    x0 = c.x * (T)0.5;
+                    x1 = c.y * (T)0.5;
+                } else {
+                    x0 = V.x;
+                    x1 = -V.y;
+                }
+                if constexpr (MODE == CY_CORRECT) {
+                    const int oi = qb * (RL / 2) + u;
+                    if (!a.init) {
+                        x0 += beta * pold0[oi];
+                        x1 += beta * pold1[oi];
+                    }
+                }
+                a.out[o0 + K] = x0;
+                if (has1) a.out[o1 + K] = x1;
+            }
+    }
+    if constexpr (MODE == CY_UPDATE) {
+        const double s = block_sum(rr, red);
+        if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + bif] = s;
+    }
+}
+
+// ===========================================================================
+// r-systems: one lane per (wavenumber, field); forward sweep stores the
+// intermediate values, back substitution overwrites them.  (rhat, zhat) is
+// accumulated in the forward sweep from the LDL^T form (sum g_i dp_i) and
+// weighted by the transform's inverse weights (1/Nz for k = 0, else 2/Nz).
+// ===========================================================================
+template <typename T>
+struct CylTdArgs {
+    const T* rhat;
+    T* z;
+    const T* cp;         // [nz1][nx1] upper factors
+    const T* invden;     // [nz1][nx1] inverse pivots
+    const T* lowr;       // [nz1] coupling to the previous row (0 for the first)
+    int nx1, nz1;
+    ShotCtl* ctl;        // mode != 0: masked, partials
+    double* partial;
+    size_t pstride;
+    int mode;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void cyl_thomas_kernel(CylTdArgs<T> a) {
+    // Rows are taken in chunks of CY_TU: the loads of a chunk do not depend
+    // on the recurrence, so they are all issued before its first step.  Rows
+    // past either end load as 0 (buffer range check) and leave the recurrence
+    // values 0; their stores are dropped.
+    constexpr int U = CY_TU;
+    __shared__ double red[4];
+    const int nx1 = a.nx1, nz1 = a.nz1;
+    const int field = blockIdx.y;
+    if (a.mode != 0 && a.ctl[field].active == 0) return;    // uniform per block
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const bool live = k < nx1;
+    constexpr uint32_t SZ = sizeof(T);
+    const uint32_t nf = (uint32_t)nx1 * (uint32_t)nz1;
+    const size_t fo = (size_t)field * nf;
+    const rsrc_t rR = buf_rsrc(a.rhat + fo, nf * SZ);
+    const rsrc_t rZ = buf_rsrc(a.z + fo, nf * SZ);
+    const rsrc_t rC = buf_rsrc(a.cp, nf * SZ);
+    const rsrc_t rI = buf_rsrc(a.invden, nf * SZ);
+    const rsrc_t rL = buf_rsrc(a.lowr, (uint32_t)nz1 * SZ);
+    auto off = [&](int j) -> uint32_t {
+        return (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB;
+    };
+    double acc = 0.0;
+    T dp = (T)0;
+    for (int j0 = 0; j0 < nz1; j0 += U) {
+        T rv[U], iv[U], lv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = j0 + u;
+            rv[u] = bload<T>(rR, off(j));
+            iv[u] = bload<T>(rI, off(j));
+            lv[u] = bload<T>(rL, j < nz1 ? (uint32_t)j * SZ : BUF_OOB);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const T g = rv[u] - lv[u] * dp;
+            dp = g * iv[u];
+            acc += (double)g * (double)dp;
+            bstore<T>(dp, rZ, off(j0 + u));
+        }
+    }
+    T xn = (T)0;
+    for (int jt = nz1 - 1; jt >= 0; jt -= U) {
+        T zv[U], cv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            zv[u] = bload<T>(rZ, off(jt - u));
+            cv[u] = bload<T>(rC, off(jt - u));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            xn = zv[u] - cv[u] * xn;
+            bstore<T>(xn, rZ, off(jt - u));
+        }
+    }
+    if (a.mode == 0) return;
+    acc = live ? acc * ((k == 0) ? 1.0 / nx1 : 2.0 / nx1) : 0.0;
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + blockIdx.x] = s;
+}
+
+// ===========================================================================
+// launchers
+// ===========================================================================
+namespace {
+
+template <typename T>
+hipError_t cyl_stencil_T(lg_plan* p, const T* x, T* y, bool reduce, int nfields) {
+    CylStArgs<T> a;
+    a.p = x;
+    a.q = y;
+    a.a1 = (const T*)p->cy_a1;
+    a.a2 = (const T*)p->cy_a2;
+    a.w = (const T*)p->w;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.gx = (p->nx1 + 63) / 64;
+    a.gy = (p->nz1 + 4 * CY_RPT - 1) / (4 * CY_RPT);
+    a.ctl = reduce ? p->ctl : nullptr;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    hipLaunchKernelGGL(cyl_stencil_kernel<T>, dim3(a.gx * a.gy * nfields), dim3(256), 0, p->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !reduce) return e;
+    return launch_finalize(p, 0 /* (p, Ap) */, a.gx * a.gy, 0, 0.0, 0, 0.0);
+}
+
+template <typename T, int M, int MODE>
+hipError_t cyl_dct_M(lg_plan* pl, CylDctArgs<T>& a, int nfields) {
+    constexpr int R = M >= 16 ? 16 : M;
+    constexpr int TPF = M / R;
+    constexpr int FPB = TPF >= 256 ? 1 : 256 / TPF;
+    const int npairs = (a.nz1 + 1) / 2;
+    a.bpf = (npairs + FPB - 1) / FPB;
+    hipLaunchKernelGGL((cyl_dct_kernel<T, M, R, FPB, MODE>), dim3(a.bpf * nfields), dim3(FPB * TPF), 0,
+                       pl->stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, int MODE>
+hipError_t cyl_dct_dispatch(lg_plan* pl, CylDctArgs<T>& a, int nfields) {
+    switch (2 * pl->nx1) {
+        case 4: return cyl_dct_M<T, 4, MODE>(pl, a, nfields);
+        case 8: return cyl_dct_M<T, 8, MODE>(pl, a, nfields);
+        case 16: return cyl_dct_M<T, 16, MODE>(pl, a, nfields);
+        case 32: return cyl_dct_M<T, 32, MODE>(pl, a, nfields);
+        case 64: return cyl_dct_M<T, 64, MODE>(pl, a, nfields);
+        case 128: return cyl_dct_M<T, 128, MODE>(pl, a, nfields);
+        case 256: return cyl_dct_M<T, 256, MODE>(pl, a, nfields);
+        case 512: return cyl_dct_M<T, 512, MODE>(pl, a, nfields);
+        case 1024: return cyl_dct_M<T, 1024, MODE>(pl, a, nfields);
+        case 2048: return cyl_dct_M<T, 2048, MODE>(pl, a, nfields);
+        case 4096: return cyl_dct_M<T, 4096, MODE>(pl, a, nfields);
+        case 8192: return cyl_dct_M<T, 8192, MODE>(pl, a, nfields);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+CylDctArgs<T> cyl_dct_args(lg_plan* p) {
+    CylDctArgs<T> a{};
+    a.tw = (const cpx<T>*)p->tw;
+    a.ctw = (const cpx<T>*)p->cy_ctw;
+    a.nz1 = p->nz1;
+    a.ctl = p->ctl;
+    a.xslot = p->xslot;
+    a.r = p->r;
+    a.p = (const T*)p->p;
+    a.q = (const T*)p->qv;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    return a;
+}
+
+template <typename T>
+hipError_t cyl_thomas_T(lg_plan* p, const T* rhat, T* z, int nfields, int mode) {
+    CylTdArgs<T> a;
+    a.rhat = rhat;
+    a.z = z;
+    a.cp = (const T*)p->cy_cp;
+    a.invden = (const T*)p->cy_invden;
+    a.lowr = (const T*)p->cy_lowr;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.ctl = p->ctl;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    a.mode = mode;
+    const dim3 grid((p->nx1 + 255) / 256, nfields);
+    hipLaunchKernelGGL(cyl_thomas_kernel<T>, grid, dim3(256), 0, p->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || mode == 0) return e;
+    return launch_finalize(p, 2 /* (r, z) */, (int)grid.x, mode, 0.0, 0, 1.0);
+}
+
+}  // namespace
+
+hipError_t cyl_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce) {
+    const int nf = p->S * p->C;
+    if (p->prec == LG_FP64) return cyl_stencil_T<double>(p, (const double*)x, (double*)y, reduce, nf);
+    return cyl_stencil_T<float>(p, (const float*)x, (float*)y, reduce, nf);
+}
+
+hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields) {
+    if (p->prec == LG_FP64) {
+        CylDctArgs<double> a = cyl_dct_args<double>(p);
+        a.in = (const double*)in;
+        a.out = (double*)out;
+        return inverse ? cyl_dct_dispatch<double, CY_INV>(p, a, nfields)
+                       : cyl_dct_dispatch<double, CY_FWD>(p, a, nfields);
+    }
+    CylDctArgs<float> a = cyl_dct_args<float>(p);
+    a.in = (const float*)in;
+    a.out = (float*)out;
+    return inverse ? cyl_dct_dispatch<float, CY_INV>(p, a, nfields) : cyl_dct_dispatch<float, CY_FWD>(p, a, nfields);
+}
+
+hipError_t cyl_launch_thomas(lg_plan* p, const void* rhat, void* z, int nfields, int mode) {
+    if (p->prec == LG_FP64) return cyl_thomas_T<double>(p, (const double*)rhat, (double*)z, nfields, mode);
+    return cyl_thomas_T<float>(p, (const float*)rhat, (float*)z, nfields, mode);
+}
+
+hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, double tol, int max_iter) {
+    const int nf = p->S * p->C;
+    hipError_t e;
+    int bpf;
+    if (p->prec == LG_FP64) {
+        CylDctArgs<double> a = cyl_dct_args<double>(p);
+        a.out = (double*)p->rhat;
+        a.init = init;
+        a.b = b;
+        a.x = x;
+        e = cyl_dct_dispatch<double, CY_UPDATE>(p, a, nf);
+        bpf = a.bpf;
+    } else {
+        CylDctArgs<float> a = cyl_dct_args<float>(p);
+        a.out = (float*)p->rhat;
+        a.init = init;
+        a.b = b;
+        a.x = x;
+        e = cyl_dct_dispatch<float, CY_UPDATE>(p, a, nf);
+        bpf = a.bpf;
+    }
+    if (e != hipSuccess) return e;
+    return launch_finalize(p, 1 /* ||r||^2 */, bpf, init, tol * tol, max_iter, 0.0);
+}
+
+hipError_t cyl_launch_correct(lg_plan* p, int init) {
+    const int nf = p->S * p->C;
+    if (p->prec == LG_FP64) {
+        CylDctArgs<double> a = cyl_dct_args<double>(p);
+        a.in = (const double*)p->y;
+        a.out = (double*)p->p;
+        a.init = init;
+        return cyl_dct_dispatch<double, CY_CORRECT>(p, a, nf);
+    }
+    CylDctArgs<float> a = cyl_dct_args<float>(p);
+    a.in = (const float*)p->y;
+    a.out = (float*)p->p;
+    a.init = init;
+    return cyl_dct_dispatch<float, CY_CORRECT>(p, a, nf);
+}
+
+}  // namespace lg

@@ -85,6 +85,17 @@ struct lg_plan {
     void* sm_g = nullptr;      // [nz-1][nx-1] working type: g_k(j)
     double* sm_t = nullptr;    // [2][nx-1]: 1 / (1 - g_k(0)), u_{Ls-1}(k)
     double* sm_c = nullptr;    // [fields][nx-1]: coef_k of the current solve
+    // 2.5D axisymmetric plans (geometry LG_CYLINDRICAL): fields are
+    // [Nr-1][Nz] with z fastest (nx1 = Nz, nz1 = Nr - 1); cosine transform
+    // along z, non-Toeplitz r-systems solved by Thomas per wavenumber.
+    bool cyl = false;
+    void* cy_a1 = nullptr;     // [nz1][nx1] working type: a1 / h_r^2 on the face below row j
+    void* cy_a2 = nullptr;     // [nz1][nx1+1]: a2 / h_z^2 on the face left of column k (0 at both ends)
+    void* cy_ctw = nullptr;    // [nx1] complex working type: exp(-i pi k / (2 Nz))
+    void* cy_cp = nullptr;     // [nz1][nx1]: Thomas upper factors of B's r-systems
+    void* cy_invden = nullptr; // [nz1][nx1]: inverse pivots
+    void* cy_lowr = nullptr;   // [nz1]: coupling of row j to row j-1 (0 for the first)
+    double src_scale = 0.0;    // discrete delta: 1/(dx dz), or 1/(2 pi h_r h_z)
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
@@ -155,6 +166,15 @@ hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter);
 hipError_t launch_correct_idst(lg_plan* p, int init);
+// finalize kernel over nparts per-block partials per shot: kind 0 (p, Ap)
+// -> alpha; 1 ||r||^2 -> convergence; 2 (r, z) * scale -> beta
+hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale);
+// 2.5D axisymmetric plans
+hipError_t cyl_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce);
+hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields);
+hipError_t cyl_launch_thomas(lg_plan* p, const void* rhat, void* z, int nfields, int mode);
+hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, double tol, int max_iter);
+hipError_t cyl_launch_correct(lg_plan* p, int init);
 hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,
                       const double* fsrc_host, double* rhs);
 hipError_t launch_synth(lg_plan* p, int m, const double* R, const double* Wsnap, int nsnap,

@@ -1240,12 +1240,19 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, 
 
 }  // namespace
 
+hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter,
+                           double scale) {
+    return finalize(p, kind, nparts, init, tol2, max_iter, scale);
+}
+
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq) {
+    if (p->cyl) return cyl_launch_stencil(p, x, y, reduce_pq);
     if (p->prec == LG_FP64) return stencil_T<double>(p, (const double*)x, (double*)y, reduce_pq);
     return stencil_T<float>(p, (const float*)x, (float*)y, reduce_pq);
 }
 
 hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nfields) {
+    if (p->cyl) return cyl_launch_dct(p, inverse, in, out, nfields);
     if (p->prec == LG_FP64) {
         DstArgs<double> a = dst_args<double>(p);
         a.in = (const double*)in;
@@ -1357,7 +1364,7 @@ hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double
                        Rprev, Ph, Qh, p->rho64, hh, rp, rq, rhs, p->npts, total);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const double inv = 1.0 / (p->g.dx * p->g.dz);
+    const double inv = p->src_scale;
     for (int s0 = 0; s0 < p->S; s0 += SRC_CHUNK) {
         SrcArgs sa;
         sa.n = std::min(SRC_CHUNK, p->S - s0);

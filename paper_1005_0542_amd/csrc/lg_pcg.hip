@@ -16,6 +16,13 @@ namespace {
 
 hipError_t enqueue_iteration(lg_plan* p) {
     const int nf = p->S * p->C;
+    if (p->cyl) {   // axisymmetric: q = A p stored, Thomas per wavenumber
+        hipError_t e = launch_stencil(p, p->p, p->qv, true);                     // (p, Ap), alpha
+        if (e == hipSuccess) e = cyl_launch_update(p, 0, nullptr, nullptr, 0.0, 0);  // x, r, rhat
+        if (e == hipSuccess) e = cyl_launch_thomas(p, p->rhat, p->y, nf, 2);       // zhat, beta
+        if (e == hipSuccess) e = cyl_launch_correct(p, 0);                         // z, p = z + beta p
+        return e;
+    }
     // (p, A p) and alpha; q = A p is stored only when the update does not
     // recompute it
     hipError_t e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);
@@ -82,10 +89,16 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
     }
     // start: x = 0, r = b (or, from a given x, r = b - A x in FP64), rhat = DST(r),
     // z = B^{-1} r, p = z, rz = (r, z)
-    LG_HIP(launch_update_fdst(p, o->x0_given ? 4 : 1, b, x, o->tol, o->max_iter));
-    LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
-    LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
-    LG_HIP(launch_correct_idst(p, 1));
+    if (p->cyl) {
+        LG_HIP(cyl_launch_update(p, 1, b, x, o->tol, o->max_iter));
+        LG_HIP(cyl_launch_thomas(p, p->rhat, p->y, nf, 1));
+        LG_HIP(cyl_launch_correct(p, 1));
+    } else {
+        LG_HIP(launch_update_fdst(p, o->x0_given ? 4 : 1, b, x, o->tol, o->max_iter));
+        LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
+        LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
+        LG_HIP(launch_correct_idst(p, 1));
+    }
 
     // Replay batches of captured iterations until every shot has stopped.
     // Consecutive harmonics take similar iteration counts, so as many batches
@@ -159,10 +172,17 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
 
 lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* ms) {
     const int nf = p->S * p->C;
-    LG_HIP(launch_update_fdst(p, 1, b, x, 0.0, iters + 1));
-    LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
-    LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
-    LG_HIP(launch_correct_idst(p, 1));
+    const bool cy = p->cyl;
+    if (cy) {
+        LG_HIP(cyl_launch_update(p, 1, b, x, 0.0, iters + 1));
+        LG_HIP(cyl_launch_thomas(p, p->rhat, p->y, nf, 1));
+        LG_HIP(cyl_launch_correct(p, 1));
+    } else {
+        LG_HIP(launch_update_fdst(p, 1, b, x, 0.0, iters + 1));
+        LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
+        LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
+        LG_HIP(launch_correct_idst(p, 1));
+    }
     hipEvent_t ev[6] = {};
     for (int i = 0; i < 6; ++i) LG_HIP(hipEventCreate(&ev[i]));
     double acc[5] = {0, 0, 0, 0, 0};
@@ -171,13 +191,16 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
         e = hipEventRecord(ev[0], p->stream);
         if (e == hipSuccess) e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);
         if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
-        if (e == hipSuccess) e = launch_update_fdst(p, 0, nullptr, nullptr, 0.0, 0);
+        if (e == hipSuccess)
+            e = cy ? cyl_launch_update(p, 0, nullptr, nullptr, 0.0, 0)
+                   : launch_update_fdst(p, 0, nullptr, nullptr, 0.0, 0);
         if (e == hipSuccess) e = hipEventRecord(ev[2], p->stream);
-        if (e == hipSuccess) e = launch_td(p, 0, p->rhat, p->y, nf, 1);
+        if (e == hipSuccess)
+            e = cy ? cyl_launch_thomas(p, p->rhat, p->y, nf, 2) : launch_td(p, 0, p->rhat, p->y, nf, 1);
         if (e == hipSuccess) e = hipEventRecord(ev[3], p->stream);
-        if (e == hipSuccess) e = launch_rs(p, 0, p->rhat, p->y, nf, 2);
+        if (e == hipSuccess && !cy) e = launch_rs(p, 0, p->rhat, p->y, nf, 2);
         if (e == hipSuccess) e = hipEventRecord(ev[4], p->stream);
-        if (e == hipSuccess) e = launch_correct_idst(p, 0);
+        if (e == hipSuccess) e = cy ? cyl_launch_correct(p, 0) : launch_correct_idst(p, 0);
         if (e == hipSuccess) e = hipEventRecord(ev[5], p->stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
         for (int k = 0; k < 5 && e == hipSuccess; ++k) {

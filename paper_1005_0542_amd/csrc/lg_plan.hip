@@ -119,6 +119,64 @@ lg_status prepare_free_surface(lg_plan* pl, const PrecBlock& B) {
     return dev_alloc(pl, &pl->sm_c, (size_t)pl->S * pl->C * nx1 * 8);
 }
 
+// 2.5D axisymmetric tables (Sec. 2.3, eq. precond1).  kap: node kappa
+// [Nr][Nz].  Operator faces: a1 = rbar_j kappa_face / h_r^2 between rows j
+// and j+1 (rbar_j = (j+1) h_r; the last face borders the Dirichlet row),
+// a2 = r_j kappa_face / h_z^2 between columns k-1 and k (zero at both ends).
+// Preconditioner: per z-wavenumber k the r-system with off-diagonals
+// -rbar_j kappa~/h_r^2 and diagonal (A1_j + A1_{j-1} + r_j rho~ h^2/4 +
+// r_j kappa~ lambda_k), lambda_k = (4/h_z^2) sin^2(pi k / (2 Nz)); its
+// Thomas factors (upper factors and inverse pivots) in long double.
+lg_status prepare_cylindrical(lg_plan* pl, const double* kap) {
+    const int nx = pl->g.nx, nz1 = pl->nz1, nx1 = pl->nx1;   // nx1 = Nz
+    const long double hr = pl->g.dz, hz = pl->g.dx;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double> a1((size_t)nz1 * nx1), a2((size_t)nz1 * (nx1 + 1), 0.0);
+    for (int j = 0; j < nz1; ++j) {
+        const long double r = (j + 0.5L) * hr, rbar = (j + 1.0L) * hr;
+        for (int k = 0; k < nx1; ++k) {
+            const long double kf = 0.5L * ((long double)kap[(size_t)j * nx + k] + kap[(size_t)(j + 1) * nx + k]);
+            a1[(size_t)j * nx1 + k] = (double)(rbar * kf / (hr * hr));
+            if (k > 0) {
+                const long double kz = 0.5L * ((long double)kap[(size_t)j * nx + k - 1] + kap[(size_t)j * nx + k]);
+                a2[(size_t)j * (nx1 + 1) + k] = (double)(r * kz / (hz * hz));
+            }
+        }
+    }
+    lg_status st = upload_working(pl, &pl->cy_a1, a1);
+    if (st != LG_OK) return st;
+    if ((st = upload_working(pl, &pl->cy_a2, a2)) != LG_OK) return st;
+    std::vector<double> ctw(2 * (size_t)nx1);
+    for (int k = 0; k < nx1; ++k) {
+        ctw[2 * k] = (double)std::cos(pi * k / (2.0L * nx1));
+        ctw[2 * k + 1] = (double)(-std::sin(pi * k / (2.0L * nx1)));
+    }
+    if ((st = upload_working(pl, &pl->cy_ctw, ctw)) != LG_OK) return st;
+    const long double kt = pl->kappa_t, dsh = (long double)pl->rho_t * pl->lag.h * pl->lag.h / 4.0L;
+    std::vector<long double> A1(nz1);
+    for (int j = 0; j < nz1; ++j) A1[j] = (j + 1.0L) * hr * kt / (hr * hr);
+    std::vector<double> cp((size_t)nz1 * nx1), inv((size_t)nz1 * nx1), lowr(nz1);
+    for (int j = 0; j < nz1; ++j) lowr[j] = (j > 0) ? (double)(-A1[j - 1]) : 0.0;
+    for (int k = 0; k < nx1; ++k) {
+        const long double s = std::sin(pi * k / (2.0L * nx1));
+        const long double lam = 4.0L / (hz * hz) * s * s;
+        long double cprev = 0.0L;
+        for (int j = 0; j < nz1; ++j) {
+            const long double r = (j + 0.5L) * hr;
+            const long double diag = A1[j] + (j > 0 ? A1[j - 1] : 0.0L) + r * dsh + r * kt * lam;
+            const long double lo = (j > 0) ? -A1[j - 1] : 0.0L;
+            const long double up = (j + 1 < nz1) ? -A1[j] : 0.0L;
+            const long double den = diag - lo * cprev;
+            cprev = up / den;
+            cp[(size_t)j * nx1 + k] = (double)cprev;
+            inv[(size_t)j * nx1 + k] = (double)(1.0L / den);
+        }
+    }
+    if ((st = upload_working(pl, &pl->cy_cp, cp)) != LG_OK) return st;
+    if ((st = upload_working(pl, &pl->cy_invden, inv)) != LG_OK) return st;
+    return upload_working(pl, &pl->cy_lowr, lowr);
+}
+
 // Prepare the Dichotomy tables of one preconditioner block (done once).
 lg_status prepare_block(lg_plan* pl, PrecBlock& B, double kx, double kz, double d, int P) {
     const int nx = pl->g.nx, nz = pl->g.nz, nx1 = pl->nx1;
@@ -193,7 +251,7 @@ void free_plan(lg_plan* p) {
                     p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
-                    p->sm_c};
+                    p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -344,6 +402,11 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         return fail(LG_ERR_INVALID_ARG, "top_bc must be LG_TOP_DIRICHLET or LG_TOP_FREE");
     if (grid->top_bc == LG_TOP_FREE && kind != LG_ACOUSTIC)
         return fail(LG_ERR_UNSUPPORTED, "the free surface is implemented for acoustic plans");
+    if (grid->geometry != LG_CARTESIAN && grid->geometry != LG_CYLINDRICAL)
+        return fail(LG_ERR_INVALID_ARG, "geometry must be LG_CARTESIAN or LG_CYLINDRICAL");
+    const bool cyl = grid->geometry == LG_CYLINDRICAL;
+    if (cyl && (kind != LG_ACOUSTIC || prec != LG_FP64))
+        return fail(LG_ERR_UNSUPPORTED, "the axisymmetric geometry is implemented for FP64 acoustic plans");
     int P = 0, gi = 8, osh = 8, spw = 0, fus = 1;
     if (tuning != nullptr) {
         P = tuning->segments;
@@ -357,11 +420,16 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (osh < 1 || osh > 64) return fail(LG_ERR_INVALID_ARG, "op_shots must be in 1..64");
     if (spw != 0 && spw != 1 && spw != 2 && spw != 4)
         return fail(LG_ERR_INVALID_ARG, "seg_per_wave must be 0, 1, 2 or 4");
+    if (cyl) {
+        if (P > 1) return fail(LG_ERR_UNSUPPORTED, "axisymmetric plans solve the r-systems unsegmented");
+        P = 1;
+    }
     if (P == 0) P = std::max(1, std::min(64, grid->nz / 16));
-    if (!is_pow2(P) || P > 64 || grid->nz % P != 0 || grid->nz / P < 2 || grid->nz / P > 64)
+    if (!cyl && (!is_pow2(P) || P > 64 || grid->nz % P != 0 || grid->nz / P < 2 || grid->nz / P > 64))
         return fail(LG_ERR_INVALID_ARG, "segments must be a power of two <= 64 with nz/segments in 2..64");
     const int F = (kind == LG_ACOUSTIC) ? 2 : 3;
-    const size_t nn = (size_t)(grid->nx + 1) * (grid->nz + 1);
+    // node arrays: (nz+1)(nx+1) Cartesian nodes, or Nr x Nz axisymmetric nodes
+    const size_t nn = cyl ? (size_t)grid->nx * grid->nz : (size_t)(grid->nx + 1) * (grid->nz + 1);
     for (size_t i = 0; i < (size_t)F * nn; ++i)
         if (!std::isfinite(medium_host[i])) return fail(LG_ERR_INVALID_ARG, "medium has a non-finite value");
 
@@ -376,15 +444,17 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->prec = prec;
     p->S = nshots;
     p->C = (kind == LG_ACOUSTIC) ? 1 : 2;
-    p->nx1 = grid->nx - 1;
+    p->cyl = cyl;
+    p->nx1 = cyl ? grid->nx : grid->nx - 1;
     p->nz1 = grid->nz - 1;
     p->npts = (size_t)p->nx1 * p->nz1;
     p->nvec = (size_t)p->S * p->C * p->npts;
     p->graph_iters = gi;
     p->op_shots = osh;
     p->td_spw = spw;
-    p->fuse_op = (fus == 1);
-    p->free_top = (grid->top_bc == LG_TOP_FREE);
+    p->fuse_op = (fus == 1) && !cyl;
+    p->free_top = (grid->top_bc == LG_TOP_FREE) && !cyl;
+    p->src_scale = cyl ? 1.0 / (2.0 * 3.141592653589793 * grid->dx * grid->dz) : 1.0 / (grid->dx * grid->dz);
     p->device = dev;
     p->stream = (hipStream_t)hip_stream;
 
@@ -400,6 +470,13 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     const double* rho_node = medium_host + (size_t)(F - 1) * nn;
     for (int j = 0; j < p->nz1; ++j)
         for (int i = 0; i < p->nx1; ++i) {
+            if (cyl) {   // the equation multiplied by r_j: w = r rho h^2/4, history weight r rho
+                const double rj = (j + 0.5) * grid->dz;
+                const double r = rho_node[(size_t)j * grid->nx + i];
+                rho_int[(size_t)j * p->nx1 + i] = rj * r;
+                w_int[(size_t)j * p->nx1 + i] = rj * r * hh4;
+                continue;
+            }
             const double r = rho_node[(size_t)(j + 1) * (grid->nx + 1) + (i + 1)];
             rho_int[(size_t)j * p->nx1 + i] = r;
             w_int[(size_t)j * p->nx1 + i] = r * hh4;
@@ -410,7 +487,16 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if ((he = hipMemcpy(p->rho64, rho_int.data(), p->npts * 8, hipMemcpyHostToDevice)) != hipSuccess)
         return bail(hip_fail(he, "hipMemcpy"));
 
-    if (kind == LG_ACOUSTIC) {
+    if (cyl) {
+        p->kappa_t = midrange(medium_host, nn);
+        p->rho_t = midrange(rho_node, nn);
+        if (!(p->kappa_t > 0.0) || !(p->rho_t >= 0.0))
+            return bail(fail(LG_ERR_INVALID_ARG,
+                             "midrange kappa must be > 0 and midrange rho >= 0 (SPD preconditioner)"));
+        p->blk[0].P = 1;
+        p->blk[0].Ls = grid->nz;
+        if ((st = prepare_cylindrical(p, medium_host)) != LG_OK) return bail(st);
+    } else if (kind == LG_ACOUSTIC) {
         std::vector<double> kap(medium_host, medium_host + nn);
         if ((st = upload_working(p, &p->kap, kap)) != LG_OK) return bail(st);
         if (prec == LG_MIXED) {   // FP64 medium for the true residual of the refinement
@@ -655,6 +741,10 @@ lg_status lg_precond_dichotomy_tdma(lg_plan* plan, int32_t block, const void* rh
     }
     LG_HIP(hipSetDevice(plan->device));
     const int nf = plan->S;   // acoustic: S fields; elastic: one component per shot
+    if (plan->cyl) {          // non-Toeplitz r-systems, one per z-wavenumber
+        LG_HIP(cyl_launch_thomas(plan, rhs_hat, sol_hat, nf, 0));
+        return LG_OK;
+    }
     LG_HIP(launch_td(plan, bi, rhs_hat, sol_hat, nf, 0));
     if (plan->blk[bi].P > 1 || plan->free_top) {
         LG_HIP(launch_rs(plan, bi, rhs_hat, sol_hat, nf, 0));
@@ -710,6 +800,7 @@ lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) return fail(LG_ERR_INVALID_ARG, "tol must be >= 0");
     if (opts->max_iter < 1) return fail(LG_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (opts->x0_given != 0 && opts->x0_given != 1) return fail(LG_ERR_INVALID_ARG, "x0_given must be 0 or 1");
+    if (opts->x0_given && plan->cyl) return fail(LG_ERR_UNSUPPORTED, "axisymmetric plans start from x0 = 0");
     LG_HIP(hipSetDevice(plan->device));
     return lg::pcg_solve(plan, b, x, opts, info_host);
 }
@@ -744,6 +835,11 @@ extern "C" lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z) {
     }
     const int nf = plan->S;
     LG_HIP(launch_dst(plan, 0, r, plan->rhat, nf));
+    if (plan->cyl) {
+        LG_HIP(cyl_launch_thomas(plan, plan->rhat, plan->y, nf, 0));
+        LG_HIP(launch_dst(plan, 1, plan->y, z, nf));
+        return LG_OK;
+    }
     LG_HIP(launch_td(plan, 0, plan->rhat, plan->y, nf, 0));
     if (plan->blk[0].P > 1 || plan->free_top) {
         LG_HIP(launch_rs(plan, 0, plan->rhat, plan->y, nf, 0));

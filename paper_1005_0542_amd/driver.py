@@ -18,13 +18,20 @@ from . import api, inputs
 
 
 class AcousticRun:
-    """One workload on one GPU: medium, sources, buffers, plan."""
+    """One workload on one GPU: medium, sources, buffers, plan.
+
+    ``geometry="cylindrical"`` runs the 2.5D axisymmetric problem on an
+    N_r x N_z = N x N mesh (Sec. 2.3): the workload's layered medium with its
+    depth axis along z, fields [shots][1][N-1][N] with z fastest, and every
+    source on the axis (row i = 1) at the depth index the Cartesian recipe
+    gives as its x position."""
 
     def __init__(self, w: inputs.Workload, precision: Optional[str] = None, shots: Optional[int] = None,
                  n_harm: Optional[int] = None, segments: int = 0, graph_iters: int = 0,
                  snapshots: bool = True, rec: bool = True, tol: Optional[float] = None,
                  max_iter: int = 10000, medium=None, op_shots: int = 0, seg_per_wave: int = 0,
-                 op_fusion: int = 0, top: str = "dirichlet", warm_start: bool = False):
+                 op_fusion: int = 0, top: str = "dirichlet", warm_start: bool = False,
+                 geometry: str = "cartesian"):
         import torch
         self.torch = torch
         self.w = w
@@ -37,31 +44,44 @@ class AcousticRun:
         self.max_iter = max_iter
         self.warm_start = warm_start      # start each solve from the previous harmonic
         N = w.n_cells
-        kappa, rho = medium if medium is not None else inputs.acoustic_medium_for(w)
+        cyl = geometry == "cylindrical"
+        self.geometry = geometry
+        if medium is not None:
+            kappa, rho = medium
+        else:
+            kappa, rho = inputs.acoustic_medium_for(w)
+            if cyl:   # node arrays [N_r][N_z], depth along z
+                kappa = np.ascontiguousarray(kappa[:N, :N].T)
+                rho = np.ascontiguousarray(rho[:N, :N].T)
         self.kappa, self.rho = kappa, rho
         self.plan = api.Plan("acoustic", N, N, w.d, w.d, w.alpha, w.h, self.n_harm,
                              np.stack([kappa, rho]), precision=self.precision, nshots=self.shots,
                              segments=segments, graph_iters=graph_iters, op_shots=op_shots,
-                             seg_per_wave=seg_per_wave, op_fusion=op_fusion, top=top)
+                             seg_per_wave=seg_per_wave, op_fusion=op_fusion, top=top, geometry=geometry)
         if self.shots == w.shots:
             src = inputs.sources_for(w)
         else:
             src = inputs.shot_positions(N, self.shots, w.shot_seed, w.src_row) if self.shots > 1 \
                 else np.array([w.src or (N // 2, w.src_row)], dtype=np.int32)
+        if cyl:       # (depth index k, axis row 1)
+            src = np.ascontiguousarray(np.stack([src[:, 0], np.ones(len(src), dtype=np.int32)], axis=1),
+                                       dtype=np.int32)
         self.src = src
         self.plan.set_sources(src)
         self.f_m = api.source_coeffs(w.f0, w.t0, w.alpha, w.h, self.n_harm)
         self.t_snap = inputs.snapshot_times(w)
         self.W_snap = api.laguerre_weights(self.t_snap, w.alpha, w.h, self.n_harm)   # [4, n]
         dev = "cuda"
-        shape = (self.shots, 1, N - 1, N - 1)
+        ncol = N if cyl else N - 1          # row length
+        self.ncol = ncol
+        shape = (self.shots, 1, N - 1, ncol)
         f64 = torch.float64
         self.R = torch.zeros(shape, dtype=f64, device=dev)
         self.Ph = torch.zeros(shape, dtype=f64, device=dev)
         self.Qh = torch.zeros(shape, dtype=f64, device=dev)
         self.rhs = torch.zeros(shape, dtype=f64, device=dev)
         self.snap = torch.zeros((len(self.t_snap),) + shape, dtype=f64, device=dev) if snapshots else None
-        self.rec = torch.zeros((self.shots, 1, self.n_harm, N - 1), dtype=f64, device=dev) if rec else None
+        self.rec = torch.zeros((self.shots, 1, self.n_harm, ncol), dtype=f64, device=dev) if rec else None
         self.iters: List[List[int]] = []
         self.status: List[int] = []
         self.m = 0
@@ -105,8 +125,7 @@ class AcousticRun:
 
     def traces(self, t: np.ndarray):
         W = api.laguerre_weights(t, self.w.alpha, self.w.h, self.n_harm)
-        out = self.torch.zeros((self.shots, 1, len(t), self.w.n_cells - 1), dtype=self.torch.float64,
-                               device="cuda")
+        out = self.torch.zeros((self.shots, 1, len(t), self.ncol), dtype=self.torch.float64, device="cuda")
         self.plan.trace_synthesize(self.rec, W, out)
         return out
 
