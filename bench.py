@@ -55,16 +55,16 @@ def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True):
     }
 
 
-def cyl_kernel_bytes(shots: int):
-    """The same for the FP64 axisymmetric iteration (Sec. 2.3): q = A p is
-    stored; the r-systems read rhat and write zhat once (their forward-sweep
-    intermediate round trip through memory is not counted); the Thomas
-    factors (upper factors, inverse pivots) are shared by all shots."""
+def cyl_kernel_bytes(ws: int, shots: int):
+    """The same for the axisymmetric iteration (Sec. 2.3): q = A p is stored;
+    the r-systems read rhat and write zhat once (their forward-sweep
+    intermediate round trip through memory is not counted); the face tables,
+    shift and Thomas factors are shared by all shots."""
     return {
-        "operator": 16 + 24.0 / shots,                        # p in, q out; a1, a2, w once per batch
-        "update_fdct": 56,                                    # x, r, p, q in; x, r, rhat out
-        "r_systems": 16 + 16.0 / shots,                       # rhat in, zhat out; factors once per batch
-        "correct_idct": 24,                                   # zhat in, p in/out
+        "operator": 2 * ws + 3 * ws / shots,                  # p in, q out; a1, a2, w once per batch
+        "update_fdct": 32 + 3 * ws,                           # x, r in/out (f64); p, q in; rhat out
+        "r_systems": 2 * ws + 2 * ws / shots,                 # rhat in, zhat out; factors once per batch
+        "correct_idct": 3 * ws,                               # zhat in, p in/out
     }
 
 
@@ -183,7 +183,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     seg, seg_len = run.plan.layout()
     out["segments"] = seg
     ws = 8 if precision == "fp64" else 4
-    kb = cyl_kernel_bytes(shots) if cyl else kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
+    kb = cyl_kernel_bytes(ws, shots) if cyl else kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
     slots = [0, 1, 2, 4] if cyl else [0, 1, 2, 3, 4]          # the profile helper's kernel slots
     per_iter_bytes = sum(kb.values()) * npts * shots
     mean_it = max(out["mean_iters"], 1e-9)

@@ -12,9 +12,10 @@
  * variables: a sine transform along x, then one tridiagonal system per
  * wavenumber along z, solved by a segmented Dichotomy-style solver.
  *
- * Geometry of this library: 2D Cartesian, nx x nz cells, nodes i = 0..nx,
- * j = 0..nz, zero Dirichlet values on all boundary nodes.  The unknowns are the
- * (nx-1)(nz-1) interior nodes.
+ * Geometry: 2D Cartesian, nx x nz cells, nodes i = 0..nx, j = 0..nz, zero
+ * Dirichlet values on all boundary nodes (the top one optionally flux-free).
+ * The unknowns are the (nx-1)(nz-1) interior nodes.  The paper's 2.5D
+ * axisymmetric problem is selected by lg_grid.geometry (layout below).
  *
  * ---------------------------------------------------------------------------
  * Conventions for every call below
@@ -23,6 +24,8 @@
  *           element (i, j) (1-based interior node) is at [(j-1)(nx-1) + (i-1)].
  *           A "vector" is S shots x C components x field, contiguous
  *           ([S][C][nz-1][nx-1]); C = 1 (acoustic) or 2 (elastic: x then z).
+ *           Axisymmetric plans: a field is nz-1 rows of nx values, so every
+ *           row length nx-1 below reads nx for them.
  * Memory.   Vector and field pointers are DEVICE pointers owned by the caller
  *           (contiguous, no padding, naturally aligned).  Pointers suffixed
  *           _host are host pointers.  The plan owns only its tables and
@@ -79,7 +82,9 @@ typedef enum { LG_TOP_DIRICHLET = 0, LG_TOP_FREE = 1 } lg_top_bc;
  * 1..nz, z_k = (k-1/2) dx, k = 1..nx: the unknowns are i = 1..nz-1 (y = 0 on
  * the side r = l1, row i = nz), with the symmetry condition at r = 0 and no
  * flux through the two z-ends; fields [nz-1][nx] (z fastest), medium node
- * arrays [F][nz][nx]; FP64 acoustic plans only (top_bc is not used). */
+ * arrays [F][nz][nx]; acoustic plans, FP64 or mixed, unsegmented r-systems
+ * (tuning.segments 0 or 1; top_bc is not used).  The source term carries
+ * 1/(2 pi dx dz) (the 2.5D point source). */
 typedef enum { LG_CARTESIAN = 0, LG_CYLINDRICAL = 1 } lg_geometry;
 
 /* Grid: nx, nz cells (powers of two, 2..4096), spacings dx, dz > 0 (metres),

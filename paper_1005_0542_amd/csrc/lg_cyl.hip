@@ -18,6 +18,10 @@
 //   cyl_dct_kernel<UPDATE>    x += alpha p, r -= alpha q, ||r||^2, rhat = DCT r
 //   cyl_thomas_kernel         zhat = B_k^{-1} rhat per wavenumber, (r, z) partials
 //   cyl_dct_kernel<CORRECT>   z = DCT^{-1} zhat, p = z + beta p
+// Mixed plans keep p, q, rhat, zhat and the tables in FP32 and x, r in FP64;
+// a solve that converges on the FP32 operator is restarted from the FP64
+// true residual b - A x (cyl_stencil_kernel<double, true>) until that
+// residual meets the tolerance.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,39 +45,32 @@ struct CylStArgs {
     const T* a1;         // [nz1][nx1]: a1 / h_r^2 on the face between rows j and j+1
     const T* a2;         // [nz1][nx1+1]: a2 / h_z^2 on the face left of column k (0 at both ends)
     const T* w;          // [nz1][nx1]
+    const double* b;     // residual mode: q = b - A p
     int nx1, nz1;
-    int gx, gy;          // column tiles, row strips; 1D grid of gx*gy*fields blocks
+    int gx, gy;          // column tiles, row strips; 1D grid of gx*gy*ceil(fields/nsh) blocks
+    int nfields, nsh;    // fields, fields per block (the medium stays in registers)
     ShotCtl* ctl;        // nullptr: plain application
     double* partial;
     size_t pstride;
 };
 
-template <typename T>
+template <typename T, bool RES>
 __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
     __shared__ double red[4];
     const int nx1 = a.nx1, nz1 = a.nz1;
     const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int L = xcd_linear(blockIdx.x, gridDim.x);
-    const int bx = L % a.gx, by = (L / a.gx) % a.gy, field = L / (a.gx * a.gy);
-    if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
+    const int bx = L % a.gx, by = (L / a.gx) % a.gy, grp = L / (a.gx * a.gy);
     const int k = bx * 64 + lane;
     const int j0 = (by * 4 + ty) * CY_RPT;
     const bool live = k < nx1;
     constexpr uint32_t SZ = sizeof(T);
     const uint32_t nf = (uint32_t)nx1 * (uint32_t)nz1;
-    const size_t fo = (size_t)field * nf;
-    const rsrc_t rp = buf_rsrc(a.p + fo, nf * SZ);
     const rsrc_t r1 = buf_rsrc(a.a1, nf * SZ);
     const rsrc_t r2 = buf_rsrc(a.a2, (uint32_t)nz1 * (uint32_t)(nx1 + 1) * SZ);
     const rsrc_t rw = buf_rsrc(a.w, nf * SZ);
-    // rows j0-1 .. j0+RPT of p (0 outside: the r = 0 face has no coefficient,
-    // the row past the last unknown is the Dirichlet side)
-    T pv[CY_RPT + 2], pe[CY_RPT], pw[CY_RPT], f1[CY_RPT + 1], fl[CY_RPT], fr[CY_RPT], wv[CY_RPT];
-#pragma unroll
-    for (int r = 0; r < CY_RPT + 2; ++r) {
-        const int j = j0 - 1 + r;
-        pv[r] = bload<T>(rp, (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
-    }
+    // medium of the tile, shared by the block's fields
+    T f1[CY_RPT + 1], fl[CY_RPT], fr[CY_RPT], wv[CY_RPT];
 #pragma unroll
     for (int r = 0; r < CY_RPT + 1; ++r) {       // faces j0-1|j0 .. j0+RPT-1|j0+RPT
         const int j = j0 - 1 + r;
@@ -83,28 +80,51 @@ __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
     for (int r = 0; r < CY_RPT; ++r) {
         const int j = j0 + r;
         const bool ok = live && j < nz1;
-        const uint32_t e = (uint32_t)(j * nx1 + k);
-        pe[r] = bload<T>(rp, (ok && k + 1 < nx1) ? (e + 1) * SZ : BUF_OOB);
-        pw[r] = bload<T>(rp, (ok && k > 0) ? (e - 1) * SZ : BUF_OOB);
         const uint32_t e2 = (uint32_t)(j * (nx1 + 1) + k);
         fl[r] = bload<T>(r2, ok ? e2 * SZ : BUF_OOB);
         fr[r] = bload<T>(r2, ok ? (e2 + 1) * SZ : BUF_OOB);
-        wv[r] = bload<T>(rw, ok ? e * SZ : BUF_OOB);
+        wv[r] = bload<T>(rw, ok ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
     }
-    double pq = 0.0;
-    const rsrc_t rq = buf_rsrc((a.q != nullptr ? a.q : const_cast<T*>(a.p)) + fo, a.q != nullptr ? nf * SZ : 0u);
+    const int f0 = grp * a.nsh, f1e = min(a.nfields, f0 + a.nsh);
+    for (int field = f0; field < f1e; ++field) {
+        if (a.ctl != nullptr && a.ctl[field].active == 0) continue;   // uniform per block
+        const size_t fo = (size_t)field * nf;
+        const rsrc_t rp = buf_rsrc(a.p + fo, nf * SZ);
+        // rows j0-1 .. j0+RPT of p (0 outside: the r = 0 face has no
+        // coefficient, the row past the last unknown is the Dirichlet side)
+        T pv[CY_RPT + 2], pe[CY_RPT], pw[CY_RPT];
 #pragma unroll
-    for (int r = 0; r < CY_RPT; ++r) {
-        const int j = j0 + r;
-        const T c = pv[r + 1];
-        const T v = fmad(f1[r + 1], c - pv[r + 2], f1[r] * (c - pv[r])) +
-                    fmad(fr[r], c - pe[r], fl[r] * (c - pw[r])) + wv[r] * c;
-        bstore<T>(v, rq, (live && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
-        pq += (double)c * (double)v;
+        for (int r = 0; r < CY_RPT + 2; ++r) {
+            const int j = j0 - 1 + r;
+            pv[r] = bload<T>(rp, (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
+        }
+#pragma unroll
+        for (int r = 0; r < CY_RPT; ++r) {
+            const int j = j0 + r;
+            const bool ok = live && j < nz1;
+            const uint32_t e = (uint32_t)(j * nx1 + k);
+            pe[r] = bload<T>(rp, (ok && k + 1 < nx1) ? (e + 1) * SZ : BUF_OOB);
+            pw[r] = bload<T>(rp, (ok && k > 0) ? (e - 1) * SZ : BUF_OOB);
+        }
+        double pq = 0.0;
+        const rsrc_t rq = buf_rsrc((a.q != nullptr ? a.q : const_cast<T*>(a.p)) + fo,
+                                   a.q != nullptr ? nf * SZ : 0u);
+        const rsrc_t rb = buf_rsrc(a.b + fo, RES ? nf * 8u : 0u);
+#pragma unroll
+        for (int r = 0; r < CY_RPT; ++r) {
+            const int j = j0 + r;
+            const uint32_t o = (live && j < nz1) ? (uint32_t)(j * nx1 + k) : BUF_OOB / 8u;
+            const T c = pv[r + 1];
+            T v = fmad(f1[r + 1], c - pv[r + 2], f1[r] * (c - pv[r])) +
+                  fmad(fr[r], c - pe[r], fl[r] * (c - pw[r])) + wv[r] * c;
+            if constexpr (RES) v = (T)(bload<double>(rb, o * 8u) - (double)v);
+            bstore<T>(v, rq, o * SZ);
+            pq += (double)c * (double)v;
+        }
+        if (a.ctl == nullptr) continue;
+        const double s = block_sum(pq, red);
+        if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + by * a.gx + bx] = s;
     }
-    if (a.ctl == nullptr) return;
-    const double s = block_sum(pq, red);
-    if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + by * a.gx + bx] = s;
 }
 
 // ===========================================================================
@@ -176,13 +196,15 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
             // rows of the input (or, UPDATE, the updated residual) -> symmetric extension
             T v0[NIT], v1[NIT];
             if constexpr (MODE == CY_UPDATE) {
+                // init 0: x += alpha p, r -= alpha q; 1: x = 0, r = b;
+                // 2: r as stored (x untouched)
                 const int init = a.init;
                 double* X = init ? a.x : *a.xslot;
-                if (init && blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
+                if (init == 1 && blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
                 const double alpha = init ? 0.0 : a.ctl[field].alpha;
                 const rsrc_t rX = buf_rsrc(X + fbase, init ? 0u : nfe * 8u);
-                const rsrc_t rXs = buf_rsrc(X + fbase, nfe * 8u);
-                const rsrc_t rR = buf_rsrc(init ? a.b + fbase : a.r + fbase, nfe * 8u);
+                const rsrc_t rXs = buf_rsrc(X + fbase, init == 2 ? 0u : nfe * 8u);
+                const rsrc_t rR = buf_rsrc(init == 1 ? a.b + fbase : a.r + fbase, nfe * 8u);
                 const rsrc_t rRs = buf_rsrc(a.r + fbase, nfe * 8u);
                 const rsrc_t rP = buf_rsrc(a.p + fbase, init ? 0u : nfe * SZ);
                 const rsrc_t rQ = buf_rsrc(a.q + fbase, init ? 0u : nfe * SZ);
@@ -391,22 +413,27 @@ __global__ __launch_bounds__(256) void cyl_thomas_kernel(CylTdArgs<T> a) {
 // ===========================================================================
 namespace {
 
-template <typename T>
-hipError_t cyl_stencil_T(lg_plan* p, const T* x, T* y, bool reduce, int nfields) {
+template <typename T, bool RES>
+hipError_t cyl_stencil_T(lg_plan* p, const T* x, T* y, bool reduce, int nfields, const T* a1, const T* a2,
+                         const T* w, const double* b) {
     CylStArgs<T> a;
     a.p = x;
     a.q = y;
-    a.a1 = (const T*)p->cy_a1;
-    a.a2 = (const T*)p->cy_a2;
-    a.w = (const T*)p->w;
+    a.a1 = a1;
+    a.a2 = a2;
+    a.w = w;
+    a.b = b;
     a.nx1 = p->nx1;
     a.nz1 = p->nz1;
     a.gx = (p->nx1 + 63) / 64;
     a.gy = (p->nz1 + 4 * CY_RPT - 1) / (4 * CY_RPT);
+    a.nfields = nfields;
+    a.nsh = std::max(1, std::min(nfields, p->op_shots));
     a.ctl = reduce ? p->ctl : nullptr;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
-    hipLaunchKernelGGL(cyl_stencil_kernel<T>, dim3(a.gx * a.gy * nfields), dim3(256), 0, p->stream, a);
+    const int groups = (nfields + a.nsh - 1) / a.nsh;
+    hipLaunchKernelGGL((cyl_stencil_kernel<T, RES>), dim3(a.gx * a.gy * groups), dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !reduce) return e;
     return launch_finalize(p, 0 /* (p, Ap) */, a.gx * a.gy, 0, 0.0, 0, 0.0);
@@ -484,8 +511,25 @@ hipError_t cyl_thomas_T(lg_plan* p, const T* rhat, T* z, int nfields, int mode) 
 
 hipError_t cyl_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce) {
     const int nf = p->S * p->C;
-    if (p->prec == LG_FP64) return cyl_stencil_T<double>(p, (const double*)x, (double*)y, reduce, nf);
-    return cyl_stencil_T<float>(p, (const float*)x, (float*)y, reduce, nf);
+    if (p->prec == LG_FP64)
+        return cyl_stencil_T<double, false>(p, (const double*)x, (double*)y, reduce, nf, (const double*)p->cy_a1,
+                                            (const double*)p->cy_a2, (const double*)p->w, nullptr);
+    return cyl_stencil_T<float, false>(p, (const float*)x, (float*)y, reduce, nf, (const float*)p->cy_a1,
+                                       (const float*)p->cy_a2, (const float*)p->w, nullptr);
+}
+
+hipError_t cyl_launch_restart(lg_plan* p, const double* b, double* x, double tol, int max_iter) {
+    // r = b - A x with the FP64 operator (FP64 tables of a mixed plan), then
+    // the transform pass from the stored r; the finalize re-checks the shots
+    // that had met the tolerance
+    const int nf = p->S * p->C;
+    const bool f64 = p->prec == LG_FP64;
+    const double* a1 = f64 ? (const double*)p->cy_a1 : p->cy_a1_64;
+    const double* a2 = f64 ? (const double*)p->cy_a2 : p->cy_a2_64;
+    const double* w = f64 ? (const double*)p->w : p->w64;
+    hipError_t e = cyl_stencil_T<double, true>(p, x, p->r, false, nf, a1, a2, w, b);
+    if (e != hipSuccess) return e;
+    return cyl_launch_update(p, 2, b, x, tol, max_iter);
 }
 
 hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields) {
@@ -529,7 +573,7 @@ hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, d
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;
-    return launch_finalize(p, 1 /* ||r||^2 */, bpf, init, tol * tol, max_iter, 0.0);
+    return launch_finalize(p, 1 /* ||r||^2 */, bpf, init, tol * tol, max_iter, 0.0);   // init 2: restart check
 }
 
 hipError_t cyl_launch_correct(lg_plan* p, int init) {

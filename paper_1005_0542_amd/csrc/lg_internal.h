@@ -95,6 +95,8 @@ struct lg_plan {
     void* cy_cp = nullptr;     // [nz1][nx1]: Thomas upper factors of B's r-systems
     void* cy_invden = nullptr; // [nz1][nx1]: inverse pivots
     void* cy_lowr = nullptr;   // [nz1]: coupling of row j to row j-1 (0 for the first)
+    double* cy_a1_64 = nullptr;   // mixed plans: FP64 copies of cy_a1, cy_a2 (true residual)
+    double* cy_a2_64 = nullptr;
     double src_scale = 0.0;    // discrete delta: 1/(dx dz), or 1/(2 pi h_r h_z)
     int device = 0;
     hipStream_t stream = nullptr;
@@ -173,7 +175,10 @@ hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double to
 hipError_t cyl_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce);
 hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields);
 hipError_t cyl_launch_thomas(lg_plan* p, const void* rhat, void* z, int nfields, int mode);
+// init 0 iteration, 1 start (x = 0, r = b), 2 restart from the stored r
 hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, double tol, int max_iter);
+// FP64 true residual r = b - A x, then the update pass with init 2
+hipError_t cyl_launch_restart(lg_plan* p, const double* b, double* x, double tol, int max_iter);
 hipError_t cyl_launch_correct(lg_plan* p, int init);
 hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,
                       const double* fsrc_host, double* rhs);

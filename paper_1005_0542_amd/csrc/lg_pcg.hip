@@ -133,10 +133,16 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
     // restart CG from it (iterative refinement with an FP64 residual).
     if (p->prec == LG_MIXED) {
         for (int rep = 0; rep < 4; ++rep) {
-            LG_HIP(launch_update_fdst(p, 3, b, x, o->tol, o->max_iter));   // r = b - A x (FP64), restart
-            LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
-            LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
-            LG_HIP(launch_correct_idst(p, 1));
+            if (p->cyl) {                                                  // r = b - A x (FP64), restart
+                LG_HIP(cyl_launch_restart(p, b, x, o->tol, o->max_iter));
+                LG_HIP(cyl_launch_thomas(p, p->rhat, p->y, nf, 1));
+                LG_HIP(cyl_launch_correct(p, 1));
+            } else {
+                LG_HIP(launch_update_fdst(p, 3, b, x, o->tol, o->max_iter));
+                LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
+                LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
+                LG_HIP(launch_correct_idst(p, 1));
+            }
             LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
                                   p->stream));
             LG_HIP(hipStreamSynchronize(p->stream));

@@ -146,6 +146,12 @@ lg_status prepare_cylindrical(lg_plan* pl, const double* kap) {
     lg_status st = upload_working(pl, &pl->cy_a1, a1);
     if (st != LG_OK) return st;
     if ((st = upload_working(pl, &pl->cy_a2, a2)) != LG_OK) return st;
+    if (pl->prec == LG_MIXED) {   // FP64 operator for the true residual
+        if ((st = dev_alloc(pl, &pl->cy_a1_64, a1.size() * 8)) != LG_OK) return st;
+        if ((st = dev_alloc(pl, &pl->cy_a2_64, a2.size() * 8)) != LG_OK) return st;
+        LG_HIP(hipMemcpy(pl->cy_a1_64, a1.data(), a1.size() * 8, hipMemcpyHostToDevice));
+        LG_HIP(hipMemcpy(pl->cy_a2_64, a2.data(), a2.size() * 8, hipMemcpyHostToDevice));
+    }
     std::vector<double> ctw(2 * (size_t)nx1);
     for (int k = 0; k < nx1; ++k) {
         ctw[2 * k] = (double)std::cos(pi * k / (2.0L * nx1));
@@ -251,7 +257,7 @@ void free_plan(lg_plan* p) {
                     p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
-                    p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr};
+                    p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -405,8 +411,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (grid->geometry != LG_CARTESIAN && grid->geometry != LG_CYLINDRICAL)
         return fail(LG_ERR_INVALID_ARG, "geometry must be LG_CARTESIAN or LG_CYLINDRICAL");
     const bool cyl = grid->geometry == LG_CYLINDRICAL;
-    if (cyl && (kind != LG_ACOUSTIC || prec != LG_FP64))
-        return fail(LG_ERR_UNSUPPORTED, "the axisymmetric geometry is implemented for FP64 acoustic plans");
+    if (cyl && kind != LG_ACOUSTIC)
+        return fail(LG_ERR_UNSUPPORTED, "the axisymmetric geometry is implemented for acoustic plans");
     int P = 0, gi = 8, osh = 8, spw = 0, fus = 1;
     if (tuning != nullptr) {
         P = tuning->segments;
@@ -496,6 +502,11 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         p->blk[0].P = 1;
         p->blk[0].Ls = grid->nz;
         if ((st = prepare_cylindrical(p, medium_host)) != LG_OK) return bail(st);
+        if (prec == LG_MIXED) {
+            if ((st = dev_alloc(p, &p->w64, p->npts * 8)) != LG_OK) return bail(st);
+            if ((he = hipMemcpy(p->w64, w_int.data(), p->npts * 8, hipMemcpyHostToDevice)) != hipSuccess)
+                return bail(hip_fail(he, "hipMemcpy"));
+        }
     } else if (kind == LG_ACOUSTIC) {
         std::vector<double> kap(medium_host, medium_host + nn);
         if ((st = upload_working(p, &p->kap, kap)) != LG_OK) return bail(st);

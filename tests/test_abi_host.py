@@ -84,10 +84,9 @@ def test_plan_create_unsupported_shapes():
     assert _create(nx=8192, nz=16) == _lib.LG_ERR_UNSUPPORTED
     # the free surface is implemented for acoustic plans only
     assert _create(kind=_lib.LG_ELASTIC, top=_lib.LG_TOP_FREE) == _lib.LG_ERR_UNSUPPORTED
-    # the axisymmetric geometry: FP64 acoustic plans, unsegmented r-systems
+    # the axisymmetric geometry: acoustic plans, unsegmented r-systems
     cyl = _lib.LG_CYLINDRICAL
     assert _create(kind=_lib.LG_ELASTIC, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
-    assert _create(prec=_lib.LG_MIXED, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
     assert _create(segments=4, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
     assert _create(nx=24, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
 

@@ -24,75 +24,87 @@ def _medium(nr, nz, seed=1):
     return np.ascontiguousarray(kappa[:nz, :nr].T), np.ascontiguousarray(rho[:nz, :nr].T)
 
 
-def _plan(nr, nz, kappa, rho, hr=10.0, hz=10.0, h=200.0, shots=1, graph_iters=0, n=8):
-    return api.Plan("acoustic", nz, nr, hz, hr, 9, h, n, np.stack([kappa, rho]), precision="fp64",
-                    nshots=shots, graph_iters=graph_iters, geometry="cylindrical")
+def _plan(nr, nz, kappa, rho, hr=10.0, hz=10.0, h=200.0, shots=1, graph_iters=0, n=8, precision="fp64",
+          op_shots=0):
+    return api.Plan("acoustic", nz, nr, hz, hr, 9, h, n, np.stack([kappa, rho]), precision=precision,
+                    nshots=shots, graph_iters=graph_iters, op_shots=op_shots, geometry="cylindrical")
+
+
+def _wdt(prec):
+    torch = torch_cuda()
+    return torch.float64 if prec == "fp64" else torch.float32
+
+
+# FP64: rounding level; mixed: the FP32 working type (operator and transforms
+# a few FP32 ulps of the largest term, the r-recurrences a few hundred)
+TOL = {"fp64": {"op": 1e-13, "dct": 1e-13, "tdma": 1e-12},
+       "mixed": {"op": 2e-6, "dct": 5e-6, "tdma": 5e-5}}
 
 
 SHAPES = [(16, 16, 1), (32, 64, 3), (2, 4, 1), (4, 2, 2), (256, 128, 2), (64, 512, 1), (1024, 8, 1)]
 
 
-@pytest.mark.parametrize("nr,nz,shots", SHAPES)
-def test_cylindrical_stencil_parity(nr, nz, shots):
-    torch = torch_cuda()
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("nr,nz,shots,osh", [s + (0,) for s in SHAPES] + [(64, 128, 5, 2), (32, 64, 7, 3)])
+def test_cylindrical_stencil_parity(prec, nr, nz, shots, osh):
     kappa, rho = _medium(nr, nz)
     hr, hz, h = 7.0, 5.0, 300.0
-    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots)
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots, precision=prec, op_shots=osh)
     x = np.random.default_rng(nr + 3 * nz).standard_normal((shots, 1, nr - 1, nz))
-    log(f"cylindrical stencil Nr={nr} Nz={nz} shots={shots}")
-    xd = to_dev(x, torch.float64)
-    yd = torch.empty_like(xd)
+    log(f"cylindrical stencil {prec} Nr={nr} Nz={nz} shots={shots} op_shots={osh}")
+    xd = to_dev(x, _wdt(prec))
+    yd = torch_cuda().empty_like(xd)
     plan.stencil_apply(xd, yd)
     a1, a2, w = cyl.coefficients(kappa, rho, h, hr)
-    ref = cyl.apply_A(x, a1, a2, w, hr, hz)
-    assert rel(to_np(yd), ref) < 1e-13
+    ref = cyl.apply_A(to_np(xd), a1, a2, w, hr, hz)
+    assert rel(to_np(yd), ref) < TOL[prec]["op"]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("nr,nz,shots", SHAPES)
-def test_cylindrical_dct_parity(nr, nz, shots):
-    torch = torch_cuda()
+def test_cylindrical_dct_parity(prec, nr, nz, shots):
     kappa, rho = _medium(nr, nz)
-    plan = _plan(nr, nz, kappa, rho, shots=shots)
+    plan = _plan(nr, nz, kappa, rho, shots=shots, precision=prec)
     x = np.random.default_rng(nz).standard_normal((shots, 1, nr - 1, nz))
-    log(f"cylindrical dct Nr={nr} Nz={nz} shots={shots}")
-    xd = to_dev(x, torch.float64)
-    cd = torch.empty_like(xd)
+    log(f"cylindrical dct {prec} Nr={nr} Nz={nz} shots={shots}")
+    xd = to_dev(x, _wdt(prec))
+    cd = torch_cuda().empty_like(xd)
     plan.precond_dst(False, xd, cd)
-    assert rel(to_np(cd), cyl.dct2_direct(x)) < 1e-13
-    back = torch.empty_like(xd)
+    assert rel(to_np(cd), cyl.dct2_direct(to_np(xd))) < TOL[prec]["dct"]
+    back = torch_cuda().empty_like(xd)
     plan.precond_dst(True, cd, back)
-    assert rel(to_np(back), cyl.idct2(to_np(cd))) < 1e-13
-    assert rel(to_np(back), x) < 1e-13
+    assert rel(to_np(back), cyl.idct2(to_np(cd))) < TOL[prec]["dct"]
+    assert rel(to_np(back), to_np(xd)) < TOL[prec]["dct"]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("nr,nz,shots", SHAPES)
-def test_cylindrical_thomas_parity(nr, nz, shots):
-    torch = torch_cuda()
+def test_cylindrical_thomas_parity(prec, nr, nz, shots):
     kappa, rho = _medium(nr, nz)
     hr, hz, h = 6.0, 9.0, 250.0
-    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots)
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots, precision=prec)
     B = cyl.preconditioner(kappa, rho, h, hr, hz)
     rhs = np.random.default_rng(nr).standard_normal((shots, nr - 1, nz))
-    log(f"cylindrical thomas Nr={nr} Nz={nz} shots={shots}")
-    rd = to_dev(rhs, torch.float64)
-    sd = torch.empty_like(rd)
+    log(f"cylindrical thomas {prec} Nr={nr} Nz={nz} shots={shots}")
+    rd = to_dev(rhs, _wdt(prec))
+    sd = torch_cuda().empty_like(rd)
     plan.precond_dichotomy_tdma(0, rd, sd)
-    assert rel(to_np(sd), B.tridiag_solve(rhs)) < 1e-12
+    assert rel(to_np(sd), B.tridiag_solve(to_np(rd))) < TOL[prec]["tdma"]
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("nr,nz", [(16, 16), (64, 64), (256, 256), (128, 1024)])
-def test_cylindrical_precond_apply_parity(nr, nz):
-    torch = torch_cuda()
+def test_cylindrical_precond_apply_parity(prec, nr, nz):
     kappa, rho = _medium(nr, nz)
     hr, hz, h = 5.0, 5.0, 300.0
-    plan = _plan(nr, nz, kappa, rho, hr, hz, h)
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, precision=prec)
     B = cyl.preconditioner(kappa, rho, h, hr, hz)
     r = np.random.default_rng(nr + nz).standard_normal((1, 1, nr - 1, nz))
-    log(f"cylindrical precond_apply Nr={nr} Nz={nz}")
-    rd = to_dev(r, torch.float64)
-    zd = torch.empty_like(rd)
+    log(f"cylindrical precond_apply {prec} Nr={nr} Nz={nz}")
+    rd = to_dev(r, _wdt(prec))
+    zd = torch_cuda().empty_like(rd)
     plan.precond_apply(rd, zd)
-    assert rel(to_np(zd)[0, 0], B.solve(r[0, 0])) < 1e-12
+    assert rel(to_np(zd)[0, 0], B.solve(to_np(rd)[0, 0])) < TOL[prec]["tdma"]
 
 
 def _oracle_pcg(kappa, rho, h, hr, hz, b, tol, max_iter=2000):
@@ -118,6 +130,28 @@ def test_cylindrical_pcg_parity_fp64(nr, nz, shots, gi):
         assert res.statuses[s] == OK and sto == OK
         assert res.iters[s] == ito, (s, res.iters, ito)
         assert rel(to_np(xd)[s, 0], xo) < 1e-12
+
+
+@pytest.mark.parametrize("nr,nz,shots", [(64, 64, 2), (256, 512, 3)])
+def test_cylindrical_pcg_mixed_true_residual(nr, nz, shots):
+    """Mixed plans: CG on the FP32 operator and preconditioner, restarted from
+    the FP64 true residual b - A x until it meets the tolerance."""
+    torch = torch_cuda()
+    kappa, rho = _medium(nr, nz)
+    hr, hz, h = 10.0, 10.0, 200.0
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots, precision="mixed", graph_iters=8)
+    b = np.random.default_rng(9).standard_normal((shots, 1, nr - 1, nz))
+    log(f"cylindrical pcg mixed Nr={nr} Nz={nz} shots={shots}")
+    bd = to_dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    res = plan.pcg_solve(bd, xd, tol=1e-9, max_iter=2000)
+    assert res.statuses == [OK] * shots
+    a1, a2, w = cyl.coefficients(kappa, rho, h, hr)
+    for s in range(shots):
+        r = b[s, 0] - cyl.apply_A(to_np(xd)[s, 0], a1, a2, w, hr, hz)
+        assert np.linalg.norm(r) <= 1.5e-9 * np.linalg.norm(b[s, 0])
+        xo = _oracle_pcg(kappa, rho, h, hr, hz, b[s, 0], 1e-12)[0]
+        assert rel(to_np(xd)[s, 0], xo) < 1e-6
 
 
 def test_cylindrical_pcg_zero_rhs_and_constant_medium():
@@ -171,7 +205,8 @@ def test_cylindrical_profile_runs_the_iteration():
         assert rel(to_np(xd)[s, 0], xo) < 1e-12
 
 
-def test_cylindrical_harmonic_chain_fp64():
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cylindrical_harmonic_chain(prec):
     """16 harmonics of an axisymmetric point source on the axis (row i = 1):
     the right-hand side (1/2 pi) delta_h f_m - h^2 r rho Q_m from the library's
     running sums, PCG per harmonic and the snapshot synthesis against the
@@ -180,13 +215,15 @@ def test_cylindrical_harmonic_chain_fp64():
     problem is sensitive to rounding: two FP64 oracle chains whose
     preconditioner outputs differ by 1e-16 relative noise stop one iteration
     apart on some harmonics and differ by up to 3e-13 per harmonic at this
-    tolerance (3e-11 at tolerance 1e-10)."""
+    tolerance (3e-11 at tolerance 1e-10).  Mixed plans (CG tolerance 1e-9,
+    FP64 true-residual refinement) stay within 1e-6 of the FP64 chain."""
     torch = torch_cuda()
     nr, nz, n_harm = 64, 128, 16
     hr = hz = 10.0
     alpha, h = 9, 400.0
     kappa, rho = _medium(nr, nz, seed=5)
-    plan = _plan(nr, nz, kappa, rho, hr, hz, h, n=n_harm)
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, n=n_harm, precision=prec)
+    mixed = prec == "mixed"
     src = np.array([[nz // 2, 1]], dtype=np.int32)       # (k, i): axis row, mid-depth
     plan.set_sources(src)
     f_m = laguerre.ricker_coeffs(25.0, 0.05, h, alpha, n_harm)
@@ -206,21 +243,21 @@ def test_cylindrical_harmonic_chain_fp64():
     Rprev, snap_o = None, np.zeros((2, nr - 1, nz))
     worst = 0.0
     for m in range(n_harm):
-        log(f"cylindrical chain harmonic {m}")
+        log(f"cylindrical chain {prec} harmonic {m}")
         plan.laguerre_rhs(m, R if m else None, Ph, Qh, [f_m[m]], rhs)
         phi = cyl.source_field((nr - 1, nz), (nz // 2, 1), f_m[m], hr, hz) - \
             h * h * r_rho * sums.step(m, Rprev)
-        assert rel(to_np(rhs)[0, 0], phi) < 1e-11, m
-        res = plan.pcg_solve(rhs, R, tol=1e-12, max_iter=2000)
+        assert rel(to_np(rhs)[0, 0], phi) < (1e-6 if mixed else 1e-11), m
+        res = plan.pcg_solve(rhs, R, tol=1e-9 if mixed else 1e-12, max_iter=2000)
         plan.laguerre_synthesize(m, R, Ws[:, m], snap)
         Ro, ito, _, sto = krylov.pcg(lambda y: cyl.apply_A(y, a1, a2, w, hr, hz), B.solve, phi, 1e-12, 2000)
         assert res.statuses == [OK] and sto == OK
-        assert abs(res.iters[0] - ito) <= 2, (m, res.iters, ito)
+        assert mixed or abs(res.iters[0] - ito) <= 2, (m, res.iters, ito)
         e = rel(to_np(R)[0, 0], Ro)
         worst = max(worst, e)
-        assert e < 1e-11, (m, e)
+        assert e < (1e-6 if mixed else 1e-11), (m, e)
         snap_o += Ws[:, m][:, None, None] * Ro[None]
         Rprev = Ro
     es = rel(to_np(snap)[:, 0, 0], snap_o)
-    print(f"cylindrical chain: worst per-harmonic error {worst:.2e}, snapshots {es:.2e}")
-    assert es < 1e-11
+    print(f"cylindrical chain {prec}: worst per-harmonic error {worst:.2e}, snapshots {es:.2e}")
+    assert es < (1e-6 if mixed else 1e-11)
