@@ -609,3 +609,139 @@ def test_cylindrical_radial_operator_converges_to_bessel_eigenvalue():
     assert errs[-1] < 1e-3 * (j01 / l1) ** 2
     for e0, e1 in zip(errs, errs[1:]):
         assert 3.0 < e0 / e1 < 5.0          # second order
+
+
+# ---------------------------------------------------------------------------
+# Fourth-order operator preconditioned by the second-order B (Sec. 3.3)
+# ---------------------------------------------------------------------------
+from oracle import highorder as ho
+
+
+def _ho_medium(nx, nz, seed=3, jump=True):
+    rng = np.random.default_rng(seed)
+    k = 1.0 + 0.3 * rng.uniform(size=(nz + 1, nx + 1))
+    if jump:
+        k[: (nz + 1) // 2] *= 3.0
+    return k, rng.uniform(1e-7, 5e-7, (nz + 1, nx + 1))
+
+
+def test_order4_operator_dense_symmetric_positive():
+    nx, nz, dx, dz, h = 9, 7, 3.0, 5.0, 300.0
+    kappa, rho = _ho_medium(nx, nz)
+    kx, kz = ho.face_coeffs4(kappa)
+    w = operator.shift_coeff(rho, h)
+    M = ho.assemble_A4(kx, kz, w, dx, dz)
+    y = np.random.default_rng(1).standard_normal((2, nz - 1, nx - 1))
+    Ay = ho.apply_A4(y, kx, kz, w, dx, dz)
+    for s in range(2):
+        assert np.max(np.abs(M @ y[s].ravel() - Ay[s].ravel())) < 1e-13 * np.max(np.abs(Ay))
+    assert np.allclose(M, M.T, rtol=0, atol=1e-15 * np.max(np.abs(M)))
+    assert np.linalg.eigvalsh(M).min() > 0
+    # a strong jump (contrast 20): the interpolant would turn negative there,
+    # the guard takes the two-point mean; every face stays >= half its smaller node
+    k = np.ones(11)
+    k[6:] = 20.0
+    f = ho.interp_faces4(k)
+    assert np.all(f >= 0.5 * np.minimum(k[:-1], k[1:]))
+    assert f[4] == 1.0                                        # (-1 + 9 + 9 - 20)/16 < 1/2: the mean
+    assert f[5] == (-1 + 9 + 180 - 20) / 16 and f[6] == (-1 + 180 + 180 - 20) / 16
+    assert f[2] == 1.0 and f[7] == 20.0
+
+
+def test_order4_sine_modes_have_the_closed_form_eigenvalues():
+    """Constant kappa, w = 0: grid sine modes are eigenvectors (the odd
+    reflection is exact for them) with [(27 sin(t/2) - sin(3t/2))/(12 h)]^2
+    per axis, t = pi k / N; against the second-order [2 sin(t/2)/h]^2 the
+    ratio lies in [1, (7/6)^2]."""
+    nx, nz, dx, dz = 16, 8, 2.0, 3.0
+    kappa = np.ones((nz + 1, nx + 1))
+    kx, kz = ho.face_coeffs4(kappa)
+    w = np.zeros((nz - 1, nx - 1))
+    x = np.arange(1, nx)[None, :]
+    z = np.arange(1, nz)[:, None]
+    for k, l in ((1, 1), (3, 5), (15, 7), (8, 2)):
+        mode = np.sin(np.pi * k * x / nx) * np.sin(np.pi * l * z / nz)
+        lam = ho.sine_eigenvalue4(k, nx, dx) + ho.sine_eigenvalue4(l, nz, dz)
+        assert np.max(np.abs(ho.apply_A4(mode, kx, kz, w, dx, dz) - lam * mode)) < 1e-12 * lam
+    t = np.linspace(1e-3, np.pi, 200)
+    ratio = ho.sine_eigenvalue4(t * 64 / np.pi, 64, 1.0) / (2.0 * np.sin(t / 2)) ** 2
+    assert ratio.min() >= 1.0 - 1e-9 and ratio.max() <= (7.0 / 6.0) ** 2 + 1e-9
+
+
+def _manufactured(n, even_medium):
+    """Unit square, N x N cells: y = sin(pi x) sin(2 pi z) (zero on the sides,
+    with y'' = 0 there), kappa = 1 + 0.3 cos(2 pi x) cos(2 pi z) (even about every
+    side: the flux kappa y' is then even there, as the odd reflection assumes)
+    or 1 + 0.3 sin(2x + 1) cos(3z); f = -div(kappa grad y), w = 0."""
+    hg = 1.0 / n
+    xs = np.arange(n + 1) * hg
+    X, Z = np.meshgrid(xs, xs)                           # [z][x]
+    if even_medium:
+        kap = 1.0 + 0.3 * np.cos(2 * np.pi * X) * np.cos(2 * np.pi * Z)
+        kdx = -0.6 * np.pi * np.sin(2 * np.pi * X) * np.cos(2 * np.pi * Z)
+        kdz = -0.6 * np.pi * np.cos(2 * np.pi * X) * np.sin(2 * np.pi * Z)
+    else:
+        kap = 1.0 + 0.3 * np.sin(2 * X + 1) * np.cos(3 * Z)
+        kdx = 0.6 * np.cos(2 * X + 1) * np.cos(3 * Z)
+        kdz = -0.9 * np.sin(2 * X + 1) * np.sin(3 * Z)
+    y = np.sin(np.pi * X) * np.sin(2 * np.pi * Z)
+    yx = np.pi * np.cos(np.pi * X) * np.sin(2 * np.pi * Z)
+    yz = 2 * np.pi * np.sin(np.pi * X) * np.cos(2 * np.pi * Z)
+    f = -(kap * (-5 * np.pi ** 2) * y + kdx * yx + kdz * yz)
+    return hg, kap, y[1:-1, 1:-1], f[1:-1, 1:-1]
+
+
+def test_order4_truncation_error_is_fourth_order_inside():
+    """Away from the sides (3 nodes in) the truncation error falls 16x per
+    halving for any smooth medium (8x for the second-order operator is 4x)."""
+    e4, e2 = [], []
+    for n in (16, 32, 64):
+        hg, kap, y, f = _manufactured(n, even_medium=False)
+        kx, kz = ho.face_coeffs4(kap)
+        w = np.zeros_like(y)
+        e4.append(np.max(np.abs(ho.apply_A4(y, kx, kz, w, hg, hg) - f)[3:-3, 3:-3]))
+        e2.append(np.max(np.abs(operator.apply_A(y, kap, w, hg, hg) - f)[3:-3, 3:-3]))
+    for a, b in zip(e4, e4[1:]):
+        assert 14.0 < a / b < 18.0
+    for a, b in zip(e2, e2[1:]):
+        assert 3.5 < a / b < 4.5
+
+
+def test_order4_solution_error_is_fourth_order():
+    """The discrete solution of A4 y = f converges at fourth order (the
+    second-order operator at second) when the reflection at the sides is
+    consistent with the solution (y'' = 0 and an even flux there: for the
+    Laguerre harmonics the right-hand side vanishes on the sides)."""
+    e4, e2 = [], []
+    for n in (16, 32, 64):
+        hg, kap, y, f = _manufactured(n, even_medium=True)
+        kx, kz = ho.face_coeffs4(kap)
+        w = np.zeros_like(y)
+        B = precond.acoustic_preconditioner(kap, np.zeros_like(kap), 0.0, n, n, hg, hg)
+        s4 = krylov.pcg(lambda v: ho.apply_A4(v, kx, kz, w, hg, hg), B.solve, f, 1e-13, 2000)[0]
+        s2 = krylov.pcg(lambda v: operator.apply_A(v, kap, w, hg, hg), B.solve, f, 1e-13, 2000)[0]
+        e4.append(np.max(np.abs(s4 - y)))
+        e2.append(np.max(np.abs(s2 - y)))
+    for a, b in zip(e4, e4[1:]):
+        assert 14.0 < a / b < 18.0
+    for a, b in zip(e2, e2[1:]):
+        assert 3.5 < a / b < 4.5
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_order4_pcg_with_second_order_preconditioner(n):
+    """PCG on A4 with the second-order B converges to the dense solution, in
+    at most (7/6) times the iterations of the second-order operator plus a few."""
+    kappa, rho = _ho_medium(n, n, seed=5, jump=False)
+    h, d = 200.0, 10.0
+    w = operator.shift_coeff(rho, h)
+    kx, kz = ho.face_coeffs4(kappa)
+    B = precond.acoustic_preconditioner(kappa, rho, h, n, n, d, d)
+    b = np.random.default_rng(2).standard_normal((n - 1, n - 1))
+    x4, it4, rr4, st4 = krylov.pcg(lambda y: ho.apply_A4(y, kx, kz, w, d, d), B.solve, b, 1e-10, 500)
+    x2, it2, rr2, st2 = krylov.pcg(lambda y: operator.apply_A(y, kappa, w, d, d), B.solve, b, 1e-10, 500)
+    assert st4 == OK and st2 == OK
+    assert it2 <= it4 <= 7 * it2 / 6 + 3
+    if n == 32:
+        xs = np.linalg.solve(ho.assemble_A4(kx, kz, w, d, d), b.ravel()).reshape(b.shape)
+        assert np.max(np.abs(x4 - xs)) < 1e-8 * np.max(np.abs(xs))
