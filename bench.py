@@ -36,15 +36,17 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True):
+def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True, medium: int = 2):
     """Algorithmic HBM bytes per shot-point for each kernel of one CG iteration
     (every array touched once per launch; medium arrays shared by all shots).
-    fused: the update recomputes A p, so the operator kernel stores no q."""
+    fused: the update recomputes A p, so the operator kernel stores no q.
+    medium: operator tables per point (kappa, w; the fourth-order operator
+    reads its x- and z-face tables and w)."""
     if fused:
         op = ws + 2 * ws / shots                              # p in; kappa, w once per batch
         upd = 32 + 2 * ws + 2 * ws / shots                    # x, r in/out (f64); p in; rhat out; medium
     else:
-        op = 2 * ws + 2 * ws / shots                          # p in, q out; kappa, w once per batch
+        op = 2 * ws + medium * ws / shots                     # p in, q out; medium once per batch
         upd = 32 + 3 * ws                                     # x, r in/out (f64); p, q in; rhat out
     return {
         "operator": op,
@@ -139,7 +141,7 @@ def tuned_params(name, precision, shots, enabled=True):
 
 
 def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0, profile=True,
-                tuned=None, profile_iters=20, top="dirichlet", geometry="cartesian"):
+                tuned=None, profile_iters=20, top="dirichlet", geometry="cartesian", order=2):
     import torch
     from paper_1005_0542_amd import inputs
     from paper_1005_0542_amd.driver import AcousticRun
@@ -156,7 +158,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2),
                       segments=tuned.get("segments", 0), graph_iters=tuned.get("graph_iters", 0),
                       op_shots=tuned.get("op_shots", 0), seg_per_wave=tuned.get("seg_per_wave", 0),
-                      op_fusion=tuned.get("op_fusion", 0), top=top, geometry=geometry)
+                      op_fusion=tuned.get("op_fusion", 0), top=top, geometry=geometry, order=order)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     cyl = geometry == "cylindrical"
@@ -174,6 +176,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     pt_iters = float(npts) * float(np.sum(iters))
     out = {
         "workload": name, "precision": precision, "shots": shots, "top": top, "geometry": geometry,
+        "order": order,
         "value": pt_iters / el / 1e6, "ms_per_step": 1e3 * el / steps,
         "iters_per_harmonic": [int(max(i)) for i in iters],
         "mean_iters": float(np.mean(iters)),
@@ -183,7 +186,12 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     seg, seg_len = run.plan.layout()
     out["segments"] = seg
     ws = 8 if precision == "fp64" else 4
-    kb = cyl_kernel_bytes(ws, shots) if cyl else kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
+    if cyl:
+        kb = cyl_kernel_bytes(ws, shots)
+    elif order == 4:
+        kb = kernel_bytes(ws, shots, seg_len, fused=False, medium=3)
+    else:
+        kb = kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
     slots = [0, 1, 2, 4] if cyl else [0, 1, 2, 3, 4]          # the profile helper's kernel slots
     per_iter_bytes = sum(kb.values()) * npts * shots
     mean_it = max(out["mean_iters"], 1e-9)
@@ -294,7 +302,9 @@ def main():
     ap.add_argument("--seg-per-wave", type=int, default=0, help="override (profile-only)")
     ap.add_argument("--op-fusion", type=int, default=0, help="override (profile-only): 1 fused, 2 stored q")
     ap.add_argument("--geometry", default="cartesian", choices=("cartesian", "cylindrical"),
-                    help="profile-only: the 2D Cartesian or the 2.5D axisymmetric problem (FP64)")
+                    help="profile-only: the 2D Cartesian or the 2.5D axisymmetric problem")
+    ap.add_argument("--order", type=int, default=2, choices=(2, 4),
+                    help="profile-only: the second- or fourth-order operator (Cartesian)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -323,10 +333,13 @@ def main():
         geo = args.geometry
         tp = tuned_params(args.workload, prec, shots, not args.no_tune and geo == "cartesian")
         tp.update({k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion") if getattr(args, k)})
+        if args.order == 4:
+            tp["op_fusion"] = 2
         v = run_variant(args.workload, prec, shots, args.steps, args.warmup, segments=args.segments,
-                        graph_iters=args.graph_iters, tuned=tp, profile_iters=args.profile_iters, geometry=geo)
+                        graph_iters=args.graph_iters, tuned=tp, profile_iters=args.profile_iters, geometry=geo,
+                        order=args.order)
         v.pop("_run")
-        print(json.dumps({k: v[k] for k in ("workload", "precision", "shots", "geometry", "segments", "kernels",
+        print(json.dumps({k: v[k] for k in ("workload", "precision", "shots", "geometry", "order", "segments", "kernels",
                                             "iteration_ms_profiled")} | {"tuned": tp,
                                                                          "profile_iterations": args.profile_iters}))
         return
@@ -347,15 +360,21 @@ def main():
             ("acoustic2048x64_mixed", "mixed", 64, "mixed_64shot_2048_free_surface", "free"),
             # the paper's 2.5D axisymmetric problem, N_r x N_z = 2048 x 2048, sources on the axis
             ("acoustic2048x64_mixed", "fp64", 64, "fp64_64shot_2048_axisymmetric", "cylindrical"),
+            ("acoustic2048x64_mixed", "mixed", 64, "mixed_64shot_2048_axisymmetric", "cylindrical"),
+            # the fourth-order operator preconditioned by the same second-order B
+            ("acoustic2048x64_mixed", "mixed", 64, "mixed_64shot_2048_order4", "order4"),
         ]
         for name, prec, shots, key, top in plan:
             geo = "cylindrical" if top == "cylindrical" else "cartesian"
-            v = run_variant(name, prec, shots, max(2, args.steps // 2), 1,
-                            tuned=tuned_params(name, prec, shots, not args.no_tune and geo == "cartesian"),
-                            profile_iters=args.profile_iters, top="dirichlet" if geo != "cartesian" else top,
-                            geometry=geo)
+            order = 4 if top == "order4" else 2
+            tp = tuned_params(name, prec, shots, not args.no_tune and geo == "cartesian")
+            if order == 4:
+                tp["op_fusion"] = 2                            # the update reads a stored q
+            v = run_variant(name, prec, shots, max(2, args.steps // 2), 1, tuned=tp,
+                            profile_iters=args.profile_iters, top=top if top in ("dirichlet", "free") else "dirichlet",
+                            geometry=geo, order=order)
             v.pop("_run")
-            variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "top", "geometry", "value",
+            variants[key] = {k: v[k] for k in ("workload", "precision", "shots", "top", "geometry", "order", "value",
                                                "ms_per_step", "mean_iters", "whole_iteration_GBps", "dominant")}
             variants[key]["kernels_GBps"] = {k: round(x["GBps"], 1) for k, x in v["kernels"].items()}
             torch.cuda.empty_cache()

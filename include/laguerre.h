@@ -87,9 +87,29 @@ typedef enum { LG_TOP_DIRICHLET = 0, LG_TOP_FREE = 1 } lg_top_bc;
  * 1/(2 pi dx dz) (the 2.5D point source). */
 typedef enum { LG_CARTESIAN = 0, LG_CYLINDRICAL = 1 } lg_geometry;
 
+/* Spatial order of the acoustic operator (Sec. 3.3: higher-order schemes are
+ * preconditioned by the same second-order B).  2 (or 0): the five-point
+ * operator above.  4: A4 = Dx^T Kx Dx + Dz^T Kz Dz + w with the fourth-order
+ * staggered difference (D u)_{m+1/2} = [27 (u_{m+1} - u_m) - (u_{m+2} -
+ * u_{m-1})] / (24 h), the Dirichlet sides taken by odd reflection (u_{-1} =
+ * -u_1, u_{N+1} = -u_{N-1}, folded into D so that A4 stays symmetric), and
+ * face coefficients from the fourth-order interpolant of the node values
+ * (one-sided cubic at the end faces; the two-point mean where the interpolant
+ * falls under half the smaller of the face's two nodes).  A 13-point operator
+ * (radius 3 along each axis).  Cartesian acoustic plans with Dirichlet sides
+ * only; the CG update reads a stored q = A p (op_fusion is taken as 2) and a
+ * solve starts from x0 = 0. */
 /* Grid: nx, nz cells (powers of two, 2..4096), spacings dx, dz > 0 (metres),
- * top boundary (lg_top_bc), geometry (lg_geometry). */
-typedef struct { int32_t nx, nz; double dx, dz; int32_t top_bc; int32_t geometry; } lg_grid;
+ * top boundary (lg_top_bc), geometry (lg_geometry), operator order (2 or 4;
+ * 0 means 2); reserved must be 0. */
+typedef struct {
+    int32_t nx, nz;
+    double dx, dz;
+    int32_t top_bc;
+    int32_t geometry;
+    int32_t order;
+    int32_t reserved;
+} lg_grid;
 
 /* Laguerre transform (Sec. 2.1): order alpha >= 2, scale h > 0 (1/s), n >= 1
  * harmonics. */

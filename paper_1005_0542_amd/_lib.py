@@ -29,7 +29,7 @@ LG_RICKER, LG_GAUSS_SINE = 0, 1
 
 class Grid(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("nz", c_int32), ("dx", c_double), ("dz", c_double),
-                ("top_bc", c_int32), ("geometry", c_int32)]
+                ("top_bc", c_int32), ("geometry", c_int32), ("order", c_int32), ("reserved", c_int32)]
 
 
 class Laguerre(ctypes.Structure):

@@ -60,7 +60,7 @@ class Plan:
                  n: int, medium: np.ndarray, precision: str = "fp64", nshots: int = 1,
                  segments: int = 0, graph_iters: int = 0, op_shots: int = 0, seg_per_wave: int = 0,
                  op_fusion: int = 0, top: str = "dirichlet", geometry: str = "cartesian",
-                 stream=None):
+                 order: int = 2, stream=None):
         import torch
         self.lib = _lib.load()
         self.kind = kind
@@ -75,8 +75,9 @@ class Plan:
         if geometry not in ("cartesian", "cylindrical"):
             raise ValueError("geometry must be 'cartesian' or 'cylindrical'")
         self.geometry = geometry
+        self.order = order
         grid = _lib.Grid(nx, nz, dx, dz, _lib.LG_TOP_FREE if top == "free" else _lib.LG_TOP_DIRICHLET,
-                         _lib.LG_CYLINDRICAL if geometry == "cylindrical" else _lib.LG_CARTESIAN)
+                         _lib.LG_CYLINDRICAL if geometry == "cylindrical" else _lib.LG_CARTESIAN, order, 0)
         lag = _lib.Laguerre(alpha, h, n)
         tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion)
         if stream is None:

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblaguerre.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
-SOURCES = ["lg_plan.hip", "lg_kernels.hip", "lg_pcg.hip", "lg_elastic.hip", "lg_cyl.hip"]
+SOURCES = ["lg_plan.hip", "lg_kernels.hip", "lg_pcg.hip", "lg_elastic.hip", "lg_cyl.hip", "lg_ho.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wall",

@@ -98,6 +98,14 @@ struct lg_plan {
     double* cy_a1_64 = nullptr;   // mixed plans: FP64 copies of cy_a1, cy_a2 (true residual)
     double* cy_a2_64 = nullptr;
     double src_scale = 0.0;    // discrete delta: 1/(dx dz), or 1/(2 pi h_r h_z)
+    // Fourth-order operator (order 4): face tables with the 1/(576 h^2)
+    // scale folded in; the x-faces m+1/2 (m = 0..nx-1) of the interior rows
+    // and the z-faces n+1/2 (n = 0..nz-1) of the interior columns.
+    int order = 2;
+    void* ho_kx = nullptr;     // [nz-1][nx] working type
+    void* ho_kz = nullptr;     // [nz][nx-1] working type
+    double* ho_kx64 = nullptr; // mixed plans: FP64 copies (true residual)
+    double* ho_kz64 = nullptr;
     int device = 0;
     hipStream_t stream = nullptr;
     hipStream_t cap_stream = nullptr;   // private stream used only for graph capture
@@ -180,6 +188,9 @@ hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, d
 // FP64 true residual r = b - A x, then the update pass with init 2
 hipError_t cyl_launch_restart(lg_plan* p, const double* b, double* x, double tol, int max_iter);
 hipError_t cyl_launch_correct(lg_plan* p, int init);
+// fourth-order operator (lg_ho.hip)
+hipError_t ho_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce);
+hipError_t ho_launch_residual(lg_plan* p, const double* b, const double* x);   // p->r = b - A4 x, FP64
 hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,
                       const double* fsrc_host, double* rhs);
 hipError_t launch_synth(lg_plan* p, int m, const double* R, const double* Wsnap, int nsnap,

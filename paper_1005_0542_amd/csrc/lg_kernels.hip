@@ -1247,6 +1247,7 @@ hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double to
 
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq) {
     if (p->cyl) return cyl_launch_stencil(p, x, y, reduce_pq);
+    if (p->order == 4) return ho_launch_stencil(p, x, y, reduce_pq);
     if (p->prec == LG_FP64) return stencil_T<double>(p, (const double*)x, (double*)y, reduce_pq);
     return stencil_T<float>(p, (const float*)x, (float*)y, reduce_pq);
 }
@@ -1271,6 +1272,10 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
                               int max_iter) {
     hipError_t e;
     int bpf;
+    if (init == 3 && p->order == 4) {   // FP64 true residual of A4, then the pass from the stored r
+        if ((e = ho_launch_residual(p, b, x)) != hipSuccess) return e;
+        init = 2;
+    }
     if (p->prec == LG_FP64) {
         DstArgs<double> a = dst_args<double>(p);
         a.out = (double*)p->rhat;
@@ -1303,7 +1308,7 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;
-    return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, tol * tol, max_iter, 0.0);   // init 4: given x
+    return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, tol * tol, max_iter, 0.0);   // init 2, 3: restart; 4: given x
 }
 
 hipError_t launch_correct_idst(lg_plan* p, int init) {

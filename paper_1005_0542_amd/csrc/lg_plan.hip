@@ -183,6 +183,53 @@ lg_status prepare_cylindrical(lg_plan* pl, const double* kap) {
     return upload_working(pl, &pl->cy_lowr, lowr);
 }
 
+// Face values of the fourth-order operator along one line of n+1 nodes
+// k[0], k[s], ..., k[n s]: the cubic interpolant at the face midpoints
+// (one-sided at the two end faces), or the two-point mean where it falls
+// under half the smaller of the face's two nodes (keeps every face > 0).
+static void faces4(const double* k, int n, size_t s, double* out) {
+    for (int m = 0; m < n; ++m) {
+        const double a = k[(size_t)m * s], b = k[(size_t)(m + 1) * s];
+        double f = 0.5 * (a + b);
+        if (n >= 3) {
+            if (m == 0)
+                f = (5.0 * a + 15.0 * b - 5.0 * k[2 * s] + k[3 * s]) / 16.0;
+            else if (m == n - 1)
+                f = (5.0 * b + 15.0 * a - 5.0 * k[(size_t)(n - 2) * s] + k[(size_t)(n - 3) * s]) / 16.0;
+            else
+                f = (9.0 * (a + b) - k[(size_t)(m - 1) * s] - k[(size_t)(m + 2) * s]) / 16.0;
+            if (f < 0.5 * std::min(a, b)) f = 0.5 * (a + b);
+        }
+        out[m] = f;
+    }
+}
+
+// Tables of the fourth-order operator (order 4): x-faces of the interior
+// rows and z-faces of the interior columns, times 1/(24 h)^2.
+lg_status prepare_order4(lg_plan* pl, const double* kap) {
+    const int nx = pl->g.nx, nz = pl->g.nz;
+    const double sx = 1.0 / (576.0 * pl->g.dx * pl->g.dx), sz = 1.0 / (576.0 * pl->g.dz * pl->g.dz);
+    std::vector<double> kx((size_t)(nz - 1) * nx), kz((size_t)nz * (nx - 1)), line(std::max(nx, nz));
+    for (int j = 1; j < nz; ++j) {
+        faces4(kap + (size_t)j * (nx + 1), nx, 1, line.data());
+        for (int m = 0; m < nx; ++m) kx[(size_t)(j - 1) * nx + m] = line[m] * sx;
+    }
+    for (int i = 1; i < nx; ++i) {
+        faces4(kap + i, nz, (size_t)(nx + 1), line.data());
+        for (int n = 0; n < nz; ++n) kz[(size_t)n * (nx - 1) + (i - 1)] = line[n] * sz;
+    }
+    lg_status st = upload_working(pl, &pl->ho_kx, kx);
+    if (st != LG_OK) return st;
+    if ((st = upload_working(pl, &pl->ho_kz, kz)) != LG_OK) return st;
+    if (pl->prec == LG_MIXED) {
+        if ((st = dev_alloc(pl, &pl->ho_kx64, kx.size() * 8)) != LG_OK) return st;
+        if ((st = dev_alloc(pl, &pl->ho_kz64, kz.size() * 8)) != LG_OK) return st;
+        LG_HIP(hipMemcpy(pl->ho_kx64, kx.data(), kx.size() * 8, hipMemcpyHostToDevice));
+        LG_HIP(hipMemcpy(pl->ho_kz64, kz.data(), kz.size() * 8, hipMemcpyHostToDevice));
+    }
+    return LG_OK;
+}
+
 // Prepare the Dichotomy tables of one preconditioner block (done once).
 lg_status prepare_block(lg_plan* pl, PrecBlock& B, double kx, double kz, double d, int P) {
     const int nx = pl->g.nx, nz = pl->g.nz, nx1 = pl->nx1;
@@ -257,7 +304,8 @@ void free_plan(lg_plan* p) {
                     p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
-                    p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64};
+                    p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64,
+                    p->ho_kx, p->ho_kz, p->ho_kx64, p->ho_kz64};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
@@ -413,6 +461,13 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     const bool cyl = grid->geometry == LG_CYLINDRICAL;
     if (cyl && kind != LG_ACOUSTIC)
         return fail(LG_ERR_UNSUPPORTED, "the axisymmetric geometry is implemented for acoustic plans");
+    if (grid->order != 0 && grid->order != 2 && grid->order != 4)
+        return fail(LG_ERR_INVALID_ARG, "order must be 0, 2 or 4");
+    if (grid->reserved != 0) return fail(LG_ERR_INVALID_ARG, "lg_grid.reserved must be 0");
+    const int order = grid->order == 4 ? 4 : 2;
+    if (order == 4 && (kind != LG_ACOUSTIC || cyl || grid->top_bc != LG_TOP_DIRICHLET))
+        return fail(LG_ERR_UNSUPPORTED, "the fourth-order operator is implemented for Cartesian acoustic plans "
+                                        "with Dirichlet sides");
     int P = 0, gi = 8, osh = 8, spw = 0, fus = 1;
     if (tuning != nullptr) {
         P = tuning->segments;
@@ -458,7 +513,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->graph_iters = gi;
     p->op_shots = osh;
     p->td_spw = spw;
-    p->fuse_op = (fus == 1) && !cyl;
+    p->order = order;
+    p->fuse_op = (fus == 1) && !cyl && order == 2;
     p->free_top = (grid->top_bc == LG_TOP_FREE) && !cyl;
     p->src_scale = cyl ? 1.0 / (2.0 * 3.141592653589793 * grid->dx * grid->dz) : 1.0 / (grid->dx * grid->dz);
     p->device = dev;
@@ -526,6 +582,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         if ((st = prepare_block(p, p->blk[0], p->kappa_t, p->kappa_t, p->rho_t * hh4, P)) != LG_OK)
             return bail(st);
         if (p->free_top && (st = prepare_free_surface(p, p->blk[0])) != LG_OK) return bail(st);
+        if (order == 4 && (st = prepare_order4(p, medium_host)) != LG_OK) return bail(st);
     } else {
         const double* lam = medium_host;
         const double* mu = medium_host + nn;
@@ -573,7 +630,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if ((st = dev_alloc(p, (char**)&p->y, p->nvec * ws)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, &p->E, (size_t)SC * P * 3 * p->nx1 * 8)) != LG_OK) return bail(st);
     {
-        const size_t sb = (size_t)((p->nx1 + 63) / 64) * ((p->nz1 + 31) / 32);
+        const size_t sb = (size_t)((p->nx1 + 63) / 64) * ((p->nz1 + 15) / 16);   // operator tiles (<= 16 rows)
         const size_t db = (size_t)dst_blocks_per_field(grid->nx, p->nz1);
         const size_t rb = (size_t)((p->nx1 + 15) / 16);
         // the transform kernel's start from a given x writes two partial sets
@@ -811,7 +868,8 @@ lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve
     if (!(opts->tol >= 0.0) || !std::isfinite(opts->tol)) return fail(LG_ERR_INVALID_ARG, "tol must be >= 0");
     if (opts->max_iter < 1) return fail(LG_ERR_INVALID_ARG, "max_iter must be >= 1");
     if (opts->x0_given != 0 && opts->x0_given != 1) return fail(LG_ERR_INVALID_ARG, "x0_given must be 0 or 1");
-    if (opts->x0_given && plan->cyl) return fail(LG_ERR_UNSUPPORTED, "axisymmetric plans start from x0 = 0");
+    if (opts->x0_given && (plan->cyl || plan->order == 4))
+        return fail(LG_ERR_UNSUPPORTED, "axisymmetric and fourth-order plans start from x0 = 0");
     LG_HIP(hipSetDevice(plan->device));
     return lg::pcg_solve(plan, b, x, opts, info_host);
 }

@@ -45,7 +45,7 @@ def test_status_strings():
 
 def _create(kind=_lib.LG_ACOUSTIC, nx=16, nz=16, dx=5.0, dz=5.0, alpha=9, h=200.0, n=8,
             prec=_lib.LG_FP64, shots=1, medium="ok", segments=0, graph_iters=0, top=0, op_shots=0,
-            seg_per_wave=0, op_fusion=0, geometry=0):
+            seg_per_wave=0, op_fusion=0, geometry=0, order=0):
     lib = _lib.load()
     F = 2 if kind == _lib.LG_ACOUSTIC else 3
     if isinstance(medium, str):
@@ -53,7 +53,7 @@ def _create(kind=_lib.LG_ACOUSTIC, nx=16, nz=16, dx=5.0, dz=5.0, alpha=9, h=200.
     else:
         med = medium
     med = np.ascontiguousarray(med, dtype=np.float64)
-    grid = _lib.Grid(nx, nz, dx, dz, top, geometry)
+    grid = _lib.Grid(nx, nz, dx, dz, top, geometry, order)
     lag = _lib.Laguerre(alpha, h, n)
     tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion)
     handle = ctypes.c_void_p()
@@ -68,6 +68,7 @@ def _create(kind=_lib.LG_ACOUSTIC, nx=16, nz=16, dx=5.0, dz=5.0, alpha=9, h=200.
     dict(segments=3), dict(segments=128), dict(segments=16, nz=16), dict(graph_iters=-5),
     dict(graph_iters=1000), dict(top=2), dict(top=-1), dict(op_shots=65), dict(op_shots=-1),
     dict(seg_per_wave=3), dict(seg_per_wave=8), dict(op_fusion=3), dict(geometry=2), dict(geometry=-1),
+    dict(order=3), dict(order=6), dict(order=-2),
 ])
 def test_plan_create_rejects_invalid_arguments(kw):
     assert _create(**kw) == _lib.LG_ERR_INVALID_ARG
@@ -89,6 +90,10 @@ def test_plan_create_unsupported_shapes():
     assert _create(kind=_lib.LG_ELASTIC, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
     assert _create(segments=4, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
     assert _create(nx=24, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
+    # the fourth-order operator: Cartesian acoustic plans with Dirichlet sides
+    assert _create(kind=_lib.LG_ELASTIC, order=4) == _lib.LG_ERR_UNSUPPORTED
+    assert _create(geometry=cyl, order=4) == _lib.LG_ERR_UNSUPPORTED
+    assert _create(top=_lib.LG_TOP_FREE, order=4) == _lib.LG_ERR_UNSUPPORTED
 
 
 def test_null_arguments_rejected():
