@@ -10,10 +10,12 @@
 // N+1/2 (needed at i = 1 and i = N-1) equal their mirrors 1/2 and N-1/2,
 // which is the reflection folded into D.  Kx, Kz carry 1/(24 h)^2.
 //
-// One thread computes a column strip of HO_RPT rows; the face tables and w of
-// the strip stay in registers while the block works through `nsh` shots.
-// All loads are buffer loads: nodes outside the grid read 0 through the
-// range check, and the two reflected nodes are set from their mirrors.
+// A block covers 64 columns x 16 rows and stages that tile of the field with
+// a 3-node halo in LDS (one coalesced pass, the reflected nodes loaded from
+// their mirrors with the sign flipped, nodes outside the grid read as 0
+// through the buffer range check); each thread then computes a column strip
+// of HO_RPT rows from LDS, while the next shot's tile is already in flight.  The face tables and w of the strip stay in
+// registers while the block works through `nsh` shots.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -24,6 +26,9 @@
 namespace lg {
 
 constexpr int HO_RPT = 4;
+constexpr int HO_TW = 64 + 6;            // LDS tile width (columns + halo)
+constexpr int HO_TH = 4 * HO_RPT + 6;    // LDS tile height (rows + halo)
+constexpr int HO_LPT = (HO_TH * HO_TW + 255) / 256;   // tile elements per thread
 
 template <typename T>
 struct HoArgs {
@@ -93,43 +98,62 @@ __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
         kz[f] = bload<T>(rkz, live ? (uint32_t)(n * nx1 + ci) * SZ : BUF_OOB);
     }
 
+    __shared__ T tile[HO_TH * HO_TW];
+    const int ni0 = bx * 64 + 1 - 3, nj0 = by * 4 * HO_RPT + 1 - 3;   // node of tile[0]
     const int f0 = grp * a.nsh, f1e = min(a.nfields, f0 + a.nsh);
-    for (int field = f0; field < f1e; ++field) {
-        if (a.ctl != nullptr && a.ctl[field].active == 0) continue;   // uniform per block
+    // the next field's tile is loaded into registers while the current one is
+    // computed from LDS
+    auto next_active = [&](int f) {
+        while (f < f1e && a.ctl != nullptr && a.ctl[f].active == 0) ++f;   // uniform per block
+        return f;
+    };
+    // tile element u of this thread: field offset (or out of range) and the
+    // sign of the odd reflection, the same for every shot
+    uint32_t toff[HO_LPT];
+    T tsgn[HO_LPT];
+#pragma unroll
+    for (int u = 0; u < HO_LPT; ++u) {
+        const int t = threadIdx.x + u * 256;
+        const int rr = t / HO_TW, cc = t - rr * HO_TW;
+        int nj = nj0 + rr, ni = ni0 + cc;
+        T sgn = (T)1;
+        if (nj == -1) { nj = 1; sgn = -sgn; }
+        if (nj == nz + 1) { nj = nz - 1; sgn = -sgn; }
+        if (ni == -1) { ni = 1; sgn = -sgn; }
+        if (ni == nx + 1) { ni = nx - 1; sgn = -sgn; }
+        const bool in = t < HO_TH * HO_TW && nj >= 1 && nj <= nz1 && ni >= 1 && ni <= nx1;
+        toff[u] = in ? (uint32_t)((nj - 1) * nx1 + ni - 1) * SZ : BUF_OOB;
+        tsgn[u] = sgn;
+    }
+    auto load_tile = [&](int f, T* v) {
+        const rsrc_t rp = buf_rsrc(a.p + (size_t)f * nf, nf * SZ);
+#pragma unroll
+        for (int u = 0; u < HO_LPT; ++u) v[u] = bload<T>(rp, toff[u]);
+    };
+    T nxt[HO_LPT];
+    int field = next_active(f0);
+    if (field < f1e) load_tile(field, nxt);
+    while (field < f1e) {
         const size_t fo = (size_t)field * nf;
-        const rsrc_t rp = buf_rsrc(a.p + fo, nf * SZ);
-        // column: node rows j0-2 .. j0+HO_RPT+3 (interior rows j0-3 .. j0+HO_RPT+2)
+        __syncthreads();                            // the previous field's reads are done
+#pragma unroll
+        for (int u = 0; u < HO_LPT; ++u) {
+            const int t = threadIdx.x + u * 256;
+            if (t < HO_TH * HO_TW) tile[t] = tsgn[u] * nxt[u];
+        }
+        __syncthreads();
+        const int fn = next_active(field + 1);
+        if (fn < f1e) load_tile(fn, nxt);
+        // column: node rows j0-2 .. j0+HO_RPT+3; rows: node columns i-3 .. i+3
+        const int lc = lane + 3, lr = ty * HO_RPT;       // tile column of node i; tile row of node row j0-2
         T col[HO_RPT + 6];
 #pragma unroll
-        for (int r = 0; r < HO_RPT + 6; ++r) {
-            const int nj = j0 - 2 + r;              // node row
-            col[r] = bload<T>(rp, (live && nj >= 1 && nj <= nz1) ? (uint32_t)((nj - 1) * nx1 + ci) * SZ : BUF_OOB);
-        }
-#pragma unroll
-        for (int r = 0; r < HO_RPT + 6; ++r) {      // odd reflection of the rows -1 and nz+1
-            const int nj = j0 - 2 + r;
-            if (nj == -1 && r + 2 < HO_RPT + 6) col[r] = -col[r + 2];
-            if (nj == nz + 1 && r >= 2) col[r] = -col[r - 2];
-        }
+        for (int r = 0; r < HO_RPT + 6; ++r) col[r] = tile[(lr + r) * HO_TW + lc];
         T row[HO_RPT][7];
 #pragma unroll
-        for (int r = 0; r < HO_RPT; ++r) {
-            const int cj = j0 + r;
-            const bool ok = live && cj < nz1;
+        for (int r = 0; r < HO_RPT; ++r)
 #pragma unroll
-            for (int o = 0; o < 7; ++o) {
-                if (o == 3) continue;
-                const int ni = i - 3 + o;           // node column
-                row[r][o] = bload<T>(rp, (ok && ni >= 1 && ni <= nx1) ? (uint32_t)(cj * nx1 + ni - 1) * SZ : BUF_OOB);
-            }
-            row[r][3] = col[r + 3];
-#pragma unroll
-            for (int o = 0; o < 7; ++o) {
-                const int ni = i - 3 + o;
-                if (ni == -1) row[r][o] = -row[r][o + 2];
-                if (ni == nx + 1) row[r][o] = -row[r][o - 2];
-            }
-        }
+            for (int o = 0; o < 7; ++o) row[r][o] = tile[(lr + r + 3) * HO_TW + lc - 3 + o];
         double pq = 0.0;
         const rsrc_t rq = buf_rsrc((a.q != nullptr ? a.q : const_cast<T*>(a.p)) + fo,
                                    a.q != nullptr ? nf * SZ : 0u);
@@ -145,9 +169,11 @@ __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
             bstore<T>(v, rq, o * SZ);
             pq += (double)c * (double)v;
         }
-        if (a.ctl == nullptr) continue;
-        const double s = block_sum(pq, red);
-        if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + by * a.gx + bx] = s;
+        if (a.ctl != nullptr) {
+            const double s = block_sum(pq, red);
+            if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + by * a.gx + bx] = s;
+        }
+        field = fn;
     }
 }
 
