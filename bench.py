@@ -57,14 +57,21 @@ def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True, medium: 
     }
 
 
-def cyl_kernel_bytes(ws: int, shots: int):
-    """The same for the axisymmetric iteration (Sec. 2.3): q = A p is stored;
+def cyl_kernel_bytes(ws: int, shots: int, fused: bool = True):
+    """The same for the axisymmetric iteration (Sec. 2.3): fused, the update
+    recomputes A p (stored-q form: the operator writes q, the update reads it);
     the r-systems read rhat and write zhat once (their forward-sweep
     intermediate round trip through memory is not counted); the face tables,
     shift and Thomas factors are shared by all shots."""
+    if fused:
+        op = ws + 3 * ws / shots                              # p in; a1, a2, w once per batch
+        upd = 32 + 2 * ws + 3 * ws / shots                    # x, r in/out (f64); p in; rhat out; medium
+    else:
+        op = 2 * ws + 3 * ws / shots                          # p in, q out; a1, a2, w once per batch
+        upd = 32 + 3 * ws                                     # x, r in/out (f64); p, q in; rhat out
     return {
-        "operator": 2 * ws + 3 * ws / shots,                  # p in, q out; a1, a2, w once per batch
-        "update_fdct": 32 + 3 * ws,                           # x, r in/out (f64); p, q in; rhat out
+        "operator": op,
+        "update_fdct": upd,
         "r_systems": 2 * ws + 2 * ws / shots,                 # rhat in, zhat out; factors once per batch
         "correct_idct": 3 * ws,                               # zhat in, p in/out
     }
@@ -187,7 +194,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     out["segments"] = seg
     ws = 8 if precision == "fp64" else 4
     if cyl:
-        kb = cyl_kernel_bytes(ws, shots)
+        kb = cyl_kernel_bytes(ws, shots, tuned.get("op_fusion", 0) != 2)
     elif order == 4:
         kb = kernel_bytes(ws, shots, seg_len, fused=False, medium=3)
     else:

@@ -14,8 +14,9 @@
 // once per plan and the systems are solved one lane per wavenumber.
 //
 // Kernels of one CG iteration:
-//   cyl_stencil_kernel        q = A p, (p, Ap) partials
-//   cyl_dct_kernel<UPDATE>    x += alpha p, r -= alpha q, ||r||^2, rhat = DCT r
+//   cyl_stencil_kernel        (p, Ap) partials (q = A p stored only in the stored-q form)
+//   cyl_dct_kernel<UPDATE_OP> A p recomputed, x += alpha p, r -= alpha A p, ||r||^2, rhat = DCT r
+//                             (UPDATE: the stored q is read instead)
 //   cyl_thomas_kernel         zhat = B_k^{-1} rhat per wavenumber, (r, z) partials
 //   cyl_dct_kernel<CORRECT>   z = DCT^{-1} zhat, p = z + beta p
 // Mixed plans keep p, q, rhat, zhat and the tables in FP32 and x, r in FP64;
@@ -37,6 +38,16 @@ namespace lg {
 // ===========================================================================
 constexpr int CY_RPT = 8;   // operator: rows per thread
 constexpr int CY_TU = 8;    // r-systems: rows per load chunk
+
+// (A p) at one node from the node value c, its r-neighbours pn (row j-1),
+// ps (row j+1), z-neighbours pw, pe, the r-face coefficients fn (face
+// j-1|j), fs (face j|j+1), the z-face coefficients fl, fr and the shift w.
+// One chain of explicit fused multiply-adds with no free addition left for
+// the compiler to contract, so every kernel that forms A p gets the same bits.
+template <typename T>
+__device__ __forceinline__ T cyl_point(T c, T pn, T ps, T pw, T pe, T fn, T fs, T fl, T fr, T w) {
+    return fmad(fs, c - ps, fmad(fn, c - pn, fmad(fr, c - pe, fmad(fl, c - pw, w * c))));
+}
 
 template <typename T>
 struct CylStArgs {
@@ -115,8 +126,7 @@ __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
             const int j = j0 + r;
             const uint32_t o = (live && j < nz1) ? (uint32_t)(j * nx1 + k) : BUF_OOB / 8u;
             const T c = pv[r + 1];
-            T v = fmad(f1[r + 1], c - pv[r + 2], f1[r] * (c - pv[r])) +
-                  fmad(fr[r], c - pe[r], fl[r] * (c - pw[r])) + wv[r] * c;
+            T v = cyl_point<T>(c, pv[r], pv[r + 2], pw[r], pe[r], f1[r], f1[r + 1], fl[r], fr[r], wv[r]);
             if constexpr (RES) v = (T)(bload<double>(rb, o * 8u) - (double)v);
             bstore<T>(v, rq, o * SZ);
             pq += (double)c * (double)v;
@@ -136,7 +146,9 @@ __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
 // conjugate of the DFT of conj(U), U_k = D_k e^{i pi k/M}/Nz,
 // U_{M-k} = D_k e^{-i pi k/M}/Nz (k > 0), U_0 = D_0/Nz, U_{Nz} = 0.
 // ===========================================================================
-enum CylMode { CY_FWD = 0, CY_INV = 1, CY_UPDATE = 2, CY_CORRECT = 3 };
+// CY_UPDATE_OP: the update recomputes q = A p for its two rows from p and the
+// face tables (the operator kernel then only forms (p, Ap)).
+enum CylMode { CY_FWD = 0, CY_INV = 1, CY_UPDATE = 2, CY_CORRECT = 3, CY_UPDATE_OP = 4 };
 
 template <typename T>
 struct CylDctArgs {
@@ -153,6 +165,9 @@ struct CylDctArgs {
     const double* b;
     const T* p;
     const T* q;
+    const T* a1;           // CY_UPDATE_OP: face tables and shift
+    const T* a2;
+    const T* w;
     double* partial;
     size_t pstride;
     int init;
@@ -169,6 +184,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
     constexpr int NWAVE = (FPB * TPF + 63) / 64;
     constexpr int NIT = (N + TPF - 1) / TPF;
     constexpr bool INVERSE = MODE == CY_INV || MODE == CY_CORRECT;
+    constexpr bool UPD = MODE == CY_UPDATE || MODE == CY_UPDATE_OP;
     __shared__ cpx<T> lds[FPB * LL];
     __shared__ double red[NWAVE];
 
@@ -181,7 +197,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
     const bool live = pair < npairs;
     const int j0 = 2 * pair, j1 = j0 + 1;
     const bool has1 = live && (j1 < a.nz1);
-    if constexpr (MODE == CY_UPDATE || MODE == CY_CORRECT) {
+    if constexpr (UPD || MODE == CY_CORRECT) {
         if (!a.init && a.ctl[field].active == 0) return;   // uniform per block
     }
     cpx<T>* buf = lds + fid * LL;
@@ -195,7 +211,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
         if constexpr (!INVERSE) {
             // rows of the input (or, UPDATE, the updated residual) -> symmetric extension
             T v0[NIT], v1[NIT];
-            if constexpr (MODE == CY_UPDATE) {
+            if constexpr (UPD) {
                 // init 0: x += alpha p, r -= alpha q; 1: x = 0, r = b;
                 // 2: r as stored (x untouched)
                 const int init = a.init;
@@ -207,7 +223,10 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
                 const rsrc_t rR = buf_rsrc(init == 1 ? a.b + fbase : a.r + fbase, nfe * 8u);
                 const rsrc_t rRs = buf_rsrc(a.r + fbase, nfe * 8u);
                 const rsrc_t rP = buf_rsrc(a.p + fbase, init ? 0u : nfe * SZ);
-                const rsrc_t rQ = buf_rsrc(a.q + fbase, init ? 0u : nfe * SZ);
+                const rsrc_t rQ = buf_rsrc(a.q + fbase, (init || MODE == CY_UPDATE_OP) ? 0u : nfe * SZ);
+                const rsrc_t rA1 = buf_rsrc(a.a1, MODE == CY_UPDATE_OP ? nfe * SZ : 0u);
+                const rsrc_t rA2 = buf_rsrc(a.a2, MODE == CY_UPDATE_OP ? (uint32_t)a.nz1 * (N + 1) * SZ : 0u);
+                const rsrc_t rW = buf_rsrc(a.w, MODE == CY_UPDATE_OP ? nfe * SZ : 0u);
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     const int n = t + it * TPF;
@@ -217,7 +236,34 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
                     const double x0 = bload<double>(rX, e0 * 8u), x1 = bload<double>(rX, e1 * 8u);
                     const double r0 = bload<double>(rR, e0 * 8u), r1 = bload<double>(rR, e1 * 8u);
                     const T p0 = bload<T>(rP, e0 * SZ), p1 = bload<T>(rP, e1 * SZ);
-                    const T q0 = bload<T>(rQ, e0 * SZ), q1 = bload<T>(rQ, e1 * SZ);
+                    T q0, q1;
+                    if constexpr (MODE == CY_UPDATE_OP) {
+                        // q = A p for rows j0, j1 from p rows j0-1 .. j1+1 (0 outside: no
+                        // face at r = 0, Dirichlet row past the last unknown, no z-end flux)
+                        const int jm = j0 - 1, jp = j1 + 1;
+                        const bool w0 = in && n > 0, e0ok = in && n + 1 < N;
+                        const T pn0 = bload<T>(rP, (in && jm >= 0) ? (uint32_t)(jm * N + n) * SZ : BUF_OOB);
+                        const T ps1 = bload<T>(rP, (in && has1 && jp < a.nz1) ? (uint32_t)(jp * N + n) * SZ : BUF_OOB);
+                        const T pw0 = bload<T>(rP, w0 ? (e0 - 1) * SZ : BUF_OOB);
+                        const T pe0 = bload<T>(rP, e0ok ? (e0 + 1) * SZ : BUF_OOB);
+                        const T pw1 = bload<T>(rP, (w0 && has1) ? (e1 - 1) * SZ : BUF_OOB);
+                        const T pe1 = bload<T>(rP, (e0ok && has1) ? (e1 + 1) * SZ : BUF_OOB);
+                        const T fn0 = bload<T>(rA1, (in && jm >= 0) ? (uint32_t)(jm * N + n) * SZ : BUF_OOB);
+                        const T fs0 = bload<T>(rA1, e0 * SZ);
+                        const T fs1 = bload<T>(rA1, e1 * SZ);
+                        const uint32_t g0 = in ? (uint32_t)(j0 * (N + 1) + n) : BUF_OOB / 8u;
+                        const uint32_t g1 = (in && has1) ? (uint32_t)(j1 * (N + 1) + n) : BUF_OOB / 8u;
+                        const T fl0 = bload<T>(rA2, g0 * SZ), fr0 = bload<T>(rA2, (g0 + 1) * SZ);
+                        const T fl1 = bload<T>(rA2, g1 * SZ), fr1 = bload<T>(rA2, (g1 + 1) * SZ);
+                        const T wv0 = bload<T>(rW, e0 * SZ), wv1 = bload<T>(rW, e1 * SZ);
+                        q0 = cyl_point<T>(p0, pn0, p1, pw0, pe0, fn0, fs0, fl0, fr0, wv0);
+                        // no second row in the last pair (N_r - 1 is odd): q1 must be 0, or
+                        // the phantom row's -alpha q1 would enter ||r||^2 and the transform
+                        q1 = has1 ? cyl_point<T>(p1, p0, ps1, pw1, pe1, fs0, fs1, fl1, fr1, wv1) : (T)0;
+                    } else {
+                        q0 = bload<T>(rQ, e0 * SZ);
+                        q1 = bload<T>(rQ, e1 * SZ);
+                    }
                     const double ra = r0 - alpha * (double)q0, rb = r1 - alpha * (double)q1;
                     bstore<double>(x0 + alpha * (double)p0, rXs, e0 * 8u);
                     bstore<double>(x1 + alpha * (double)p1, rXs, e1 * 8u);
@@ -319,7 +365,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
                 if (has1) a.out[o1 + K] = x1;
             }
     }
-    if constexpr (MODE == CY_UPDATE) {
+    if constexpr (UPD) {
         const double s = block_sum(rr, red);
         if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + bif] = s;
     }
@@ -481,6 +527,9 @@ CylDctArgs<T> cyl_dct_args(lg_plan* p) {
     a.r = p->r;
     a.p = (const T*)p->p;
     a.q = (const T*)p->qv;
+    a.a1 = (const T*)p->cy_a1;
+    a.a2 = (const T*)p->cy_a2;
+    a.w = (const T*)p->w;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
     return a;
@@ -561,7 +610,8 @@ hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, d
         a.init = init;
         a.b = b;
         a.x = x;
-        e = cyl_dct_dispatch<double, CY_UPDATE>(p, a, nf);
+        e = (init == 0 && p->fuse_op) ? cyl_dct_dispatch<double, CY_UPDATE_OP>(p, a, nf)
+                                      : cyl_dct_dispatch<double, CY_UPDATE>(p, a, nf);
         bpf = a.bpf;
     } else {
         CylDctArgs<float> a = cyl_dct_args<float>(p);
@@ -569,7 +619,8 @@ hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, d
         a.init = init;
         a.b = b;
         a.x = x;
-        e = cyl_dct_dispatch<float, CY_UPDATE>(p, a, nf);
+        e = (init == 0 && p->fuse_op) ? cyl_dct_dispatch<float, CY_UPDATE_OP>(p, a, nf)
+                                      : cyl_dct_dispatch<float, CY_UPDATE>(p, a, nf);
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;

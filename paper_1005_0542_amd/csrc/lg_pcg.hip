@@ -16,8 +16,8 @@ namespace {
 
 hipError_t enqueue_iteration(lg_plan* p) {
     const int nf = p->S * p->C;
-    if (p->cyl) {   // axisymmetric: q = A p stored, Thomas per wavenumber
-        hipError_t e = launch_stencil(p, p->p, p->qv, true);                     // (p, Ap), alpha
+    if (p->cyl) {   // axisymmetric: transforms along z, Thomas per wavenumber
+        hipError_t e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);   // (p, Ap), alpha
         if (e == hipSuccess) e = cyl_launch_update(p, 0, nullptr, nullptr, 0.0, 0);  // x, r, rhat
         if (e == hipSuccess) e = cyl_launch_thomas(p, p->rhat, p->y, nf, 2);       // zhat, beta
         if (e == hipSuccess) e = cyl_launch_correct(p, 0);                         // z, p = z + beta p

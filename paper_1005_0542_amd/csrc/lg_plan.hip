@@ -514,7 +514,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->op_shots = osh;
     p->td_spw = spw;
     p->order = order;
-    p->fuse_op = (fus == 1) && !cyl && order == 2;
+    p->fuse_op = (fus == 1) && order == 2;
     p->free_top = (grid->top_bc == LG_TOP_FREE) && !cyl;
     p->src_scale = cyl ? 1.0 / (2.0 * 3.141592653589793 * grid->dx * grid->dz) : 1.0 / (grid->dx * grid->dz);
     p->device = dev;

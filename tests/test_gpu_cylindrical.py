@@ -25,9 +25,10 @@ def _medium(nr, nz, seed=1):
 
 
 def _plan(nr, nz, kappa, rho, hr=10.0, hz=10.0, h=200.0, shots=1, graph_iters=0, n=8, precision="fp64",
-          op_shots=0):
+          op_shots=0, op_fusion=0):
     return api.Plan("acoustic", nz, nr, hz, hr, 9, h, n, np.stack([kappa, rho]), precision=precision,
-                    nshots=shots, graph_iters=graph_iters, op_shots=op_shots, geometry="cylindrical")
+                    nshots=shots, graph_iters=graph_iters, op_shots=op_shots, op_fusion=op_fusion,
+                    geometry="cylindrical")
 
 
 def _wdt(prec):
@@ -113,15 +114,16 @@ def _oracle_pcg(kappa, rho, h, hr, hz, b, tol, max_iter=2000):
     return krylov.pcg(lambda y: cyl.apply_A(y, a1, a2, w, hr, hz), B.solve, b, tol, max_iter)
 
 
+@pytest.mark.parametrize("fus", [1, 2])
 @pytest.mark.parametrize("nr,nz,shots,gi", [(16, 16, 1, 0), (64, 64, 2, 4), (128, 256, 2, 0),
-                                            (256, 64, 1, 8), (2, 4, 1, 0)])
-def test_cylindrical_pcg_parity_fp64(nr, nz, shots, gi):
+                                            (256, 64, 1, 8), (2, 4, 1, 0), (4, 2, 2, 0)])
+def test_cylindrical_pcg_parity_fp64(nr, nz, shots, gi, fus):
     torch = torch_cuda()
     kappa, rho = _medium(nr, nz)
     hr, hz, h = 10.0, 10.0, 200.0
-    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots, graph_iters=gi)
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots, graph_iters=gi, op_fusion=fus)
     b = np.random.default_rng(6).standard_normal((shots, 1, nr - 1, nz))
-    log(f"cylindrical pcg Nr={nr} Nz={nz} shots={shots} graph_iters={gi}")
+    log(f"cylindrical pcg Nr={nr} Nz={nz} shots={shots} graph_iters={gi} op_fusion={fus}")
     bd = to_dev(b, torch.float64)
     xd = torch.empty_like(bd)
     res = plan.pcg_solve(bd, xd, tol=1e-10, max_iter=2000)
@@ -152,6 +154,27 @@ def test_cylindrical_pcg_mixed_true_residual(nr, nz, shots):
         assert np.linalg.norm(r) <= 1.5e-9 * np.linalg.norm(b[s, 0])
         xo = _oracle_pcg(kappa, rho, h, hr, hz, b[s, 0], 1e-12)[0]
         assert rel(to_np(xd)[s, 0], xo) < 1e-6
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_cylindrical_fused_and_stored_q_iterates_are_bitwise_equal(prec):
+    """The update's recomputed A p uses the operator kernel's arithmetic, so the
+    two forms give the same iterates bit for bit."""
+    torch = torch_cuda()
+    nr, nz = 128, 256
+    kappa, rho = _medium(nr, nz)
+    b = np.random.default_rng(8).standard_normal((3, 1, nr - 1, nz))
+    bd = to_dev(b, torch.float64)
+    out = []
+    for fus in (1, 2):
+        log(f"cylindrical fused vs stored q {prec} op_fusion={fus}")
+        plan = _plan(nr, nz, kappa, rho, shots=3, precision=prec, op_fusion=fus, graph_iters=4)
+        xd = torch.empty_like(bd)
+        res = plan.pcg_solve(bd, xd, tol=1e-9, max_iter=2000)
+        assert res.statuses == [OK] * 3
+        out.append((res.iters, to_np(xd)))
+    assert out[0][0] == out[1][0]
+    assert np.array_equal(out[0][1], out[1][1])
 
 
 def test_cylindrical_pcg_zero_rhs_and_constant_medium():
