@@ -134,10 +134,12 @@ typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
  *  seg_per_wave  Dichotomy segments solved by one wave (1, 2 or 4; default:
  *                chosen from the grid size).
  *  op_fusion     where the update x += alpha p, r -= alpha A p takes A p from
- *                (acoustic CG): 0 or 1 = recomputed inside the update kernel
+ *                (acoustic CG): 1 = recomputed inside the update kernel
  *                from p and the medium, so the operator kernel only forms
- *                (p, A p) (default); 2 = stored by the operator kernel and read
- *                back.  Both give bitwise the same iterates. */
+ *                (p, A p); 2 = stored by the operator kernel and read back.
+ *                Both give bitwise the same iterates.  0 = default: 1, except
+ *                2 for FP64 axisymmetric plans (faster there) and for the
+ *                fourth-order operator (which has only the stored form). */
 typedef struct {
     int32_t segments;
     int32_t graph_iters;

@@ -67,7 +67,9 @@ struct CylStArgs {
 
 template <typename T, bool RES>
 __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
-    __shared__ double red[4];
+    constexpr int MAXSH = 64;                   // fields per block at most (op_shots)
+    __shared__ double red[MAXSH][4];
+    __shared__ int act[MAXSH];
     const int nx1 = a.nx1, nz1 = a.nz1;
     const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int L = xcd_linear(blockIdx.x, gridDim.x);
@@ -80,13 +82,25 @@ __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
     const rsrc_t r1 = buf_rsrc(a.a1, nf * SZ);
     const rsrc_t r2 = buf_rsrc(a.a2, (uint32_t)nz1 * (uint32_t)(nx1 + 1) * SZ);
     const rsrc_t rw = buf_rsrc(a.w, nf * SZ);
+    // offsets of the strip's rows j0-1 .. j0+RPT (0 outside: the r = 0 face has
+    // no coefficient, the row past the last unknown is the Dirichlet side) and
+    // of the E/W neighbours (none past the z-ends)
+    uint32_t oc[CY_RPT + 2], oe[CY_RPT], ow[CY_RPT];
+#pragma unroll
+    for (int r = 0; r < CY_RPT + 2; ++r) {
+        const int j = j0 - 1 + r;
+        oc[r] = (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB;
+    }
+#pragma unroll
+    for (int r = 0; r < CY_RPT; ++r) {
+        const uint32_t c = oc[r + 1];
+        oe[r] = (c != BUF_OOB && k + 1 < nx1) ? c + SZ : BUF_OOB;
+        ow[r] = (c != BUF_OOB && k > 0) ? c - SZ : BUF_OOB;
+    }
     // medium of the tile, shared by the block's fields
     T f1[CY_RPT + 1], fl[CY_RPT], fr[CY_RPT], wv[CY_RPT];
 #pragma unroll
-    for (int r = 0; r < CY_RPT + 1; ++r) {       // faces j0-1|j0 .. j0+RPT-1|j0+RPT
-        const int j = j0 - 1 + r;
-        f1[r] = bload<T>(r1, (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
-    }
+    for (int r = 0; r < CY_RPT + 1; ++r) f1[r] = bload<T>(r1, oc[r]);    // faces j0-1|j0 .. j0+RPT-1|j0+RPT
 #pragma unroll
     for (int r = 0; r < CY_RPT; ++r) {
         const int j = j0 + r;
@@ -94,28 +108,23 @@ __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
         const uint32_t e2 = (uint32_t)(j * (nx1 + 1) + k);
         fl[r] = bload<T>(r2, ok ? e2 * SZ : BUF_OOB);
         fr[r] = bload<T>(r2, ok ? (e2 + 1) * SZ : BUF_OOB);
-        wv[r] = bload<T>(rw, ok ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
+        wv[r] = bload<T>(rw, oc[r + 1]);
     }
-    const int f0 = grp * a.nsh, f1e = min(a.nfields, f0 + a.nsh);
-    for (int field = f0; field < f1e; ++field) {
-        if (a.ctl != nullptr && a.ctl[field].active == 0) continue;   // uniform per block
-        const size_t fo = (size_t)field * nf;
+    const int f0 = grp * a.nsh, ns = min(a.nsh, a.nfields - f0);
+    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr) ? a.ctl[f0 + threadIdx.x].active : 1;
+    __syncthreads();
+    // per field: loads, A p, store, per-wave (p, Ap); one barrier at the end
+    for (int kf = 0; kf < ns; ++kf) {
+        if (act[kf] == 0) continue;                 // uniform per block
+        const size_t fo = (size_t)(f0 + kf) * nf;
         const rsrc_t rp = buf_rsrc(a.p + fo, nf * SZ);
-        // rows j0-1 .. j0+RPT of p (0 outside: the r = 0 face has no
-        // coefficient, the row past the last unknown is the Dirichlet side)
         T pv[CY_RPT + 2], pe[CY_RPT], pw[CY_RPT];
 #pragma unroll
-        for (int r = 0; r < CY_RPT + 2; ++r) {
-            const int j = j0 - 1 + r;
-            pv[r] = bload<T>(rp, (live && j >= 0 && j < nz1) ? (uint32_t)(j * nx1 + k) * SZ : BUF_OOB);
-        }
+        for (int r = 0; r < CY_RPT + 2; ++r) pv[r] = bload<T>(rp, oc[r]);
 #pragma unroll
         for (int r = 0; r < CY_RPT; ++r) {
-            const int j = j0 + r;
-            const bool ok = live && j < nz1;
-            const uint32_t e = (uint32_t)(j * nx1 + k);
-            pe[r] = bload<T>(rp, (ok && k + 1 < nx1) ? (e + 1) * SZ : BUF_OOB);
-            pw[r] = bload<T>(rp, (ok && k > 0) ? (e - 1) * SZ : BUF_OOB);
+            pe[r] = bload<T>(rp, oe[r]);
+            pw[r] = bload<T>(rp, ow[r]);
         }
         double pq = 0.0;
         const rsrc_t rq = buf_rsrc((a.q != nullptr ? a.q : const_cast<T*>(a.p)) + fo,
@@ -123,17 +132,21 @@ __global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
         const rsrc_t rb = buf_rsrc(a.b + fo, RES ? nf * 8u : 0u);
 #pragma unroll
         for (int r = 0; r < CY_RPT; ++r) {
-            const int j = j0 + r;
-            const uint32_t o = (live && j < nz1) ? (uint32_t)(j * nx1 + k) : BUF_OOB / 8u;
             const T c = pv[r + 1];
             T v = cyl_point<T>(c, pv[r], pv[r + 2], pw[r], pe[r], f1[r], f1[r + 1], fl[r], fr[r], wv[r]);
-            if constexpr (RES) v = (T)(bload<double>(rb, o * 8u) - (double)v);
-            bstore<T>(v, rq, o * SZ);
+            if constexpr (RES) v = (T)(bload<double>(rb, oc[r + 1] == BUF_OOB ? BUF_OOB : oc[r + 1] / SZ * 8u) - (double)v);
+            bstore<T>(v, rq, oc[r + 1]);
             pq += (double)c * (double)v;
         }
         if (a.ctl == nullptr) continue;
-        const double s = block_sum(pq, red);
-        if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + by * a.gx + bx] = s;
+        pq = wave_sum(pq);
+        if (lane == 0) red[kf][ty] = pq;
+    }
+    if (a.ctl == nullptr) return;
+    __syncthreads();
+    if (threadIdx.x < ns && act[threadIdx.x] != 0) {
+        const int kf = threadIdx.x;
+        a.partial[(size_t)(f0 + kf) * a.pstride + by * a.gx + bx] = ((red[kf][0] + red[kf][1]) + red[kf][2]) + red[kf][3];
     }
 }
 

@@ -61,7 +61,7 @@ __device__ __forceinline__ T ho_axis(const T* v, const T* k, bool lo, bool hi) {
 
 template <typename T, bool RES>
 __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
-    __shared__ double red[4];
+    __shared__ double red[64][4];                  // per-wave (p, Ap) of the block's fields
     const int nx = a.nx, nz = a.nz, nx1 = nx - 1, nz1 = nz - 1;
     const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int L = xcd_linear(blockIdx.x, gridDim.x);
@@ -170,11 +170,16 @@ __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
             pq += (double)c * (double)v;
         }
         if (a.ctl != nullptr) {
-            const double s = block_sum(pq, red);
-            if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + by * a.gx + bx] = s;
+            pq = wave_sum(pq);
+            if (lane == 0) red[field - f0][ty] = pq;
         }
         field = fn;
     }
+    if (a.ctl == nullptr) return;
+    __syncthreads();
+    const int kf = threadIdx.x;
+    if (kf < f1e - f0 && a.ctl[f0 + kf].active != 0)
+        a.partial[(size_t)(f0 + kf) * a.pstride + by * a.gx + bx] = ((red[kf][0] + red[kf][1]) + red[kf][2]) + red[kf][3];
 }
 
 namespace {

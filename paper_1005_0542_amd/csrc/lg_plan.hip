@@ -477,6 +477,9 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         if (tuning->op_fusion != 0) fus = tuning->op_fusion;
     }
     if (fus != 1 && fus != 2) return fail(LG_ERR_INVALID_ARG, "op_fusion must be 0, 1 or 2");
+    // default form: the FP64 axisymmetric update is register-bound with A p
+    // recomputed (measured faster with the stored q)
+    if ((tuning == nullptr || tuning->op_fusion == 0) && cyl && prec == LG_FP64) fus = 2;
     if (gi < -1 || gi == 0 || gi > 64) return fail(LG_ERR_INVALID_ARG, "graph_iters must be -1 or 1..64");
     if (osh < 1 || osh > 64) return fail(LG_ERR_INVALID_ARG, "op_shots must be in 1..64");
     if (spw != 0 && spw != 1 && spw != 2 && spw != 4)
