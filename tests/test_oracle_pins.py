@@ -745,3 +745,14 @@ def test_order4_pcg_with_second_order_preconditioner(n):
     if n == 32:
         xs = np.linalg.solve(ho.assemble_A4(kx, kz, w, d, d), b.ravel()).reshape(b.shape)
         assert np.max(np.abs(x4 - xs)) < 1e-8 * np.max(np.abs(xs))
+
+
+def test_cylindrical_source_carries_unit_volume_strength():
+    """The source (1/2 pi) delta(x - x0) / r of eq. acoustic_problem has unit
+    strength over the volume element 2 pi r dr dz; in the r-weighted discrete
+    equation it is f/(2 pi h_r h_z) at one node, so 2 pi h_r h_z times the
+    field summed over the mesh gives f back."""
+    hr, hz, f = 7.0, 3.0, 2.5
+    src = cyl.source_field((15, 32), (9, 1), f, hr, hz)
+    assert np.count_nonzero(src) == 1 and src[0, 8] != 0.0
+    assert abs(2 * np.pi * hr * hz * src.sum() - f) < 1e-15 * f
