@@ -65,8 +65,12 @@ struct CylStArgs {
     size_t pstride;
 };
 
+// The waves-per-EU bound leaves the register room to keep every load of a
+// shot in flight at once (without it the scheduler sinks each load to its use
+// behind a full vmcnt(0) wait, which halves the kernel's bandwidth).
 template <typename T, bool RES>
-__global__ __launch_bounds__(256) void cyl_stencil_kernel(CylStArgs<T> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, sizeof(T) == 4 ? 4 : 2))) void
+cyl_stencil_kernel(CylStArgs<T> a) {
     constexpr int MAXSH = 64;                   // fields per block at most (op_shots)
     __shared__ double red[MAXSH][4];
     __shared__ int act[MAXSH];

@@ -133,31 +133,44 @@ constexpr int GM_MAXK = 32;            // largest restart length supported
 constexpr int GM_BLK = 256;
 constexpr int GM_CHUNK = 4096;         // elements per block per shot in reductions
 
-// partial[s][i][b] = sum over block b of the shot's chunk of V_i * w (i < m);
-// one sweep reads w and every V_i once.
+// partial[s][i][b] = sum over block b of the shot's chunk of V_i * w (i < m).
+// The basis vectors are taken 8 at a time; within a group every load of an
+// element step is an unconditional buffer load (vectors past m have a
+// resource of size 0 and read 0), so they are all in flight together.
 __global__ __launch_bounds__(GM_BLK) void gm_multidot_kernel(const double* __restrict__ V, size_t vstride,
                                                              int m, const double* __restrict__ w, size_t n_s,
                                                              const int* __restrict__ active,
                                                              double* __restrict__ partial, int nblk) {
+    constexpr int G = 8;
     __shared__ double red[GM_BLK / 64];
     const int s = blockIdx.y, b = blockIdx.x;
     if (active[s] == 0) return;
     const size_t base = (size_t)s * n_s;
     const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
-    double acc[GM_MAXK + 1];
+    const uint32_t nbytes = (uint32_t)(n_s * 8);
+    const rsrc_t rw = buf_rsrc(w + base, nbytes);
+    for (int i0 = 0; i0 < m; i0 += G) {           // uniform over the block
+        rsrc_t rv[G];
 #pragma unroll
-    for (int i = 0; i <= GM_MAXK; ++i) acc[i] = 0.0;
-    for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) {
-        const double wv = w[base + e];
+        for (int u = 0; u < G; ++u) rv[u] = buf_rsrc(V + (size_t)(i0 + u) * vstride + base, i0 + u < m ? nbytes : 0u);
+        double acc[G];
 #pragma unroll
-        for (int i = 0; i <= GM_MAXK; ++i)
-            if (i < m) acc[i] += V[i * vstride + base + e] * wv;
-    }
+        for (int u = 0; u < G; ++u) acc[u] = 0.0;
+        for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) {
+            const uint32_t off = (uint32_t)(e * 8);
+            const double wv = bload<double>(rw, off);
+            double vv[G];
 #pragma unroll
-    for (int i = 0; i <= GM_MAXK; ++i) {
-        if (i < m) {                       // uniform over the block
-            const double t = block_sum(acc[i], red);
-            if (threadIdx.x == 0) partial[((size_t)s * (GM_MAXK + 1) + i) * nblk + b] = t;
+            for (int u = 0; u < G; ++u) vv[u] = bload<double>(rv[u], off);
+#pragma unroll
+            for (int u = 0; u < G; ++u) acc[u] += vv[u] * wv;
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            if (i0 + u < m) {                      // uniform over the block
+                const double t = block_sum(acc[u], red);
+                if (threadIdx.x == 0) partial[((size_t)s * (GM_MAXK + 1) + i0 + u) * nblk + b] = t;
+            }
         }
     }
 }
