@@ -240,8 +240,12 @@ __device__ __forceinline__ void apply_pair(rsrc_t rP, const T* __restrict__ kap,
 // M-1-i.  The Stockham passes then run LDS -> LDS, except the last pass,
 // which leaves its outputs in registers; they are stored straight to global
 // memory (coalesced: output K = t + qb M/R + u NS_LAST).
+// The update modes get a waves-per-EU bound of 3: the register room keeps
+// more of their loads in flight (measured 1.8 % faster at 64 shots 2048^2).
 template <typename T, int M, int R, int FPB, int MODE>
-__global__ __launch_bounds__(FPB*(M / R)) void dst_kernel(DstArgs<T> a) {
+__global__ __launch_bounds__(FPB*(M / R)) __attribute__((amdgpu_waves_per_eu(
+    1, (MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART) ? 3 : 8))) void
+dst_kernel(DstArgs<T> a) {
     using FP = FftPlan<M, R>;
     constexpr int TPF = M / R;
     constexpr int NX = M / 2;
