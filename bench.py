@@ -57,12 +57,14 @@ def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True, medium: 
     }
 
 
-def cyl_kernel_bytes(ws: int, shots: int, fused: bool = True):
+def cyl_kernel_bytes(ws: int, shots: int, fused: bool = True, dichotomy: bool = True):
     """The same for the axisymmetric iteration (Sec. 2.3): fused, the update
     recomputes A p (stored-q form: the operator writes q, the update reads it);
-    the r-systems read rhat and write zhat once (their forward-sweep
-    intermediate round trip through memory is not counted); the face tables,
-    shift and Thomas factors are shared by all shots."""
+    the r-systems read rhat and write zhat once (the Thomas sweep's
+    intermediate, or the Dichotomy's three values per segment, are not
+    counted); the face tables, shift and r-system factors are shared by all
+    shots; with the Dichotomy the inverse transform also reads the two
+    separator responses of every row (shared by all shots)."""
     if fused:
         op = ws + 3 * ws / shots                              # p in; a1, a2, w once per batch
         upd = 32 + 2 * ws + 3 * ws / shots                    # x, r in/out (f64); p in; rhat out; medium
@@ -73,7 +75,7 @@ def cyl_kernel_bytes(ws: int, shots: int, fused: bool = True):
         "operator": op,
         "update_fdct": upd,
         "r_systems": 2 * ws + 2 * ws / shots,                 # rhat in, zhat out; factors once per batch
-        "correct_idct": 3 * ws,                               # zhat in, p in/out
+        "correct_idct": 3 * ws + (2 * ws / shots if dichotomy else 0),   # zhat in, p in/out
     }
 
 
@@ -193,12 +195,15 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     seg, seg_len = run.plan.layout()
     out["segments"] = seg
     ws = 8 if precision == "fp64" else 4
+    # the library's default op_fusion: stored q for FP64 axisymmetric plans
+    # and the fourth-order operator, else recomputed in the update
+    fusion = tuned.get("op_fusion", 0) or (2 if (cyl and precision == "fp64") or order == 4 else 1)
     if cyl:
-        kb = cyl_kernel_bytes(ws, shots, tuned.get("op_fusion", 0) != 2)
+        kb = cyl_kernel_bytes(ws, shots, fusion != 2, seg > 1)
     elif order == 4:
         kb = kernel_bytes(ws, shots, seg_len, fused=False, medium=3)
     else:
-        kb = kernel_bytes(ws, shots, seg_len, tuned.get("op_fusion", 0) != 2)
+        kb = kernel_bytes(ws, shots, seg_len, fusion != 2)
     slots = [0, 1, 2, 4] if cyl else [0, 1, 2, 3, 4]          # the profile helper's kernel slots
     per_iter_bytes = sum(kb.values()) * npts * shots
     mean_it = max(out["mean_iters"], 1e-9)

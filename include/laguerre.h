@@ -82,9 +82,12 @@ typedef enum { LG_TOP_DIRICHLET = 0, LG_TOP_FREE = 1 } lg_top_bc;
  * 1..nz, z_k = (k-1/2) dx, k = 1..nx: the unknowns are i = 1..nz-1 (y = 0 on
  * the side r = l1, row i = nz), with the symmetry condition at r = 0 and no
  * flux through the two z-ends; fields [nz-1][nx] (z fastest), medium node
- * arrays [F][nz][nx]; acoustic plans, FP64 or mixed, unsegmented r-systems
- * (tuning.segments 0 or 1; top_bc is not used).  The source term carries
- * 1/(2 pi dx dz) (the 2.5D point source). */
+ * arrays [F][nz][nx]; acoustic plans, FP64 or mixed (top_bc is not used).
+ * The r-systems vary with r (non-Toeplitz); with tuning.segments = P > 1 they
+ * are solved by the Dichotomy with factors of every segment prepared once
+ * per plan, with P = 1 by Thomas (default: segments of 64 rows from 128 rows
+ * on, Thomas below).  The source term carries 1/(2 pi dx dz) (the 2.5D
+ * point source). */
 typedef enum { LG_CARTESIAN = 0, LG_CYLINDRICAL = 1 } lg_geometry;
 
 /* Spatial order of the acoustic operator (Sec. 3.3: higher-order schemes are
@@ -125,8 +128,9 @@ typedef struct { double tol; int32_t max_iter; int32_t restart; int32_t x0_given
 typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
 
 /* Optional tuning (zero fields = library default).
- *  segments      number P of Dichotomy segments per z-system (power of two,
- *                1..64, with nz/P in {2,4,...,64}).
+ *  segments      number P of Dichotomy segments per z-system (axisymmetric
+ *                plans: per r-system) (power of two, 1..64, with nz/P in
+ *                {2,4,...,64}; axisymmetric plans also take P = 1 at any nz).
  *  graph_iters   Krylov iterations captured per HIP graph (0: default 8,
  *                -1: no graph, plain stream launches).
  *  op_shots      shots per block of the operator kernel, which reuses the

@@ -10,15 +10,18 @@
 // shift w = r rho h^2/4.  Preconditioner B (eq. precond1, midrange
 // coefficients): the cosine transform (DCT-II) along z diagonalises the
 // no-flux z-part; each z-wavenumber leaves one symmetric tridiagonal system
-// along r whose coefficients vary with r.  Its Thomas factors are prepared
-// once per plan and the systems are solved one lane per wavenumber.
+// along r whose coefficients vary with r.  These systems are solved by
+// Thomas (one lane per system, the default) or by the Dichotomy (segments
+// > 1), with the factors of every segment prepared once per plan.
 //
 // Kernels of one CG iteration:
 //   cyl_stencil_kernel        (p, Ap) partials (q = A p stored only in the stored-q form)
 //   cyl_dct_kernel<UPDATE_OP> A p recomputed, x += alpha p, r -= alpha A p, ||r||^2, rhat = DCT r
 //                             (UPDATE: the stored q is read instead)
-//   cyl_thomas_kernel         zhat = B_k^{-1} rhat per wavenumber, (r, z) partials
-//   cyl_dct_kernel<CORRECT>   z = DCT^{-1} zhat, p = z + beta p
+//   cyl_thomas_kernel         r-systems by Thomas, (r, z) partials (default), or
+//   cyl_seg_kernel +          the Dichotomy: segments of the r-systems, then the
+//   cyl_red_kernel            reduced systems over the separators, (r, z) partials
+//   cyl_dct_kernel<CORRECT>   (Dichotomy: segment correction,) z = DCT^{-1} zhat, p = z + beta p
 // Mixed plans keep p, q, rhat, zhat and the tables in FP32 and x, r in FP64;
 // a solve that converges on the FP32 operator is restarted from the FP64
 // true residual b - A x (cyl_stencil_kernel<double, true>) until that
@@ -165,7 +168,9 @@ cyl_stencil_kernel(CylStArgs<T> a) {
 // ===========================================================================
 // CY_UPDATE_OP: the update recomputes q = A p for its two rows from p and the
 // face tables (the operator kernel then only forms (p, Ap)).
-enum CylMode { CY_FWD = 0, CY_INV = 1, CY_UPDATE = 2, CY_CORRECT = 3, CY_UPDATE_OP = 4 };
+// CY_INV_D / CY_CORRECT_D: the same with the r-system Dichotomy correction
+// applied to the input rows first.
+enum CylMode { CY_FWD = 0, CY_INV = 1, CY_UPDATE = 2, CY_CORRECT = 3, CY_UPDATE_OP = 4, CY_INV_D = 5, CY_CORRECT_D = 6 };
 
 template <typename T>
 struct CylDctArgs {
@@ -185,6 +190,8 @@ struct CylDctArgs {
     const T* a1;           // CY_UPDATE_OP: face tables and shift
     const T* a2;
     const T* w;
+    const cpx<T>* UV;      // CY_*_D: Dichotomy correction of the input rows
+    int Ls, P;
     double* partial;
     size_t pstride;
     int init;
@@ -200,7 +207,9 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
     constexpr int LL = LdsLen<M>::value;
     constexpr int NWAVE = (FPB * TPF + 63) / 64;
     constexpr int NIT = (N + TPF - 1) / TPF;
-    constexpr bool INVERSE = MODE == CY_INV || MODE == CY_CORRECT;
+    constexpr bool CORRM = MODE == CY_CORRECT || MODE == CY_CORRECT_D;    // p = z + beta p
+    constexpr bool DCH = MODE == CY_INV_D || MODE == CY_CORRECT_D;        // Dichotomy correction
+    constexpr bool INVERSE = MODE == CY_INV || MODE == CY_INV_D || CORRM;
     constexpr bool UPD = MODE == CY_UPDATE || MODE == CY_UPDATE_OP;
     __shared__ cpx<T> lds[FPB * LL];
     __shared__ double red[NWAVE];
@@ -214,7 +223,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
     const bool live = pair < npairs;
     const int j0 = 2 * pair, j1 = j0 + 1;
     const bool has1 = live && (j1 < a.nz1);
-    if constexpr (UPD || MODE == CY_CORRECT) {
+    if constexpr (UPD || CORRM) {
         if (!a.init && a.ctl[field].active == 0) return;   // uniform per block
     }
     cpx<T>* buf = lds + fid * LL;
@@ -222,7 +231,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
     const uint32_t nfe = (uint32_t)a.nz1 * (uint32_t)N;
     const size_t fbase = (size_t)field * nfe;
     double rr = 0.0;
-    T pold0[MODE == CY_CORRECT ? NOUT : 1], pold1[MODE == CY_CORRECT ? NOUT : 1];
+    T pold0[CORRM ? NOUT : 1], pold1[CORRM ? NOUT : 1];
 
     if (live) {
         if constexpr (!INVERSE) {
@@ -316,8 +325,21 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
             for (int it = 0; it < NIT; ++it) {
                 const int k = t + it * TPF;
                 const bool in = k < N;
-                const T d0 = bload<T>(rI, in ? (uint32_t)(j0 * N + k) * SZ : BUF_OOB);
-                const T d1 = bload<T>(rI, (in && has1) ? (uint32_t)(j1 * N + k) * SZ : BUF_OOB);
+                T d0 = bload<T>(rI, in ? (uint32_t)(j0 * N + k) * SZ : BUF_OOB);
+                T d1 = bload<T>(rI, (in && has1) ? (uint32_t)(j1 * N + k) * SZ : BUF_OOB);
+                if constexpr (DCH) {   // Dichotomy correction: y + x_{c_{s-1}} U + x_{c_s} V
+                    // j0 is even and separators are odd, so j1 lies in j0's segment or is
+                    // its separator (U = V = 0 there): one pair of separator values serves both
+                    const rsrc_t rUV = buf_rsrc(a.UV, nfe * 2 * SZ);
+                    const int sg = j0 / a.Ls;
+                    const T xl = bload<T>(rI, (in && sg > 0) ? (uint32_t)((sg * a.Ls - 1) * N + k) * SZ : BUF_OOB);
+                    const T xr = bload<T>(rI, (in && sg < a.P - 1) ? (uint32_t)((sg * a.Ls + a.Ls - 1) * N + k) * SZ
+                                                                  : BUF_OOB);
+                    const cpx<T> uv0 = bload2<T>(rUV, in ? (uint32_t)(j0 * N + k) * 2 * SZ : BUF_OOB);
+                    const cpx<T> uv1 = bload2<T>(rUV, (in && has1) ? (uint32_t)(j1 * N + k) * 2 * SZ : BUF_OOB);
+                    d0 = fmad(xr, uv0.y, fmad(xl, uv0.x, d0));
+                    d1 = fmad(xr, uv1.y, fmad(xl, uv1.x, d1));
+                }
                 if (in) {
                     const cpx<T> cd = {d0 * inv_n, -d1 * inv_n};         // conj(D) / Nz
                     if (k == 0) {
@@ -330,7 +352,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
                 }
             }
             if (t == 0) buf[lpad(N)] = {(T)0, (T)0};
-            if constexpr (MODE == CY_CORRECT) {
+            if constexpr (CORRM) {
                 const rsrc_t rPo = buf_rsrc(a.out + fbase, a.init ? 0u : nfe * SZ);
 #pragma unroll
                 for (int qb = 0; qb < NBL; ++qb)
@@ -354,7 +376,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
 
     if (live) {
         T beta = (T)0;
-        if constexpr (MODE == CY_CORRECT) beta = (T)a.ctl[field].beta;
+        if constexpr (CORRM) beta = (T)a.ctl[field].beta;
         const size_t o0 = fbase + (size_t)j0 * N, o1 = fbase + (size_t)j1 * N;
 #pragma unroll
         for (int qb = 0; qb < NBL; ++qb)
@@ -371,7 +393,7 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
                     x0 = V.x;
                     x1 = -V.y;
                 }
-                if constexpr (MODE == CY_CORRECT) {
+                if constexpr (CORRM) {
                     const int oi = qb * (RL / 2) + u;
                     if (!a.init) {
                         x0 += beta * pold0[oi];
@@ -389,10 +411,12 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
 }
 
 // ===========================================================================
-// r-systems: one lane per (wavenumber, field); forward sweep stores the
-// intermediate values, back substitution overwrites them.  (rhat, zhat) is
-// accumulated in the forward sweep from the LDL^T form (sum g_i dp_i) and
-// weighted by the transform's inverse weights (1/Nz for k = 0, else 2/Nz).
+// r-systems by Thomas (one segment, the default): one lane per (wavenumber,
+// field); the forward sweep stores its intermediate values, back
+// substitution overwrites them.  (rhat, zhat) is accumulated in the forward
+// sweep from the LDL^T form (sum g_i dp_i) and weighted by the transform's
+// inverse weights (1/Nz for k = 0, else 2/Nz).  Rows are taken in chunks of
+// CY_TU whose loads are all issued before the chunk's recurrence steps.
 // ===========================================================================
 template <typename T>
 struct CylTdArgs {
@@ -472,6 +496,176 @@ __global__ __launch_bounds__(256) void cyl_thomas_kernel(CylTdArgs<T> a) {
 }
 
 // ===========================================================================
+// r-systems by the Dichotomy (Sec. 1; eq. precond1 in the axisymmetric form).
+// Every wavenumber's system is split into P segments of Ls-1 rows, separated
+// by the rows c_s = s Ls + Ls - 1.  The coefficients vary with r, so every
+// segment has factors of its own (prepared once per plan, shared by every
+// shot and iteration):
+//   1. cyl_seg_kernel: each lane solves one (wavenumber, segment) with zero
+//      separator values, its rows held in registers; it stores y, the two
+//      end values and the local (r, T_s^{-1} r) (LDL^T form, sum g dp);
+//   2. cyl_red_kernel: per (shot, wavenumber) the reduced (Schur) tridiagonal
+//      system over the separators, serial Thomas with prepared factors; the
+//      separator values go into the separator rows of the solution, and
+//      (rhat, zhat) = sum of the local terms + G^T x (the reduced LDL^T sum);
+//   3. the correction x_j = y_j + x_{c_{s-1}} U_j + x_{c_s} V_j (U, V: the
+//      segment's responses to unit separator values, 0 on separator rows),
+//      fused into the inverse cosine transform, or cyl_corr_kernel.
+// ===========================================================================
+template <typename T>
+struct CylSegArgs {
+    const T* rhat;
+    T* y;
+    const T* cp;         // [nz1][nx1] segment-local upper factors
+    const T* inv;        // [nz1][nx1] segment-local inverse pivots
+    const T* lowr;       // [nz1] coupling to the previous row
+    double* E;           // [fields][P][3][nx1]: y(first row), y(last row), local (r, T_s^{-1} r)
+    int nx1, nz1, P;
+    int segtiles;        // ceil(P / 4)
+    ShotCtl* ctl;        // masked: skip inactive shots
+    int masked;
+};
+
+template <typename T, int LS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, sizeof(T) == 4 ? 4 : 2))) void
+cyl_seg_kernel(CylSegArgs<T> a) {
+    constexpr int L = LS - 1;
+    const int field = blockIdx.y;
+    if (a.masked && a.ctl[field].active == 0) return;        // uniform per block
+    const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int kt = blockIdx.x / a.segtiles, sg = (blockIdx.x - kt * a.segtiles) * 4 + ty;
+    const int k = kt * 64 + lane;
+    const bool live = k < a.nx1 && sg < a.P;
+    const int nx1 = a.nx1;
+    constexpr uint32_t SZ = sizeof(T);
+    const uint32_t nf = (uint32_t)nx1 * (uint32_t)a.nz1;
+    const rsrc_t rR = buf_rsrc(a.rhat + (size_t)field * nf, nf * SZ);
+    const rsrc_t rY = buf_rsrc(a.y + (size_t)field * nf, nf * SZ);
+    const rsrc_t rC = buf_rsrc(a.cp, nf * SZ);
+    const rsrc_t rI = buf_rsrc(a.inv, nf * SZ);
+    const rsrc_t rL = buf_rsrc(a.lowr, (uint32_t)a.nz1 * SZ);
+    const int row0 = sg * LS;
+    auto off = [&](int i) -> uint32_t { return live ? (uint32_t)((row0 + i) * nx1 + k) * SZ : BUF_OOB; };
+    T dp[L];
+    double acc = 0.0;
+    T prev = (T)0;
+#pragma unroll
+    for (int i0 = 0; i0 < L; i0 += 8) {
+        T rv[8], iv[8], lv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (i0 + u < L) {
+                rv[u] = bload<T>(rR, off(i0 + u));
+                iv[u] = bload<T>(rI, off(i0 + u));
+                lv[u] = bload<T>(rL, live ? (uint32_t)(row0 + i0 + u) * SZ : BUF_OOB);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (i0 + u < L) {
+                const T g = (i0 + u == 0) ? rv[u] : rv[u] - lv[u] * prev;
+                prev = g * iv[u];
+                dp[i0 + u] = prev;
+                acc += (double)g * (double)prev;
+            }
+        }
+    }
+    T x = dp[L - 1];
+    bstore<T>(x, rY, off(L - 1));
+    const T ylast = x;
+#pragma unroll
+    for (int i0 = L - 2; i0 >= 0; i0 -= 8) {
+        T cv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 - u >= 0) cv[u] = bload<T>(rC, off(i0 - u));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (i0 - u >= 0) {
+                x = dp[i0 - u] - cv[u] * x;
+                bstore<T>(x, rY, off(i0 - u));
+            }
+        }
+    }
+    if (!live) return;
+    double* e = a.E + ((size_t)field * a.P + sg) * 3 * nx1 + k;
+    e[0] = (double)x;
+    e[nx1] = (double)ylast;
+    e[2 * (size_t)nx1] = acc;
+}
+
+template <typename T>
+struct CylRedArgs {
+    const T* rhat;
+    T* y;                // separator rows receive the separator values
+    const double* E;
+    const double* cpl;   // [2][nz1]: couplings to rows j-1, j+1
+    const double* red;   // [nx1][P-1][3]
+    int nx1, nz1, Ls;
+    ShotCtl* ctl;        // mode != 0: masked, partials
+    double* partial;
+    size_t pstride;
+    int mode;
+};
+
+template <typename T, int P>
+__global__ __launch_bounds__(256) void cyl_red_kernel(CylRedArgs<T> a) {
+    __shared__ double redsum[4];
+    const int nx1 = a.nx1, field = blockIdx.y;
+    if (a.mode != 0 && a.ctl[field].active == 0) return;      // uniform per block
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    const bool live = k < nx1;
+    const int kc = min(k, nx1 - 1);
+    const size_t fo = (size_t)field * nx1 * a.nz1;
+    const double* E = a.E + (size_t)field * P * 3 * nx1 + kc;
+    double acc = 0.0;
+#pragma unroll
+    for (int sg = 0; sg < P; ++sg) acc += E[(3 * sg + 2) * (size_t)nx1];
+    if constexpr (P > 1) {
+        const double* rw = a.red + (size_t)kc * 3 * (P - 1);
+        double dpr[P - 1];
+        double prev = 0.0;
+#pragma unroll
+        for (int c = 0; c < P - 1; ++c) {
+            const int row = c * a.Ls + a.Ls - 1;
+            const double G = (double)a.rhat[fo + (size_t)row * nx1 + kc] - a.cpl[row] * E[(3 * c + 1) * (size_t)nx1] -
+                             a.cpl[a.nz1 + row] * E[(3 * (c + 1)) * (size_t)nx1];
+            const double g = G - rw[3 * c] * prev;
+            prev = g * rw[3 * c + 2];
+            dpr[c] = prev;
+            acc += g * prev;
+        }
+        double x = dpr[P - 2];
+        if (live) a.y[fo + (size_t)((P - 1) * a.Ls - 1) * nx1 + kc] = (T)x;
+#pragma unroll
+        for (int c = P - 3; c >= 0; --c) {
+            x = dpr[c] - rw[3 * c + 1] * x;
+            if (live) a.y[fo + (size_t)(c * a.Ls + a.Ls - 1) * nx1 + kc] = (T)x;
+        }
+    }
+    if (a.mode == 0) return;
+    acc = live ? acc * ((k == 0) ? 1.0 / nx1 : 2.0 / nx1) : 0.0;
+    const double sblk = block_sum(acc, redsum);
+    if (threadIdx.x == 0) a.partial[(size_t)field * a.pstride + blockIdx.x] = sblk;
+}
+
+// z = y + x_{c_{s-1}} U + x_{c_s} V in place (the plain r-system call)
+template <typename T>
+__global__ __launch_bounds__(256) void cyl_corr_kernel(T* z, const cpx<T>* UV, int nx1, int nz1, int Ls, int P) {
+    const size_t nf = (size_t)nx1 * nz1;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const int field = blockIdx.y;
+    if (e >= nf) return;
+    const int j = (int)(e / nx1), k = (int)(e - (size_t)j * nx1);
+    const int sg = j / Ls;
+    if (j - sg * Ls == Ls - 1) return;                 // separator rows already hold their values
+    T* zf = z + (size_t)field * nf;
+    const T xl = sg > 0 ? zf[(size_t)(sg * Ls - 1) * nx1 + k] : (T)0;
+    const T xr = sg < P - 1 ? zf[(size_t)(sg * Ls + Ls - 1) * nx1 + k] : (T)0;
+    zf[e] = fmad(xr, UV[e].y, fmad(xl, UV[e].x, zf[e]));
+}
+
+// ===========================================================================
 // launchers
 // ===========================================================================
 namespace {
@@ -547,6 +741,9 @@ CylDctArgs<T> cyl_dct_args(lg_plan* p) {
     a.a1 = (const T*)p->cy_a1;
     a.a2 = (const T*)p->cy_a2;
     a.w = (const T*)p->w;
+    a.UV = (const cpx<T>*)p->cy_UV;
+    a.Ls = p->blk[0].Ls;
+    a.P = p->blk[0].P;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
     return a;
@@ -571,6 +768,85 @@ hipError_t cyl_thomas_T(lg_plan* p, const T* rhat, T* z, int nfields, int mode) 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || mode == 0) return e;
     return launch_finalize(p, 2 /* (r, z) */, (int)grid.x, mode, 0.0, 0, 1.0);
+}
+
+template <typename T, int LS>
+hipError_t cyl_seg_L(lg_plan* p, const T* rhat, T* y, int nfields, int masked) {
+    CylSegArgs<T> a;
+    a.rhat = rhat;
+    a.y = y;
+    a.cp = (const T*)p->cy_cp;
+    a.inv = (const T*)p->cy_invden;
+    a.lowr = (const T*)p->cy_lowr;
+    a.E = p->E;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.P = p->blk[0].P;
+    a.segtiles = (a.P + 3) / 4;
+    a.ctl = p->ctl;
+    a.masked = masked;
+    const dim3 grid((unsigned)(((p->nx1 + 63) / 64) * a.segtiles), (unsigned)nfields);
+    hipLaunchKernelGGL((cyl_seg_kernel<T, LS>), grid, dim3(256), 0, p->stream, a);
+    return hipGetLastError();
+}
+
+template <typename T, int P>
+hipError_t cyl_red_P(lg_plan* p, CylRedArgs<T>& a, int nfields) {
+    const dim3 grid((unsigned)((p->nx1 + 255) / 256), (unsigned)nfields);
+    hipLaunchKernelGGL((cyl_red_kernel<T, P>), grid, dim3(256), 0, p->stream, a);
+    return hipGetLastError();
+}
+
+// segments, then the reduced systems (mode 0: plain; 1: CG start; 2: CG
+// iteration, masked, with the (r, z) finalize)
+template <typename T>
+hipError_t cyl_rsys_T(lg_plan* p, const T* rhat, T* y, int nfields, int mode) {
+    if (p->blk[0].P == 1) return cyl_thomas_T<T>(p, rhat, y, nfields, mode);
+    hipError_t e;
+    switch (p->blk[0].Ls) {
+        case 2: e = cyl_seg_L<T, 2>(p, rhat, y, nfields, mode != 0); break;
+        case 4: e = cyl_seg_L<T, 4>(p, rhat, y, nfields, mode != 0); break;
+        case 8: e = cyl_seg_L<T, 8>(p, rhat, y, nfields, mode != 0); break;
+        case 16: e = cyl_seg_L<T, 16>(p, rhat, y, nfields, mode != 0); break;
+        case 32: e = cyl_seg_L<T, 32>(p, rhat, y, nfields, mode != 0); break;
+        case 64: e = cyl_seg_L<T, 64>(p, rhat, y, nfields, mode != 0); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    CylRedArgs<T> a;
+    a.rhat = rhat;
+    a.y = y;
+    a.E = p->E;
+    a.cpl = p->cy_cpl64;
+    a.red = p->cy_red;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.Ls = p->blk[0].Ls;
+    a.ctl = p->ctl;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    a.mode = mode;
+    switch (p->blk[0].P) {
+        case 1: e = cyl_red_P<T, 1>(p, a, nfields); break;
+        case 2: e = cyl_red_P<T, 2>(p, a, nfields); break;
+        case 4: e = cyl_red_P<T, 4>(p, a, nfields); break;
+        case 8: e = cyl_red_P<T, 8>(p, a, nfields); break;
+        case 16: e = cyl_red_P<T, 16>(p, a, nfields); break;
+        case 32: e = cyl_red_P<T, 32>(p, a, nfields); break;
+        case 64: e = cyl_red_P<T, 64>(p, a, nfields); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess || mode == 0) return e;
+    return launch_finalize(p, 2 /* (r, z) */, (p->nx1 + 255) / 256, mode, 0.0, 0, 1.0);
+}
+
+template <typename T>
+hipError_t cyl_corr_T(lg_plan* p, T* z, int nfields) {
+    const size_t nf = (size_t)p->nx1 * p->nz1;
+    const dim3 grid((unsigned)((nf + 255) / 256), (unsigned)nfields);
+    hipLaunchKernelGGL(cyl_corr_kernel<T>, grid, dim3(256), 0, p->stream, z, (const cpx<T>*)p->cy_UV, p->nx1,
+                       p->nz1, p->blk[0].Ls, p->blk[0].P);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -598,23 +874,30 @@ hipError_t cyl_launch_restart(lg_plan* p, const double* b, double* x, double tol
     return cyl_launch_update(p, 2, b, x, tol, max_iter);
 }
 
-hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields) {
+hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields, int corr) {
     if (p->prec == LG_FP64) {
         CylDctArgs<double> a = cyl_dct_args<double>(p);
         a.in = (const double*)in;
         a.out = (double*)out;
+        if (inverse && corr) return cyl_dct_dispatch<double, CY_INV_D>(p, a, nfields);
         return inverse ? cyl_dct_dispatch<double, CY_INV>(p, a, nfields)
                        : cyl_dct_dispatch<double, CY_FWD>(p, a, nfields);
     }
     CylDctArgs<float> a = cyl_dct_args<float>(p);
     a.in = (const float*)in;
     a.out = (float*)out;
+    if (inverse && corr) return cyl_dct_dispatch<float, CY_INV_D>(p, a, nfields);
     return inverse ? cyl_dct_dispatch<float, CY_INV>(p, a, nfields) : cyl_dct_dispatch<float, CY_FWD>(p, a, nfields);
 }
 
-hipError_t cyl_launch_thomas(lg_plan* p, const void* rhat, void* z, int nfields, int mode) {
-    if (p->prec == LG_FP64) return cyl_thomas_T<double>(p, (const double*)rhat, (double*)z, nfields, mode);
-    return cyl_thomas_T<float>(p, (const float*)rhat, (float*)z, nfields, mode);
+hipError_t cyl_launch_rsys(lg_plan* p, const void* rhat, void* y, int nfields, int mode) {
+    if (p->prec == LG_FP64) return cyl_rsys_T<double>(p, (const double*)rhat, (double*)y, nfields, mode);
+    return cyl_rsys_T<float>(p, (const float*)rhat, (float*)y, nfields, mode);
+}
+
+hipError_t cyl_launch_corr(lg_plan* p, void* z, int nfields) {
+    if (p->prec == LG_FP64) return cyl_corr_T<double>(p, (double*)z, nfields);
+    return cyl_corr_T<float>(p, (float*)z, nfields);
 }
 
 hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, double tol, int max_iter) {
@@ -651,13 +934,15 @@ hipError_t cyl_launch_correct(lg_plan* p, int init) {
         a.in = (const double*)p->y;
         a.out = (double*)p->p;
         a.init = init;
-        return cyl_dct_dispatch<double, CY_CORRECT>(p, a, nf);
+        return p->blk[0].P > 1 ? cyl_dct_dispatch<double, CY_CORRECT_D>(p, a, nf)
+                               : cyl_dct_dispatch<double, CY_CORRECT>(p, a, nf);
     }
     CylDctArgs<float> a = cyl_dct_args<float>(p);
     a.in = (const float*)p->y;
     a.out = (float*)p->p;
     a.init = init;
-    return cyl_dct_dispatch<float, CY_CORRECT>(p, a, nf);
+    return p->blk[0].P > 1 ? cyl_dct_dispatch<float, CY_CORRECT_D>(p, a, nf)
+                           : cyl_dct_dispatch<float, CY_CORRECT>(p, a, nf);
 }
 
 }  // namespace lg

@@ -208,6 +208,18 @@ template <>
 __device__ __forceinline__ double bload<double>(rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
 }
+// a pair of consecutive values (one 8- or 16-byte load)
+template <typename T>
+__device__ __forceinline__ cpx<T> bload2(rsrc_t r, uint32_t off);
+template <>
+__device__ __forceinline__ cpx<float> bload2<float>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(cpx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0));
+}
+template <>
+__device__ __forceinline__ cpx<double> bload2<double>(rsrc_t r, uint32_t off) {
+    return __builtin_bit_cast(cpx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
+}
+
 template <typename T>
 __device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t off);
 template <>

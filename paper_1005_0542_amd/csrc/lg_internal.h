@@ -92,9 +92,15 @@ struct lg_plan {
     void* cy_a1 = nullptr;     // [nz1][nx1] working type: a1 / h_r^2 on the face below row j
     void* cy_a2 = nullptr;     // [nz1][nx1+1]: a2 / h_z^2 on the face left of column k (0 at both ends)
     void* cy_ctw = nullptr;    // [nx1] complex working type: exp(-i pi k / (2 Nz))
-    void* cy_cp = nullptr;     // [nz1][nx1]: Thomas upper factors of B's r-systems
-    void* cy_invden = nullptr; // [nz1][nx1]: inverse pivots
+    // r-systems by the Dichotomy (blk[0].P segments of blk[0].Ls - 1 rows and
+    // P - 1 separator rows c_s = s Ls + Ls - 1): per wavenumber k and row j
+    void* cy_cp = nullptr;     // [nz1][nx1]: segment-local Thomas upper factors
+    void* cy_invden = nullptr; // [nz1][nx1]: segment-local inverse pivots
+    void* cy_UV = nullptr;     // [nz1][nx1] pairs (U, V): responses to the left / right separator
+                               // value 1 (0 on separator rows); allocated for more than one segment
     void* cy_lowr = nullptr;   // [nz1]: coupling of row j to row j-1 (0 for the first)
+    double* cy_cpl64 = nullptr;   // [2][nz1] FP64: couplings to rows j-1 and j+1
+    double* cy_red = nullptr;     // [nx1][P-1][3] FP64: reduced system (sub-diagonal, upper factor, inverse pivot)
     double* cy_a1_64 = nullptr;   // mixed plans: FP64 copies of cy_a1, cy_a2 (true residual)
     double* cy_a2_64 = nullptr;
     double src_scale = 0.0;    // discrete delta: 1/(dx dz), or 1/(2 pi h_r h_z)
@@ -181,8 +187,12 @@ hipError_t launch_correct_idst(lg_plan* p, int init);
 hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale);
 // 2.5D axisymmetric plans
 hipError_t cyl_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce);
-hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields);
-hipError_t cyl_launch_thomas(lg_plan* p, const void* rhat, void* z, int nfields, int mode);
+// corr (inverse only): apply the r-system Dichotomy correction to the input rows
+hipError_t cyl_launch_dct(lg_plan* p, int inverse, const void* in, void* out, int nfields, int corr = 0);
+// r-systems: segments + reduced systems (mode 0 plain, 1 CG start, 2 CG
+// iteration with the (r, z) finalize); the correction follows separately
+hipError_t cyl_launch_rsys(lg_plan* p, const void* rhat, void* y, int nfields, int mode);
+hipError_t cyl_launch_corr(lg_plan* p, void* z, int nfields);
 // init 0 iteration, 1 start (x = 0, r = b), 2 restart from the stored r
 hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, double tol, int max_iter);
 // FP64 true residual r = b - A x, then the update pass with init 2

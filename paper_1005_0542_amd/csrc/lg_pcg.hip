@@ -19,7 +19,7 @@ hipError_t enqueue_iteration(lg_plan* p) {
     if (p->cyl) {   // axisymmetric: transforms along z, Thomas per wavenumber
         hipError_t e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);   // (p, Ap), alpha
         if (e == hipSuccess) e = cyl_launch_update(p, 0, nullptr, nullptr, 0.0, 0);  // x, r, rhat
-        if (e == hipSuccess) e = cyl_launch_thomas(p, p->rhat, p->y, nf, 2);       // zhat, beta
+        if (e == hipSuccess) e = cyl_launch_rsys(p, p->rhat, p->y, nf, 2);         // zhat, beta
         if (e == hipSuccess) e = cyl_launch_correct(p, 0);                         // z, p = z + beta p
         return e;
     }
@@ -91,7 +91,7 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
     // z = B^{-1} r, p = z, rz = (r, z)
     if (p->cyl) {
         LG_HIP(cyl_launch_update(p, 1, b, x, o->tol, o->max_iter));
-        LG_HIP(cyl_launch_thomas(p, p->rhat, p->y, nf, 1));
+        LG_HIP(cyl_launch_rsys(p, p->rhat, p->y, nf, 1));
         LG_HIP(cyl_launch_correct(p, 1));
     } else {
         LG_HIP(launch_update_fdst(p, o->x0_given ? 4 : 1, b, x, o->tol, o->max_iter));
@@ -135,7 +135,7 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
         for (int rep = 0; rep < 4; ++rep) {
             if (p->cyl) {                                                  // r = b - A x (FP64), restart
                 LG_HIP(cyl_launch_restart(p, b, x, o->tol, o->max_iter));
-                LG_HIP(cyl_launch_thomas(p, p->rhat, p->y, nf, 1));
+                LG_HIP(cyl_launch_rsys(p, p->rhat, p->y, nf, 1));
                 LG_HIP(cyl_launch_correct(p, 1));
             } else {
                 LG_HIP(launch_update_fdst(p, 3, b, x, o->tol, o->max_iter));
@@ -181,7 +181,7 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
     const bool cy = p->cyl;
     if (cy) {
         LG_HIP(cyl_launch_update(p, 1, b, x, 0.0, iters + 1));
-        LG_HIP(cyl_launch_thomas(p, p->rhat, p->y, nf, 1));
+        LG_HIP(cyl_launch_rsys(p, p->rhat, p->y, nf, 1));
         LG_HIP(cyl_launch_correct(p, 1));
     } else {
         LG_HIP(launch_update_fdst(p, 1, b, x, 0.0, iters + 1));
@@ -202,7 +202,7 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
                    : launch_update_fdst(p, 0, nullptr, nullptr, 0.0, 0);
         if (e == hipSuccess) e = hipEventRecord(ev[2], p->stream);
         if (e == hipSuccess)
-            e = cy ? cyl_launch_thomas(p, p->rhat, p->y, nf, 2) : launch_td(p, 0, p->rhat, p->y, nf, 1);
+            e = cy ? cyl_launch_rsys(p, p->rhat, p->y, nf, 2) : launch_td(p, 0, p->rhat, p->y, nf, 1);
         if (e == hipSuccess) e = hipEventRecord(ev[3], p->stream);
         if (e == hipSuccess && !cy) e = launch_rs(p, 0, p->rhat, p->y, nf, 2);
         if (e == hipSuccess) e = hipEventRecord(ev[4], p->stream);

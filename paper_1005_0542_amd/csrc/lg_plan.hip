@@ -126,7 +126,8 @@ lg_status prepare_free_surface(lg_plan* pl, const PrecBlock& B) {
 // Preconditioner: per z-wavenumber k the r-system with off-diagonals
 // -rbar_j kappa~/h_r^2 and diagonal (A1_j + A1_{j-1} + r_j rho~ h^2/4 +
 // r_j kappa~ lambda_k), lambda_k = (4/h_z^2) sin^2(pi k / (2 Nz)); its
-// Thomas factors (upper factors and inverse pivots) in long double.
+// Dichotomy tables (segment factors, separator responses, reduced system)
+// in long double.
 lg_status prepare_cylindrical(lg_plan* pl, const double* kap) {
     const int nx = pl->g.nx, nz1 = pl->nz1, nx1 = pl->nx1;   // nx1 = Nz
     const long double hr = pl->g.dz, hz = pl->g.dx;
@@ -158,29 +159,98 @@ lg_status prepare_cylindrical(lg_plan* pl, const double* kap) {
         ctw[2 * k + 1] = (double)(-std::sin(pi * k / (2.0L * nx1)));
     }
     if ((st = upload_working(pl, &pl->cy_ctw, ctw)) != LG_OK) return st;
+    // r-systems by the Dichotomy: P segments of Ls-1 rows, separated by the
+    // rows c_s = s Ls + Ls - 1 (s < P-1); n = nz1 = P Ls - 1.
+    const int Ls = pl->blk[0].Ls, P = pl->blk[0].P;
     const long double kt = pl->kappa_t, dsh = (long double)pl->rho_t * pl->lag.h * pl->lag.h / 4.0L;
-    std::vector<long double> A1(nz1);
+    std::vector<long double> A1(nz1), lo(nz1), up(nz1);
     for (int j = 0; j < nz1; ++j) A1[j] = (j + 1.0L) * hr * kt / (hr * hr);
-    std::vector<double> cp((size_t)nz1 * nx1), inv((size_t)nz1 * nx1), lowr(nz1);
-    for (int j = 0; j < nz1; ++j) lowr[j] = (j > 0) ? (double)(-A1[j - 1]) : 0.0;
+    for (int j = 0; j < nz1; ++j) {
+        lo[j] = (j > 0) ? -A1[j - 1] : 0.0L;          // coupling of row j to row j-1
+        up[j] = (j + 1 < nz1) ? -A1[j] : 0.0L;        // coupling of row j to row j+1
+    }
+    std::vector<double> cp((size_t)nz1 * nx1, 0.0), inv((size_t)nz1 * nx1, 0.0), U((size_t)nz1 * nx1, 0.0),
+        V((size_t)nz1 * nx1, 0.0), lowr(nz1), cpl64(2 * (size_t)nz1), red((size_t)nx1 * 3 * std::max(1, P - 1), 0.0);
+    for (int j = 0; j < nz1; ++j) {
+        lowr[j] = (double)lo[j];
+        cpl64[j] = (double)lo[j];
+        cpl64[nz1 + j] = (double)up[j];
+    }
+    std::vector<long double> d(nz1), c(Ls), w(Ls), Us(nz1), Vs(nz1);
     for (int k = 0; k < nx1; ++k) {
-        const long double s = std::sin(pi * k / (2.0L * nx1));
-        const long double lam = 4.0L / (hz * hz) * s * s;
-        long double cprev = 0.0L;
+        const long double sn = std::sin(pi * k / (2.0L * nx1));
+        const long double lam = 4.0L / (hz * hz) * sn * sn;
         for (int j = 0; j < nz1; ++j) {
             const long double r = (j + 0.5L) * hr;
-            const long double diag = A1[j] + (j > 0 ? A1[j - 1] : 0.0L) + r * dsh + r * kt * lam;
-            const long double lo = (j > 0) ? -A1[j - 1] : 0.0L;
-            const long double up = (j + 1 < nz1) ? -A1[j] : 0.0L;
-            const long double den = diag - lo * cprev;
-            cprev = up / den;
-            cp[(size_t)j * nx1 + k] = (double)cprev;
-            inv[(size_t)j * nx1 + k] = (double)(1.0L / den);
+            d[j] = A1[j] + (j > 0 ? A1[j - 1] : 0.0L) + r * dsh + r * kt * lam;
+        }
+        for (int sg = 0; sg < P; ++sg) {
+            const int a = sg * Ls, b = a + Ls - 2, L = Ls - 1;
+            // local Thomas factors of the segment (no coupling to its separators)
+            long double cprev = 0.0L;
+            for (int i = 0; i < L; ++i) {
+                const int j = a + i;
+                const long double den = d[j] - (i > 0 ? lo[j] * cprev : 0.0L);
+                cprev = (i + 1 < L) ? up[j] / den : 0.0L;
+                c[i] = cprev;
+                w[i] = 1.0L / den;
+                cp[(size_t)j * nx1 + k] = (double)cprev;
+                inv[(size_t)j * nx1 + k] = (double)w[i];
+            }
+            // responses to the separator values: U = T_s^{-1}(-lo_a e_1), V = T_s^{-1}(-up_b e_L)
+            auto solve = [&](int unit, long double val, std::vector<long double>& out) {
+                long double dp = 0.0L;
+                std::vector<long double> t(L);
+                for (int i = 0; i < L; ++i) {
+                    const int j = a + i;
+                    const long double g = (i == unit ? val : 0.0L) - (i > 0 ? lo[j] * dp : 0.0L);
+                    dp = g * w[i];
+                    t[i] = dp;
+                }
+                long double x = 0.0L;
+                for (int i = L - 1; i >= 0; --i) {
+                    x = t[i] - c[i] * x;
+                    out[a + i] = x;
+                }
+            };
+            solve(0, -lo[a], Us);
+            solve(L - 1, -up[b], Vs);
+            for (int i = 0; i < L; ++i) {
+                U[(size_t)(a + i) * nx1 + k] = (double)Us[a + i];
+                V[(size_t)(a + i) * nx1 + k] = (double)Vs[a + i];
+            }
+        }
+        // reduced (Schur) system over the separators, with its Thomas factors
+        long double cR = 0.0L;
+        for (int sg = 0; sg + 1 < P; ++sg) {
+            const int cs = sg * Ls + Ls - 1, b = cs - 1, a1n = cs + 1;
+            const long double al = lo[cs] * Us[b];
+            const long double D = d[cs] + lo[cs] * Vs[b] + up[cs] * Us[a1n];
+            const long double ga = up[cs] * Vs[a1n];
+            const long double den = D - (sg > 0 ? al * cR : 0.0L);
+            cR = ga / den;
+            double* row = &red[(size_t)k * 3 * (P - 1) + 3 * sg];
+            row[0] = (double)al;
+            row[1] = (double)cR;
+            row[2] = (double)(1.0L / den);
         }
     }
     if ((st = upload_working(pl, &pl->cy_cp, cp)) != LG_OK) return st;
     if ((st = upload_working(pl, &pl->cy_invden, inv)) != LG_OK) return st;
-    return upload_working(pl, &pl->cy_lowr, lowr);
+    if (P > 1) {   // the correction table, (U, V) pairs (zero for one segment)
+        std::vector<double> uv(2 * U.size());
+        for (size_t i = 0; i < U.size(); ++i) {
+            uv[2 * i] = U[i];
+            uv[2 * i + 1] = V[i];
+        }
+        if ((st = upload_working(pl, &pl->cy_UV, uv)) != LG_OK) return st;
+    }
+    if ((st = upload_working(pl, &pl->cy_lowr, lowr)) != LG_OK) return st;
+    if ((st = dev_alloc(pl, &pl->cy_cpl64, cpl64.size() * 8)) != LG_OK) return st;
+    LG_HIP(hipMemcpy(pl->cy_cpl64, cpl64.data(), cpl64.size() * 8, hipMemcpyHostToDevice));
+    if ((st = dev_alloc(pl, &pl->cy_red, red.size() * 8)) != LG_OK) return st;
+    LG_HIP(hipMemcpy(pl->cy_red, red.data(), red.size() * 8, hipMemcpyHostToDevice));
+    return LG_OK;
 }
 
 // Face values of the fourth-order operator along one line of n+1 nodes
@@ -305,6 +375,7 @@ void free_plan(lg_plan* p) {
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
                     p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64,
+                    p->cy_UV, p->cy_cpl64, p->cy_red,
                     p->ho_kx, p->ho_kz, p->ho_kx64, p->ho_kz64};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -484,12 +555,10 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (osh < 1 || osh > 64) return fail(LG_ERR_INVALID_ARG, "op_shots must be in 1..64");
     if (spw != 0 && spw != 1 && spw != 2 && spw != 4)
         return fail(LG_ERR_INVALID_ARG, "seg_per_wave must be 0, 1, 2 or 4");
-    if (cyl) {
-        if (P > 1) return fail(LG_ERR_UNSUPPORTED, "axisymmetric plans solve the r-systems unsegmented");
-        P = 1;
-    }
-    if (P == 0) P = std::max(1, std::min(64, grid->nz / 16));
-    if (!cyl && (!is_pow2(P) || P > 64 || grid->nz % P != 0 || grid->nz / P < 2 || grid->nz / P > 64))
+    // default segment counts: segments of 16 rows (z-systems), 64 rows
+    // (r-systems of axisymmetric plans; below 128 rows one segment: Thomas)
+    if (P == 0) P = cyl ? (grid->nz >= 128 ? std::min(64, grid->nz / 64) : 1) : std::max(1, std::min(64, grid->nz / 16));
+    if (!(cyl && P == 1) && (!is_pow2(P) || P > 64 || grid->nz % P != 0 || grid->nz / P < 2 || grid->nz / P > 64))
         return fail(LG_ERR_INVALID_ARG, "segments must be a power of two <= 64 with nz/segments in 2..64");
     const int F = (kind == LG_ACOUSTIC) ? 2 : 3;
     // node arrays: (nz+1)(nx+1) Cartesian nodes, or Nr x Nz axisymmetric nodes
@@ -558,8 +627,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         if (!(p->kappa_t > 0.0) || !(p->rho_t >= 0.0))
             return bail(fail(LG_ERR_INVALID_ARG,
                              "midrange kappa must be > 0 and midrange rho >= 0 (SPD preconditioner)"));
-        p->blk[0].P = 1;
-        p->blk[0].Ls = grid->nz;
+        p->blk[0].P = P;
+        p->blk[0].Ls = grid->nz / P;
         if ((st = prepare_cylindrical(p, medium_host)) != LG_OK) return bail(st);
         if (prec == LG_MIXED) {
             if ((st = dev_alloc(p, &p->w64, p->npts * 8)) != LG_OK) return bail(st);
@@ -813,7 +882,8 @@ lg_status lg_precond_dichotomy_tdma(lg_plan* plan, int32_t block, const void* rh
     LG_HIP(hipSetDevice(plan->device));
     const int nf = plan->S;   // acoustic: S fields; elastic: one component per shot
     if (plan->cyl) {          // non-Toeplitz r-systems, one per z-wavenumber
-        LG_HIP(cyl_launch_thomas(plan, rhs_hat, sol_hat, nf, 0));
+        LG_HIP(cyl_launch_rsys(plan, rhs_hat, sol_hat, nf, 0));
+        if (plan->blk[0].P > 1) LG_HIP(cyl_launch_corr(plan, sol_hat, nf));
         return LG_OK;
     }
     LG_HIP(launch_td(plan, bi, rhs_hat, sol_hat, nf, 0));
@@ -908,8 +978,8 @@ extern "C" lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z) {
     const int nf = plan->S;
     LG_HIP(launch_dst(plan, 0, r, plan->rhat, nf));
     if (plan->cyl) {
-        LG_HIP(cyl_launch_thomas(plan, plan->rhat, plan->y, nf, 0));
-        LG_HIP(launch_dst(plan, 1, plan->y, z, nf));
+        LG_HIP(cyl_launch_rsys(plan, plan->rhat, plan->y, nf, 0));
+        LG_HIP(cyl_launch_dct(plan, 1, plan->y, z, nf, plan->blk[0].P > 1));
         return LG_OK;
     }
     LG_HIP(launch_td(plan, 0, plan->rhat, plan->y, nf, 0));

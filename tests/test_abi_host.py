@@ -88,7 +88,6 @@ def test_plan_create_unsupported_shapes():
     # the axisymmetric geometry: acoustic plans, unsegmented r-systems
     cyl = _lib.LG_CYLINDRICAL
     assert _create(kind=_lib.LG_ELASTIC, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
-    assert _create(segments=4, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
     assert _create(nx=24, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
     # the fourth-order operator: Cartesian acoustic plans with Dirichlet sides
     assert _create(kind=_lib.LG_ELASTIC, order=4) == _lib.LG_ERR_UNSUPPORTED

@@ -25,10 +25,10 @@ def _medium(nr, nz, seed=1):
 
 
 def _plan(nr, nz, kappa, rho, hr=10.0, hz=10.0, h=200.0, shots=1, graph_iters=0, n=8, precision="fp64",
-          op_shots=0, op_fusion=0):
+          op_shots=0, op_fusion=0, segments=0):
     return api.Plan("acoustic", nz, nr, hz, hr, 9, h, n, np.stack([kappa, rho]), precision=precision,
                     nshots=shots, graph_iters=graph_iters, op_shots=op_shots, op_fusion=op_fusion,
-                    geometry="cylindrical")
+                    segments=segments, geometry="cylindrical")
 
 
 def _wdt(prec):
@@ -94,6 +94,25 @@ def test_cylindrical_thomas_parity(prec, nr, nz, shots):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("nr,nz,P", [(64, 32, 1), (64, 32, 2), (64, 32, 32), (256, 64, 4), (256, 64, 8),
+                                     (512, 16, 16), (2048, 8, 32), (2048, 8, 64), (4096, 4, 64)])
+def test_cylindrical_dichotomy_segment_counts(prec, nr, nz, P):
+    """The r-systems by the Dichotomy for every segment count (segments of
+    2..64 rows) against the oracle's Thomas solve of the same systems."""
+    kappa, rho = _medium(nr, nz)
+    hr, hz, h = 6.0, 9.0, 250.0
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, 2, precision=prec, segments=P)
+    assert plan.layout() == (P, nr // P)
+    B = cyl.preconditioner(kappa, rho, h, hr, hz)
+    rhs = np.random.default_rng(P + nr).standard_normal((2, nr - 1, nz))
+    log(f"cylindrical dichotomy {prec} Nr={nr} Nz={nz} P={P}")
+    rd = to_dev(rhs, _wdt(prec))
+    sd = torch_cuda().empty_like(rd)
+    plan.precond_dichotomy_tdma(0, rd, sd)
+    assert rel(to_np(sd), B.tridiag_solve(to_np(rd))) < TOL[prec]["tdma"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
 @pytest.mark.parametrize("nr,nz", [(16, 16), (64, 64), (256, 256), (128, 1024)])
 def test_cylindrical_precond_apply_parity(prec, nr, nz):
     kappa, rho = _medium(nr, nz)
@@ -115,15 +134,16 @@ def _oracle_pcg(kappa, rho, h, hr, hz, b, tol, max_iter=2000):
 
 
 @pytest.mark.parametrize("fus", [1, 2])
-@pytest.mark.parametrize("nr,nz,shots,gi", [(16, 16, 1, 0), (64, 64, 2, 4), (128, 256, 2, 0),
-                                            (256, 64, 1, 8), (2, 4, 1, 0), (4, 2, 2, 0)])
-def test_cylindrical_pcg_parity_fp64(nr, nz, shots, gi, fus):
+@pytest.mark.parametrize("nr,nz,shots,gi,P", [(16, 16, 1, 0, 0), (64, 64, 2, 4, 0), (128, 256, 2, 0, 0),
+                                              (256, 64, 1, 8, 0), (2, 4, 1, 0, 0), (4, 2, 2, 0, 0),
+                                              (256, 64, 2, 0, 64), (512, 32, 1, 4, 8)])
+def test_cylindrical_pcg_parity_fp64(nr, nz, shots, gi, fus, P):
     torch = torch_cuda()
     kappa, rho = _medium(nr, nz)
     hr, hz, h = 10.0, 10.0, 200.0
-    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots, graph_iters=gi, op_fusion=fus)
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, shots, graph_iters=gi, op_fusion=fus, segments=P)
     b = np.random.default_rng(6).standard_normal((shots, 1, nr - 1, nz))
-    log(f"cylindrical pcg Nr={nr} Nz={nz} shots={shots} graph_iters={gi} op_fusion={fus}")
+    log(f"cylindrical pcg Nr={nr} Nz={nz} shots={shots} graph_iters={gi} op_fusion={fus} P={P}")
     bd = to_dev(b, torch.float64)
     xd = torch.empty_like(bd)
     res = plan.pcg_solve(bd, xd, tol=1e-10, max_iter=2000)
