@@ -118,7 +118,9 @@ cyl_stencil_kernel(CylStArgs<T> a) {
         wv[r] = bload<T>(rw, oc[r + 1]);
     }
     const int f0 = grp * a.nsh, ns = min(a.nsh, a.nfields - f0);
-    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr) ? a.ctl[f0 + threadIdx.x].active : 1;
+    // residual mode with a reduction: ||b - A x||^2 of every shot (the check
+    // before a restart covers the shots that have stopped)
+    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr && !RES) ? a.ctl[f0 + threadIdx.x].active : 1;
     __syncthreads();
     // per field: loads, A p, store, per-wave (p, Ap); one barrier at the end
     for (int kf = 0; kf < ns; ++kf) {
@@ -141,9 +143,13 @@ cyl_stencil_kernel(CylStArgs<T> a) {
         for (int r = 0; r < CY_RPT; ++r) {
             const T c = pv[r + 1];
             T v = cyl_point<T>(c, pv[r], pv[r + 2], pw[r], pe[r], f1[r], f1[r + 1], fl[r], fr[r], wv[r]);
-            if constexpr (RES) v = (T)(bload<double>(rb, oc[r + 1] == BUF_OOB ? BUF_OOB : oc[r + 1] / SZ * 8u) - (double)v);
+            if constexpr (RES) {
+                v = (T)(bload<double>(rb, oc[r + 1] == BUF_OOB ? BUF_OOB : oc[r + 1] / SZ * 8u) - (double)v);
+                if (oc[r + 1] != BUF_OOB) pq += (double)v * (double)v;     // rows past the grid: none
+            } else {
+                pq += (double)c * (double)v;
+            }
             bstore<T>(v, rq, oc[r + 1]);
-            pq += (double)c * (double)v;
         }
         if (a.ctl == nullptr) continue;
         pq = wave_sum(pq);
@@ -693,7 +699,9 @@ hipError_t cyl_stencil_T(lg_plan* p, const T* x, T* y, bool reduce, int nfields,
     hipLaunchKernelGGL((cyl_stencil_kernel<T, RES>), dim3(a.gx * a.gy * groups), dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !reduce) return e;
-    return launch_finalize(p, 0 /* (p, Ap) */, a.gx * a.gy, 0, 0.0, 0, 0.0);
+    // residual mode: the restart check on ||b - A x||^2; else (p, Ap)
+    return RES ? launch_finalize(p, 1 /* ||r||^2 */, a.gx * a.gy, 2, 0.0, 0, 0.0)
+               : launch_finalize(p, 0 /* (p, Ap) */, a.gx * a.gy, 0, 0.0, 0, 0.0);
 }
 
 template <typename T, int M, int MODE>
@@ -860,17 +868,21 @@ hipError_t cyl_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce) {
                                        (const float*)p->cy_a2, (const float*)p->w, nullptr);
 }
 
-hipError_t cyl_launch_restart(lg_plan* p, const double* b, double* x, double tol, int max_iter) {
-    // r = b - A x with the FP64 operator (FP64 tables of a mixed plan), then
-    // the transform pass from the stored r; the finalize re-checks the shots
-    // that had met the tolerance
+hipError_t cyl_launch_residual_check(lg_plan* p, const double* b, const double* x) {
+    // r = b - A x with the FP64 operator (FP64 tables of a mixed plan), stored,
+    // and ||r||^2 per shot; the finalize re-checks the shots that had met the
+    // tolerance on the recursive residual
     const int nf = p->S * p->C;
     const bool f64 = p->prec == LG_FP64;
     const double* a1 = f64 ? (const double*)p->cy_a1 : p->cy_a1_64;
     const double* a2 = f64 ? (const double*)p->cy_a2 : p->cy_a2_64;
     const double* w = f64 ? (const double*)p->w : p->w64;
-    hipError_t e = cyl_stencil_T<double, true>(p, x, p->r, false, nf, a1, a2, w, b);
-    if (e != hipSuccess) return e;
+    return cyl_stencil_T<double, true>(p, x, p->r, true, nf, a1, a2, w, b);
+}
+
+hipError_t cyl_launch_restart(lg_plan* p, const double* b, double* x, double tol, int max_iter) {
+    // after the check: the transform pass from the stored r (its finalize
+    // re-checks the shots that had met the tolerance, as the check did)
     return cyl_launch_update(p, 2, b, x, tol, max_iter);
 }
 

@@ -104,7 +104,7 @@ __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
     // the next field's tile is loaded into registers while the current one is
     // computed from LDS
     auto next_active = [&](int f) {
-        while (f < f1e && a.ctl != nullptr && a.ctl[f].active == 0) ++f;   // uniform per block
+        while (f < f1e && a.ctl != nullptr && !RES && a.ctl[f].active == 0) ++f;   // uniform per block
         return f;
     };
     // tile element u of this thread: field offset (or out of range) and the
@@ -165,9 +165,13 @@ __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
             const T c = col[r + 3];
             T v = ho_axis<T>(row[r], kx[r], i == 1, i == nx1) + ho_axis<T>(&col[r], &kz[r], nj == 1, nj == nz1) +
                   wv[r] * c;
-            if constexpr (RES) v = (T)(bload<double>(rb, o * 8u) - (double)v);
+            if constexpr (RES) {
+                v = (T)(bload<double>(rb, o * 8u) - (double)v);
+                if (o != BUF_OOB / 8u) pq += (double)v * (double)v;     // rows past the grid: none
+            } else {
+                pq += (double)c * (double)v;
+            }
             bstore<T>(v, rq, o * SZ);
-            pq += (double)c * (double)v;
         }
         if (a.ctl != nullptr) {
             pq = wave_sum(pq);
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
     if (a.ctl == nullptr) return;
     __syncthreads();
     const int kf = threadIdx.x;
-    if (kf < f1e - f0 && a.ctl[f0 + kf].active != 0)
+    if (kf < f1e - f0 && (RES || a.ctl[f0 + kf].active != 0))
         a.partial[(size_t)(f0 + kf) * a.pstride + by * a.gx + bx] = ((red[kf][0] + red[kf][1]) + red[kf][2]) + red[kf][3];
 }
 
@@ -207,7 +211,9 @@ hipError_t ho_T(lg_plan* p, const T* x, T* y, bool reduce, const T* kx, const T*
     hipLaunchKernelGGL((ho_stencil_kernel<T, RES>), dim3(a.gx * a.gy * groups), dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !reduce) return e;
-    return launch_finalize(p, 0 /* (p, Ap) */, a.gx * a.gy, 0, 0.0, 0, 0.0);
+    // residual mode: the restart check on ||b - A x||^2; else (p, Ap)
+    return RES ? launch_finalize(p, 1 /* ||r||^2 */, a.gx * a.gy, 2, 0.0, 0, 0.0)
+               : launch_finalize(p, 0 /* (p, Ap) */, a.gx * a.gy, 0, 0.0, 0, 0.0);
 }
 
 }  // namespace
@@ -225,7 +231,7 @@ hipError_t ho_launch_residual(lg_plan* p, const double* b, const double* x) {
     const double* kx = f64 ? (const double*)p->ho_kx : p->ho_kx64;
     const double* kz = f64 ? (const double*)p->ho_kz : p->ho_kz64;
     const double* w = f64 ? (const double*)p->w : p->w64;
-    return ho_T<double, true>(p, x, p->r, false, kx, kz, w, b);
+    return ho_T<double, true>(p, x, p->r, true, kx, kz, w, b);
 }
 
 }  // namespace lg

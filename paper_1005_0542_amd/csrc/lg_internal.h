@@ -182,6 +182,11 @@ hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter);
 hipError_t launch_correct_idst(lg_plan* p, int init);
+// FP64 ||b - A x||^2 per shot and the finalize kernel's restart check: shots
+// that had met the tolerance on the recursive residual stop if the true one
+// meets it too, else resume (active); the axisymmetric and fourth-order
+// variants also store r = b - A x for the restart
+hipError_t launch_residual_check(lg_plan* p, const double* b, const double* x);
 // finalize kernel over nparts per-block partials per shot: kind 0 (p, Ap)
 // -> alpha; 1 ||r||^2 -> convergence; 2 (r, z) * scale -> beta
 hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale);
@@ -195,12 +200,15 @@ hipError_t cyl_launch_rsys(lg_plan* p, const void* rhat, void* y, int nfields, i
 hipError_t cyl_launch_corr(lg_plan* p, void* z, int nfields);
 // init 0 iteration, 1 start (x = 0, r = b), 2 restart from the stored r
 hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, double tol, int max_iter);
-// FP64 true residual r = b - A x, then the update pass with init 2
+// FP64 true residual r = b - A x, stored, ||r||^2 and the restart check
+hipError_t cyl_launch_residual_check(lg_plan* p, const double* b, const double* x);
+// the update pass with init 2 from the r stored by the check
 hipError_t cyl_launch_restart(lg_plan* p, const double* b, double* x, double tol, int max_iter);
 hipError_t cyl_launch_correct(lg_plan* p, int init);
 // fourth-order operator (lg_ho.hip)
 hipError_t ho_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce);
-hipError_t ho_launch_residual(lg_plan* p, const double* b, const double* x);   // p->r = b - A4 x, FP64
+// p->r = b - A4 x (FP64), ||r||^2 per shot and the restart check
+hipError_t ho_launch_residual(lg_plan* p, const double* b, const double* x);
 hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,
                       const double* fsrc_host, double* rhs);
 hipError_t launch_synth(lg_plan* p, int m, const double* R, const double* Wsnap, int nsnap,

@@ -39,6 +39,7 @@ template <typename T>
 struct StArgs {
     const T* p;
     T* q;                // nullptr: no store (dot only)
+    const double* b;     // residual-norm mode: right-hand side
     const T* kap;        // node kappa, (nz+1) x (nx+1)
     const T* w;          // interior shift
     int nx1, nz1;
@@ -58,9 +59,12 @@ struct StArgs {
 // as the Dirichlet zero through the range check), q is written by buffer
 // stores (rows past the grid are dropped), and the (p, A p) partial is
 // reduced per wave without barriers; one block barrier at the end combines
-// the waves of every shot.
-template <typename T>
+// the waves of every shot.  RESN (FP64 only): p is x and the partial is
+// ||b - A x||^2 over every shot, nothing is stored (the check of the true
+// residual that precedes a restart).
+template <typename T, bool RESN>
 __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
+    static_assert(!RESN || sizeof(T) == 8, "the residual norm is formed in FP64");
     __shared__ double red[ST_MAXSH][4];
     const int nx1 = a.nx1, nz1 = a.nz1, NXN = nx1 + 2;
     const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;   // 1D block of 256 = 64 x 4
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
     const int s0 = bz * a.nsh;
     const int ns = min(a.nsh, a.nfields - s0);
     __shared__ int act[ST_MAXSH];               // the chunk's active flags, read once
-    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr) ? a.ctl[s0 + threadIdx.x].active : 1;
+    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr && !RESN) ? a.ctl[s0 + threadIdx.x].active : 1;
     __syncthreads();
     for (int k = 0; k < ns; ++k) {
         const int field = s0 + k;
@@ -123,6 +127,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
             pe[r] = bload<T>(rp, oe[r]);
             pw[r] = bload<T>(rp, ow[r]);
         }
+        T bv[RESN ? ST_RPT : 1];
+        if constexpr (RESN) {
+            const rsrc_t rb = buf_rsrc(a.b + fb, fbytes);
+#pragma unroll
+            for (int r = 0; r < ST_RPT; ++r) bv[r] = bload<double>(rb, oc[r + 1]);
+        }
         double pq = 0.0;
         T v[ST_RPT];
 #pragma unroll
@@ -132,7 +142,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
             const T c = pv[r + 1];                  // 0 outside the grid, so no dot term
             v[r] = stencil_point(c, pe[r], pw[r], pv[r + 2], pv[r], fE[r], fW[r], fS, fN, wv[r],
                                  a.idx2, a.idz2);
-            pq += (double)c * (double)v[r];
+            if constexpr (RESN) {
+                const double rv = (oc[r + 1] != BUF_OOB) ? bv[r] - v[r] : 0.0;   // rows past the grid: none
+                pq += rv * rv;
+            } else {
+                pq += (double)c * (double)v[r];
+            }
         }
         if (a.q != nullptr) {
             const rsrc_t rq = buf_rsrc(a.q + fb, fbytes);
@@ -1062,6 +1077,7 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     StArgs<T> a;
     a.p = x;
     a.q = y;
+    a.b = nullptr;
     a.kap = (const T*)p->kap;
     a.w = (const T*)p->w;
     a.nx1 = p->nx1;
@@ -1077,10 +1093,38 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.gx = (p->nx1 + 63) / 64;
     a.gy = (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT);
     const dim3 grid(a.gx * a.gy * ((a.nfields + a.nsh - 1) / a.nsh));
-    hipLaunchKernelGGL(stencil_kernel<T>, grid, dim3(256), 0, p->stream, a);
+    hipLaunchKernelGGL((stencil_kernel<T, false>), grid, dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !reduce) return e;
     return finalize(p, FIN_PQ, a.gx * a.gy, 0, 0.0, 0, 0.0);
+}
+
+// ||b - A x||^2 per shot with the FP64 medium, then the restart check of the
+// finalize kernel (shots that met the tolerance recursively stop or resume)
+hipError_t residual_check_T(lg_plan* p, const double* b, const double* x) {
+    StArgs<double> a;
+    a.p = x;
+    a.q = nullptr;
+    a.b = b;
+    a.kap = (p->prec == LG_FP64) ? (const double*)p->kap : p->kap64;
+    a.w = (p->prec == LG_FP64) ? (const double*)p->w : p->w64;
+    a.nx1 = p->nx1;
+    a.nz1 = p->nz1;
+    a.idx2 = 1.0 / (p->g.dx * p->g.dx);
+    a.idz2 = 1.0 / (p->g.dz * p->g.dz);
+    a.ctl = p->ctl;
+    a.free_top = p->free_top ? 1 : 0;
+    a.partial = p->partial;
+    a.pstride = p->partial_stride;
+    a.nfields = p->S * p->C;
+    a.nsh = std::min(a.nfields, p->op_shots);
+    a.gx = (p->nx1 + 63) / 64;
+    a.gy = (p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT);
+    const dim3 grid(a.gx * a.gy * ((a.nfields + a.nsh - 1) / a.nsh));
+    hipLaunchKernelGGL((stencil_kernel<double, true>), grid, dim3(256), 0, p->stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return finalize(p, FIN_RR, a.gx * a.gy, 2, 0.0, 0, 0.0);
 }
 
 template <typename T, int M, int MODE>
@@ -1272,11 +1316,17 @@ hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nf
                    : dst_dispatch<float, DST_FWD>(p, a, nfields);
 }
 
+hipError_t launch_residual_check(lg_plan* p, const double* b, const double* x) {
+    if (p->cyl) return cyl_launch_residual_check(p, b, x);
+    if (p->order == 4) return ho_launch_residual(p, b, x);     // stores r = b - A4 x as well
+    return residual_check_T(p, b, x);
+}
+
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter) {
     hipError_t e;
     int bpf;
-    if (init == 3 && p->order == 4) {   // FP64 true residual of A4, then the pass from the stored r
+    if (init == 3 && p->order == 4) {   // FP64 true residual of A4 (and its check), then the pass from the stored r
         if ((e = ho_launch_residual(p, b, x)) != hipSuccess) return e;
         init = 2;
     }

@@ -130,24 +130,42 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
     if (st != LG_OK) return st;
     // Mixed precision: the recursive residual converges on the FP32 operator;
     // check the FP64 true residual b - A x and, where it misses the tolerance,
-    // restart CG from it (iterative refinement with an FP64 residual).
+    // restart CG from it (iterative refinement with an FP64 residual).  The
+    // check alone reads x and b; the restart also stores r and transforms it.
+    // Nearly every shot resumes after the first check and almost none after
+    // a later one, so the first restart of the Cartesian second-order path is
+    // the fused pass (residual and transform at once) and every other one is
+    // preceded by the check.
+    auto any_active = [&](bool& any) -> lg_status {
+        LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
+                              p->stream));
+        LG_HIP(hipStreamSynchronize(p->stream));
+        any = false;
+        for (int s = 0; s < nf; ++s) any = any || (p->ctl_host[s].active != 0);
+        return LG_OK;
+    };
     if (p->prec == LG_MIXED) {
         for (int rep = 0; rep < 4; ++rep) {
-            if (p->cyl) {                                                  // r = b - A x (FP64), restart
+            bool any = false;
+            const bool fused = !p->cyl && p->order == 2 && rep == 0;
+            if (!fused) {
+                LG_HIP(launch_residual_check(p, b, x));       // axisymmetric, fourth order: stores r too
+                if ((st = any_active(any)) != LG_OK) return st;
+                if (!any) break;
+            }
+            if (p->cyl) {                                                  // transform of the stored r
                 LG_HIP(cyl_launch_restart(p, b, x, o->tol, o->max_iter));
                 LG_HIP(cyl_launch_rsys(p, p->rhat, p->y, nf, 1));
                 LG_HIP(cyl_launch_correct(p, 1));
             } else {
-                LG_HIP(launch_update_fdst(p, 3, b, x, o->tol, o->max_iter));
+                // second order: r = b - A x and its transform in one pass (init 3);
+                // fourth order: the transform of the r stored by the check (init 2)
+                LG_HIP(launch_update_fdst(p, p->order == 4 ? 2 : 3, b, x, o->tol, o->max_iter));
                 LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
                 LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
                 LG_HIP(launch_correct_idst(p, 1));
             }
-            LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
-                                  p->stream));
-            LG_HIP(hipStreamSynchronize(p->stream));
-            bool any = false;
-            for (int s = 0; s < nf; ++s) any = any || (p->ctl_host[s].active != 0);
+            if ((st = any_active(any)) != LG_OK) return st;
             if (!any) break;
             launched = 0;
             st = iterate(launched);
