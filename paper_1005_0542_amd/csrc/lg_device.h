@@ -182,6 +182,18 @@ __device__ __forceinline__ void fft_last(const cpx<T>* __restrict__ buf, const c
 // sharing cache lines (halo rows and columns, medium rows) are neighbours in
 // that order and therefore meet in the same L2.
 constexpr int NUM_XCD = 8;
+
+// A pointer that every lane holds the same value of but that the compiler
+// cannot prove uniform (it was loaded from memory): taken through
+// readfirstlane, so buffer resources built on it stay in scalar registers
+// instead of a per-lane loop around every load and store that uses them.
+template <typename P>
+__device__ __forceinline__ P* wave_uniform(P* ptr) {
+    const uint64_t v = (uint64_t)ptr;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (P*)(((uint64_t)hi << 32) | (uint64_t)lo);
+}
 __device__ __forceinline__ int xcd_linear(int b, int n) {
     const int q = n / NUM_XCD, r = n - q * NUM_XCD;
     const int x = b % NUM_XCD, i = b / NUM_XCD;

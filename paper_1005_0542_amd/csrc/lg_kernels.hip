@@ -360,12 +360,16 @@ dst_kernel(DstArgs<T> a) {
                 X = a.x;
                 if (blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
             } else if (init == 0) {
-                X = *a.xslot;
+                X = wave_uniform(*a.xslot);
                 alpha = a.ctl[field].alpha;
             }                                // init 2 (restart): x is not touched
-            const rsrc_t rX = buf_rsrc(X != nullptr ? X + fbase : a.r, init == 0 ? nfe * 8u : 0u);
-            const rsrc_t rXs = buf_rsrc(X != nullptr ? X + fbase : a.r, init == 2 ? 0u : nfe * 8u);
-            const rsrc_t rR = buf_rsrc(init == 1 ? a.b + fbase : a.r + fbase, nfe * 8u);
+            // (the bases join paths around the lane-0 slot store above, which
+            // the compiler otherwise takes as divergent)
+            double* const Xb = wave_uniform(X != nullptr ? X + fbase : a.r);
+            const double* const Rb = wave_uniform(init == 1 ? a.b + fbase : a.r + fbase);
+            const rsrc_t rX = buf_rsrc(Xb, init == 0 ? nfe * 8u : 0u);
+            const rsrc_t rXs = buf_rsrc(Xb, init == 2 ? 0u : nfe * 8u);
+            const rsrc_t rR = buf_rsrc(Rb, nfe * 8u);
             const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 2 ? 0u : nfe * 8u);
             const rsrc_t rP = buf_rsrc(a.p + fbase, init == 0 ? nfe * SZ : 0u);
             const rsrc_t rQ = buf_rsrc(a.q + fbase, (init == 0 && MODE == DST_UPDATE) ? nfe * SZ : 0u);
