@@ -270,7 +270,9 @@ dst_kernel(DstArgs<T> a) {
     constexpr int LL = LdsLen<M>::value;
     constexpr int NWAVE = (FPB * TPF + 63) / 64;
     constexpr int NIT = (NX1 + TPF - 1) / TPF;
-    constexpr int CHMAX = (MODE == DST_UPDATE_OP && sizeof(T) == 8) ? 2 : 4;
+    // loads per chunk of phase A (all in flight together): the FP32 correction
+    // takes every element of the row pair at once
+    constexpr int CHMAX = (MODE == DST_UPDATE_OP && sizeof(T) == 8) ? 2 : (MODE == DST_CORRECT && sizeof(T) == 4) ? 8 : 4;
     constexpr int CH = NIT < CHMAX ? NIT : CHMAX;
     constexpr bool UPD = MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART;
     __shared__ cpx<T> lds[FPB * LL];
@@ -699,6 +701,7 @@ struct RsArgs {
 // systems, each by one wave with one lane per separator, and overwrites G by
 // the separator values; phase 3 writes them back row by row and forms this
 // block's share of (rhat, zhat) / b.  PM >= P bounds the phase-1 unroll.
+constexpr int RS_ILP = 4;       // wavenumbers per wave in flight in phase 2
 template <typename T, int KT, int PM>
 __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
     constexpr int KS = KT + 1;             // padded LDS row
@@ -749,11 +752,23 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
     const int sig = lane;
     const bool sepl = sig < P - 1;
     double c = d0;
-    for (int kk = wave; kk < KT; kk += 4) {
-        if (k0 + kk >= nx1) break;                          // uniform per wave
-        const double* tab = Ws + kk * RW;
-        const double G = sepl ? Gs[sig * KS + kk] : 0.0;
-        double x = 0.0;
+    // RS_ILP wavenumbers of a wave at a time: independent shuffle chains
+    // (each level waits on the previous one's broadcast) interleave; c is
+    // accumulated in wavenumber order as with one at a time
+    for (int kb = wave; kb < KT; kb += 4 * RS_ILP) {
+        if (k0 + kb >= nx1) break;                          // uniform per wave
+        double G[RS_ILP], x[RS_ILP];
+        const double* tab[RS_ILP];
+        bool okk[RS_ILP];
+#pragma unroll
+        for (int j = 0; j < RS_ILP; ++j) {
+            const int kk = kb + 4 * j;
+            okk[j] = kk < KT && k0 + kk < nx1;              // uniform per wave
+            const int kc = okk[j] ? kk : kb;
+            tab[j] = Ws + kc * RW;
+            G[j] = sepl ? Gs[sig * KS + kc] : 0.0;
+            x[j] = 0.0;
+        }
         int woff = 2 + q;
 #pragma unroll
         for (int l = 0; l < 6; ++l) {
@@ -762,31 +777,43 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
             const int pos = sig & (size - 1);
             const bool member = sepl && (pos != size - 1);
             const int widx = min(pos, size - 2 - pos);
-            double tv = member ? tab[woff + (widx < 0 ? 0 : widx)] * G : 0.0;
-            for (int off = 1; off < size; off <<= 1) tv += __shfl_xor(tv, off, 64);
             const int base = sig - pos;
             const int ll = base - 1, rl = base + size - 1;
-            const double xl_ = __shfl(x, ll < 0 ? 0 : ll, 64);
-            const double xr_ = __shfl(x, rl > 63 ? 63 : rl, 64);
-            const double xl = (ll < 0) ? 0.0 : xl_;
-            const double xr = (rl >= P - 1) ? 0.0 : xr_;
-            if (member && pos == (size >> 1) - 1) x = tv + tab[2 + l] * (xl + xr);
+            double tv[RS_ILP];
+#pragma unroll
+            for (int j = 0; j < RS_ILP; ++j) tv[j] = member ? tab[j][woff + (widx < 0 ? 0 : widx)] * G[j] : 0.0;
+            for (int off = 1; off < size; off <<= 1)
+#pragma unroll
+                for (int j = 0; j < RS_ILP; ++j) tv[j] += __shfl_xor(tv[j], off, 64);
+#pragma unroll
+            for (int j = 0; j < RS_ILP; ++j) {
+                const double xl_ = __shfl(x[j], ll < 0 ? 0 : ll, 64);
+                const double xr_ = __shfl(x[j], rl > 63 ? 63 : rl, 64);
+                const double xl = (ll < 0) ? 0.0 : xl_;
+                const double xr = (rl >= P - 1) ? 0.0 : xr_;
+                if (member && pos == (size >> 1) - 1) x[j] = tv[j] + tab[j][2 + l] * (xl + xr);
+            }
             woff += size >> 1;
         }
-        if (sepl) {
-            c += x * G;
-            Gs[sig * KS + kk] = x;
-        }
-        if (a.free_top && sig == 0) {
-            // first row of the Dirichlet solution: zhat_0 = y_0 + x_0 u_{Ls-1}
-            // (u_{Ls-1} = Br; x = 0 when there is no separator); the rank-one
-            // term adds coef g with coef = zhat_0 / (1 - g_0), and
-            // (rhat, g) = b zhat_0 adds coef zhat_0 to (rhat, zhat) / b
-            const int kg = k0 + kk;
-            const double zh0 = bload<double>(rE, (uint32_t)kg * 8u) + x * tab[1];
-            const double cf = zh0 * a.smt[kg];
-            a.smc[(size_t)field * nx1 + kg] = cf;
-            c += cf * zh0;
+#pragma unroll
+        for (int j = 0; j < RS_ILP; ++j) {
+            if (!okk[j]) continue;                          // uniform per wave
+            const int kk = kb + 4 * j;
+            if (sepl) {
+                c += x[j] * G[j];
+                Gs[sig * KS + kk] = x[j];
+            }
+            if (a.free_top && sig == 0) {
+                // first row of the Dirichlet solution: zhat_0 = y_0 + x_0 u_{Ls-1}
+                // (u_{Ls-1} = Br; x = 0 when there is no separator); the rank-one
+                // term adds coef g with coef = zhat_0 / (1 - g_0), and
+                // (rhat, g) = b zhat_0 adds coef zhat_0 to (rhat, zhat) / b
+                const int kg = k0 + kk;
+                const double zh0 = bload<double>(rE, (uint32_t)kg * 8u) + x[j] * tab[j][1];
+                const double cf = zh0 * a.smt[kg];
+                a.smc[(size_t)field * nx1 + kg] = cf;
+                c += cf * zh0;
+            }
         }
     }
     __syncthreads();
