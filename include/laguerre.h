@@ -249,7 +249,11 @@ lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z);
 /* Preconditioned CG (Sec. 2.3) for A x = b, every shot independently, from
  * x0 = 0 (or from x on entry when opts->x0_given: r0 = b - A x0 in FP64, and
  * 0 iterations when it already meets the tolerance), stopping per shot when
- * ||r||_2 <= tol ||b||_2 on the recursively updated residual.  A zero b gives
+ * ||r||_2 <= tol ||b||_2 on the recursively updated residual.  Mixed plans
+ * then check the FP64 true residual b - A x and restart CG from it where it
+ * misses the tolerance (at most 4 restarts; a shot still missing it after
+ * the last one reports LG_ERR_NOT_CONVERGED with relres of its true
+ * residual); iters counts every CG iteration of the solve.  A zero b gives
  * x = 0, iters = 0.  Converged shots drop out by masking.  b, x: FP64
  * vectors.  info_host: [S] (may be NULL).  Returns the worst per-shot status. */
 lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve_opts* opts,

@@ -135,7 +135,10 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
     // Nearly every shot resumes after the first check and almost none after
     // a later one, so the first restart of the Cartesian second-order path is
     // the fused pass (residual and transform at once) and every other one is
-    // preceded by the check.
+    // preceded by the check.  After the last allowed restart the check still
+    // runs: a shot that misses the tolerance there ends NOT_CONVERGED with its
+    // true residual reported.
+    constexpr int MAX_RESTARTS = 4;
     auto any_active = [&](bool& any) -> lg_status {
         LG_HIP(hipMemcpyAsync(p->ctl_host, p->ctl, (size_t)nf * sizeof(ShotCtl), hipMemcpyDeviceToHost,
                               p->stream));
@@ -145,13 +148,13 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
         return LG_OK;
     };
     if (p->prec == LG_MIXED) {
-        for (int rep = 0; rep < 4; ++rep) {
+        for (int rep = 0; rep <= MAX_RESTARTS; ++rep) {
             bool any = false;
             const bool fused = !p->cyl && p->order == 2 && rep == 0;
             if (!fused) {
                 LG_HIP(launch_residual_check(p, b, x));       // axisymmetric, fourth order: stores r too
                 if ((st = any_active(any)) != LG_OK) return st;
-                if (!any) break;
+                if (!any || rep == MAX_RESTARTS) break;
             }
             if (p->cyl) {                                                  // transform of the stored r
                 LG_HIP(cyl_launch_restart(p, b, x, o->tol, o->max_iter));
