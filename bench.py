@@ -319,8 +319,8 @@ def main():
                     help="profile-only: the second- or fourth-order operator (Cartesian)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(shots would shard across GPUs with no exchange; see DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library drives one GPU per process "
+              "(a batch of shots would shard across GPUs with no exchange during the solve).", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
