@@ -277,6 +277,9 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
     if (!p->gm_w) LG_HIP(hipMalloc((void**)&p->gm_w, nvec * 8));
     if (!p->gm_z) LG_HIP(hipMalloc((void**)&p->gm_z, nvec * 8));
     if (!p->gm_x) LG_HIP(hipMalloc((void**)&p->gm_x, ((size_t)S * (GM_MAXK + 1) * nblk + (size_t)S * DS) * 8 + S * 4 + 64));
+    if (!p->gm_hb) LG_HIP(hipHostMalloc((void**)&p->gm_hb, (size_t)2 * S * DS * 8, hipHostMallocDefault));
+    for (hipEvent_t& e : p->gm_ev)
+        if (!e) LG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     GmState g;
     g.V = p->gm_V;
     g.w = p->gm_w;
@@ -384,32 +387,52 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                            V0, n_s, S, g.active);
         LG_HIP(hipGetLastError());
         std::vector<int> inner = act;   // shots still in this cycle's Arnoldi
+        // Arnoldi step j on the device: w = C K^{-1} v_j, classical Gram-Schmidt
+        // twice, v_{j+1} = w / ||w||; its inner products then go to pinned host
+        // set j % 2 and an event marks them.  Step j + 1 needs only v_{j+1}, so
+        // it is queued before the host waits for step j's numbers (the GPU
+        // works through it meanwhile).  A shot that stops at step j still runs
+        // through that queued step (with the mask of step j), which writes only
+        // v_{j+2} and scratch of that shot, never used for it.
+        auto queue_step = [&](int j) -> hipError_t {
+            double* Vj = g.V + (size_t)j * nvec;
+            double* Vn = g.V + (size_t)(j + 1) * nvec;
+            hipError_t e = launch_elastic_precond(p, Vj, g.z);
+            if (e == hipSuccess) e = launch_elastic_stencil(p, g.z, g.w);
+            if (e == hipSuccess) e = dot_into(g.V, nvec, j + 1, g.w, 0);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1, g.dots, DS, g.w,
+                               n_s, S, g.active);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = dot_into(g.V, nvec, j + 1, g.w, GM_MAXK + 1)) != hipSuccess) return e;
+            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1,
+                               g.dots + GM_MAXK + 1, DS, g.w, n_s, S, g.active);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = dot_into(g.w, 0, 1, g.w, 2 * (GM_MAXK + 1))) != hipSuccess) return e;
+            hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.w, g.dots + 2 * (GM_MAXK + 1),
+                               DS, Vn, n_s, S, g.active);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            e = hipMemcpyAsync(p->gm_hb + (size_t)(j & 1) * S * DS, g.dots, (size_t)S * DS * 8,
+                               hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipEventRecord(p->gm_ev[j & 1], st);
+            return e;
+        };
+        {
+            bool anyin = false;
+            for (int s = 0; s < S; ++s) anyin = anyin || inner[s];
+            if (anyin) LG_HIP(queue_step(0));
+        }
         for (int j = 0; j < k; ++j) {
             bool anyin = false;
             for (int s = 0; s < S; ++s) anyin = anyin || inner[s];
             if (!anyin) break;
-            double* Vj = g.V + (size_t)j * nvec;
-            double* Vn = g.V + (size_t)(j + 1) * nvec;
-            // w = C K^{-1} v_j
-            LG_HIP(launch_elastic_precond(p, Vj, g.z));
-            LG_HIP(launch_elastic_stencil(p, g.z, g.w));
-            // classical Gram-Schmidt, twice
-            LG_HIP(dot_into(g.V, nvec, j + 1, g.w, 0));
-            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1, g.dots, DS, g.w,
-                               n_s, S, g.active);
-            LG_HIP(hipGetLastError());
-            LG_HIP(dot_into(g.V, nvec, j + 1, g.w, GM_MAXK + 1));
-            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1,
-                               g.dots + GM_MAXK + 1, DS, g.w, n_s, S, g.active);
-            LG_HIP(hipGetLastError());
-            LG_HIP(dot_into(g.w, 0, 1, g.w, 2 * (GM_MAXK + 1)));
-            hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.w, g.dots + 2 * (GM_MAXK + 1),
-                               DS, Vn, n_s, S, g.active);
-            LG_HIP(hipGetLastError());
-            LG_HIP(fetch_dots());
+            if (j + 1 < k) LG_HIP(queue_step(j + 1));
+            LG_HIP(hipEventSynchronize(p->gm_ev[j & 1]));
+            const double* dset = p->gm_hb + (size_t)(j & 1) * S * DS;
+            bool stopped = false;
             for (int s = 0; s < S; ++s) {
                 if (!inner[s]) continue;
-                const double* d = &dots_h[(size_t)s * DS];
+                const double* d = &dset[(size_t)s * DS];
                 double* Hs = &H[(size_t)s * (k + 1) * k];
                 auto Hc = [&](int r, int c) -> double& { return Hs[(size_t)r * k + c]; };
                 for (int i = 0; i <= j; ++i) Hc(i, j) = d[i] + d[GM_MAXK + 1 + i];
@@ -430,6 +453,7 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                     status[s] = LG_ERR_BREAKDOWN;
                     act[s] = inner[s] = cyc[s] = 0;
                     jused[s] = 0;
+                    stopped = true;
                     continue;
                 }
                 csv[j] = Hc(j, j) / den;
@@ -443,21 +467,27 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                     status[s] = LG_ERR_NONFINITE;
                     act[s] = inner[s] = cyc[s] = 0;
                     jused[s] = 0;
+                    stopped = true;
                     continue;
                 }
                 if (est[s] <= tol || hj1 == 0.0) {
                     status[s] = LG_OK;
                     act[s] = 0;          // converged: finish after this cycle's update
                     inner[s] = 0;
+                    stopped = true;
                 } else if (total[s] >= o->max_iter) {
                     status[s] = LG_ERR_NOT_CONVERGED;
                     act[s] = 0;
                     inner[s] = 0;
+                    stopped = true;
                 }
             }
-            // shots that stopped keep their basis; the kernels skip them from now on
-            std::vector<int> mask = inner;
-            LG_HIP(hipMemcpyAsync(g.active, mask.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+            // shots that stopped keep their basis; the kernels skip them from
+            // the step after the one already queued
+            if (stopped) {
+                std::vector<int> mask = inner;
+                LG_HIP(hipMemcpyAsync(g.active, mask.data(), S * sizeof(int), hipMemcpyHostToDevice, st));
+            }
         }
         // x += K^{-1} (V y) for every shot that ran an Arnoldi cycle
         bool anyupd = false;

@@ -156,6 +156,8 @@ struct lg_plan {
     double* gm_z = nullptr;
     double* gm_x = nullptr;
     double* gm_dots = nullptr;
+    double* gm_hb = nullptr;   // pinned host: the inner iterations' inner products, two sets
+    hipEvent_t gm_ev[2] = {nullptr, nullptr};
     int gm_k = 0;
 
     size_t bytes_allocated = 0;

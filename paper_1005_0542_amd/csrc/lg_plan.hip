@@ -380,6 +380,9 @@ void free_plan(lg_plan* p) {
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
     if (p->ctl_host) (void)hipHostFree(p->ctl_host);
+    if (p->gm_hb) (void)hipHostFree(p->gm_hb);
+    for (hipEvent_t e : p->gm_ev)
+        if (e) (void)hipEventDestroy(e);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
 }
