@@ -148,7 +148,8 @@ struct lg_plan {
 
     // HIP graph of graph_iters CG iterations
     hipGraphExec_t cg_graph = nullptr;
-    int last_iters = 0;
+    int last_iters = 0;        // the previous solve: most CG iterations of a shot before the first
+    int last_iters_restart = 0;  // stop, and after the first restart (mixed plans)
 
     // elastic GMRES workspace
     double* gm_V = nullptr;    // (k+1) basis vectors, FP64

@@ -102,9 +102,11 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
 
     // Replay batches of captured iterations until every shot has stopped.
     // Consecutive harmonics take similar iteration counts, so as many batches
-    // as the previous solve needed are queued before the first check.
-    auto iterate = [&](long& launched) -> lg_status {
-        long ahead = std::max(1L, (long)((p->last_iters + chunk - 1) / chunk));
+    // as the previous solve needed in the same phase (up to the first stop,
+    // or after the first restart) are queued before the first check; batches
+    // past a shot's stop run masked, which still costs every launch.
+    auto iterate = [&](long& launched, int expect) -> lg_status {
+        long ahead = std::max(1L, (long)((expect + chunk - 1) / chunk));
         const long cap = (long)o->max_iter + chunk;
         while (true) {
             for (long bt = 0; bt < ahead && launched < cap; ++bt) {
@@ -125,9 +127,16 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
         }
         return LG_OK;
     };
+    auto max_iters = [&]() {
+        int m = 0;
+        for (int s = 0; s < nf; ++s) m = std::max(m, (int)p->ctl_host[s].iters);
+        return m;
+    };
     long launched = 0;
-    lg_status st = iterate(launched);
+    lg_status st = iterate(launched, p->last_iters);
     if (st != LG_OK) return st;
+    const int first_stop = max_iters();      // ctl_host is current after iterate
+    int after_restart = -1;
     // Mixed precision: the recursive residual converges on the FP32 operator;
     // check the FP64 true residual b - A x and, where it misses the tolerance,
     // restart CG from it (iterative refinement with an FP64 residual).  The
@@ -171,8 +180,9 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
             if ((st = any_active(any)) != LG_OK) return st;
             if (!any) break;
             launched = 0;
-            st = iterate(launched);
+            st = iterate(launched, rep == 0 ? p->last_iters_restart : 1);
             if (st != LG_OK) return st;
+            if (rep == 0) after_restart = max_iters() - first_stop;
         }
     }
     if (o->x0_given) {                    // b = 0 from a given x: the solution is 0
@@ -180,20 +190,20 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
             if (p->ctl_host[s].bb == 0.0 && p->ctl_host[s].status == LG_OK)
                 LG_HIP(hipMemsetAsync(x + (size_t)s * p->npts, 0, p->npts * sizeof(double), p->stream));
     }
-    int worst = LG_OK, maxit = 0;
+    int worst = LG_OK;
     for (int s = 0; s < nf; ++s) {
         const ShotCtl& c = p->ctl_host[s];
         int st = c.status;
         if (c.active) st = LG_ERR_NOT_CONVERGED;   // only if the safety cap was hit
         if (severity(st) > severity(worst)) worst = st;
-        maxit = std::max(maxit, (int)c.iters);
         if (info) {
             info[s].iters = c.iters;
             info[s].status = st;
             info[s].relres = (c.bb > 0.0) ? std::sqrt(c.rr / c.bb) : 0.0;
         }
     }
-    p->last_iters = maxit;
+    p->last_iters = first_stop;
+    if (after_restart >= 0) p->last_iters_restart = after_restart;
     return (lg_status)worst;
 }
 
