@@ -81,6 +81,16 @@ cyl_stencil_kernel(CylStArgs<T> a) {
     const int lane = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int L = xcd_linear(blockIdx.x, gridDim.x);
     const int bx = L % a.gx, by = (L / a.gx) % a.gy, grp = L / (a.gx * a.gy);
+    // residual mode with a reduction: ||b - A x||^2 of every shot (the check
+    // before a restart covers the shots that have stopped); otherwise a block
+    // whose shots have all stopped leaves before loading the medium
+    const int f0 = grp * a.nsh, ns = min(a.nsh, a.nfields - f0);
+    int mine = 0;
+    if (threadIdx.x < ns) {
+        act[threadIdx.x] = (a.ctl != nullptr && !RES) ? a.ctl[f0 + threadIdx.x].active : 1;
+        mine = act[threadIdx.x];
+    }
+    if (__syncthreads_or(mine != 0) == 0) return;   // (also the barrier for act) uniform per block
     const int k = bx * 64 + lane;
     const int j0 = (by * 4 + ty) * CY_RPT;
     const bool live = k < nx1;
@@ -117,11 +127,6 @@ cyl_stencil_kernel(CylStArgs<T> a) {
         fr[r] = bload<T>(r2, ok ? (e2 + 1) * SZ : BUF_OOB);
         wv[r] = bload<T>(rw, oc[r + 1]);
     }
-    const int f0 = grp * a.nsh, ns = min(a.nsh, a.nfields - f0);
-    // residual mode with a reduction: ||b - A x||^2 of every shot (the check
-    // before a restart covers the shots that have stopped)
-    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr && !RES) ? a.ctl[f0 + threadIdx.x].active : 1;
-    __syncthreads();
     // per field: loads, A p, store, per-wave (p, Ap); one barrier at the end
     for (int kf = 0; kf < ns; ++kf) {
         if (act[kf] == 0) continue;                 // uniform per block

@@ -72,6 +72,17 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
     // tile (sharing its boundary cache lines) run next to it in the same L2
     const int L = xcd_linear(blockIdx.x, gridDim.x);
     const int bx = L % a.gx, by = (L / a.gx) % a.gy, bz = L / (a.gx * a.gy);
+    // the chunk's active flags first: a block whose shots have all stopped
+    // leaves before loading the medium (the masked iterations of a replay)
+    const int s0 = bz * a.nsh;
+    const int ns = min(a.nsh, a.nfields - s0);
+    __shared__ int act[ST_MAXSH];
+    int mine = 0;
+    if (threadIdx.x < ns) {
+        act[threadIdx.x] = (a.ctl != nullptr && !RESN) ? a.ctl[s0 + threadIdx.x].active : 1;
+        mine = act[threadIdx.x];
+    }
+    if (__syncthreads_or(mine != 0) == 0) return;   // (also the barrier for act) uniform per block
     const int i = bx * 64 + lane;
     const int j0 = (by * 4 + ty) * ST_RPT;
     const bool live = i < nx1;
@@ -109,11 +120,6 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
         ow[r] = (c != BUF_OOB && i > 0) ? c - SZ : BUF_OOB;
     }
     const uint32_t fbytes = (uint32_t)nx1 * (uint32_t)nz1 * SZ;
-    const int s0 = bz * a.nsh;
-    const int ns = min(a.nsh, a.nfields - s0);
-    __shared__ int act[ST_MAXSH];               // the chunk's active flags, read once
-    if (threadIdx.x < ns) act[threadIdx.x] = (a.ctl != nullptr && !RESN) ? a.ctl[s0 + threadIdx.x].active : 1;
-    __syncthreads();
     for (int k = 0; k < ns; ++k) {
         const int field = s0 + k;
         if (act[k] == 0) continue;              // uniform per block
