@@ -282,9 +282,11 @@ lg_status lg_trace_synthesize(lg_plan* plan, const double* rec_coeff, const doub
                               int32_t nt, double* traces);
 
 /* Measurement helper (not part of the method): starts CG on b with tol = 0
- * (so no shot converges) and runs `iters` (1..1000) eager iterations with HIP
- * events on the plan stream around each of the five kernels of one
- * iteration.  ms_host[0..4] receives the average duration in milliseconds of
+ * (so no shot converges) and runs iters + 1 (iters in 1..1000) eager
+ * iterations, the last `iters` with HIP events on the plan stream around each
+ * of the five kernels (the first update after the start reads b for r and no
+ * x, so it is not timed).  ms_host[0..4] receives the average duration in
+ * milliseconds of
  *   0 operator q = A p (+ (p,q), alpha),
  *   1 x/r update + forward DST of r (+ ||r||^2, convergence test),
  *   2 Dichotomy segment solves,
@@ -293,7 +295,8 @@ lg_status lg_trace_synthesize(lg_plan* plan, const double* rec_coeff, const doub
  * Axisymmetric plans (LG_CYLINDRICAL) report 0 operator, 1 update + forward
  * cosine transform, 2 the r-systems (+ (r,z), beta), 3 zero (no interface
  * stage), 4 inverse cosine transform + p update.
- * x is overwritten with the iterate.  Acoustic plans only. */
+ * x is overwritten with the iterate after iters + 1 iterations.  Acoustic
+ * plans only. */
 lg_status lg_pcg_profile(lg_plan* plan, const double* b, double* x, int32_t iters, float* ms_host);
 
 #ifdef __cplusplus

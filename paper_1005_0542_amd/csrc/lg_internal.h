@@ -40,6 +40,8 @@ struct ShotCtl {
     int32_t active;   // 1 while the shot still iterates
     int32_t status;   // lg_status of the shot
     int32_t max_iter;
+    int32_t fresh;    // 1 from a cold start until the first update: x = 0 and r = b
+                      // are implied, not stored (the update reads b, takes x as 0)
 };
 
 // ---------------------------------------------------------------------------
@@ -144,7 +146,7 @@ struct lg_plan {
     size_t partial_stride = 0; // per shot
     lg::ShotCtl* ctl = nullptr;    // [S*C]
     lg::ShotCtl* ctl_host = nullptr;  // pinned mirror
-    double** xslot = nullptr;  // device slot holding the caller's x pointer
+    double** xslot = nullptr;  // device slots holding the caller's x and b pointers
 
     // HIP graph of graph_iters CG iterations
     hipGraphExec_t cg_graph = nullptr;

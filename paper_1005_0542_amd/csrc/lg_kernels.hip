@@ -197,7 +197,7 @@ struct DstArgs {
     int bpf;               // blocks per field
     // CG (UPDATE / CORRECT)
     ShotCtl* ctl;
-    double* x;             // UPDATE init: caller x (stored into *xslot)
+    double* x;             // UPDATE init: caller x (stored into xslot[0], b into xslot[1])
     double** xslot;
     double* r;
     const double* b;       // UPDATE init: right-hand side
@@ -361,24 +361,35 @@ dst_kernel(DstArgs<T> a) {
                 }
             }
         } else if constexpr (UPD) {
+            // init 1 (cold start): only rhat = DST b and ||b||^2; x = 0 and
+            // r = b are not stored: the shot's first update (ShotCtl.fresh)
+            // reads b for r and takes x as 0, and writes both.  init 2
+            // (restart from the stored r): x is not touched.
             const int init = a.init;
             double* X = nullptr;
+            const double* B0 = nullptr;
             double alpha = 0.0;
+            bool fresh = false;
             if (init == 1) {
-                X = a.x;
-                if (blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
+                if (blockIdx.x == 0 && threadIdx.x == 0) {
+                    a.xslot[0] = a.x;
+                    a.xslot[1] = const_cast<double*>(a.b);
+                }
             } else if (init == 0) {
-                X = wave_uniform(*a.xslot);
+                X = wave_uniform(a.xslot[0]);
                 alpha = a.ctl[field].alpha;
-            }                                // init 2 (restart): x is not touched
-            // (the bases join paths around the lane-0 slot store above, which
+                fresh = a.ctl[field].fresh != 0;                     // uniform per block
+                if (fresh) B0 = wave_uniform(a.xslot[1]);
+            }
+            // (the bases join paths around the lane-0 slot stores above, which
             // the compiler otherwise takes as divergent)
             double* const Xb = wave_uniform(X != nullptr ? X + fbase : a.r);
-            const double* const Rb = wave_uniform(init == 1 ? a.b + fbase : a.r + fbase);
-            const rsrc_t rX = buf_rsrc(Xb, init == 0 ? nfe * 8u : 0u);
-            const rsrc_t rXs = buf_rsrc(Xb, init == 2 ? 0u : nfe * 8u);
+            const double* const Rb =
+                wave_uniform(init == 1 ? a.b + fbase : (B0 != nullptr ? B0 + fbase : a.r + fbase));
+            const rsrc_t rX = buf_rsrc(Xb, (init == 0 && !fresh) ? nfe * 8u : 0u);
+            const rsrc_t rXs = buf_rsrc(Xb, init == 0 ? nfe * 8u : 0u);
             const rsrc_t rR = buf_rsrc(Rb, nfe * 8u);
-            const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 2 ? 0u : nfe * 8u);
+            const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 0 ? nfe * 8u : 0u);
             const rsrc_t rP = buf_rsrc(a.p + fbase, init == 0 ? nfe * SZ : 0u);
             const rsrc_t rQ = buf_rsrc(a.q + fbase, (init == 0 && MODE == DST_UPDATE) ? nfe * SZ : 0u);
 #pragma unroll
@@ -886,6 +897,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.bb = bbt;
             c.tol2 = a.tol2 * bbt;
             c.iters = 0;
+            c.fresh = 0;                     // x and r are stored
             c.max_iter = a.max_iter;
             c.alpha = 0.0;
             c.beta = 0.0;
@@ -925,6 +937,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.max_iter = a.max_iter;
             c.alpha = 0.0;
             c.beta = 0.0;
+            c.fresh = 1;                         // cold start: x = 0, r = b implied
             if (!isfinite(tot)) {
                 c.status = LG_ERR_NONFINITE;
                 c.active = 0;
@@ -938,6 +951,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         } else {
             const int it = c.iters + 1;
             c.iters = it;
+            c.fresh = 0;
             if (!isfinite(tot)) {
                 c.status = LG_ERR_NONFINITE;
                 c.active = 0;

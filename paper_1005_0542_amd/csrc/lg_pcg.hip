@@ -185,6 +185,11 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
             if (rep == 0) after_restart = max_iters() - first_stop;
         }
     }
+    if (!p->cyl && !o->x0_given) {        // a cold start stores no x: a shot that never
+        for (int s = 0; s < nf; ++s)      // iterated (b = 0, or not finite) gets x = 0
+            if (p->ctl_host[s].iters == 0)
+                LG_HIP(hipMemsetAsync(x + (size_t)s * p->npts, 0, p->npts * sizeof(double), p->stream));
+    }
     if (o->x0_given) {                    // b = 0 from a given x: the solution is 0
         for (int s = 0; s < nf; ++s)
             if (p->ctl_host[s].bb == 0.0 && p->ctl_host[s].status == LG_OK)
@@ -211,11 +216,11 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
     const int nf = p->S * p->C;
     const bool cy = p->cyl;
     if (cy) {
-        LG_HIP(cyl_launch_update(p, 1, b, x, 0.0, iters + 1));
+        LG_HIP(cyl_launch_update(p, 1, b, x, 0.0, iters + 2));
         LG_HIP(cyl_launch_rsys(p, p->rhat, p->y, nf, 1));
         LG_HIP(cyl_launch_correct(p, 1));
     } else {
-        LG_HIP(launch_update_fdst(p, 1, b, x, 0.0, iters + 1));
+        LG_HIP(launch_update_fdst(p, 1, b, x, 0.0, iters + 2));
         LG_HIP(launch_td(p, 0, p->rhat, p->y, nf, 1));
         LG_HIP(launch_rs(p, 0, p->rhat, p->y, nf, 1));
         LG_HIP(launch_correct_idst(p, 1));
@@ -224,7 +229,9 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
     for (int i = 0; i < 6; ++i) LG_HIP(hipEventCreate(&ev[i]));
     double acc[5] = {0, 0, 0, 0, 0};
     hipError_t e = hipSuccess;
-    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+    // iteration 0 is not timed: after a cold start the first update reads b
+    // for r and no x (fewer bytes than every later one)
+    for (int it = 0; it <= iters && e == hipSuccess; ++it) {
         e = hipEventRecord(ev[0], p->stream);
         if (e == hipSuccess) e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);
         if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
@@ -240,7 +247,7 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
         if (e == hipSuccess) e = cy ? cyl_launch_correct(p, 0) : launch_correct_idst(p, 0);
         if (e == hipSuccess) e = hipEventRecord(ev[5], p->stream);
         if (e == hipSuccess) e = hipEventSynchronize(ev[5]);
-        for (int k = 0; k < 5 && e == hipSuccess; ++k) {
+        for (int k = 0; k < 5 && e == hipSuccess && it > 0; ++k) {
             float t = 0.f;
             e = hipEventElapsedTime(&t, ev[k], ev[k + 1]);
             acc[k] += t;

@@ -718,7 +718,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if ((he = hipHostMalloc((void**)&p->ctl_host, (size_t)SC * sizeof(ShotCtl), hipHostMallocDefault)) !=
         hipSuccess)
         return bail(hip_fail(he, "hipHostMalloc"));
-    if ((st = dev_alloc(p, &p->xslot, sizeof(double*))) != LG_OK) return bail(st);
+    if ((st = dev_alloc(p, &p->xslot, 2 * sizeof(double*))) != LG_OK) return bail(st);
     if ((he = hipDeviceSynchronize()) != hipSuccess) return bail(hip_fail(he, "hipDeviceSynchronize"));
     *out = p;
     return LG_OK;

@@ -231,7 +231,8 @@ def test_cylindrical_rejects_unsupported_options():
 def test_cylindrical_profile_runs_the_iteration():
     """The measurement helper times the four kernels of an axisymmetric CG
     iteration (no interface stage) and leaves x equal to the same number of
-    eager iterations of the solver."""
+    eager iterations of the solver (the timed iterations and one untimed
+    first one)."""
     torch = torch_cuda()
     nr, nz = 64, 128
     kappa, rho = _medium(nr, nz)
@@ -244,7 +245,7 @@ def test_cylindrical_profile_runs_the_iteration():
     assert ms[3] < 0.05 and all(m > 0.0 for k, m in enumerate(ms) if k != 3)   # slot 3: no kernel
     for s in range(2):
         xo = krylov.pcg(lambda y: cyl.apply_A(y, *cyl.coefficients(kappa, rho, 200.0, 10.0), 10.0, 10.0),
-                        cyl.preconditioner(kappa, rho, 200.0, 10.0, 10.0).solve, b[s, 0], 0.0, 5)[0]
+                        cyl.preconditioner(kappa, rho, 200.0, 10.0, 10.0).solve, b[s, 0], 0.0, 6)[0]
         assert rel(to_np(xd)[s, 0], xo) < 1e-12
 
 

@@ -98,7 +98,8 @@ def test_order4_pcg_mixed_true_residual(nx, nz, shots):
 
 def test_order4_options_and_profile():
     """x0_given is rejected; the profile helper runs the fourth-order
-    iteration (stored q) and leaves x equal to 5 oracle iterations."""
+    iteration (stored q) and leaves x equal to 6 oracle iterations (5 timed,
+    one untimed first one)."""
     torch = torch_cuda()
     nx = nz = 64
     kappa, rho = heterogeneous(nx, nz)
@@ -113,7 +114,7 @@ def test_order4_options_and_profile():
     ms = plan.pcg_profile(bd, xd, iters=5)
     assert all(m > 0.0 for m in ms)
     for s in range(2):
-        xo = _oracle_pcg(kappa, rho, 200.0, nx, nz, b[s], 0.0, max_iter=5)[0]
+        xo = _oracle_pcg(kappa, rho, 200.0, nx, nz, b[s], 0.0, max_iter=6)[0]
         assert rel(to_np(xd)[s], xo) < 1e-12
 
 
