@@ -255,7 +255,8 @@ lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z);
  * the last one reports LG_ERR_NOT_CONVERGED with relres of its true
  * residual); iters counts every CG iteration of the solve.  A zero b gives
  * x = 0, iters = 0.  Converged shots drop out by masking.  b, x: FP64
- * vectors.  info_host: [S] (may be NULL).  Returns the worst per-shot status. */
+ * vectors, b != x (b is read until the solve returns).  info_host: [S] (may
+ * be NULL).  Returns the worst per-shot status. */
 lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve_opts* opts,
                        lg_solve_info* info_host);
 
