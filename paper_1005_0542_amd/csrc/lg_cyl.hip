@@ -249,16 +249,28 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
             // rows of the input (or, UPDATE, the updated residual) -> symmetric extension
             T v0[NIT], v1[NIT];
             if constexpr (UPD) {
-                // init 0: x += alpha p, r -= alpha q; 1: x = 0, r = b;
-                // 2: r as stored (x untouched)
+                // init 0: x += alpha p, r -= alpha q; 1 (cold start): only the
+                // transform of b and ||b||^2, x = 0 and r = b are not stored: the
+                // shot's first update (ShotCtl.fresh) reads b for r, takes x as 0
+                // and writes both; 2: r as stored (x untouched)
                 const int init = a.init;
-                double* X = init ? a.x : *a.xslot;
-                if (init == 1 && blockIdx.x == 0 && threadIdx.x == 0) *a.xslot = a.x;
+                bool fresh = false;
+                const double* B0 = nullptr;
+                if (init == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+                    a.xslot[0] = a.x;
+                    a.xslot[1] = const_cast<double*>(a.b);
+                }
+                if (init == 0) {
+                    fresh = a.ctl[field].fresh != 0;                   // uniform per block
+                    if (fresh) B0 = wave_uniform(a.xslot[1]);
+                }
+                double* const X = wave_uniform(init ? a.x : a.xslot[0]);
                 const double alpha = init ? 0.0 : a.ctl[field].alpha;
-                const rsrc_t rX = buf_rsrc(X + fbase, init ? 0u : nfe * 8u);
-                const rsrc_t rXs = buf_rsrc(X + fbase, init == 2 ? 0u : nfe * 8u);
-                const rsrc_t rR = buf_rsrc(init == 1 ? a.b + fbase : a.r + fbase, nfe * 8u);
-                const rsrc_t rRs = buf_rsrc(a.r + fbase, nfe * 8u);
+                const rsrc_t rX = buf_rsrc(X + fbase, (init == 0 && !fresh) ? nfe * 8u : 0u);
+                const rsrc_t rXs = buf_rsrc(X + fbase, init == 0 ? nfe * 8u : 0u);
+                const rsrc_t rR = buf_rsrc(
+                    wave_uniform(init == 1 ? a.b + fbase : (B0 != nullptr ? B0 + fbase : a.r + fbase)), nfe * 8u);
+                const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 0 ? nfe * 8u : 0u);
                 const rsrc_t rP = buf_rsrc(a.p + fbase, init ? 0u : nfe * SZ);
                 const rsrc_t rQ = buf_rsrc(a.q + fbase, (init || MODE == CY_UPDATE_OP) ? 0u : nfe * SZ);
                 const rsrc_t rA1 = buf_rsrc(a.a1, MODE == CY_UPDATE_OP ? nfe * SZ : 0u);

@@ -185,7 +185,7 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
             if (rep == 0) after_restart = max_iters() - first_stop;
         }
     }
-    if (!p->cyl && !o->x0_given) {        // a cold start stores no x: a shot that never
+    if (!o->x0_given) {                   // a cold start stores no x: a shot that never
         for (int s = 0; s < nf; ++s)      // iterated (b = 0, or not finite) gets x = 0
             if (p->ctl_host[s].iters == 0)
                 LG_HIP(hipMemsetAsync(x + (size_t)s * p->npts, 0, p->npts * sizeof(double), p->stream));
