@@ -175,6 +175,65 @@ __global__ __launch_bounds__(GM_BLK) void gm_multidot_kernel(const double* __res
     }
 }
 
+// Classical Gram-Schmidt twice, with each subtraction fused into the sweep
+// that follows it (one read of the basis instead of two):
+//   NORM = false: w -= sum_{i<m} coef[s][i] V_i, then the block partials of
+//                 (V_i, w) for i < m (the second pass's inner products);
+//   NORM = true:  w -= sum_{i<m} coef[s][i] V_i, then the block partial of
+//                 (w, w) in slot 0.
+// Per element the subtraction is gm_subtract_kernel's and the products and
+// per-thread sums are gm_multidot_kernel's, in the same order, so the
+// results are those of the separate kernels.  MB >= m bounds the unroll.
+template <int MB, bool NORM>
+__global__ __launch_bounds__(GM_BLK) void gm_subdot_kernel(const double* __restrict__ V, size_t vstride, int m,
+                                                           const double* __restrict__ coef, int coef_stride,
+                                                           double* __restrict__ w, size_t n_s,
+                                                           const int* __restrict__ active,
+                                                           double* __restrict__ partial, int nblk) {
+    __shared__ double red[GM_BLK / 64];
+    const int s = blockIdx.y, b = blockIdx.x;
+    if (active[s] == 0) return;
+    const size_t base = (size_t)s * n_s;
+    const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
+    const uint32_t nbytes = (uint32_t)(n_s * 8);
+    const rsrc_t rw = buf_rsrc(w + base, nbytes);
+    rsrc_t rv[MB];
+    double c[MB];
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+        rv[u] = buf_rsrc(V + (size_t)u * vstride + base, u < m ? nbytes : 0u);
+        c[u] = u < m ? coef[(size_t)s * coef_stride + u] : 0.0;
+    }
+    constexpr int NA = NORM ? 1 : MB;
+    double acc[NA];
+#pragma unroll
+    for (int u = 0; u < NA; ++u) acc[u] = 0.0;
+    for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) {
+        const uint32_t off = (uint32_t)(e * 8);
+        double vv[MB];
+#pragma unroll
+        for (int u = 0; u < MB; ++u) vv[u] = bload<double>(rv[u], off);
+        double wv = bload<double>(rw, off);
+#pragma unroll
+        for (int u = 0; u < MB; ++u)
+            if (u < m) wv -= c[u] * vv[u];
+        bstore<double>(wv, rw, off);
+        if constexpr (NORM) {
+            acc[0] += wv * wv;
+        } else {
+#pragma unroll
+            for (int u = 0; u < MB; ++u) acc[u] += vv[u] * wv;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+        if (u < (NORM ? 1 : m)) {                  // uniform over the block
+            const double t = block_sum(acc[u], red);
+            if (threadIdx.x == 0) partial[((size_t)s * (GM_MAXK + 1) + u) * nblk + b] = t;
+        }
+    }
+}
+
 // out[s][i] = sum_b partial[s][i][b] (fixed order), i < m; plus add[s][i] if given
 __global__ __launch_bounds__(GM_BLK) void gm_reduce_kernel(const double* __restrict__ partial, int m, int nblk,
                                                            const int* __restrict__ active,
@@ -304,6 +363,35 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                            g.dots + slot, DS);
         return hipGetLastError();
     };
+    // one classical Gram-Schmidt subtraction fused with the sweep after it
+    // (the inner products of the second pass, or the norm); m > 16 takes the
+    // separate kernels
+    auto subdot = [&](int m, int coef_slot, bool norm, int out_slot) -> hipError_t {
+        const dim3 grid(nblk, S);
+        const double* cf = g.dots + coef_slot;
+        if (m <= 8) {
+            if (norm) hipLaunchKernelGGL((gm_subdot_kernel<8, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
+                                         g.w, n_s, g.active, g.partial, nblk);
+            else hipLaunchKernelGGL((gm_subdot_kernel<8, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
+                                    g.w, n_s, g.active, g.partial, nblk);
+        } else if (m <= 16) {
+            if (norm) hipLaunchKernelGGL((gm_subdot_kernel<16, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
+                                         g.w, n_s, g.active, g.partial, nblk);
+            else hipLaunchKernelGGL((gm_subdot_kernel<16, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
+                                    g.w, n_s, g.active, g.partial, nblk);
+        } else {
+            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS, g.w, n_s, S,
+                               g.active);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            return norm ? dot_into(g.w, 0, 1, g.w, out_slot) : dot_into(g.V, nvec, m, g.w, out_slot);
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(gm_reduce_kernel, dim3(S), dim3(GM_BLK), 0, st, g.partial, norm ? 1 : m, nblk, g.active,
+                           g.dots + out_slot, DS);
+        return hipGetLastError();
+    };
     auto fetch_dots = [&]() -> hipError_t {
         hipError_t e = hipMemcpyAsync(dots_h.data(), g.dots, (size_t)S * DS * 8, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -399,16 +487,10 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             double* Vn = g.V + (size_t)(j + 1) * nvec;
             hipError_t e = launch_elastic_precond(p, Vj, g.z);
             if (e == hipSuccess) e = launch_elastic_stencil(p, g.z, g.w);
-            if (e == hipSuccess) e = dot_into(g.V, nvec, j + 1, g.w, 0);
+            if (e == hipSuccess) e = dot_into(g.V, nvec, j + 1, g.w, 0);                    // pass 1 products
+            if (e == hipSuccess) e = subdot(j + 1, 0, false, GM_MAXK + 1);                  // subtract, pass 2 products
+            if (e == hipSuccess) e = subdot(j + 1, GM_MAXK + 1, true, 2 * (GM_MAXK + 1));   // subtract, ||w||^2
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1, g.dots, DS, g.w,
-                               n_s, S, g.active);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if ((e = dot_into(g.V, nvec, j + 1, g.w, GM_MAXK + 1)) != hipSuccess) return e;
-            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, j + 1,
-                               g.dots + GM_MAXK + 1, DS, g.w, n_s, S, g.active);
-            if ((e = hipGetLastError()) != hipSuccess) return e;
-            if ((e = dot_into(g.w, 0, 1, g.w, 2 * (GM_MAXK + 1))) != hipSuccess) return e;
             hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.w, g.dots + 2 * (GM_MAXK + 1),
                                DS, Vn, n_s, S, g.active);
             if ((e = hipGetLastError()) != hipSuccess) return e;
