@@ -90,7 +90,7 @@ typedef enum { LG_TOP_DIRICHLET = 0, LG_TOP_FREE = 1 } lg_top_bc;
  * point source). */
 typedef enum { LG_CARTESIAN = 0, LG_CYLINDRICAL = 1 } lg_geometry;
 
-/* Spatial order of the acoustic operator (Sec. 3.3: higher-order schemes are
+/* Spatial order of the acoustic operator (Sec. 3.2: higher-order schemes are
  * preconditioned by the same second-order B).  2 (or 0): the five-point
  * operator above.  4: A4 = Dx^T Kx Dx + Dz^T Kz Dz + w with the fourth-order
  * staggered difference (D u)_{m+1/2} = [27 (u_{m+1} - u_m) - (u_{m+2} -
@@ -168,7 +168,10 @@ typedef struct lg_plan lg_plan;
  *   elastic  F = 3: lambda, mu, rho (Lame parameters and density).
  * The preconditioner uses the midrange values (min+max)/2 of these arrays
  * (footnote to eq. precond1).  hip_stream may be NULL (null stream).
- * tuning may be NULL.  On success *out owns device tables and workspace. */
+ * tuning may be NULL.  On success *out owns device tables and workspace.
+ * Returns LG_ERR_UNSUPPORTED, before any device call, when nshots times the
+ * components (1 acoustic, 2 elastic) times the interior points reaches 2^32
+ * (element-wise kernels launch one work-item per vector element). */
 lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid,
                          const lg_laguerre* lag, lg_precision prec, int32_t nshots,
                          const double* medium_host, const lg_tuning* tuning,

@@ -1,6 +1,6 @@
 """Fourth-order acoustic operator (oracle, test infrastructure only).
 
-The paper remarks (Sec. 3.3, after the accuracy study) that higher-order
+The paper remarks (Sec. 3.2, after the accuracy study) that higher-order
 schemes fit the method, preconditioned by the same second-order Laplace
 operator B, at the price of somewhat more CG iterations.  It names no scheme;
 the one used here keeps the flux form of Sec. 2.3 and its symmetry:

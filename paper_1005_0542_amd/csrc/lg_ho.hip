@@ -1,4 +1,4 @@
-// Fourth-order acoustic operator (Sec. 3.3: a higher-order scheme, still
+// Fourth-order acoustic operator (Sec. 3.2: a higher-order scheme, still
 // preconditioned by the second-order B) on gfx950.
 //
 //   A4 u = Dx^T Kx Dx u + Dz^T Kz Dz u + w u,

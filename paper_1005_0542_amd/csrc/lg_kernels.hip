@@ -1037,7 +1037,7 @@ __global__ __launch_bounds__(256) void rhs_kernel(int m, const double* __restric
 constexpr int SRC_CHUNK = 64;
 struct SrcArgs {
     int n;
-    int32_t idx[SRC_CHUNK];     // element offset of the source node, per shot
+    int64_t idx[SRC_CHUNK];     // element offset of the source node, per shot
     double val[SRC_CHUNK];
 };
 
@@ -1482,7 +1482,7 @@ hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double
             const int s = s0 + t;
             const int i = p->src_host[2 * s], j = p->src_host[2 * s + 1];
             const int comp = p->C - 1;   // acoustic: 0; elastic: z component
-            sa.idx[t] = (int32_t)(((size_t)s * p->C + comp) * p->npts + (size_t)(j - 1) * p->nx1 + (i - 1));
+            sa.idx[t] = (int64_t)(((size_t)s * p->C + comp) * p->npts + (size_t)(j - 1) * p->nx1 + (i - 1));
             sa.val[t] = fsrc_host[s] * inv;
         }
         hipLaunchKernelGGL(src_kernel, dim3(1), dim3(SRC_CHUNK), 0, p->stream, sa, rhs);

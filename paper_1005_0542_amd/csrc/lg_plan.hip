@@ -563,6 +563,14 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (P == 0) P = cyl ? (grid->nz >= 128 ? std::min(64, grid->nz / 64) : 1) : std::max(1, std::min(64, grid->nz / 16));
     if (!(cyl && P == 1) && (!is_pow2(P) || P > 64 || grid->nz % P != 0 || grid->nz / P < 2 || grid->nz / P > 64))
         return fail(LG_ERR_INVALID_ARG, "segments must be a power of two <= 64 with nz/segments in 2..64");
+    // one-dimensional launches map every element of a vector to a work-item,
+    // and a grid dimension holds fewer than 2^32 work-items
+    {
+        const size_t C = (kind == LG_ACOUSTIC) ? 1 : 2;
+        const size_t nvec = (size_t)nshots * C * (size_t)(cyl ? grid->nx : grid->nx - 1) * (size_t)(grid->nz - 1);
+        if (nvec >= ((size_t)1 << 32))
+            return fail(LG_ERR_UNSUPPORTED, "shots x components x interior points must be below 2^32");
+    }
     const int F = (kind == LG_ACOUSTIC) ? 2 : 3;
     // node arrays: (nz+1)(nx+1) Cartesian nodes, or Nr x Nz axisymmetric nodes
     const size_t nn = cyl ? (size_t)grid->nx * grid->nz : (size_t)(grid->nx + 1) * (grid->nz + 1);

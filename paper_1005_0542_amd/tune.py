@@ -30,6 +30,9 @@ from . import api
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
+# CG iterations per captured graph tried by the tuner
+GRAPH_ITERS_CANDIDATES = (2, 4, 8, 16)
+
 def segment_candidates(nz: int) -> List[int]:
     """Powers of two P <= 64 with segment length nz/P in 2..64."""
     out = []
@@ -105,7 +108,7 @@ def tune_acoustic(nx: int, nz: int, dx: float, dz: float, alpha: int, h: float, 
     best = min(trials, key=lambda t: t["iteration_ms"])
     # iterations per captured graph: time short solves with the best tiles
     gtrials = []
-    for gi in (2, 4, 8, 16):
+    for gi in GRAPH_ITERS_CANDIDATES:
         plan = api.Plan("acoustic", nx, nz, dx, dz, alpha, h, 2, medium, precision=precision, nshots=shots,
                         segments=best["segments"], op_shots=best["op_shots"],
                         seg_per_wave=best["seg_per_wave"], op_fusion=best["op_fusion"], graph_iters=gi)

@@ -95,6 +95,16 @@ def test_plan_create_unsupported_shapes():
     assert _create(top=_lib.LG_TOP_FREE, order=4) == _lib.LG_ERR_UNSUPPORTED
 
 
+def test_plan_create_rejects_vectors_of_2_to_the_32_elements():
+    # shots x components x interior points >= 2^32 is refused before the medium
+    # is read (a 4-element medium stands in) and before any device call
+    tiny = np.ones(4)
+    assert _create(nx=2048, nz=2048, shots=1026, medium=tiny) == _lib.LG_ERR_UNSUPPORTED      # 4.299e9
+    assert _create(kind=_lib.LG_ELASTIC, nx=2048, nz=2048, shots=513, medium=tiny) == _lib.LG_ERR_UNSUPPORTED
+    assert _create(nx=4096, nz=4096, shots=257, medium=tiny) == _lib.LG_ERR_UNSUPPORTED
+    assert "2^32" in _lib.load().lg_last_error().decode()
+
+
 def test_null_arguments_rejected():
     lib = _lib.load()
     assert lib.lg_plan_create(None, 0, None, None, 0, 1, None, None, None) == _lib.LG_ERR_INVALID_ARG

@@ -1,4 +1,4 @@
-"""GPU parity of the fourth-order acoustic operator (Sec. 3.3: a higher-order
+"""GPU parity of the fourth-order acoustic operator (Sec. 3.2: a higher-order
 scheme preconditioned by the same second-order B) against the FP64 oracle:
 the 13-point operator, PCG with the second-order preconditioner (FP64 and
 mixed with FP64 refinement) and a whole harmonic chain."""

@@ -612,7 +612,7 @@ def test_cylindrical_radial_operator_converges_to_bessel_eigenvalue():
 
 
 # ---------------------------------------------------------------------------
-# Fourth-order operator preconditioned by the second-order B (Sec. 3.3)
+# Fourth-order operator preconditioned by the second-order B (Sec. 3.2)
 # ---------------------------------------------------------------------------
 from oracle import highorder as ho
 
