@@ -756,3 +756,171 @@ def test_cylindrical_source_carries_unit_volume_strength():
     src = cyl.source_field((15, 32), (9, 1), f, hr, hz)
     assert np.count_nonzero(src) == 1 and src[0, 8] != 0.0
     assert abs(2 * np.pi * hr * hz * src.sum() - f) < 1e-15 * f
+
+
+# ---------------------------------------------------------------------------
+# Laguerre functions at large h t against multiprecision (the exponent-rescale
+# branch of the recurrence engages there)
+# ---------------------------------------------------------------------------
+
+def _psi_mp(m, alpha, x):
+    """n_m e^{-x/2} L_m^alpha(x) by mpmath's hypergeometric Laguerre
+    polynomial at 40 digits (independent of the three-term recurrence)."""
+    import mpmath as mp
+    with mp.workdps(40):
+        return mp.sqrt(mp.factorial(m) / mp.factorial(m + alpha)) * mp.exp(-mp.mpf(x) / 2) * mp.laguerre(m, alpha, x)
+
+
+def _envelope_error(got, ref):
+    """max_m |got_m - ref_m| / max(|ref_{m-1}|, |ref_m|, |ref_{m+1}|): a relative
+    error that stays meaningful next to the zeros of L_m."""
+    worst = 0.0
+    for m in range(len(ref)):
+        env = max(abs(ref[k]) for k in range(max(0, m - 1), min(len(ref) - 1, m + 1) + 1))
+        worst = max(worst, float(abs(got[m] - ref[m]) / env))
+    return worst
+
+
+@pytest.mark.parametrize("x", [600.0, 1200.0, 2000.0])
+def test_psi_large_argument_matches_multiprecision(x):
+    """psi_m(x) for m < 1024 at x = 600, 1200 (h t of the 4096^2 workload's last
+    snapshot: h = 600, t = 2 s) and 2000, where e^{-x/2} alone underflows FP64
+    and the recurrence carries its exponent separately."""
+    import mpmath as mp
+    alpha, n = 9, 1024
+    mant, e2 = laguerre.psi_scaled(n, np.array([x]), alpha)
+    if x >= 1200.0:
+        assert len(set(e2[:, 0].tolist())) > 1          # the rescale branch ran
+    with mp.workdps(40):
+        got = [mp.mpf(float(mant[m, 0])) * mp.power(2, mp.mpf(float(e2[m, 0]))) for m in range(n)]
+        ref = [_psi_mp(m, alpha, x) for m in range(n)]
+        assert _envelope_error(got, ref) < 1e-12
+
+
+def test_synthesis_weights_large_ht_match_multiprecision():
+    """W_m(t) = sqrt(h) (ht)^alpha psi_m(ht) at the 4096^2 workload's snapshot
+    times (h = 600, T = 2 s, n = 1024) against mpmath."""
+    import mpmath as mp
+    h, alpha, n = 600.0, 9, 1024
+    t = np.array([0.5, 1.0, 2.0])
+    W = laguerre.synthesis_weights(t, h, alpha, n)
+    with mp.workdps(40):
+        for q, tq in enumerate(t):
+            x = h * tq
+            pre = mp.sqrt(h) * mp.mpf(x) ** alpha
+            ref = [pre * _psi_mp(m, alpha, x) for m in range(0, n, 3)]
+            got = [mp.mpf(float(W[q, m])) for m in range(0, n, 3)]
+            assert _envelope_error(got, ref) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Whole harmonic chain in a homogeneous medium (one sine mode in closed form)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mode", [(3, 2), (1, 5)])
+def test_homogeneous_chain_sine_mode_closed_form(mode):
+    """In a homogeneous medium the grid sine modes phi_pq(i, j) = sin(pi p i/Nx)
+    sin(pi q j/Nz) diagonalise A with eigenvalue
+    kappa (mu_p + nu_q) + rho h^2/4, mu_p = (4/dx^2) sin^2(pi p/(2Nx)),
+    nu_q = (4/dz^2) sin^2(pi q/(2Nz)).  The semi-discrete problem
+    rho u_tt + A0 u = delta_h e_src f(t) then decouples: mode (p, q) obeys
+    c'' + omega^2 c = (s_pq/rho) f with omega^2 = kappa (mu_p + nu_q)/rho and
+    s_pq the mode's share of a unit point source (delta of unit integral over
+    the cell, dx dz, at the source node).  With f = u'' + omega^2 u for
+    u = (ht)^alpha e^{-beta t} (u(0) = u'(0) = 0), the mode's exact solution is
+    (s_pq/rho) u, whose Laguerre coefficients are closed-form.  The oracle's
+    chain (running sums, PCG, point source) must reproduce them.  dx != dz and
+    Nx != Nz, so the source scale 1/(dx dz), its sign, the source position and
+    the mode indices are all fixed by this."""
+    nx, nz, dx, dz = 16, 8, 10.0, 7.0
+    v, kap0 = 2000.0, 1.0
+    rho0 = kap0 / v ** 2
+    h, alpha, beta, n = 200.0, 9, 50.0, 60
+    src = (5, 3)
+    p, q = mode
+    mu = (4.0 / dx ** 2) * math.sin(math.pi * p / (2 * nx)) ** 2
+    nu = (4.0 / dz ** 2) * math.sin(math.pi * q / (2 * nz)) ** 2
+    om2 = kap0 * (mu + nu) / rho0
+
+    def u(t):
+        t = np.asarray(t); return (h * t) ** alpha * np.exp(-beta * t)
+
+    def f(t):
+        t = np.asarray(t); a = alpha
+        upp = (a * (a - 1) * h * h * (h * t) ** (a - 2) - 2 * a * beta * h * (h * t) ** (a - 1)
+               + beta * beta * (h * t) ** a) * np.exp(-beta * t)
+        return upp + om2 * u(t)
+
+    f_m = laguerre.source_coeffs(f, 3.0, h, alpha, n)
+    kappa = np.full((nz + 1, nx + 1), kap0)
+    rho = np.full((nz + 1, nx + 1), rho0)
+    A, Minv, _ = _acoustic_setup(nx, nz, kappa, rho, dx, dz, h)
+    state = harmonics.harmonic_loop(n, lambda phi: krylov.pcg(A, Minv, phi, 1e-14, 20), rho[1:-1, 1:-1],
+                                    h, alpha, f_m, src, dx, dz)
+    assert set(state["iters"]) == {1}                   # B = A: one CG iteration each
+    ii = np.arange(1, nx)
+    jj = np.arange(1, nz)
+    phi = np.outer(np.sin(np.pi * q * jj / nz), np.sin(np.pi * p * ii / nx))    # [j][i]
+    norm2 = (nx / 2.0) * (nz / 2.0)                     # sum of phi^2
+    c = np.array([np.sum(phi * R) / norm2 for R in state["R"]])
+    s_pq = (1.0 / (dx * dz)) * math.sin(math.pi * p * src[0] / nx) * math.sin(math.pi * q * src[1] / nz) / norm2
+    ref = (s_pq / rho0) * _closed_form_coeffs(h, alpha, beta, n)
+    assert np.max(np.abs(c - ref)) < 1e-11 * np.max(np.abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# Physics: a point source in a homogeneous medium against the 2D free-space
+# Green's function, at second order in the mesh step (Sec. 3.2, eq. accuracy)
+# ---------------------------------------------------------------------------
+
+def _greens_2d_trace(f, v, r, t):
+    """u(r, t) = (v/2 pi) int_0^{t-r/v} f(tau) / sqrt(v^2 (t-tau)^2 - r^2) dtau,
+    the solution of u_tt = v^2 lap u + v^2 delta(x) f(t) in the plane (the
+    constant-density acoustic equation with kappa = 1, rho = 1/v^2), zero before
+    the first arrival.  With t - tau = (r/v) cosh(theta) the integrand is smooth:
+    u = (1/2 pi) int_0^{acosh(vt/r)} f(t - (r/v) cosh theta) dtheta."""
+    import scipy.integrate
+    out = np.zeros(len(t))
+    for k, tk in enumerate(t):
+        if v * tk > r:
+            th = math.acosh(v * tk / r)
+            out[k] = scipy.integrate.quad(lambda s: float(f(tk - (r / v) * math.cosh(s))), 0.0, th,
+                                          limit=400, epsabs=1e-14, epsrel=1e-12)[0] / (2.0 * math.pi)
+    return out
+
+
+def test_point_source_trace_converges_to_free_space_solution():
+    """A 25 Hz Ricker point source at the centre of a homogeneous 2000 m/s
+    medium (512 m x 384 m, dz = 0.75 dx), a receiver 100 m away on the source
+    row, compared over 0..0.19 s (before the first boundary reflection arrives)
+    with the 2D Green's-function solution by the paper's error measure eps (the
+    relative L2 norm over time).  eps must fall about 4x per halving of the mesh
+    step (second-order scheme) and be small on the finest mesh: this fixes the
+    absolute amplitude of the whole chain (source scale, sign, recurrence,
+    synthesis)."""
+    v, f0 = 2000.0, 25.0
+    t0 = 1.5 / f0
+    h, alpha, n = 600.0, 9, 400
+    r, t1 = 100.0, 0.19
+    t = np.linspace(0.0, t1, 381)
+    wavelet = laguerre.ricker(f0, t0)
+    exact = _greens_2d_trace(wavelet, v, r, t)
+    f_m = laguerre.ricker_coeffs(f0, t0, h, alpha, n)
+    W = laguerre.synthesis_weights(t, h, alpha, n)
+    eps = []
+    for k in range(3):
+        nx = nz = 128 * 2 ** k
+        dx, dz = 4.0 / 2 ** k, 3.0 / 2 ** k
+        kappa = np.ones((nz + 1, nx + 1))
+        rho = np.full((nz + 1, nx + 1), 1.0 / v ** 2)
+        A, Minv, _ = _acoustic_setup(nx, nz, kappa, rho, dx, dz, h)
+        src = (nx // 2, nz // 2)
+        rec_i = nx // 2 + int(round(r / dx))
+        state = harmonics.harmonic_loop(n, lambda phi: krylov.pcg(A, Minv, phi, 1e-13, 20),
+                                        rho[1:-1, 1:-1], h, alpha, f_m, src, dx, dz, rec_row=src[1],
+                                        keep_all=False)
+        uh = W @ np.array(state["rec"])[:, rec_i - 1]
+        eps.append(math.sqrt(np.trapezoid((exact - uh) ** 2, t) / np.trapezoid(exact ** 2, t)))
+    ratios = [eps[0] / eps[1], eps[1] / eps[2]]
+    assert all(3.5 < q < 4.6 for q in ratios), (eps, ratios)
+    assert eps[2] < 5e-3, eps
