@@ -83,12 +83,15 @@ def pcg(apply_A: Op, apply_Minv: Op, b: np.ndarray, tol: float,
 
 
 def gmres(apply_A: Op, apply_Minv: Op, b: np.ndarray, tol: float, restart: int,
-          max_cycles: int = 200) -> Tuple[np.ndarray, int, float, int]:
+          max_cycles: int = 200, max_iter: int = None) -> Tuple[np.ndarray, int, float, int]:
     """Right-preconditioned restarted GMRES(k) from ``x0 = 0``.
 
     Inner iterations use the Givens estimate ``|g_{j+1}|`` of the residual
     norm; each restart recomputes the true residual ``b - A x``.  Returns
-    ``(x, inner_iterations, relres_estimate, status)``.
+    ``(x, inner_iterations, relres_estimate, status)``.  ``max_iter``, if
+    given, caps the total number of inner iterations: the cycle in progress
+    then ends with its update of x and the status is NOT_CONVERGED (with
+    ``tol = 0`` this runs exactly ``max_iter`` iterations).
     """
     b = np.asarray(b, dtype=np.float64)
     x = np.zeros_like(b)
@@ -114,6 +117,7 @@ def gmres(apply_A: Op, apply_Minv: Op, b: np.ndarray, tol: float, restart: int,
         g = np.zeros(k + 1)
         g[0] = beta
         done = False
+        capped = False
         j_used = 0
         for j in range(k):
             w = apply_A(apply_Minv(V[j]))
@@ -143,6 +147,9 @@ def gmres(apply_A: Op, apply_Minv: Op, b: np.ndarray, tol: float, restart: int,
             if est <= tol or hj1 == 0.0:
                 done = True
                 break
+            if max_iter is not None and total >= max_iter:
+                capped = True
+                break
             V.append(w / hj1)
         y = np.zeros(j_used)
         for i in range(j_used - 1, -1, -1):        # back substitution
@@ -153,4 +160,6 @@ def gmres(apply_A: Op, apply_Minv: Op, b: np.ndarray, tol: float, restart: int,
         x += apply_Minv(upd)
         if done:
             return x, total, est, OK
+        if capped:
+            return x, total, est, NOT_CONVERGED
     return x, total, est, NOT_CONVERGED

@@ -10,7 +10,7 @@ given at the N_r x N_z nodes.  dx is h_z and dz is h_r."""
 import numpy as np
 import pytest
 
-from oracle import OK, cylindrical as cyl, harmonics, krylov, laguerre
+from oracle import NOT_CONVERGED, OK, cylindrical as cyl, harmonics, krylov, laguerre
 from paper_1005_0542_amd import _lib, api
 
 from _gpu import heterogeneous, log, rel, to_dev, to_np, torch_cuda
@@ -305,3 +305,61 @@ def test_cylindrical_harmonic_chain(prec):
     es = rel(to_np(snap)[:, 0, 0], snap_o)
     print(f"cylindrical chain {prec}: worst per-harmonic error {worst:.2e}, snapshots {es:.2e}")
     assert es < (1e-6 if mixed else 1e-11)
+
+
+def test_cylindrical_harmonic_chain_fixed_iterations():
+    """The same 16-harmonic axisymmetric FP64 chain, each harmonic run for
+    exactly the oracle's CG iteration count (tol = 0, max_iter = the oracle's
+    count at tolerance 1e-12).  With the stopping point fixed, the library's
+    chain and the oracle's are the same computation up to rounding: every
+    harmonic and the snapshots agree to 1e-12 in relative L2 (the fields span
+    over 20 decades, so a max-norm ratio would be set by one element), and so
+    does every right-hand side, relative to the norms of its source and
+    history terms (R: 2.6e-13 and snapshots: 4.3e-13 observed)."""
+    l2 = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    torch = torch_cuda()
+    nr, nz, n_harm = 64, 128, 16
+    hr = hz = 10.0
+    alpha, h = 9, 400.0
+    kappa, rho = _medium(nr, nz, seed=5)
+    plan = _plan(nr, nz, kappa, rho, hr, hz, h, n=n_harm, precision="fp64")
+    src = np.array([[nz // 2, 1]], dtype=np.int32)
+    plan.set_sources(src)
+    f_m = laguerre.ricker_coeffs(25.0, 0.05, h, alpha, n_harm)
+    t_snap = np.array([0.1, 0.2])
+    Ws = laguerre.synthesis_weights(t_snap, h, alpha, n_harm)
+    shape = (1, 1, nr - 1, nz)
+    f64 = torch.float64
+    R = torch.zeros(shape, dtype=f64, device="cuda")
+    Ph, Qh, rhs = torch.zeros_like(R), torch.zeros_like(R), torch.zeros_like(R)
+    snap = torch.zeros((2,) + shape, dtype=f64, device="cuda")
+    a1, a2, w = cyl.coefficients(kappa, rho, h, hr)
+    B = cyl.preconditioner(kappa, rho, h, hr, hz)
+    r_rho = cyl.radii(nr, hr)[:, None] * rho[:-1, :]
+    sums = harmonics.RunningSums((nr - 1, nz), alpha)
+    Rprev, snap_o = None, np.zeros((2, nr - 1, nz))
+    errs = []
+    for m in range(n_harm):
+        plan.laguerre_rhs(m, R if m else None, Ph, Qh, [f_m[m]], rhs)
+        srcf = cyl.source_field((nr - 1, nz), (nz // 2, 1), f_m[m], hr, hz)
+        hist = h * h * r_rho * sums.step(m, Rprev)
+        phi = srcf - hist
+        # the source and history terms cancel near the source node, so the
+        # right-hand side is measured against the size of its two terms
+        er = float(np.linalg.norm(to_np(rhs)[0, 0] - phi) / (np.linalg.norm(srcf) + np.linalg.norm(hist)))
+        Ro, ito, _, sto = krylov.pcg(lambda y: cyl.apply_A(y, a1, a2, w, hr, hz), B.solve, phi, 1e-12, 2000)
+        assert sto == OK
+        log(f"cylindrical chain fixed iterations, harmonic {m}: {ito} iterations")
+        res = plan.pcg_solve(rhs, R, tol=0.0, max_iter=ito)
+        assert res.statuses == [NOT_CONVERGED] and res.iters == [ito], (m, res.iters, ito)
+        plan.laguerre_synthesize(m, R, Ws[:, m], snap)
+        e = l2(to_np(R)[0, 0], Ro)
+        errs.append((m, ito, er, e))
+        snap_o += Ws[:, m][:, None, None] * Ro[None]
+        Rprev = Ro
+    es = l2(to_np(snap)[:, 0, 0], snap_o)
+    for m, it, er, e in errs:
+        print(f"harmonic {m}: {it} iterations, rhs {er:.2e}, R {e:.2e}")
+    print(f"cylindrical chain, fixed iterations: snapshots {es:.2e}")
+    assert max(e for _, _, _, e in errs) < 1e-12 and max(er for _, _, er, _ in errs) < 1e-12
+    assert es < 1e-12

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle import elastic, krylov, harmonics, laguerre, precond
-from oracle import OK, NONFINITE
+from oracle import OK, NONFINITE, NOT_CONVERGED
 from paper_1005_0542_amd import api, inputs
 
 from _gpu import log, rel, to_dev, to_np, torch_cuda
@@ -91,6 +91,20 @@ def test_gmres_parity_fp64(nx, nz, k):
     # the true residual meets the tolerance (up to the estimate's slack)
     r = b - elastic.apply_C(to_np(xd)[0], lam, mu, w, d, d)
     assert np.linalg.norm(r) <= 10 * 1e-10 * np.linalg.norm(b)
+    # fixed iteration counts (tol = 0): the oracle's count, then two full
+    # cycles and half a third one (a restart from the true residual); both
+    # sides compute the same Krylov minimiser, so they agree to rounding
+    Cop = lambda u: elastic.apply_C(u, lam, mu, w, d, d)
+    Kop = lambda u: elastic.apply_Kinv(u, B1, B2)
+    for cap, ref in ((ito, xo), (2 * k + k // 2, None)):
+        if ref is None:
+            ref, itc, _, stc = krylov.gmres(Cop, Kop, b, 0.0, k, max_iter=cap)
+            assert itc == cap and stc == NOT_CONVERGED
+        log(f"gmres fp64 {nx}x{nz} k={k} fixed {cap} iterations")
+        xf = torch.empty_like(bd)
+        rf = plan.gmres_solve(bd, xf, tol=0.0, max_iter=cap, restart=k)
+        assert rf.statuses == [NOT_CONVERGED] and rf.iters == [cap]
+        assert rel(to_np(xf)[0], ref) < 1e-12, (cap, rel(to_np(xf)[0], ref))
 
 
 def test_gmres_status_and_batched_shots():
@@ -138,17 +152,20 @@ def test_elastic_harmonic_chain_parity():
     for m in range(nh):
         log(f"elastic harmonic {m}")
         plan.laguerre_rhs(m, R if m else None, Ph, Qh, [f[m]], rhs)
-        res = plan.gmres_solve(rhs, R, tol=1e-11, max_iter=5000, restart=10)
-        assert res.statuses == [OK]
         srcf = np.zeros((2, nz - 1, nx - 1))
         srcf[1] = harmonics.source_field((nz - 1, nx - 1), src[0], fo[m], d, d)
         Q = sums.step(m, Rprev)
         phi = srcf - h * h * rho[1:-1, 1:-1][None] * Q
-        # the oracle runs its own chain: the two differ by the GMRES tolerance
-        assert rel(to_np(rhs)[0], phi) < (1e-12 if m == 0 else 1e-8)
+        # the oracle runs its own chain; the library runs each harmonic for
+        # exactly the oracle's iteration count (tol = 0), so the two chains
+        # are the same computation up to rounding
+        assert rel(to_np(rhs)[0], phi) < 1e-12, m
         xo, ito, rro, sto = krylov.gmres(lambda u: elastic.apply_C(u, lam, mu, w, d, d),
                                          lambda u: elastic.apply_Kinv(u, B1, B2), phi, 1e-11, 10)
-        assert rel(to_np(R)[0], xo) < 1e-8
+        assert sto == OK
+        res = plan.gmres_solve(rhs, R, tol=0.0, max_iter=ito, restart=10)
+        assert res.statuses == [NOT_CONVERGED] and res.iters == [ito]
+        assert rel(to_np(R)[0], xo) < 1e-12, (m, rel(to_np(R)[0], xo))
         Rprev = xo
 
 

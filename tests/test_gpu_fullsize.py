@@ -187,7 +187,8 @@ def test_full_kernels_acoustic2048x64_sampled():
 def test_full_elastic1024_gmres():
     """Elastic 1023^2 x 2 unknowns, FP64 GMRES(10): the first harmonic matches
     the oracle's GMRES(10) (iterations within one, solution to 1e-8) and its
-    FP64 true residual meets the tolerance."""
+    FP64 true residual meets the tolerance; run for exactly the oracle's
+    iteration count it matches to 1e-12."""
     torch = torch_cuda()
     w = inputs.WORKLOADS["elastic1024"]
     lam, mu, rho = inputs.elastic_medium_for(w)
@@ -216,4 +217,11 @@ def test_full_elastic1024_gmres():
     print(f"elastic1024: {res.iters[0]} iterations (oracle {ito}), rel L2 {e:.2e}, true residual {rr:.2e}")
     assert sto == OK and abs(res.iters[0] - ito) <= 1
     assert e <= 1e-8 and rr <= 10 * w.tol
+    # the same harmonic run for exactly the oracle's iteration count (tol = 0):
+    # the same Krylov minimiser, equal to rounding
+    log(f"elastic1024 harmonic 0, fixed {ito} iterations")
+    resf = plan.gmres_solve(rhs, R, tol=0.0, max_iter=ito, restart=10)
+    ef = _l2(to_np(R)[0], xo)
+    print(f"elastic1024 fixed {ito} iterations: rel L2 {ef:.2e}")
+    assert resf.iters == [ito] and ef <= 1e-12
     plan.destroy()

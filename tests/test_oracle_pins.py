@@ -387,6 +387,39 @@ def test_elastic_gmres_matches_dense_solve():
     assert st1 == OK and np.max(np.abs(x1 - ref)) < 1e-6 * np.max(np.abs(ref))
 
 
+def test_gmres_iteration_cap_is_the_krylov_least_squares_minimiser():
+    """GMRES capped at j inner iterations (tol = 0) inside its first cycle
+    returns x = K^{-1} y with y minimising ||b - C K^{-1} y|| over the Krylov
+    space span{b, (CK^{-1}) b, ..., (CK^{-1})^{j-1} b} (dense least squares on
+    an explicitly orthonormalised basis); a cap spanning cycles equals the
+    uncapped solver run for that many whole cycles."""
+    nx = nz = 8
+    d, h = 5.0, 300.0
+    vp = inputs.perturbed_layered_velocity(nx, d, 2000.0, 4500.0, seed=1)
+    rho = inputs.perturbed_layered_velocity(nx, d, 2000.0, 2600.0, seed=2)
+    lam, mu, rho = inputs.elastic_coeffs(vp, rho)
+    w = rho[1:-1, 1:-1] * h * h / 4
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, h, nx, nz, d, d)
+    C = lambda u: elastic.apply_C(u, lam, mu, w, d, d)
+    Kinv = lambda u: elastic.apply_Kinv(u, B1, B2)
+    b = np.random.default_rng(12).standard_normal((2, nz - 1, nx - 1))
+    n = b.size
+    CK = np.column_stack([C(Kinv(e.reshape(b.shape))).ravel() for e in np.eye(n)])
+    for j in (1, 3, 6):
+        x, it, _, st = krylov.gmres(C, Kinv, b, 0.0, 10, max_iter=j)
+        assert it == j and st == NOT_CONVERGED
+        Kr = [b.ravel()]
+        for _ in range(j - 1):
+            Kr.append(CK @ Kr[-1])
+        Q, _ = np.linalg.qr(np.column_stack(Kr))
+        c, *_ = np.linalg.lstsq(CK @ Q, b.ravel(), rcond=None)
+        ref = Kinv((Q @ c).reshape(b.shape))
+        assert np.max(np.abs(x - ref)) < 1e-10 * np.max(np.abs(ref))
+    x2, it2, _, _ = krylov.gmres(C, Kinv, b, 0.0, 4, max_iter=8)
+    x3, it3, _, _ = krylov.gmres(C, Kinv, b, 0.0, 4, max_cycles=2)
+    assert it2 == it3 == 8 and np.array_equal(x2, x3)
+
+
 def test_elastic_block_preconditioner_is_diagonal_block_in_homogeneous_medium():
     """For constant lambda, mu, rho the blocks of K (eq. precond2) equal the
     diagonal blocks of C: (C (ux, 0))_x = B1 ux and (C (0, uz))_z = B2 uz."""
