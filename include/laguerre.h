@@ -285,6 +285,22 @@ lg_status lg_laguerre_synthesize(lg_plan* plan, int32_t m, const double* R_m,
 lg_status lg_trace_synthesize(lg_plan* plan, const double* rec_coeff, const double* W_host,
                               int32_t nt, double* traces);
 
+/* Largest nt * n accepted by lg_trace_synthesize_noalloc (2^21 doubles, 16 MiB). */
+#define LG_TRACE_SCRATCH_MAX (1 << 21)
+
+/* lg_trace_synthesize for callers that cannot allocate device memory (code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same traces, bit for bit, with the [nt][n] weight table
+ * staged in a static device array of LG_TRACE_SCRATCH_MAX doubles that the
+ * library holds on each GPU until the process ends, instead of a per-call
+ * allocation.  Arguments as lg_trace_synthesize.  Calls no hipMalloc or
+ * hipFree.  nt * n > LG_TRACE_SCRATCH_MAX returns LG_ERR_UNSUPPORTED with the
+ * traces untouched.  Every call on one GPU shares the staging array: calls
+ * that overlap on one GPU (other host threads, other plans) race and must be
+ * serialised by the caller.  Synchronises the plan stream before returning. */
+lg_status lg_trace_synthesize_noalloc(lg_plan* plan, const double* rec_coeff, const double* W_host,
+                                      int32_t nt, double* traces);
+
 /* Measurement helper (not part of the method): starts CG on b with tol = 0
  * (so no shot converges) and runs iters + 1 (iters in 1..1000) eager
  * iterations, the last `iters` with HIP events on the plan stream around each

@@ -25,6 +25,7 @@ LG_ACOUSTIC, LG_ELASTIC = 0, 1
 LG_TOP_DIRICHLET, LG_TOP_FREE = 0, 1
 LG_CARTESIAN, LG_CYLINDRICAL = 0, 1
 LG_RICKER, LG_GAUSS_SINE = 0, 1
+LG_TRACE_SCRATCH_MAX = 1 << 21
 
 
 class Grid(ctypes.Structure):
@@ -72,6 +73,7 @@ _SIGNATURES = {
     "lg_laguerre_synthesize": [_PLAN, c_int32, c_void_p, POINTER(c_double), c_int32, c_void_p, c_int32,
                                c_void_p],
     "lg_trace_synthesize": [_PLAN, c_void_p, POINTER(c_double), c_int32, c_void_p],
+    "lg_trace_synthesize_noalloc": [_PLAN, c_void_p, POINTER(c_double), c_int32, c_void_p],
     "lg_pcg_profile": [_PLAN, c_void_p, c_void_p, c_int32, POINTER(ctypes.c_float)],
 }
 

@@ -6,12 +6,44 @@
 #include <cmath>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "lg_internal.h"
 
+// Staging area of lg_trace_synthesize_noalloc: the [nt][n] synthesis weights
+// are copied here instead of into a per-call allocation.  One copy per GPU,
+// held until the process ends; every call on a GPU shares it.
+static __device__ __align__(256) double scratch[LG_TRACE_SCRATCH_MAX];
+
 namespace lg {
+
+namespace {
+// device address of `scratch` on each GPU, looked up once per device (the
+// host-side name of the array is not a device address)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Look up this device's copy of the staging array (device `dev` current).
+lg_status scratch_setup(int dev) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(LG_ERR_UNSUPPORTED, "device ordinal beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[dev] != nullptr) return LG_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (ptr == nullptr) return fail(LG_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[dev] = (double*)ptr;
+    return LG_OK;
+}
+
+double* scratch_ptr(int dev) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return (dev >= 0 && dev < kMaxDevices) ? g_scratch_ptr[dev] : nullptr;
+}
 
 namespace {
 thread_local std::string g_last_error;
@@ -580,6 +612,10 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     int dev = 0;
     hipError_t he = hipGetDevice(&dev);
     if (he != hipSuccess) return hip_fail(he, "hipGetDevice");
+    {
+        const lg_status ss = scratch_setup(dev);
+        if (ss != LG_OK) return ss;
+    }
 
     lg_plan* p = new lg_plan();
     p->kind = kind;
@@ -938,6 +974,28 @@ lg_status lg_trace_synthesize(lg_plan* plan, const double* rec_coeff, const doub
     if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
     (void)hipFree(Wd);
     if (e != hipSuccess) return hip_fail(e, "lg_trace_synthesize");
+    return LG_OK;
+}
+
+lg_status lg_trace_synthesize_noalloc(lg_plan* plan, const double* rec_coeff, const double* W_host,
+                                      int32_t nt, double* traces) {
+    LG_CHECK(check_plan(plan));
+    LG_CHECK(check_vec(rec_coeff, "rec_coeff"));
+    LG_CHECK(check_vec(W_host, "W_host"));
+    LG_CHECK(check_vec(traces, "traces"));
+    if (nt < 1) return fail(LG_ERR_INVALID_ARG, "nt must be >= 1");
+    const size_t count = (size_t)nt * plan->lag.n;
+    if (count > (size_t)LG_TRACE_SCRATCH_MAX)
+        return fail(LG_ERR_UNSUPPORTED, "nt * n = " + std::to_string(count) +
+                                            " exceeds the allocation-free staging limit LG_TRACE_SCRATCH_MAX = " +
+                                            std::to_string((size_t)LG_TRACE_SCRATCH_MAX));
+    LG_HIP(hipSetDevice(plan->device));
+    double* Wd = scratch_ptr(plan->device);   // looked up when the plan was created
+    if (Wd == nullptr) return fail(LG_ERR_HIP, "staging array of this device was not set up");
+    hipError_t e = hipMemcpyAsync(Wd, W_host, count * 8, hipMemcpyHostToDevice, plan->stream);
+    if (e == hipSuccess) e = launch_traces(plan, rec_coeff, Wd, nt, traces);
+    if (e == hipSuccess) e = hipStreamSynchronize(plan->stream);
+    if (e != hipSuccess) return hip_fail(e, "lg_trace_synthesize_noalloc");
     return LG_OK;
 }
 

@@ -117,6 +117,7 @@ def test_null_arguments_rejected():
     assert lib.lg_laguerre_rhs(None, 0, None, None, None, None, None) == _lib.LG_ERR_INVALID_ARG
     assert lib.lg_laguerre_synthesize(None, 0, None, None, 0, None, 0, None) == _lib.LG_ERR_INVALID_ARG
     assert lib.lg_source_coeffs(0, 10.0, 0.1, 4.0, None, None) == _lib.LG_ERR_INVALID_ARG
+    assert lib.lg_trace_synthesize_noalloc(None, None, None, 1, None) == _lib.LG_ERR_INVALID_ARG
     assert "NULL" in lib.lg_last_error().decode()
 
 
