@@ -77,8 +77,11 @@ class Laplace:
     """
 
     def __init__(self, nx: int, nz: int, dx: float, dz: float, kx: float, kz: float, d: float,
-                 free_top: bool = False):
+                 free_top: bool = False, surface_node: bool = False):
         self.free_top = bool(free_top)
+        # surface on the first unknown row (elastic traction-free reading): the
+        # z-second difference of that row is 2 (z_0 - z_1)/dz^2
+        self.surface_node = bool(surface_node)
         self.nx, self.nz, self.dx, self.dz = nx, nz, dx, dz
         self.kx, self.kz, self.d = float(kx), float(kz), float(d)
         k = np.arange(1, nx)
@@ -96,6 +99,9 @@ class Laplace:
         if self.free_top:                       # no z-flux above the first row
             diag = diag.copy()
             diag[0, :] -= self.kz / self.dz ** 2
+        if self.surface_node:                   # surface row: 2 kz (z_0 - z_1)/dz^2
+            upper = upper.copy()
+            upper[0, :] = 2.0 * self.off
         if rhat.ndim == 2:
             return thomas(lower, diag, upper, rhat)
         return np.stack([thomas(lower, diag, upper, r) for r in rhat])
@@ -113,6 +119,8 @@ class Laplace:
         c = Y[..., 1:-1, 1:-1]
         if self.free_top:                       # mirror row: the top face carries no flux
             Y[..., 0, 1:-1] = Y[..., 1, 1:-1]
+        if self.surface_node:                   # mirror about the surface row
+            Y[..., 0, 1:-1] = Y[..., 2, 1:-1]
         dxx = (Y[..., 1:-1, 2:] - 2 * c + Y[..., 1:-1, :-2]) / self.dx ** 2
         dzz = (Y[..., 2:, 1:-1] - 2 * c + Y[..., :-2, 1:-1]) / self.dz ** 2
         return -self.kx * dxx - self.kz * dzz + self.d * c

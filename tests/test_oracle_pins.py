@@ -957,3 +957,123 @@ def test_point_source_trace_converges_to_free_space_solution():
     ratios = [eps[0] / eps[1], eps[1] / eps[2]]
     assert all(3.5 < q < 4.6 for q in ratios), (eps, ratios)
     assert eps[2] < 5e-3, eps
+
+
+# ---------------------------------------------------------------------------
+# Elastic traction-free surface (Sec. 2.2, eq. boundary_elastic)
+# ---------------------------------------------------------------------------
+
+def _elastic_free_medium(nx, nz, d=5.0, h=300.0):
+    vp = inputs.perturbed_layered_velocity(max(nx, nz), d, 2000.0, 4500.0, seed=1)[: nz + 1, : nx + 1]
+    rho = inputs.perturbed_layered_velocity(max(nx, nz), d, 2000.0, 2600.0, seed=2)[: nz + 1, : nx + 1]
+    lam, mu, rho = inputs.elastic_coeffs(vp, rho)
+    return lam, mu, rho, rho[1:-1, 1:-1] * h * h / 4
+
+
+def test_free_surface_elastic_operator_is_the_energy_gradient():
+    """The Hessian of the discrete energy, assembled entry by entry from the
+    energy itself by polarisation (H_ab = E(e_a + e_b) - E(e_a) - E(e_b) for a
+    quadratic form), is symmetric positive definite, and the operator is
+    D_c^{-1} H with the surface row's half weight."""
+    nx, nz, d = 8, 6, 5.0
+    lam, mu, rho, w = _elastic_free_medium(nx, nz, d)
+    shape = (2, nz - 1, nx - 1)
+    n = int(np.prod(shape))
+    E = lambda v: elastic.energy_free(v.reshape(shape), lam, mu, w, d, d)
+    e1 = np.array([E(np.eye(n)[a]) for a in range(n)])
+    H = np.zeros((n, n))
+    for a in range(n):
+        for b in range(a, n):
+            v = np.zeros(n)
+            v[a] += 1.0
+            v[b] += 1.0
+            H[a, b] = H[b, a] = E(v) - e1[a] - e1[b] if a != b else 2.0 * e1[a]
+    assert np.min(np.linalg.eigvalsh(H)) > 0.0
+    c = np.tile(np.repeat(elastic.surface_weights(nz - 1), nx - 1), 2)
+    u = np.random.default_rng(5).standard_normal(shape)
+    got = elastic.apply_C_free(u, lam, mu, w, d, d).ravel()
+    ref = (H @ u.ravel()) / c
+    assert np.max(np.abs(got - ref)) < 1e-10 * np.max(np.abs(ref))
+
+
+def test_free_surface_elastic_equals_dirichlet_scheme_below_the_surface():
+    """Below the surface row the energy's gradient is the Dirichlet scheme
+    (the surface row's values act as ordinary unknowns there)."""
+    nx, nz, d = 12, 10, 5.0
+    lam, mu, rho, w = _elastic_free_medium(nx, nz, d)
+    u = np.random.default_rng(6).standard_normal((2, nz - 1, nx - 1))
+    free = elastic.apply_C_free(u, lam, mu, w, d, d)
+    dirichlet = elastic.apply_C(u, lam, mu, w, d, d)
+    assert np.max(np.abs(free[:, 1:] - dirichlet[:, 1:])) < 1e-12 * np.max(np.abs(dirichlet))
+    assert np.max(np.abs(free[:, 0] - dirichlet[:, 0])) > 1e-3 * np.max(np.abs(dirichlet[:, 0]))
+
+
+def test_free_surface_elastic_manufactured_solution_second_order():
+    """A smooth displacement with nonzero surface motion that meets
+    tau_xz = sigma_zz = 0 at the surface (u_x = -Lz P'(x) X(z),
+    u_z = P(x) Z(z), P = x^2 (Lx - x)^2, X = z (Lz - z), Z = Lz^2 - z^2) in a
+    smoothly varying medium; the forcing -div sigma + w u is formed
+    symbolically.  The free scheme's solution error falls at second order per
+    halving of the mesh; the Dirichlet-top scheme does not converge to it."""
+    import sympy as sp
+    from oracle import krylov
+    x, z = sp.symbols("x z")
+    R = sp.Rational
+    Lxs, Lzs = sp.Integer(400), sp.Integer(300)         # exact, so the traction check is exact
+    Lx, Lz, h, rho0 = 400.0, 300.0, 300.0, 2000.0
+    P = x ** 2 * (Lxs - x) ** 2 / Lxs ** 4
+    ux = -Lzs * sp.diff(P, x) * z * (Lzs - z) / Lzs ** 2
+    uz = P * (Lzs ** 2 - z ** 2) / Lzs ** 2
+    lam = 2 * 10 ** 9 * (1 + R(1, 5) * sp.sin(2 * sp.pi * x / Lxs) * sp.cos(sp.pi * z / Lzs))
+    mu = 10 ** 9 * (1 + R(3, 20) * sp.cos(sp.pi * x / Lxs + R(3, 10)) * sp.sin(2 * sp.pi * z / Lzs + R(1, 5)))
+    wv = sp.Integer(2000) * 300 ** 2 / 4
+    exx, ezz, exz = sp.diff(ux, x), sp.diff(uz, z), sp.diff(ux, z) + sp.diff(uz, x)
+    sxx, szz, sxz = (lam + 2 * mu) * exx + lam * ezz, (lam + 2 * mu) * ezz + lam * exx, mu * exz
+    assert sp.simplify(sxz.subs(z, 0)) == 0 and sp.simplify(szz.subs(z, 0)) == 0
+    fx = -(sp.diff(sxx, x) + sp.diff(sxz, z)) + wv * ux
+    fz = -(sp.diff(sxz, x) + sp.diff(szz, z)) + wv * uz
+    num = [sp.lambdify((x, z), e, "numpy") for e in (fx, fz, ux, uz, lam, mu)]
+    err_free, err_dir = [], []
+    for k in range(3):
+        nx, nz = 16 * 2 ** k, 12 * 2 ** k + 1          # surface: node row 1 (z = 0); bottom: row nz (z = Lz)
+        dx, dz = Lx / nx, Lz / (nz - 1)
+        Xn, Zn = np.meshgrid(np.arange(nx + 1) * dx, (np.arange(nz + 1) - 1) * dz)
+        L = num[4](Xn, Zn) * np.ones_like(Xn)
+        M = num[5](Xn, Zn) * np.ones_like(Xn)
+        Xi, Zi = Xn[1:-1, 1:-1], Zn[1:-1, 1:-1]
+        f = np.stack([num[0](Xi, Zi), num[1](Xi, Zi)])
+        ue = np.stack([num[2](Xi, Zi), num[3](Xi, Zi)])
+        w = np.full(Xi.shape, float(wv))
+        rho = np.full_like(L, rho0)
+        for free, errs in ((True, err_free), (False, err_dir)):
+            op = elastic.apply_C_free if free else elastic.apply_C
+            B1, B2 = elastic.block_preconditioner(L, M, rho, h, nx, nz, dx, dz, surface_node=free)
+            uh, it, _, st = krylov.gmres(lambda v: op(v, L, M, w, dx, dz), lambda v: elastic.apply_Kinv(v, B1, B2),
+                                         f, 1e-13, 30)
+            assert st == OK
+            errs.append(float(np.linalg.norm(uh - ue) / np.linalg.norm(ue)))
+    ratios = [err_free[0] / err_free[1], err_free[1] / err_free[2]]
+    assert all(3.2 < q < 4.8 for q in ratios), (err_free, ratios)
+    assert err_free[2] < 3e-5 and err_dir[2] > 1e3 * err_free[2], (err_free, err_dir)
+
+
+def test_free_surface_elastic_preconditioner_and_gmres():
+    """The surface block preconditioner (the z-systems' first row is the
+    surface row: 2 kz (z_0 - z_1)/dz^2) is the inverse of its 5-point form,
+    and GMRES(10) with it solves the free operator's system (dense solve)."""
+    from oracle import krylov
+    nx, nz, d, h = 12, 10, 5.0, 300.0
+    lam, mu, rho, w = _elastic_free_medium(nx, nz, d, h)
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, h, nx, nz, d, d, surface_node=True)
+    r = np.random.default_rng(8).standard_normal((nz - 1, nx - 1))
+    for B in (B1, B2):
+        Bd = np.column_stack([B.apply(e.reshape(r.shape)).ravel() for e in np.eye(r.size)])
+        ref = np.linalg.solve(Bd, r.ravel()).reshape(r.shape)
+        assert np.max(np.abs(B.solve(r) - ref)) < 1e-12 * np.max(np.abs(ref))
+    b = np.random.default_rng(9).standard_normal((2, nz - 1, nx - 1))
+    shape = b.shape
+    C = np.column_stack([elastic.apply_C_free(e.reshape(shape), lam, mu, w, d, d).ravel() for e in np.eye(b.size)])
+    ref = np.linalg.solve(C, b.ravel()).reshape(shape)
+    x, it, _, st = krylov.gmres(lambda v: elastic.apply_C_free(v, lam, mu, w, d, d),
+                                lambda v: elastic.apply_Kinv(v, B1, B2), b, 1e-12, 10)
+    assert st == OK and np.max(np.abs(x - ref)) < 1e-9 * np.max(np.abs(ref))
