@@ -72,7 +72,16 @@ typedef enum { LG_RICKER = 0, LG_GAUSS_SINE = 1 } lg_wavelet;
  * du/dz = 0 at z = 0 of Sec. 2.1 (eq. boundary_cond), in the form of the
  * paper's staggered mesh (Sec. 2.3), where the first unknown lies half a cell
  * below the surface: no flux crosses the face above the first unknown row
- * (acoustic plans only).  The preconditioner keeps the same face. */
+ * (acoustic plans).  The preconditioner keeps the same face.  Elastic plans
+ * (Cartesian, second order): the traction-free surface tau_xz = sigma_zz = 0
+ * of Sec. 2.2 (eq. boundary_elastic) on the first unknown row (node row 1):
+ * the operator's surface row is the gradient of the discrete strain energy
+ * with a half control strip there (no face above it, a one-sided
+ * z-difference in the mixed terms) divided by that half weight, and the
+ * block preconditioner's z-systems get the surface row
+ * 2 kz (s_0 - s_1)/dz^2 + ... (solved as the Dirichlet Dichotomy result plus
+ * a rank-one term).  A source on the surface row acts on half a control
+ * cell (twice delta_h). */
 typedef enum { LG_TOP_DIRICHLET = 0, LG_TOP_FREE = 1 } lg_top_bc;
 
 /* Geometry.  LG_CARTESIAN: the 2D Cartesian problem, Dirichlet sides (top:

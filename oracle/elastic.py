@@ -247,3 +247,14 @@ def apply_C_free(u: np.ndarray, lam: np.ndarray, mu: np.ndarray, w: np.ndarray,
     gx = Gx[1:-1, 1:-1] + c * w * u[0]
     gz = Gz[1:-1, 1:-1] + c * w * u[1]
     return np.stack([gx / c, gz / c])
+
+
+def source_field_free(shape, src_ij, value: float, dx: float, dz: float) -> np.ndarray:
+    """Vertical point force of strength ``value`` at node ``(i, j)`` of the
+    traction-free problem: ``value / (c_j dx dz)`` on the z component, c_j the
+    row's control-strip weight (a force on the surface row acts on half a
+    cell).  Shape ``(2, Nz-1, Nx-1)``."""
+    out = np.zeros((2,) + tuple(shape))
+    i, j = int(src_ij[0]), int(src_ij[1])
+    out[1, j - 1, i - 1] = value / (surface_weights(shape[0])[j - 1] * dx * dz)
+    return out

@@ -34,6 +34,7 @@ struct ElArgs {
     const T* mu;
     const T* w;     // interior
     int nx1, nz1, S;
+    int free_top;        // traction-free surface on the first unknown row
     T idx2, idz2, ixz;   // 1/dx^2, 1/dz^2, 1/(4 dx dz)
 };
 
@@ -64,6 +65,31 @@ __global__ __launch_bounds__(256) void elastic_stencil_kernel(ElArgs<T> a) {
     const T mE = h * (m0 + Mu(I + 1, J)), mW = h * (m0 + Mu(I - 1, J));
     const T mS = h * (m0 + Mu(I, J + 1)), mN = h * (m0 + Mu(I, J - 1));
     const T cx = U(ux, I, J), cz = U(uz, I, J);
+    const T wv = a.w[pt];
+    T* yo = a.y + s * 2 * npts;
+    if (a.free_top && J == 1) {
+        // Surface row: the gradient of the discrete strain energy divided by
+        // the row's half control strip.  x faces as below; no face above the
+        // surface, the face below counted twice; the node cross terms use the
+        // one-sided z-difference (u(J+1) - u(J))/dz on this row, and the
+        // central one on the row below (whose contribution is halved back).
+        const T t2 = (T)2 * a.ixz;   // 1/(2 dx dz)
+        T fx = (pE * (cx - U(ux, I + 1, J)) + pW * (cx - U(ux, I - 1, J))) * a.idx2 +
+               (T)2 * mS * (cx - U(ux, I, J + 1)) * a.idz2;
+        T fz = (mE * (cz - U(uz, I + 1, J)) + mW * (cz - U(uz, I - 1, J))) * a.idx2 +
+               (T)2 * pS * (cz - U(uz, I, J + 1)) * a.idz2;
+        fx -= (L(I + 1, J) * (U(uz, I + 1, J + 1) - U(uz, I + 1, J)) -
+               L(I - 1, J) * (U(uz, I - 1, J + 1) - U(uz, I - 1, J))) * t2;
+        fx -= (Mu(I, J) * (U(uz, I + 1, J) - U(uz, I - 1, J)) +
+               Mu(I, J + 1) * (U(uz, I + 1, J + 1) - U(uz, I - 1, J + 1))) * t2;
+        fz -= (L(I, J) * (U(ux, I + 1, J) - U(ux, I - 1, J)) +
+               L(I, J + 1) * (U(ux, I + 1, J + 1) - U(ux, I - 1, J + 1))) * t2;
+        fz -= (Mu(I + 1, J) * (U(ux, I + 1, J + 1) - U(ux, I + 1, J)) -
+               Mu(I - 1, J) * (U(ux, I - 1, J + 1) - U(ux, I - 1, J))) * t2;
+        yo[pt] = fx + wv * cx;
+        yo[npts + pt] = fz + wv * cz;
+        return;
+    }
     // diagonal (flux) parts
     T yx = (pE * (cx - U(ux, I + 1, J)) + pW * (cx - U(ux, I - 1, J))) * a.idx2 +
            (mS * (cx - U(ux, I, J + 1)) + mN * (cx - U(ux, I, J - 1))) * a.idz2;
@@ -81,8 +107,6 @@ __global__ __launch_bounds__(256) void elastic_stencil_kernel(ElArgs<T> a) {
     const T ezx_m = U(ux, I + 1, J - 1) - U(ux, I - 1, J - 1);
     // z-equation: -Dzc(l Dxc ux) - Dxc(m Dzc ux)
     yz -= (L(I, J + 1) * ezx_p - L(I, J - 1) * ezx_m + Mu(I + 1, J) * exz_p - Mu(I - 1, J) * exz_m) * a.ixz;
-    const T wv = a.w[pt];
-    T* yo = a.y + s * 2 * npts;
     yo[pt] = yx + wv * cx;
     yo[npts + pt] = yz + wv * cz;
 }
@@ -98,6 +122,7 @@ hipError_t el_stencil_T(lg_plan* p, const T* x, T* y) {
     a.nx1 = p->nx1;
     a.nz1 = p->nz1;
     a.S = p->S;
+    a.free_top = p->el_free ? 1 : 0;
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
     a.ixz = (T)(1.0 / (4.0 * p->g.dx * p->g.dz));
@@ -112,6 +137,51 @@ hipError_t launch_elastic_stencil(lg_plan* p, const void* x, void* y) {
     return el_stencil_T<float>(p, (const float*)x, (float*)y);
 }
 
+// Traction-free surface rows of the preconditioner (the rank-one term on the
+// Dirichlet solution y of block blk): coef = y(row 1) / (1 - g_k(1)), then
+// y += coef g_k on every row.
+template <typename T>
+__global__ __launch_bounds__(256) void surface_coef_kernel(const T* __restrict__ y, const double* __restrict__ t,
+                                                           double* __restrict__ coef, int nx1, size_t npts,
+                                                           int nfields, int fstride, int foff) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)nfields * nx1) return;
+    const size_t f = (e / nx1) * fstride + foff;
+    const int k = (int)(e % nx1);
+    coef[f * nx1 + k] = (double)y[f * npts + nx1 + k] * t[k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void surface_apply_kernel(T* __restrict__ y, const T* __restrict__ g,
+                                                            const double* __restrict__ coef, int nx1, size_t npts,
+                                                            size_t total, int fstride, int foff) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= total) return;
+    const size_t f = (e / npts) * fstride + foff;
+    const size_t pt = e % npts;
+    const int k = (int)(pt % nx1);
+    y[f * npts + pt] += (T)coef[f * nx1 + k] * g[pt];
+}
+
+template <typename T>
+hipError_t surface_rows_T(lg_plan* p, int blk, T* y, int nfields, int fstride, int foff) {
+    const unsigned gc = (unsigned)(((size_t)nfields * p->nx1 + 255) / 256);
+    hipLaunchKernelGGL(surface_coef_kernel<T>, dim3(gc), dim3(256), 0, p->stream, y, p->es_t[blk], p->sm_c, p->nx1,
+                       p->npts, nfields, fstride, foff);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const size_t total = (size_t)nfields * p->npts;
+    hipLaunchKernelGGL(surface_apply_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, p->stream, y,
+                       (const T*)p->es_g[blk], p->sm_c, p->nx1, p->npts, total, fstride, foff);
+    return hipGetLastError();
+}
+
+hipError_t launch_surface_rows(lg_plan* p, int blk, void* y, int nfields, int fstride, int foff) {
+    if (!p->el_free || p->nz1 < 2) return hipSuccess;   // one row: the surface row has no neighbour
+    if (p->prec == LG_FP64) return surface_rows_T<double>(p, blk, (double*)y, nfields, fstride, foff);
+    return surface_rows_T<float>(p, blk, (float*)y, nfields, fstride, foff);
+}
+
 // K^{-1} = diag(B1^{-1}, B2^{-1}) on working-type vectors [S][2][..]; uses the
 // plan's spectral buffers rhat and y.
 hipError_t launch_elastic_precond(lg_plan* p, const void* r, void* z) {
@@ -121,6 +191,7 @@ hipError_t launch_elastic_precond(lg_plan* p, const void* r, void* z) {
         e = launch_td(p, c, p->rhat, p->y, S, 0, 2, c);
         if (e == hipSuccess && p->blk[c].P > 1) e = launch_rs(p, c, p->rhat, p->y, S, 0, 2, c);
         if (e == hipSuccess && p->blk[c].P > 1) e = launch_correct(p, c, p->y, S, 2, c);
+        if (e == hipSuccess) e = launch_surface_rows(p, c, p->y, S, 2, c);
     }
     if (e == hipSuccess) e = launch_dst(p, 1, p->y, z, S * 2);
     return e;

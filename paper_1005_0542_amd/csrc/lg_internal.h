@@ -87,6 +87,14 @@ struct lg_plan {
     void* sm_g = nullptr;      // [nz-1][nx-1] working type: g_k(j)
     double* sm_t = nullptr;    // [2][nx-1]: 1 / (1 - g_k(0)), u_{Ls-1}(k)
     double* sm_c = nullptr;    // [fields][nx-1]: coef_k of the current solve
+    // Elastic traction-free surface on the first unknown row: the operator's
+    // surface row comes from the discrete strain energy (half control strip),
+    // and each block's z-systems have the surface row 2 kz (s_0 - s_1)/dz^2,
+    // i.e. T - b e1 e2^T, solved as the Dirichlet result plus the rank-one
+    // term g_k s_1 / (1 - g_k(1)) with g_k = T_k^{-1} e1 (normalised).
+    bool el_free = false;
+    void* es_g[2] = {nullptr, nullptr};     // per block: [nz-1][nx-1] working type, g_k(j)
+    double* es_t[2] = {nullptr, nullptr};   // per block: [nx-1], 1 / (1 - g_k(1))
     // 2.5D axisymmetric plans (geometry LG_CYLINDRICAL): fields are
     // [Nr-1][Nz] with z fastest (nx1 = Nz, nz1 = Nr - 1); cosine transform
     // along z, non-Toeplitz r-systems solved by Thomas per wavenumber.
@@ -232,5 +240,8 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                       lg_solve_info* info);
 hipError_t launch_elastic_stencil(lg_plan* p, const void* x, void* y);
 hipError_t launch_elastic_precond(lg_plan* p, const void* r, void* z);
+// elastic traction-free surface: the rank-one surface-row term on the
+// Dirichlet Dichotomy solution of block blk (fields f * fstride + foff)
+hipError_t launch_surface_rows(lg_plan* p, int blk, void* y, int nfields, int fstride, int foff);
 
 }  // namespace lg

@@ -1483,7 +1483,8 @@ hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double
             const int i = p->src_host[2 * s], j = p->src_host[2 * s + 1];
             const int comp = p->C - 1;   // acoustic: 0; elastic: z component
             sa.idx[t] = (int64_t)(((size_t)s * p->C + comp) * p->npts + (size_t)(j - 1) * p->nx1 + (i - 1));
-            sa.val[t] = fsrc_host[s] * inv;
+            // a point force on the elastic surface row acts on half a control cell
+            sa.val[t] = fsrc_host[s] * inv * ((p->el_free && j == 1) ? 2.0 : 1.0);
         }
         hipLaunchKernelGGL(src_kernel, dim3(1), dim3(SRC_CHUNK), 0, p->stream, sa, rhs);
         e = hipGetLastError();

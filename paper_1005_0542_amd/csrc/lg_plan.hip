@@ -151,6 +151,34 @@ lg_status prepare_free_surface(lg_plan* pl, const PrecBlock& B) {
     return dev_alloc(pl, &pl->sm_c, (size_t)pl->S * pl->C * nx1 * 8);
 }
 
+// Elastic traction-free surface tables of block c: with the surface on the
+// first unknown row the normalised z-system becomes T_k - e1 e2^T (the
+// surface row reads theta s_0 - 2 s_1).  Sherman-Morrison:
+// (T - e1 e2^T)^{-1} r = y + g (e2^T y) / (1 - g_1), y = T^{-1} r,
+// g = T^{-1} e1; g (all rows) and 1 / (1 - g_1) in long double.
+lg_status prepare_surface_rows(lg_plan* pl, const PrecBlock& B, int c) {
+    const int nx = pl->g.nx, nx1 = pl->nx1, nz1 = pl->nz1;
+    const long double dx = pl->g.dx, dz = pl->g.dz;
+    const long double pi = 3.141592653589793238462643383279502884L;
+    std::vector<double> g((size_t)nz1 * nx1), t(nx1);
+    std::vector<long double> col;
+    for (int kk = 0; kk < nx1; ++kk) {
+        const long double s = std::sin(pi * (kk + 1) / (2.0L * nx));
+        const long double mu = 4.0L / (dx * dx) * s * s;
+        const long double diag = 2.0L * B.kz / (dz * dz) + (long double)B.kx * mu + (long double)B.d;
+        const long double theta = diag / ((long double)B.kz / (dz * dz));
+        toeplitz_unit_solve(theta, 1.0L, nz1, 0, col);
+        for (int j = 0; j < nz1; ++j) g[(size_t)j * nx1 + kk] = (double)col[j];
+        t[kk] = nz1 >= 2 ? (double)(1.0L / (1.0L - col[1])) : 0.0;
+    }
+    lg_status st = upload_working(pl, &pl->es_g[c], g);
+    if (st != LG_OK) return st;
+    st = dev_alloc(pl, &pl->es_t[c], (size_t)nx1 * 8);
+    if (st != LG_OK) return st;
+    LG_HIP(hipMemcpy(pl->es_t[c], t.data(), (size_t)nx1 * 8, hipMemcpyHostToDevice));
+    return LG_OK;
+}
+
 // 2.5D axisymmetric tables (Sec. 2.3, eq. precond1).  kap: node kappa
 // [Nr][Nz].  Operator faces: a1 = rbar_j kappa_face / h_r^2 between rows j
 // and j+1 (rbar_j = (j+1) h_r; the last face borders the Dirichlet row),
@@ -407,7 +435,7 @@ void free_plan(lg_plan* p) {
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
                     p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64,
-                    p->cy_UV, p->cy_cpl64, p->cy_red,
+                    p->cy_UV, p->cy_cpl64, p->cy_red, p->es_g[0], p->es_g[1], p->es_t[0], p->es_t[1],
                     p->ho_kx, p->ho_kz, p->ho_kx64, p->ho_kz64};
     for (void* q : ptrs)
         if (q) (void)hipFree(q);
@@ -560,13 +588,15 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         return fail(LG_ERR_UNSUPPORTED, "nx and nz must be powers of two <= 4096");
     if (grid->top_bc != LG_TOP_DIRICHLET && grid->top_bc != LG_TOP_FREE)
         return fail(LG_ERR_INVALID_ARG, "top_bc must be LG_TOP_DIRICHLET or LG_TOP_FREE");
-    if (grid->top_bc == LG_TOP_FREE && kind != LG_ACOUSTIC)
-        return fail(LG_ERR_UNSUPPORTED, "the free surface is implemented for acoustic plans");
+
     if (grid->geometry != LG_CARTESIAN && grid->geometry != LG_CYLINDRICAL)
         return fail(LG_ERR_INVALID_ARG, "geometry must be LG_CARTESIAN or LG_CYLINDRICAL");
     const bool cyl = grid->geometry == LG_CYLINDRICAL;
     if (cyl && kind != LG_ACOUSTIC)
         return fail(LG_ERR_UNSUPPORTED, "the axisymmetric geometry is implemented for acoustic plans");
+    if (grid->top_bc == LG_TOP_FREE && kind == LG_ELASTIC && (cyl || (grid->order != 0 && grid->order != 2)))
+        return fail(LG_ERR_UNSUPPORTED, "the elastic traction-free surface is implemented for Cartesian "
+                                        "second-order plans");
     if (grid->order != 0 && grid->order != 2 && grid->order != 4)
         return fail(LG_ERR_INVALID_ARG, "order must be 0, 2 or 4");
     if (grid->reserved != 0) return fail(LG_ERR_INVALID_ARG, "lg_grid.reserved must be 0");
@@ -634,7 +664,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->td_spw = spw;
     p->order = order;
     p->fuse_op = (fus == 1) && order == 2;
-    p->free_top = (grid->top_bc == LG_TOP_FREE) && !cyl;
+    p->free_top = (grid->top_bc == LG_TOP_FREE) && !cyl && kind == LG_ACOUSTIC;
+    p->el_free = (grid->top_bc == LG_TOP_FREE) && kind == LG_ELASTIC;
     p->src_scale = cyl ? 1.0 / (2.0 * 3.141592653589793 * grid->dx * grid->dz) : 1.0 / (grid->dx * grid->dz);
     p->device = dev;
     p->stream = (hipStream_t)hip_stream;
@@ -718,6 +749,11 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
             return bail(st);
         if ((st = prepare_block(p, p->blk[1], p->mu_t, p->lp2m_t, p->rho_t * hh4, P)) != LG_OK)
             return bail(st);
+        if (p->el_free) {
+            for (int c = 0; c < 2; ++c)
+                if ((st = prepare_surface_rows(p, p->blk[c], c)) != LG_OK) return bail(st);
+            if ((st = dev_alloc(p, &p->sm_c, (size_t)p->S * p->C * p->nx1 * 8)) != LG_OK) return bail(st);
+        }
     }
 
     // FFT twiddles for length M = 2 nx
@@ -938,6 +974,7 @@ lg_status lg_precond_dichotomy_tdma(lg_plan* plan, int32_t block, const void* rh
         LG_HIP(launch_rs(plan, bi, rhs_hat, sol_hat, nf, 0));
         LG_HIP(launch_correct(plan, bi, sol_hat, nf));
     }
+    if (plan->el_free) LG_HIP(launch_surface_rows(plan, bi, sol_hat, nf, 1, 0));
     return LG_OK;
 }
 

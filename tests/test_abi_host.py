@@ -83,8 +83,10 @@ def test_plan_create_rejects_nonfinite_medium():
 def test_plan_create_unsupported_shapes():
     assert _create(nx=24, nz=16) == _lib.LG_ERR_UNSUPPORTED
     assert _create(nx=8192, nz=16) == _lib.LG_ERR_UNSUPPORTED
-    # the free surface is implemented for acoustic plans only
-    assert _create(kind=_lib.LG_ELASTIC, top=_lib.LG_TOP_FREE) == _lib.LG_ERR_UNSUPPORTED
+    # the elastic traction-free surface: Cartesian second-order plans only
+    assert _create(kind=_lib.LG_ELASTIC, top=_lib.LG_TOP_FREE, order=4) == _lib.LG_ERR_UNSUPPORTED
+    assert _create(kind=_lib.LG_ELASTIC, top=_lib.LG_TOP_FREE, geometry=_lib.LG_CYLINDRICAL) == \
+        _lib.LG_ERR_UNSUPPORTED
     # the axisymmetric geometry: acoustic plans, unsegmented r-systems
     cyl = _lib.LG_CYLINDRICAL
     assert _create(kind=_lib.LG_ELASTIC, geometry=cyl) == _lib.LG_ERR_UNSUPPORTED
