@@ -229,7 +229,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     return out
 
 
-def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10):
+def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10, shots=None, top="dirichlet"):
     """Elastic harmonics (GMRES(k) per harmonic) timed like the acoustic ones;
     reported with the time of one GMRES(k) cycle (k inner iterations), the
     unit of the paper's Table 2."""
@@ -238,8 +238,9 @@ def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10):
     from paper_1005_0542_amd.driver import ElasticRun
 
     w = inputs.WORKLOADS[name]
-    log(f"{name}: GMRES({restart}) harmonics={warmup + steps}")
-    run = ElasticRun(w, n_harm=warmup + steps, restart=restart)
+    S = shots or w.shots
+    log(f"{name}: GMRES({restart}) harmonics={warmup + steps} shots={S} top={top}")
+    run = ElasticRun(w, n_harm=warmup + steps, restart=restart, shots=S, top=top)
     for _ in range(warmup):
         run.step()
     torch.cuda.synchronize()
@@ -250,10 +251,15 @@ def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10):
     torch.cuda.synchronize()
     el = time.perf_counter() - t
     npts = 2 * (w.n_cells - 1) ** 2
-    return {"workload": name, "precision": "fp64", "shots": 1, "restart": restart,
-            "value": npts * sum(its) / el / 1e6, "unit": "Mpoint-iters/s (GMRES inner iterations, 2 components)",
-            "ms_per_step": 1e3 * el / steps, "inner_iters_per_harmonic": its,
-            "ms_per_gmres_cycle": 1e3 * el / (sum(its) / restart)}
+    out = {"workload": name, "precision": "fp64", "shots": S, "top": top, "restart": restart,
+           "value": npts * S * sum(its) / el / 1e6,
+           "unit": "Mpoint-iters/s (GMRES inner iterations, 2 components)",
+           "ms_per_step": 1e3 * el / steps, "inner_iters_per_harmonic": its,
+           "ms_per_gmres_cycle": 1e3 * el / (sum(its) / restart)}
+    run.plan.destroy()
+    del run
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(name, k_lo=2, k_hi=12):
@@ -291,6 +297,85 @@ def cpu_baseline(name, k_lo=2, k_hi=12):
     }
 
 
+def parity_leg(name, tuned, samples=(0, 63), n_harm=3):
+    """Error of the benchmarked path against the FP64 oracle, outside every
+    timed region: the workload's first harmonics in its own precision and
+    launch configuration, sampled shots against the oracle's own chains
+    (tolerance 1e-10), per harmonic and on the partial snapshots."""
+    import torch
+    from paper_1005_0542_amd import inputs
+    from paper_1005_0542_amd.driver import AcousticRun
+    from oracle import harmonics, krylov, laguerre, operator, precond
+
+    w = inputs.WORKLOADS[name]
+    samples = tuple(s for s in samples if s < w.shots)
+    run = AcousticRun(w, n_harm=n_harm, snapshots=True, rec=False,
+                      **{k: tuned.get(k, 0) for k in ("segments", "graph_iters", "op_shots", "seg_per_wave",
+                                                      "op_fusion")})
+    got = {s: [] for s in samples}
+    for _ in range(n_harm):
+        run.step()
+        for s in samples:
+            got[s].append(run.R[s, 0].cpu().numpy())
+    snap = run.snap.cpu().numpy()
+    kappa, rho = run.kappa, run.rho
+    run.plan.destroy()
+    del run
+    torch.cuda.empty_cache()
+    N, d = w.n_cells, w.d
+    wv = operator.shift_coeff(rho, w.h)
+    B = precond.acoustic_preconditioner(kappa, rho, w.h, N, N, d, d)
+    solve = lambda phi: krylov.pcg(lambda y: operator.apply_A(y, kappa, wv, d, d), B.solve, phi, 1e-10, 10000)
+    f_m = laguerre.ricker_coeffs(w.f0, w.t0, w.h, w.alpha, n_harm)
+    Wsn = laguerre.synthesis_weights(np.array(inputs.snapshot_times(w)), w.h, w.alpha, n_harm)
+    l2 = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    per_shot = {}
+    for s in samples:
+        st = harmonics.harmonic_loop(n_harm, solve, rho[1:-1, 1:-1], w.h, w.alpha, f_m, inputs.sources_for(w)[s],
+                                     d, d, snap_w=Wsn, keep_all=True)
+        per_shot[str(s)] = {"R_rel_l2": [float("%.3g" % l2(got[s][m], st["R"][m])) for m in range(n_harm)],
+                            "snapshots_rel_l2": float("%.3g" % l2(snap[:, s, 0], st["snap"]))}
+    worst = max(max(v["R_rel_l2"] + [v["snapshots_rel_l2"]]) for v in per_shot.values())
+    return {"vs": "FP64 oracle chain (tol 1e-10)", "workload": name, "precision": w.precision,
+            "harmonics": n_harm, "shots": list(samples), "per_shot": per_shot, "worst_rel_l2": worst,
+            "bar": 1e-6 if w.precision == "mixed" else 1e-12}
+
+
+def time_to_solution(name, tuned):
+    """One whole run of a workload: all its harmonics (right-hand side, PCG,
+    synthesis of the 4 snapshots and the receiver row), then the receiver
+    traces at 1 ms, timed end to end after the plan is set up."""
+    import torch
+    from paper_1005_0542_amd import inputs
+    from paper_1005_0542_amd.driver import AcousticRun
+
+    w = inputs.WORKLOADS[name]
+    t0 = time.perf_counter()
+    run = AcousticRun(w, **{k: tuned.get(k, 0) for k in ("segments", "graph_iters", "op_shots", "seg_per_wave",
+                                                         "op_fusion")})
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    log(f"{name}: time to solution over {w.n_harm} harmonics")
+    t1 = time.perf_counter()
+    its = []
+    for _ in range(w.n_harm):
+        its.append(run.step().iters)
+    tr = run.traces(inputs.trace_times(w))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    npts = (w.n_cells - 1) ** 2
+    total = int(np.sum(its))
+    out = {"harmonics": w.n_harm, "shots": w.shots, "seconds": round(el, 3), "setup_s": round(setup, 3),
+           "ms_per_harmonic": round(1e3 * el / w.n_harm, 3), "cg_iterations_summed_over_shots": total,
+           "mean_iters": round(total / (w.n_harm * w.shots), 2),
+           "Mpoint_iters_per_s": round(npts * total / el / 1e6, 1),
+           "statuses_ok": bool(all(s == 0 for s in run.status)), "traces": list(tr.shape)}
+    run.plan.destroy()
+    del run, tr
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +384,8 @@ def main():
     ap.add_argument("--workload", default="acoustic2048x64_mixed")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true", help="skip the error-vs-oracle leg")
+    ap.add_argument("--no-tts", action="store_true", help="skip the whole-run time-to-solution leg")
     ap.add_argument("--segments", type=int, default=0)
     ap.add_argument("--graph-iters", type=int, default=0)
     ap.add_argument("--profile-only", action="store_true",
@@ -310,6 +397,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="time a plain device copy of MIB MiB (counter calibration) and exit")
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuned tiles")
+    ap.add_argument("--elastic-only", action="store_true",
+                    help="only the elastic GMRES(10) harmonics (for kernel traces of the elastic path)")
     ap.add_argument("--op-shots", type=int, default=0, help="override (profile-only)")
     ap.add_argument("--seg-per-wave", type=int, default=0, help="override (profile-only)")
     ap.add_argument("--op-fusion", type=int, default=0, help="override (profile-only): 1 fused, 2 stored q")
@@ -338,6 +427,9 @@ def main():
         return
     prec = args.precision or w.precision
     shots = args.shots or w.shots
+    if args.elastic_only:
+        print(json.dumps(run_elastic(steps=args.steps, warmup=args.warmup, shots=args.shots)))
+        return
     if args.profile_only:
         # the benchmark's own path on two harmonics (one untimed), then the
         # per-kernel profile: a kernel trace of this mode ends with exactly
@@ -391,9 +483,20 @@ def main():
             variants[key]["kernels_GBps"] = {k: round(x["GBps"], 1) for k, x in v["kernels"].items()}
             torch.cuda.empty_cache()
         variants["elastic_gmres10_1024"] = run_elastic()
+        variants["elastic_gmres10_1024_free_surface"] = run_elastic(top="free")
+        variants["elastic_gmres10_1024_x8"] = run_elastic(shots=8)
         torch.cuda.empty_cache()
         fp64_1 = variants["fp64_1shot_4096"]["value"]
         variants["speedup_mixed64_vs_fp64_1shot_per_iteration"] = head["value"] / fp64_1
+        # time per harmonic for the same work (every shot-point solved to its
+        # tolerance, restart iterations included): mixed 64-shot batch against
+        # the FP64 64-shot batch, and per shot-point against FP64 single-shot
+        f64b = variants["fp64_64shot_2048"]
+        variants["speedup_mixed64_vs_fp64_64shot_time_per_harmonic"] = f64b["ms_per_step"] / head["ms_per_step"]
+        pts_head = shots * (w.n_cells - 1) ** 2
+        pts_4096 = (inputs.WORKLOADS["acoustic4096_mixed"].n_cells - 1) ** 2
+        variants["speedup_mixed64_vs_fp64_1shot_time_per_shot_point_harmonic"] = \
+            (variants["fp64_1shot_4096"]["ms_per_step"] / pts_4096) / (head["ms_per_step"] / pts_head)
 
     dom = head["dominant"]
     kd = head["kernels"][dom]
@@ -408,9 +511,26 @@ def main():
             "per_kernel_GBps": {k: round(x["GBps"], 1) for k, x in head["kernels"].items()},
             "per_kernel_ms": {k: round(x["avg_ms"], 4) for k, x in head["kernels"].items()},
             "whole_iteration_GBps": round(head["whole_iteration_GBps"], 1),
+            # solver level: one whole iteration's algorithmic bytes over the
+            # timed harmonic (per-harmonic work and masked replays included)
+            "whole_iteration_frac": round(head["whole_iteration_GBps"] / HBM_PEAK_GBS, 4),
+            "profiled_iteration_frac": round(sum(x["alg_bytes"] for x in head["kernels"].values()) /
+                                             (head["iteration_ms_profiled"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "copy_probe_GBps": round(copy_gbps, 1),
             "frac_of_copy_probe": round(achieved / copy_gbps, 4),
             "alg_bytes_per_point_iter": round(head["alg_bytes_per_point_iter"], 2)}
+    tts = {}
+    if not args.no_tts:
+        for name in (args.workload, "acoustic4096_mixed"):
+            if name in tts:
+                continue
+            wn = inputs.WORKLOADS[name]
+            tp = head_tuned if name == args.workload else tuned_params(name, wn.precision, wn.shots, not args.no_tune)
+            tts[name] = time_to_solution(name, tp)
+    parity = None
+    if not args.no_parity:
+        log("parity leg (oracle chains of sampled shots)")
+        parity = parity_leg(args.workload, head_tuned)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -430,6 +550,8 @@ def main():
         "setup_s": round(head["setup_s"], 3),
         "roofline": roof,
         "cpu_baseline": cpu,
+        "parity": parity,
+        "time_to_solution": tts,
         "variants": variants,
     }
     print(json.dumps(line), flush=True)

@@ -135,11 +135,12 @@ class ElasticRun:
     """The elastic harmonic loop on one GPU (eq. elastic_problemQn): for each
     harmonic the right-hand side from the running sums of both displacement
     components, right-preconditioned GMRES(k) with K = diag(B1, B2), and the
-    synthesis.  Vectors are [shots][2][nz-1][nx-1] (u_x, u_z)."""
+    synthesis.  Vectors are [shots][2][nz-1][nx-1] (u_x, u_z).  ``top="free"``:
+    the traction-free surface on the first unknown row (Sec. 2.2)."""
 
     def __init__(self, w: inputs.Workload, shots: Optional[int] = None, n_harm: Optional[int] = None,
                  restart: int = 10, tol: Optional[float] = None, max_iter: int = 10000, snapshots: bool = True,
-                 rec: bool = True, segments: int = 0):
+                 rec: bool = True, segments: int = 0, top: str = "dirichlet"):
         import torch
         self.torch = torch
         self.w = w
@@ -152,7 +153,7 @@ class ElasticRun:
         lam, mu, rho = inputs.elastic_medium_for(w)
         self.lam, self.mu, self.rho = lam, mu, rho
         self.plan = api.Plan("elastic", N, N, w.d, w.d, w.alpha, w.h, self.n_harm, np.stack([lam, mu, rho]),
-                             precision="fp64", nshots=self.shots, segments=segments)
+                             precision="fp64", nshots=self.shots, segments=segments, top=top)
         src = inputs.sources_for(w) if self.shots == w.shots else \
             inputs.shot_positions(N, self.shots, w.shot_seed, w.src_row)
         self.src = src
