@@ -126,8 +126,9 @@ __device__ __forceinline__ void make_twiddles(const cpx<T>* __restrict__ tw, int
 // Stockham passes (LDS -> LDS) of span Ns .. NS_LAST/R, radix R, one
 // butterfly per thread: read -> barrier -> twiddle + DFT -> write -> barrier
 // (no twiddles for the span-1 pass).  The last pass is fft_last.  All threads
-// of the block must call this.
-template <typename T, int M, int R, int Ns>
+// of the block must call this.  tw[TS j] = exp(-2 pi i j / M): a table of
+// TS M entries serves a transform of length M with stride TS.
+template <typename T, int M, int R, int Ns, int TS = 1>
 __device__ __forceinline__ void fft_mid(cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw, int t) {
     if constexpr (Ns < FftPlan<M, R>::NS_LAST) {
         cpx<T> v[R];
@@ -137,7 +138,7 @@ __device__ __forceinline__ void fft_mid(cpx<T>* __restrict__ buf, const cpx<T>* 
         const int k = t & (Ns - 1);
         if constexpr (Ns > 1) {
             cpx<T> w[R];
-            make_twiddles<T, R>(tw, k * (M / (Ns * R)), w);
+            make_twiddles<T, R>(tw, TS * k * (M / (Ns * R)), w);
 #pragma unroll
             for (int u = 1; u < R; ++u) v[u] = cmul(v[u], w[u]);
         }
@@ -146,13 +147,13 @@ __device__ __forceinline__ void fft_mid(cpx<T>* __restrict__ buf, const cpx<T>* 
 #pragma unroll
         for (int u = 0; u < R; ++u) buf[lpad(base + u * Ns)] = v[u];
         __syncthreads();
-        fft_mid<T, M, R, Ns * R>(buf, tw, t);
+        fft_mid<T, M, R, Ns * R, TS>(buf, tw, t);
     }
 }
 
 // Last Stockham pass (span NS_LAST, radix R_LAST): reads LDS, leaves the
 // results in registers: v[qb*R_LAST + u] is output K = t + qb*(M/R) + u*NS_LAST.
-template <typename T, int M, int R>
+template <typename T, int M, int R, int TS = 1>
 __device__ __forceinline__ void fft_last(const cpx<T>* __restrict__ buf, const cpx<T>* __restrict__ tw,
                                          int t, cpx<T>* v) {
     using FP = FftPlan<M, R>;
@@ -165,7 +166,7 @@ __device__ __forceinline__ void fft_last(const cpx<T>* __restrict__ buf, const c
     for (int qb = 0; qb < NB; ++qb) {
         const int k = t + qb * TPF;               // < Ns: the twiddle index is k itself
         cpx<T> w[r];
-        make_twiddles<T, r>(tw, k, w);
+        make_twiddles<T, r>(tw, TS * k, w);
 #pragma unroll
         for (int u = 1; u < r; ++u) v[qb * r + u] = cmul(v[qb * r + u], w[u]);
         dft<T, r>(&v[qb * r]);

@@ -179,6 +179,11 @@ namespace lg {
 // element size of the working type
 inline size_t wsize(const lg_plan* p) { return p->prec == LG_FP64 ? 8 : 4; }
 
+// The row DST-I of nx-cell rows runs as one complex FFT of length nx per row
+// pair (with a pre- and post-pass) where the 2 nx-point odd extension would
+// take more than 32 KB of LDS per row pair, else as the 2 nx-point transform.
+constexpr bool dst_half_form(int nx, int ws) { return 2 * nx * 2 * ws > 32768; }
+
 // launchers (implemented in lg_acoustic.hip); all enqueue on plan->stream
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq);
 hipError_t launch_dst(lg_plan* p, int inverse, const void* in, void* out, int nfields);

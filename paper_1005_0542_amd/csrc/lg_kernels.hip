@@ -176,11 +176,26 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
 
 // ===========================================================================
 // K2 / K5 and the plain transform: row-wise DST-I along x (Sec. 2.4,
-// variable separation).  Two rows (j0, j1) of one field are packed as the
-// real and imaginary parts of one complex sequence, odd-extended to length
-// M = 2 nx (w_0 = w_nx = 0, w_{M-i} = -w_i); its forward DFT is
-// V_k = -2i X_k(row j0) + 2 X_k(row j1), so the two DST-I results are
-// X(j0) = -Im V / 2, X(j1) = Re V / 2 for k = 1..nx-1.
+// variable separation), F_k = sum_{j=1}^{N-1} f_j sin(pi j k / N), N = nx, by
+// one complex FFT of length N per pair of rows.  The two rows (j0, j1) of a
+// field are packed as the real and imaginary parts of f (f_0 = 0).  A
+// pre-pass forms y_j = sin(pi j/N)(f_j + f_{N-j}) + (f_j - f_{N-j})/2
+// (y_0 = 0), whose DFT Y (of each real row) gives the even outputs
+// F_{2k} = -Im Y_k and the odd ones by a prefix sum, F_{2k+1} =
+// F_{2k-1} + Re Y_k with F_1 = Re Y_0 / 2 (the real-odd symmetry that a
+// 2N-point transform of the odd extension would carry twice; the method is
+// the classical one of Numerical Recipes' sinft).  With Z = DFT(y) of the
+// packed rows, row j0 takes Y_k = (Z_k + conj Z_{N-k})/2 and row j1
+// Y_k = (Z_k - conj Z_{N-k})/(2i).  The prefix sum runs over the thread's
+// own k, then over the transform's threads (wave shuffles, and the waves'
+// totals through LDS).
+// The other form (HALF = false) odd-extends the packed rows to length
+// M = 2N (w_0 = w_N = 0, w_{M-i} = -w_i), whose DFT is V_k = -2i F_k(j0) +
+// 2 F_k(j1): no pre- or post-pass, twice the butterflies and the LDS.  The
+// N-point form is used where a 2N-point row pair would take more than 32 KB
+// of LDS (FP64 from nx = 2048, FP32 from nx = 4096), which otherwise caps the
+// blocks per CU; below that the 2N-point form measured faster (fewer passes
+// over LDS and barriers in the CG update, the same correction time).
 // ===========================================================================
 // DST_UPDATE_OP is DST_UPDATE with A p recomputed from p and the medium
 // instead of read from a stored q.  DST_RESTART (mixed precision) forms the
@@ -257,25 +272,30 @@ __device__ __forceinline__ void apply_pair(rsrc_t rP, const T* __restrict__ kap,
 }
 
 // Phase A: each row element x_i (i = t + it TPF) is loaded once by its
-// thread, which writes it to LDS at both odd-extension positions 1+i and
-// M-1-i.  The Stockham passes then run LDS -> LDS, except the last pass,
-// which leaves its outputs in registers; they are stored straight to global
-// memory (coalesced: output K = t + qb M/R + u NS_LAST).
+// thread, which writes it to LDS at position 1+i.  The pre-pass pairs j with
+// N-j in LDS; the Stockham passes run LDS -> LDS, except the last pass,
+// which leaves its outputs in registers; they go back to LDS for the
+// post-pass (pairs k, N-k and the prefix sum), whose results are stored to
+// global memory from LDS in coalesced order (column t + u TPF).
 // The update modes get a waves-per-EU bound of 3: the register room keeps
 // more of their loads in flight (measured 1.8 % faster at 64 shots 2048^2).
-template <typename T, int M, int R, int FPB, int MODE>
+template <typename T, int M, int R, int FPB, int MODE, bool HALF>
 __global__ __launch_bounds__(FPB*(M / R)) __attribute__((amdgpu_waves_per_eu(
     1, (MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART) ? 3 : 8))) void
 dst_kernel(DstArgs<T> a) {
     using FP = FftPlan<M, R>;
     constexpr int TPF = M / R;
-    constexpr int NX = M / 2;
+    constexpr int NX = HALF ? M : M / 2;       // nx: the FFT length is nx (HALF) or 2 nx
     constexpr int NX1 = NX - 1;
+    constexpr int NH = NX / 2;                 // post-pass: k = 0 .. NH-1
+    constexpr int CK = HALF ? NH / TPF : 1;    // consecutive k per thread (R / 2)
     constexpr int RL = FP::R_LAST, NBL = FP::NB_LAST, NSL = FP::NS_LAST;
-    constexpr int NOUT = NBL * (RL / 2);       // first-half outputs per thread
     constexpr int LL = LdsLen<M>::value;
     constexpr int NWAVE = (FPB * TPF + 63) / 64;
     constexpr int NIT = (NX1 + TPF - 1) / TPF;
+    // outputs per thread: columns t + u TPF (HALF), or the first-half spectrum
+    // entries K = t + qb M/R + u NS_LAST of the last pass (2N form)
+    constexpr int NOUT = HALF ? NIT : NBL * (RL / 2);
     // loads per chunk of phase A (all in flight together): the FP32 correction
     // takes every element of the row pair at once
     constexpr int CHMAX = (MODE == DST_UPDATE_OP && sizeof(T) == 8) ? 2 : (MODE == DST_CORRECT && sizeof(T) == 4) ? 8 : 4;
@@ -283,6 +303,7 @@ dst_kernel(DstArgs<T> a) {
     constexpr bool UPD = MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART;
     __shared__ cpx<T> lds[FPB * LL];
     __shared__ double red[NWAVE];
+    __shared__ cpx<T> wtot[NWAVE];             // per-wave totals of the prefix sum
 
     const int fid = threadIdx.x / TPF;
     const int t = threadIdx.x - fid * TPF;
@@ -356,7 +377,7 @@ dst_kernel(DstArgs<T> a) {
                     bb += b0[u] * b0[u] + b1[u] * b1[u];
                     if (cb + u < NIT && i < NX1) {
                         buf[lpad(1 + i)] = {(T)ra, (T)rb};
-                        buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
+                        if constexpr (!HALF) buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
                     }
                 }
             }
@@ -431,7 +452,7 @@ dst_kernel(DstArgs<T> a) {
                     rr += ra * ra + rb * rb;
                     if (cb + u < NIT && i < NX1) {
                         buf[lpad(1 + i)] = {(T)ra, (T)rb};
-                        buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
+                        if constexpr (!HALF) buf[lpad(M - 1 - i)] = {(T)-ra, (T)-rb};
                     }
                 }
             }
@@ -504,22 +525,19 @@ dst_kernel(DstArgs<T> a) {
                     const int i = t + (cb + u) * TPF;
                     if (cb + u < NIT && i < NX1) {
                         buf[lpad(1 + i)] = {v0[u], v1[u]};
-                        buf[lpad(M - 1 - i)] = {-v0[u], -v1[u]};
+                        if constexpr (!HALF) buf[lpad(M - 1 - i)] = {-v0[u], -v1[u]};
                     }
                 }
             }
             // p of the outputs this thread will write (read now, used after the FFT)
             const rsrc_t rPo = buf_rsrc(a.out + fbase, a.init ? 0u : nfe * SZ);
 #pragma unroll
-            for (int qb = 0; qb < NBL; ++qb)
-#pragma unroll
-                for (int u = 0; u < RL / 2; ++u) {
-                    const int K = t + qb * TPF + u * NSL;
-                    const int oi = qb * (RL / 2) + u;
-                    const bool ok = K >= 1 && K <= NX1;
-                    pold0[oi] = bload<T>(rPo, ok ? (uint32_t)(j0 * NX1 + K - 1) * SZ : BUF_OOB);
-                    pold1[oi] = bload<T>(rPo, (ok && has1) ? (uint32_t)(j1 * NX1 + K - 1) * SZ : BUF_OOB);
-                }
+            for (int u = 0; u < NOUT; ++u) {
+                const int col = HALF ? t + u * TPF : t + (u / (RL / 2)) * TPF + (u % (RL / 2)) * NSL - 1;
+                const bool ok = col >= 0 && col < NX1;
+                pold0[u] = bload<T>(rPo, ok ? (uint32_t)(j0 * NX1 + col) * SZ : BUF_OOB);
+                pold1[u] = bload<T>(rPo, (ok && has1) ? (uint32_t)(j1 * NX1 + col) * SZ : BUF_OOB);
+            }
         } else {
             const rsrc_t rI = buf_rsrc(a.in + fbase, nfe * SZ);
 #pragma unroll
@@ -530,37 +548,106 @@ dst_kernel(DstArgs<T> a) {
                 const T v1 = bload<T>(rI, (in && has1) ? (uint32_t)(j1 * NX1 + i) * SZ : BUF_OOB);
                 if (in) {
                     buf[lpad(1 + i)] = {v0, v1};
-                    buf[lpad(M - 1 - i)] = {-v0, -v1};
+                    if constexpr (!HALF) buf[lpad(M - 1 - i)] = {-v0, -v1};
                 }
             }
         }
         if (t == 0) {
             buf[lpad(0)] = {(T)0, (T)0};
-            buf[lpad(NX)] = {(T)0, (T)0};
+            if constexpr (!HALF) buf[lpad(NX)] = {(T)0, (T)0};
         }
     } else {
         for (int i = t; i < M; i += TPF) buf[lpad(i)] = {(T)0, (T)0};
     }
     __syncthreads();
 
-    // ---- transform ----------------------------------------------------------
-    cpx<T> v[R];
-    fft_mid<T, M, R, 1>(buf, a.tw, t);
-    fft_last<T, M, R>(buf, a.tw, t, v);
+    if constexpr (HALF) {
+        // ---- pre-pass: y_j, y_{N-j} from f_j, f_{N-j} (j = 1 .. N/2) -------------
+        // tw[j] = exp(-i pi j / N), so sin(pi j / N) = -Im tw[j]; j = N/2 writes
+        // the same value twice (f_j - f_{N-j} = 0 there)
+#pragma unroll
+        for (int c = 0; c < CK; ++c) {
+            const int j = 1 + t + c * TPF;
+            const cpx<T> fj = buf[lpad(j)];
+            const cpx<T> fm = buf[lpad(NX - j)];
+            const T sj = -a.tw[j].y;
+            const T sx = sj * (fj.x + fm.x), sy = sj * (fj.y + fm.y);
+            const T dx = (T)0.5 * (fj.x - fm.x), dy = (T)0.5 * (fj.y - fm.y);
+            buf[lpad(j)] = {sx + dx, sy + dy};
+            buf[lpad(NX - j)] = {sx - dx, sy - dy};
+        }
+        __syncthreads();
 
-    // ---- outputs: registers -> global (first half of the spectrum) ---------
-    if (live) {
-        T beta = (T)0;
-        if constexpr (MODE == DST_CORRECT) beta = (T)a.ctl[field].beta;
+        // ---- transform (length N; the 2N-entry twiddle table with stride 2) -------
+        cpx<T> v[R];
+        fft_mid<T, M, R, 1, 2>(buf, a.tw, t);
+        fft_last<T, M, R, 2>(buf, a.tw, t, v);
+        __syncthreads();                           // every thread has read its last-pass inputs
 #pragma unroll
         for (int qb = 0; qb < NBL; ++qb)
 #pragma unroll
-            for (int u = 0; u < RL / 2; ++u) {
-                const int K = t + qb * TPF + u * NSL;
-                if (K < 1 || K > NX1) continue;
-                const int col = K - 1;
-                const cpx<T> V = v[qb * RL + u];
-                T x0 = -V.y * (T)0.5, x1 = V.x * (T)0.5;
+            for (int u = 0; u < RL; ++u) buf[lpad(t + qb * TPF + u * NSL)] = v[qb * RL + u];
+        __syncthreads();
+
+        // ---- post-pass: k = t CK + c; two-for-one split and the prefix sum --------
+        // row j0 (real part): F_{2k} = -(Im Z_k - Im Z_{N-k})/2, Re Y_k = (Re Z_k + Re Z_{N-k})/2
+        // row j1 (imag part): F_{2k} =  (Re Z_k - Re Z_{N-k})/2, Re Y_k = (Im Z_k + Im Z_{N-k})/2
+        T ev0[CK], ev1[CK], s0[CK], s1[CK];
+        T run0 = (T)0, run1 = (T)0;
+#pragma unroll
+        for (int c = 0; c < CK; ++c) {
+            const int k = t * CK + c;
+            const cpx<T> zk = buf[lpad(k)];
+            const cpx<T> zm = buf[lpad(k == 0 ? 0 : NX - k)];
+            ev0[c] = (T)-0.5 * (zk.y - zm.y);
+            ev1[c] = (T)0.5 * (zk.x - zm.x);
+            run0 += (T)0.5 * (zk.x + zm.x);
+            run1 += (T)0.5 * (zk.y + zm.y);
+            s0[c] = run0;
+            s1[c] = run1;
+        }
+        const cpx<T> z0 = buf[lpad(0)];            // Re Y_0 of both rows: (Re Z_0, Im Z_0)
+        // exclusive prefix of the thread totals over the transform's TPF threads
+        constexpr int W = TPF < 64 ? TPF : 64;     // lanes of one transform within a wave
+        const int lane = threadIdx.x & 63;
+        T inc0 = run0, inc1 = run1;
+#pragma unroll
+        for (int d = 1; d < W; d <<= 1) {
+            const T u0 = __shfl_up(inc0, d, W), u1 = __shfl_up(inc1, d, W);
+            if ((lane & (W - 1)) >= d) {
+                inc0 += u0;
+                inc1 += u1;
+            }
+        }
+        T off0 = inc0 - run0, off1 = inc1 - run1;
+        if constexpr (TPF > 64) {                  // whole waves per transform: add the earlier waves'
+            if (lane == 63) wtot[threadIdx.x >> 6] = {inc0, inc1};   // totals of the same transform
+            __syncthreads();
+            const int w0 = (fid * TPF) >> 6, wme = threadIdx.x >> 6;
+            for (int wv = w0; wv < wme; ++wv) {
+                off0 += wtot[wv].x;
+                off1 += wtot[wv].y;
+            }
+        }
+        __syncthreads();                           // every thread has read Z: reuse the LDS
+#pragma unroll
+        for (int c = 0; c < CK; ++c) {
+            const int k = t * CK + c;
+            buf[lpad(2 * k)] = {off0 + s0[c] - (T)0.5 * z0.x, off1 + s1[c] - (T)0.5 * z0.y};   // F_{2k+1}
+            if (k > 0) buf[lpad(2 * k - 1)] = {ev0[c], ev1[c]};                                   // F_{2k}
+        }
+        __syncthreads();
+
+        // ---- outputs: LDS -> global, column t + u TPF ----------------------------
+        if (live) {
+            T beta = (T)0;
+            if constexpr (MODE == DST_CORRECT) beta = (T)a.ctl[field].beta;
+#pragma unroll
+            for (int u = 0; u < NOUT; ++u) {
+                const int col = t + u * TPF;
+                if (col >= NX1) continue;
+                const cpx<T> F = buf[lpad(col)];
+                T x0 = F.x, x1 = F.y;
                 if constexpr (MODE == DST_FWD || UPD) {
                     a.out[o0 + col] = x0;
                     if (has1) a.out[o1 + col] = x1;
@@ -570,18 +657,61 @@ dst_kernel(DstArgs<T> a) {
                     if (has1) a.out[o1 + col] = x1 * sc;
                 } else {   // CORRECT: p = z + beta p  (init: p = z)
                     const T sc = (T)(2.0 / NX);
-                    const int oi = qb * (RL / 2) + u;
                     x0 *= sc;
                     x1 *= sc;
                     if (a.init) {
                         a.out[o0 + col] = x0;
                         if (has1) a.out[o1 + col] = x1;
                     } else {
-                        a.out[o0 + col] = x0 + beta * pold0[oi];
-                        if (has1) a.out[o1 + col] = x1 + beta * pold1[oi];
+                        a.out[o0 + col] = x0 + beta * pold0[u];
+                        if (has1) a.out[o1 + col] = x1 + beta * pold1[u];
                     }
                 }
             }
+        }
+
+    } else {
+        // ---- transform (2N form) ----------------------------------------------------
+        cpx<T> v[R];
+        fft_mid<T, M, R, 1>(buf, a.tw, t);
+        fft_last<T, M, R>(buf, a.tw, t, v);
+
+        // ---- outputs: registers -> global (first half of the spectrum) ---------
+        if (live) {
+            T beta = (T)0;
+            if constexpr (MODE == DST_CORRECT) beta = (T)a.ctl[field].beta;
+#pragma unroll
+            for (int qb = 0; qb < NBL; ++qb)
+#pragma unroll
+                for (int u = 0; u < RL / 2; ++u) {
+                    const int K = t + qb * TPF + u * NSL;
+                    if (K < 1 || K > NX1) continue;
+                    const int col = K - 1;
+                    const cpx<T> V = v[qb * RL + u];
+                    T x0 = -V.y * (T)0.5, x1 = V.x * (T)0.5;
+                    if constexpr (MODE == DST_FWD || UPD) {
+                        a.out[o0 + col] = x0;
+                        if (has1) a.out[o1 + col] = x1;
+                    } else if constexpr (MODE == DST_INV) {
+                        const T sc = (T)(2.0 / NX);
+                        a.out[o0 + col] = x0 * sc;
+                        if (has1) a.out[o1 + col] = x1 * sc;
+                    } else {   // CORRECT: p = z + beta p  (init: p = z)
+                        const T sc = (T)(2.0 / NX);
+                        const int oi = qb * (RL / 2) + u;
+                        x0 *= sc;
+                        x1 *= sc;
+                        if (a.init) {
+                            a.out[o0 + col] = x0;
+                            if (has1) a.out[o1 + col] = x1;
+                        } else {
+                            a.out[o0 + col] = x0 + beta * pold0[oi];
+                            if (has1) a.out[o1 + col] = x1 + beta * pold1[oi];
+                        }
+                    }
+                }
+        }
+
     }
 
     if constexpr (UPD) {
@@ -1178,21 +1308,24 @@ hipError_t residual_check_T(lg_plan* p, const double* b, const double* x) {
     return finalize(p, FIN_RR, a.gx * a.gy, 2, 0.0, 0, 0.0);
 }
 
-template <typename T, int M, int MODE>
+template <typename T, int NX, int MODE>
 hipError_t dst_launch_M(lg_plan* pl, DstArgs<T>& a, int nfields) {
+    constexpr bool H = dst_half_form(NX, (int)sizeof(T));
+    constexpr int M = H ? NX : 2 * NX;         // FFT length
     constexpr int R = M >= 16 ? 16 : M;
     constexpr int TPF = M / R;
     constexpr int FPB = TPF >= 256 ? 1 : 256 / TPF;
     const int npairs = (a.nz1 + 1) / 2;
     a.bpf = (npairs + FPB - 1) / FPB;
     const dim3 grid(a.bpf * nfields);
-    hipLaunchKernelGGL((dst_kernel<T, M, R, FPB, MODE>), grid, dim3(FPB * TPF), 0, pl->stream, a);
+    hipLaunchKernelGGL((dst_kernel<T, M, R, FPB, MODE, H>), grid, dim3(FPB * TPF), 0, pl->stream, a);
     return hipGetLastError();
 }
 
 template <typename T, int MODE>
 hipError_t dst_dispatch(lg_plan* pl, DstArgs<T>& a, int nfields) {
-    switch (2 * pl->g.nx) {
+    switch (pl->g.nx) {
+        case 2: return dst_launch_M<T, 2, MODE>(pl, a, nfields);
         case 4: return dst_launch_M<T, 4, MODE>(pl, a, nfields);
         case 8: return dst_launch_M<T, 8, MODE>(pl, a, nfields);
         case 16: return dst_launch_M<T, 16, MODE>(pl, a, nfields);
@@ -1204,7 +1337,6 @@ hipError_t dst_dispatch(lg_plan* pl, DstArgs<T>& a, int nfields) {
         case 1024: return dst_launch_M<T, 1024, MODE>(pl, a, nfields);
         case 2048: return dst_launch_M<T, 2048, MODE>(pl, a, nfields);
         case 4096: return dst_launch_M<T, 4096, MODE>(pl, a, nfields);
-        case 8192: return dst_launch_M<T, 8192, MODE>(pl, a, nfields);
         default: return hipErrorInvalidValue;
     }
 }

@@ -447,8 +447,8 @@ void free_plan(lg_plan* p) {
     delete p;
 }
 
-int dst_blocks_per_field(int nx, int nz1) {
-    const int M = 2 * nx;
+int dst_blocks_per_field(int nx, int nz1, int ws) {
+    const int M = dst_half_form(nx, ws) ? nx : 2 * nx;   // FFT length of the row transform
     const int R = M >= 16 ? 16 : M;
     const int TPF = M / R;
     const int FPB = TPF >= 256 ? 1 : 256 / TPF;
@@ -786,7 +786,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if ((st = dev_alloc(p, &p->E, (size_t)SC * P * 3 * p->nx1 * 8)) != LG_OK) return bail(st);
     {
         const size_t sb = (size_t)((p->nx1 + 63) / 64) * ((p->nz1 + 15) / 16);   // operator tiles (<= 16 rows)
-        const size_t db = (size_t)dst_blocks_per_field(grid->nx, p->nz1);
+        const size_t db = (size_t)dst_blocks_per_field(grid->nx, p->nz1, (int)wsize(p));
         const size_t rb = (size_t)((p->nx1 + 15) / 16);
         // the transform kernel's start from a given x writes two partial sets
         p->partial_stride = std::max(sb, std::max(2 * db, rb));
