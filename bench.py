@@ -229,7 +229,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     return out
 
 
-def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10, shots=None, top="dirichlet"):
+def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10, shots=None, top="dirichlet", segments=0):
     """Elastic harmonics (GMRES(k) per harmonic) timed like the acoustic ones;
     reported with the time of one GMRES(k) cycle (k inner iterations), the
     unit of the paper's Table 2."""
@@ -240,7 +240,7 @@ def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10, shots=None, t
     w = inputs.WORKLOADS[name]
     S = shots or w.shots
     log(f"{name}: GMRES({restart}) harmonics={warmup + steps} shots={S} top={top}")
-    run = ElasticRun(w, n_harm=warmup + steps, restart=restart, shots=S, top=top)
+    run = ElasticRun(w, n_harm=warmup + steps, restart=restart, shots=S, top=top, segments=segments)
     for _ in range(warmup):
         run.step()
     torch.cuda.synchronize()
@@ -252,6 +252,7 @@ def run_elastic(name="elastic1024", steps=2, warmup=1, restart=10, shots=None, t
     el = time.perf_counter() - t
     npts = 2 * (w.n_cells - 1) ** 2
     out = {"workload": name, "precision": "fp64", "shots": S, "top": top, "restart": restart,
+           "segments": run.plan.layout()[0],
            "value": npts * S * sum(its) / el / 1e6,
            "unit": "Mpoint-iters/s (GMRES inner iterations, 2 components)",
            "ms_per_step": 1e3 * el / steps, "inner_iters_per_harmonic": its,
@@ -428,7 +429,7 @@ def main():
     prec = args.precision or w.precision
     shots = args.shots or w.shots
     if args.elastic_only:
-        print(json.dumps(run_elastic(steps=args.steps, warmup=args.warmup, shots=args.shots)))
+        print(json.dumps(run_elastic(steps=args.steps, warmup=args.warmup, shots=args.shots, segments=args.segments)))
         return
     if args.profile_only:
         # the benchmark's own path on two harmonics (one untimed), then the

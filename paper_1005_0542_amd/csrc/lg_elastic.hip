@@ -246,6 +246,45 @@ __global__ __launch_bounds__(GM_BLK) void gm_multidot_kernel(const double* __res
     }
 }
 
+// Sum over the nblk per-block partials of product i of shot s, in the fixed
+// order of gm_reduce_kernel (every thread of the block gets the value), so a
+// consumer kernel can take a grid-wide result without a reduction launch.
+__device__ __forceinline__ double partial_total(const double* __restrict__ partial, int s, int i, int nblk,
+                                                double* red) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += GM_BLK) v += partial[((size_t)s * (GM_MAXK + 1) + i) * nblk + b];
+    return block_sum(v, red);
+}
+
+// partial_total for products 0..m-1 at once (m <= MB): one pass over the
+// partials and one barrier; per product the same order as partial_total.
+template <int MB>
+__device__ __forceinline__ void partial_totals(const double* __restrict__ partial, int s, int m, int nblk,
+                                               double (*red)[GM_BLK / 64], double* c) {
+    double v[MB];
+#pragma unroll
+    for (int u = 0; u < MB; ++u) v[u] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += GM_BLK) {
+#pragma unroll
+        for (int u = 0; u < MB; ++u)
+            if (u < m) v[u] += partial[((size_t)s * (GM_MAXK + 1) + u) * nblk + b];
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+        v[u] = wave_sum(v[u]);
+        if (lane == 0) red[u][wave] = v[u];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MB; ++u) {
+        double t = 0.0;
+        for (int i = 0; i < GM_BLK / 64; ++i) t += red[u][i];
+        c[u] = u < m ? t : 0.0;
+    }
+    __syncthreads();   // red may be reused by the caller
+}
+
 // Classical Gram-Schmidt twice, with each subtraction fused into the sweep
 // that follows it (one read of the basis instead of two):
 //   NORM = false: w -= sum_{i<m} coef[s][i] V_i, then the block partials of
@@ -255,9 +294,14 @@ __global__ __launch_bounds__(GM_BLK) void gm_multidot_kernel(const double* __res
 // Per element the subtraction is gm_subtract_kernel's and the products and
 // per-thread sums are gm_multidot_kernel's, in the same order, so the
 // results are those of the separate kernels.  MB >= m bounds the unroll.
+// The coefficients are the previous sweep's products: with pin != nullptr
+// every block sums them from that sweep's per-block partials (pin) and block
+// 0 of the shot also stores them to coef (for the host's Hessenberg column);
+// with pin == nullptr they are read from coef.
 template <int MB, bool NORM>
 __global__ __launch_bounds__(GM_BLK) void gm_subdot_kernel(const double* __restrict__ V, size_t vstride, int m,
-                                                           const double* __restrict__ coef, int coef_stride,
+                                                           double* __restrict__ coef, int coef_stride,
+                                                           const double* __restrict__ pin,
                                                            double* __restrict__ w, size_t n_s,
                                                            const int* __restrict__ active,
                                                            double* __restrict__ partial, int nblk) {
@@ -268,12 +312,18 @@ __global__ __launch_bounds__(GM_BLK) void gm_subdot_kernel(const double* __restr
     const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
     const uint32_t nbytes = (uint32_t)(n_s * 8);
     const rsrc_t rw = buf_rsrc(w + base, nbytes);
+    __shared__ double redm[MB][GM_BLK / 64];
     rsrc_t rv[MB];
     double c[MB];
+    if (pin != nullptr) {                          // uniform over the launch
+        partial_totals<MB>(pin, s, m, nblk, redm, c);
+        if (b == 0 && threadIdx.x == 0)
+            for (int u = 0; u < m; ++u) coef[(size_t)s * coef_stride + u] = c[u];
+    }
 #pragma unroll
     for (int u = 0; u < MB; ++u) {
         rv[u] = buf_rsrc(V + (size_t)u * vstride + base, u < m ? nbytes : 0u);
-        c[u] = u < m ? coef[(size_t)s * coef_stride + u] : 0.0;
+        if (pin == nullptr) c[u] = u < m ? coef[(size_t)s * coef_stride + u] : 0.0;
     }
     constexpr int NA = NORM ? 1 : MB;
     double acc[NA];
@@ -347,6 +397,25 @@ __global__ __launch_bounds__(GM_BLK) void gm_normalize_kernel(const double* __re
     out[e] = q > 0.0 ? x[e] / sqrt(q) : 0.0;
 }
 
+// out = x / sqrt(||x||^2) over the shot's chunk, ||x||^2 summed by every block
+// from the previous sweep's partials (product 0); block 0 of the shot stores
+// it to nrm2 (the host's Hessenberg entry).  The arithmetic is that of
+// gm_normalize_kernel after gm_reduce_kernel.
+__global__ __launch_bounds__(GM_BLK) void gm_normalize_fused_kernel(const double* __restrict__ x,
+                                                                    const double* __restrict__ pin,
+                                                                    double* __restrict__ nrm2, int nrm_stride,
+                                                                    double* __restrict__ out, size_t n_s,
+                                                                    const int* __restrict__ active, int nblk) {
+    __shared__ double red[GM_BLK / 64];
+    const int s = blockIdx.y, b = blockIdx.x;
+    if (active[s] == 0) return;
+    const double q = partial_total(pin, s, 0, nblk, red);
+    if (b == 0 && threadIdx.x == 0) nrm2[(size_t)s * nrm_stride] = q;
+    const size_t base = (size_t)s * n_s;
+    const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
+    for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) out[base + e] = q > 0.0 ? x[base + e] / sqrt(q) : 0.0;
+}
+
 // out = sum_{i<m} y[s][i] V_i
 __global__ __launch_bounds__(GM_BLK) void gm_combine_kernel(const double* __restrict__ V, size_t vstride, int m,
                                                             const double* __restrict__ y, int y_stride,
@@ -379,6 +448,7 @@ struct GmState {
     double* w = nullptr;       // [nvec]
     double* z = nullptr;       // [nvec]
     double* partial = nullptr; // [S][MAXK+1][nblk]
+    double* partial2 = nullptr;  // a second set
     double* dots = nullptr;    // [S][DS]
     int* active = nullptr;     // [S]
 };
@@ -406,7 +476,8 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
     }
     if (!p->gm_w) LG_HIP(hipMalloc((void**)&p->gm_w, nvec * 8));
     if (!p->gm_z) LG_HIP(hipMalloc((void**)&p->gm_z, nvec * 8));
-    if (!p->gm_x) LG_HIP(hipMalloc((void**)&p->gm_x, ((size_t)S * (GM_MAXK + 1) * nblk + (size_t)S * DS) * 8 + S * 4 + 64));
+    if (!p->gm_x)   // two partial sets (a sweep reads one while writing the other), dots, flags
+        LG_HIP(hipMalloc((void**)&p->gm_x, (2 * (size_t)S * (GM_MAXK + 1) * nblk + (size_t)S * DS) * 8 + S * 4 + 64));
     if (!p->gm_hb) LG_HIP(hipHostMalloc((void**)&p->gm_hb, (size_t)2 * S * DS * 8, hipHostMallocDefault));
     for (hipEvent_t& e : p->gm_ev)
         if (!e) LG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -415,7 +486,8 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
     g.w = p->gm_w;
     g.z = p->gm_z;
     g.partial = p->gm_x;
-    g.dots = g.partial + (size_t)S * (GM_MAXK + 1) * nblk;
+    g.partial2 = g.partial + (size_t)S * (GM_MAXK + 1) * nblk;
+    g.dots = g.partial2 + (size_t)S * (GM_MAXK + 1) * nblk;
     g.active = (int*)(g.dots + (size_t)S * DS);
     hipStream_t st = p->stream;
     const unsigned nb = nblocks(nvec);
@@ -435,21 +507,26 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
         return hipGetLastError();
     };
     // one classical Gram-Schmidt subtraction fused with the sweep after it
-    // (the inner products of the second pass, or the norm); m > 16 takes the
-    // separate kernels
-    auto subdot = [&](int m, int coef_slot, bool norm, int out_slot) -> hipError_t {
+    // (the inner products of the second pass, or the norm).  pin: the
+    // previous sweep's per-block partials, from which every block sums the
+    // coefficients (and stores them to dots at coef_slot), or nullptr (the
+    // coefficients are read from dots); pout: this sweep's partials; reduce:
+    // sum them into dots at out_slot with a separate kernel.  m > 16 takes
+    // the separate kernels (coefficients from dots).
+    auto subdot = [&](int m, int coef_slot, bool norm, int out_slot, const double* pin, double* pout,
+                      bool reduce) -> hipError_t {
         const dim3 grid(nblk, S);
-        const double* cf = g.dots + coef_slot;
+        double* cf = g.dots + coef_slot;
         if (m <= 8) {
             if (norm) hipLaunchKernelGGL((gm_subdot_kernel<8, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                         g.w, n_s, g.active, g.partial, nblk);
+                                         pin, g.w, n_s, g.active, pout, nblk);
             else hipLaunchKernelGGL((gm_subdot_kernel<8, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                    g.w, n_s, g.active, g.partial, nblk);
+                                    pin, g.w, n_s, g.active, pout, nblk);
         } else if (m <= 16) {
             if (norm) hipLaunchKernelGGL((gm_subdot_kernel<16, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                         g.w, n_s, g.active, g.partial, nblk);
+                                         pin, g.w, n_s, g.active, pout, nblk);
             else hipLaunchKernelGGL((gm_subdot_kernel<16, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                    g.w, n_s, g.active, g.partial, nblk);
+                                    pin, g.w, n_s, g.active, pout, nblk);
         } else {
             hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS, g.w, n_s, S,
                                g.active);
@@ -458,8 +535,8 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             return norm ? dot_into(g.w, 0, 1, g.w, out_slot) : dot_into(g.V, nvec, m, g.w, out_slot);
         }
         hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(gm_reduce_kernel, dim3(S), dim3(GM_BLK), 0, st, g.partial, norm ? 1 : m, nblk, g.active,
+        if (e != hipSuccess || !reduce) return e;
+        hipLaunchKernelGGL(gm_reduce_kernel, dim3(S), dim3(GM_BLK), 0, st, pout, norm ? 1 : m, nblk, g.active,
                            g.dots + out_slot, DS);
         return hipGetLastError();
     };
@@ -558,12 +635,31 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             double* Vn = g.V + (size_t)(j + 1) * nvec;
             hipError_t e = launch_elastic_precond(p, Vj, g.z);
             if (e == hipSuccess) e = launch_elastic_stencil(p, g.z, g.w);
-            if (e == hipSuccess) e = dot_into(g.V, nvec, j + 1, g.w, 0);                    // pass 1 products
-            if (e == hipSuccess) e = subdot(j + 1, 0, false, GM_MAXK + 1);                  // subtract, pass 2 products
-            if (e == hipSuccess) e = subdot(j + 1, GM_MAXK + 1, true, 2 * (GM_MAXK + 1));   // subtract, ||w||^2
-            if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.w, g.dots + 2 * (GM_MAXK + 1),
-                               DS, Vn, n_s, S, g.active);
+            const int m = j + 1;
+            if (m <= 16) {
+                // no reduction launches: pass-1 products (partials A); the pass-1
+                // subtraction with the pass-2 products (coefficients summed from A,
+                // partials B); the pass-2 subtraction with ||w||^2 (from B, partials
+                // A); the normalisation (||w||^2 summed from A).  Each consumer
+                // stores the sums it formed into dots for the host.
+                if (e == hipSuccess) {
+                    hipLaunchKernelGGL(gm_multidot_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, g.V, nvec, m, g.w, n_s,
+                                       g.active, g.partial, nblk);
+                    e = hipGetLastError();
+                }
+                if (e == hipSuccess) e = subdot(m, 0, false, GM_MAXK + 1, g.partial, g.partial2, false);
+                if (e == hipSuccess) e = subdot(m, GM_MAXK + 1, true, 2 * (GM_MAXK + 1), g.partial2, g.partial, false);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(gm_normalize_fused_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, g.w, g.partial,
+                                   g.dots + 2 * (GM_MAXK + 1), DS, Vn, n_s, g.active, nblk);
+            } else {
+                if (e == hipSuccess) e = dot_into(g.V, nvec, m, g.w, 0);                                 // pass 1
+                if (e == hipSuccess) e = subdot(m, 0, false, GM_MAXK + 1, nullptr, g.partial, true);     // pass 2
+                if (e == hipSuccess) e = subdot(m, GM_MAXK + 1, true, 2 * (GM_MAXK + 1), nullptr, g.partial, true);
+                if (e != hipSuccess) return e;
+                hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.w,
+                                   g.dots + 2 * (GM_MAXK + 1), DS, Vn, n_s, S, g.active);
+            }
             if ((e = hipGetLastError()) != hipSuccess) return e;
             e = hipMemcpyAsync(p->gm_hb + (size_t)(j & 1) * S * DS, g.dots, (size_t)S * DS * 8,
                                hipMemcpyDeviceToHost, st);
