@@ -90,3 +90,71 @@ def test_full_mixed_chains_against_fp64_oracle():
         assert all(st == OK for st in o["status"])
     for k, (er, es) in worst.items():
         assert er <= 1e-6 and es <= 1e-6, (k, er, es)
+
+
+@pytest.mark.timeout(900)
+def test_full_fp64_chains_at_the_oracle_iteration_counts():
+    """The FP64 workloads over more harmonics, each harmonic run for exactly the
+    oracle's own iteration count (tol = 0): the library's chain and the
+    oracle's are then the same computation up to rounding.
+    * 1023^2 acoustic FP64: 64 harmonics and the snapshots;
+    * 1023^2 x 2 elastic GMRES(10): 6 harmonics.
+    Bar: 1e-12 relative L2 per harmonic and on the snapshots."""
+    import torch
+    from paper_1005_0542_amd import api
+    torch_cuda()
+    NA, NE = 64, 6
+    ctx = multiprocessing.get_context("spawn")
+    with concurrent.futures.ProcessPoolExecutor(max_workers=2, mp_context=ctx) as pool:
+        fa = pool.submit(_oracle_chains.oracle_chain, "acoustic1024", 0, NA, 1e-10)
+        fe = pool.submit(_oracle_chains.oracle_elastic_chain, "elastic1024", NE, 1e-10)
+        t0 = time.monotonic()
+        while True:
+            done, pending = concurrent.futures.wait([fa, fe], timeout=20.0)
+            log(f"oracle chains: {len(done)} of 2 done after {time.monotonic() - t0:.0f} s")
+            if not pending:
+                break
+        oa, oe = fa.result(), fe.result()
+    # acoustic: the driver's buffers and synthesis, the solve at the oracle's counts
+    w = inputs.WORKLOADS["acoustic1024"]
+    t = tune.lookup(w.n_cells, w.n_cells, "fp64", 1)
+    run = AcousticRun(w, precision="fp64", n_harm=NA, snapshots=True, rec=False,
+                      **{k: t.get(k, 0) for k in ("segments", "graph_iters", "op_shots", "seg_per_wave", "op_fusion")})
+    # the oracle's synthesis weights feed both sides' snapshots (the library's
+    # host helper is checked against them separately)
+    from oracle import laguerre
+    Ws = laguerre.synthesis_weights(np.array(inputs.snapshot_times(w)), w.h, w.alpha, NA)
+    errs = []
+    for m in range(NA):
+        fs = np.full(1, run.f_m[m])
+        run.plan.laguerre_rhs(m, run.R if m else None, run.Ph, run.Qh, fs, run.rhs)
+        log(f"acoustic1024 harmonic {m}: {oa['iters'][m]} iterations")
+        res = run.plan.pcg_solve(run.rhs, run.R, tol=0.0, max_iter=oa["iters"][m])
+        assert res.iters == [oa["iters"][m]]
+        run.plan.laguerre_synthesize(m, run.R, Ws[:, m], run.snap)
+        errs.append(_l2(run.R[0, 0].cpu().numpy(), oa["R"][m]))
+    es = _l2(run.snap[:, 0, 0].cpu().numpy(), oa["snap"])
+    print(f"acoustic1024 {NA} harmonics at the oracle's counts: per-harmonic rel L2 max {max(errs):.1e}, "
+          f"snapshots {es:.1e}")
+    assert max(errs) <= 1e-12 and es <= 1e-12, (errs, es)
+    run.plan.destroy()
+    del run
+    # elastic
+    we = inputs.WORKLOADS["elastic1024"]
+    lam, mu, rho = inputs.elastic_medium_for(we)
+    N, d = we.n_cells, we.d
+    plan = api.Plan("elastic", N, N, d, d, we.alpha, we.h, NE, np.stack([lam, mu, rho]), precision="fp64", nshots=1)
+    plan.set_sources(inputs.sources_for(we))
+    f = api.source_coeffs(we.f0, we.t0, we.alpha, we.h, NE)
+    shape = (1, 2, N - 1, N - 1)
+    R, Ph, Qh, rhs = (torch.zeros(shape, dtype=torch.float64, device="cuda") for _ in range(4))
+    eerrs = []
+    for m in range(NE):
+        plan.laguerre_rhs(m, R if m else None, Ph, Qh, [f[m]], rhs)
+        log(f"elastic1024 harmonic {m}: {oe['iters'][m]} iterations")
+        res = plan.gmres_solve(rhs, R, tol=0.0, max_iter=oe["iters"][m], restart=10)
+        assert res.iters == [oe["iters"][m]]
+        eerrs.append(_l2(R[0].cpu().numpy(), oe["R"][m]))
+    print(f"elastic1024 {NE} harmonics at the oracle's counts: per-harmonic rel L2 {[f'{e:.1e}' for e in eerrs]}")
+    assert max(eerrs) <= 1e-12
+    plan.destroy()
