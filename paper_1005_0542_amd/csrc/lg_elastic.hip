@@ -140,19 +140,22 @@ hipError_t launch_elastic_stencil(lg_plan* p, const void* x, void* y) {
 // Traction-free surface rows of the preconditioner (the rank-one term on the
 // Dirichlet solution y of block blk): coef = y(row 1) / (1 - g_k(1)), then
 // y += coef g_k on every row.
+// (t2, g2 non-null: odd fields take the second block's tables)
 template <typename T>
 __global__ __launch_bounds__(256) void surface_coef_kernel(const T* __restrict__ y, const double* __restrict__ t,
-                                                           double* __restrict__ coef, int nx1, size_t npts,
-                                                           int nfields, int fstride, int foff) {
+                                                           const double* __restrict__ t2, double* __restrict__ coef,
+                                                           int nx1, size_t npts, int nfields, int fstride, int foff) {
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= (size_t)nfields * nx1) return;
     const size_t f = (e / nx1) * fstride + foff;
     const int k = (int)(e % nx1);
-    coef[f * nx1 + k] = (double)y[f * npts + nx1 + k] * t[k];
+    const double* __restrict__ tt = (t2 != nullptr && (f & 1)) ? t2 : t;
+    coef[f * nx1 + k] = (double)y[f * npts + nx1 + k] * tt[k];
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void surface_apply_kernel(T* __restrict__ y, const T* __restrict__ g,
+                                                            const T* __restrict__ g2,
                                                             const double* __restrict__ coef, int nx1, size_t npts,
                                                             size_t total, int fstride, int foff) {
     const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
@@ -160,19 +163,23 @@ __global__ __launch_bounds__(256) void surface_apply_kernel(T* __restrict__ y, c
     const size_t f = (e / npts) * fstride + foff;
     const size_t pt = e % npts;
     const int k = (int)(pt % nx1);
-    y[f * npts + pt] += (T)coef[f * nx1 + k] * g[pt];
+    const T* __restrict__ gg = (g2 != nullptr && (f & 1)) ? g2 : g;
+    y[f * npts + pt] += (T)coef[f * nx1 + k] * gg[pt];
 }
 
 template <typename T>
 hipError_t surface_rows_T(lg_plan* p, int blk, T* y, int nfields, int fstride, int foff) {
+    const int b0 = blk < 0 ? 0 : blk;          // blk < 0: both blocks by field parity
+    const double* t2 = blk < 0 ? p->es_t[1] : nullptr;
+    const T* g2 = blk < 0 ? (const T*)p->es_g[1] : nullptr;
     const unsigned gc = (unsigned)(((size_t)nfields * p->nx1 + 255) / 256);
-    hipLaunchKernelGGL(surface_coef_kernel<T>, dim3(gc), dim3(256), 0, p->stream, y, p->es_t[blk], p->sm_c, p->nx1,
-                       p->npts, nfields, fstride, foff);
+    hipLaunchKernelGGL(surface_coef_kernel<T>, dim3(gc), dim3(256), 0, p->stream, y, p->es_t[b0], t2, p->sm_c,
+                       p->nx1, p->npts, nfields, fstride, foff);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const size_t total = (size_t)nfields * p->npts;
     hipLaunchKernelGGL(surface_apply_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, p->stream, y,
-                       (const T*)p->es_g[blk], p->sm_c, p->nx1, p->npts, total, fstride, foff);
+                       (const T*)p->es_g[b0], g2, p->sm_c, p->nx1, p->npts, total, fstride, foff);
     return hipGetLastError();
 }
 
@@ -186,13 +193,13 @@ hipError_t launch_surface_rows(lg_plan* p, int blk, void* y, int nfields, int fs
 // plan's spectral buffers rhat and y.
 hipError_t launch_elastic_precond(lg_plan* p, const void* r, void* z) {
     const int S = p->S;
+    // both components' z-systems in one launch of each Dichotomy kernel (block
+    // -1: B1 on the x fields, B2 on the z fields; the two share P and Ls)
     hipError_t e = launch_dst(p, 0, r, p->rhat, S * 2);
-    for (int c = 0; c < 2 && e == hipSuccess; ++c) {
-        e = launch_td(p, c, p->rhat, p->y, S, 0, 2, c);
-        if (e == hipSuccess && p->blk[c].P > 1) e = launch_rs(p, c, p->rhat, p->y, S, 0, 2, c);
-        if (e == hipSuccess && p->blk[c].P > 1) e = launch_correct(p, c, p->y, S, 2, c);
-        if (e == hipSuccess) e = launch_surface_rows(p, c, p->y, S, 2, c);
-    }
+    if (e == hipSuccess) e = launch_td(p, -1, p->rhat, p->y, S * 2, 0, 1, 0);
+    if (e == hipSuccess && p->blk[0].P > 1) e = launch_rs(p, -1, p->rhat, p->y, S * 2, 0, 1, 0);
+    if (e == hipSuccess && p->blk[0].P > 1) e = launch_correct(p, -1, p->y, S * 2, 1, 0);
+    if (e == hipSuccess) e = launch_surface_rows(p, -1, p->y, S * 2, 1, 0);
     if (e == hipSuccess) e = launch_dst(p, 1, p->y, z, S * 2);
     return e;
 }

@@ -747,6 +747,8 @@ struct TdArgs {
     int ktiles, sgroups;   // 1D grid of ktiles * sgroups * fields blocks
     int fstride, foff;   // field = grid index * fstride + foff (component selection)
     T inv_b;
+    const T* etab2;  // non-null: odd fields (elastic z component) take this block's factors
+    T inv_b2;
     ShotCtl* ctl;    // nullptr: no masking
 };
 
@@ -766,10 +768,13 @@ __global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
     const int field = bz * a.fstride + a.foff;
     if (a.ctl != nullptr && a.ctl[field].active == 0) return;   // uniform per block
     const int nx1 = a.nx1;
+    const bool second = a.etab2 != nullptr && (field & 1);       // uniform per block
+    const T* __restrict__ etab = second ? a.etab2 : a.etab;
+    const T inv_b = second ? a.inv_b2 : a.inv_b;
     {
         const int kk = bx * 64 + (threadIdx.x & 63);
         for (int i = threadIdx.x >> 6; i < LS; i += 4)
-            es[i * 64 + (threadIdx.x & 63)] = (kk < nx1) ? a.etab[(size_t)i * nx1 + kk] : (T)0;
+            es[i * 64 + (threadIdx.x & 63)] = (kk < nx1) ? etab[(size_t)i * nx1 + kk] : (T)0;
     }
     __syncthreads();
     if (k >= nx1) return;
@@ -787,7 +792,7 @@ __global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
         double d0 = 0.0;
 #pragma unroll
         for (int i = 1; i <= L; ++i) {
-            const T h = d[i] * a.inv_b + prev;
+            const T h = d[i] * inv_b + prev;
             prev = h * es[i * 64 + lane];
             d[i] = prev;
             d0 += (double)h * (double)prev;
@@ -832,6 +837,8 @@ struct RsArgs {
     int nx1, nz1, P, q, Ls, RW;
     int fstride, foff;   // field = grid index * fstride + foff
     double inv_b;
+    const double* red2;  // non-null: odd fields (elastic z component) take this block's tables
+    double inv_b2;
     int mode;
     ShotCtl* ctl;
     double* partial;
@@ -872,7 +879,9 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
     const size_t fb = (size_t)field * a.nz1 * nx1;
     const rsrc_t rR = buf_rsrc(a.rhat + fb, (uint32_t)a.nz1 * (uint32_t)nx1 * SZ);
     const rsrc_t rE = buf_rsrc(a.E + (size_t)field * P * 3 * nx1, (uint32_t)P * 3u * (uint32_t)nx1 * 8u);
-    const rsrc_t rW = buf_rsrc(a.red, (uint32_t)nx1 * (uint32_t)RW * 8u);
+    const bool second = a.red2 != nullptr && (field & 1);        // uniform per block
+    const double inv_b = second ? a.inv_b2 : a.inv_b;
+    const rsrc_t rW = buf_rsrc(second ? a.red2 : a.red, (uint32_t)nx1 * (uint32_t)RW * 8u);
     // weight table rows k0 .. k0+KT-1 are contiguous
     for (int e = tid; e < KT * RW; e += 256)
         Ws[e] = bload<double>(rW, (uint32_t)(k0 * RW + e) * 8u);
@@ -883,7 +892,7 @@ __global__ __launch_bounds__(256) void rs_kernel(RsArgs<T> a) {
         const int sg = grp + it * NG;
         const bool okd = valid && sg < P, okg = valid && sg < P - 1;
         d0 += bload<double>(rE, okd ? (uint32_t)((sg * 3 + 2) * nx1 + k) * 8u : BUF_OOB);
-        gv[it] = (double)bload<T>(rR, okg ? (uint32_t)(((sg + 1) * Ls - 1) * nx1 + k) * SZ : BUF_OOB) * a.inv_b +
+        gv[it] = (double)bload<T>(rR, okg ? (uint32_t)(((sg + 1) * Ls - 1) * nx1 + k) * SZ : BUF_OOB) * inv_b +
                  bload<double>(rE, okg ? (uint32_t)((sg * 3 + 1) * nx1 + k) * 8u : BUF_OOB) +
                  bload<double>(rE, okg ? (uint32_t)(((sg + 1) * 3 + 0) * nx1 + k) * 8u : BUF_OOB);
     }
@@ -1114,7 +1123,7 @@ template <typename T>
 // phase 0: segment rows (the separator rows are read, not written); with a
 // free surface (smg != nullptr) also + coef_k g_k(j).  phase 1 (free surface
 // only, after phase 0): the separator rows' rank-one term.
-__global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, int nx1, int nz1,
+__global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, const T* utab2, int nx1, int nz1,
                                                       int Ls, int P, size_t total, int fstride,
                                                       int foff, const T* smg, const double* smc, int phase) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1135,7 +1144,8 @@ __global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, int n
     const int s = jj / Ls;
     const T xl = (s > 0) ? Y[(size_t)(s * Ls - 1) * nx1 + k] : (T)0;
     const T xr = (s < P - 1) ? Y[(size_t)((s + 1) * Ls - 1) * nx1 + k] : (T)0;
-    Y[pt] = Y[pt] + xl * utab[(size_t)rs * nx1 + k] + xr * utab[(size_t)(Ls - rs) * nx1 + k] + sm;
+    const T* __restrict__ u = (utab2 != nullptr && (f & 1)) ? utab2 : utab;   // odd fields: the second block
+    Y[pt] = Y[pt] + xl * u[(size_t)rs * nx1 + k] + xr * u[(size_t)(Ls - rs) * nx1 + k] + sm;
 }
 
 // ===========================================================================
@@ -1394,8 +1404,11 @@ hipError_t td_launch(lg_plan* p, TdArgs<T>& a, int nfields) {
 template <typename T>
 hipError_t td_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, bool masked, int fstride,
                 int foff) {
-    const PrecBlock& B = p->blk[bi];
+    // bi < 0: both elastic blocks in one launch, B1 on even fields, B2 on odd ones
+    const PrecBlock& B = p->blk[bi < 0 ? 0 : bi];
     TdArgs<T> a;
+    a.etab2 = bi < 0 ? (const T*)p->blk[1].etab : nullptr;
+    a.inv_b2 = bi < 0 ? (T)(1.0 / p->blk[1].b) : (T)0;
     a.fstride = fstride;
     a.foff = foff;
     a.rhat = rhat;
@@ -1421,8 +1434,11 @@ hipError_t td_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, bool maske
 template <typename T>
 hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, int fstride,
                 int foff) {
-    const PrecBlock& B = p->blk[bi];
+    // bi < 0: both elastic blocks in one launch, B1 on even fields, B2 on odd ones
+    const PrecBlock& B = p->blk[bi < 0 ? 0 : bi];
     RsArgs<T> a;
+    a.red2 = bi < 0 ? p->blk[1].red : nullptr;
+    a.inv_b2 = bi < 0 ? 1.0 / p->blk[1].b : 0.0;
     a.fstride = fstride;
     a.foff = foff;
     a.rhat = rhat;
@@ -1576,19 +1592,20 @@ hipError_t launch_rs(lg_plan* p, int blk, const void* rhat, void* y, int nfields
 }
 
 hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride, int foff) {
-    const PrecBlock& B = p->blk[blk];
+    const PrecBlock& B = p->blk[blk < 0 ? 0 : blk];
+    const void* u2 = blk < 0 ? p->blk[1].utab : nullptr;     // both elastic blocks by field parity
     const size_t total = (size_t)nfields * p->npts;
     const dim3 grid((unsigned)((total + 255) / 256));
     const bool sm = p->free_top && blk == 0;
     for (int phase = 0; phase < (sm ? 2 : 1); ++phase) {
         if (p->prec == LG_FP64)
             hipLaunchKernelGGL(correct_kernel<double>, grid, dim3(256), 0, p->stream, (double*)y,
-                               (const double*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff,
-                               sm ? (const double*)p->sm_g : nullptr, p->sm_c, phase);
+                               (const double*)B.utab, (const double*)u2, p->nx1, p->nz1, B.Ls, B.P, total, fstride,
+                               foff, sm ? (const double*)p->sm_g : nullptr, p->sm_c, phase);
         else
             hipLaunchKernelGGL(correct_kernel<float>, grid, dim3(256), 0, p->stream, (float*)y,
-                               (const float*)B.utab, p->nx1, p->nz1, B.Ls, B.P, total, fstride, foff,
-                               sm ? (const float*)p->sm_g : nullptr, p->sm_c, phase);
+                               (const float*)B.utab, (const float*)u2, p->nx1, p->nz1, B.Ls, B.P, total, fstride,
+                               foff, sm ? (const float*)p->sm_g : nullptr, p->sm_c, phase);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
