@@ -262,10 +262,13 @@ lg_status lg_precond_apply(lg_plan* plan, const void* r, void* z);
  * x0 = 0 (or from x on entry when opts->x0_given: r0 = b - A x0 in FP64, and
  * 0 iterations when it already meets the tolerance), stopping per shot when
  * ||r||_2 <= tol ||b||_2 on the recursively updated residual.  Mixed plans
- * then check the FP64 true residual b - A x and restart CG from it where it
- * misses the tolerance (at most 4 restarts; a shot still missing it after
- * the last one reports LG_ERR_NOT_CONVERGED with relres of its true
- * residual); iters counts every CG iteration of the solve.  A zero b gives
+ * stop that first phase at max(tol, 1e-7) (below it the FP32 recursion no
+ * longer tracks the true residual), then check the FP64 true residual
+ * b - A x and restart CG from it where it misses tol (at most 4 restarts,
+ * each phase run to tol/2 on its recursive residual so the next check passes
+ * with margin; a shot still missing tol after the last one reports
+ * LG_ERR_NOT_CONVERGED with relres of its true residual); tol = 0 runs
+ * max_iter iterations.  iters counts every CG iteration of the solve.  A zero b gives
  * x = 0, iters = 0.  Converged shots drop out by masking.  b, x: FP64
  * vectors, b != x (b is read until the solve returns).  info_host: [S] (may
  * be NULL).  Returns the worst per-shot status. */

@@ -953,7 +953,10 @@ hipError_t cyl_launch_update(lg_plan* p, int init, const double* b, double* x, d
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;
-    return launch_finalize(p, 1 /* ||r||^2 */, bpf, init, tol * tol, max_iter, 0.0);   // init 2: restart check
+    // init 1: start; init 2: restart from the true residual (the thresholds
+    // set at the start apply)
+    const double t1 = phase_tol(p, tol, false), tr = phase_tol(p, tol, true);
+    return launch_finalize(p, 1 /* ||r||^2 */, bpf, init, t1 * t1, max_iter, 0.0, tol * tol, tr * tr);
 }
 
 hipError_t cyl_launch_correct(lg_plan* p, int init) {

@@ -35,7 +35,9 @@ struct ShotCtl {
     double beta;      // CG direction update
     double rr;        // ||r||^2
     double bb;        // ||b||^2
-    double tol2;      // tol^2 ||b||^2
+    double tol2;      // stopping threshold of the recursive ||r||^2 in the current phase
+    double tol2f;     // tol^2 ||b||^2: the requested tolerance (FP64 true-residual check)
+    double tol2r;     // stopping threshold of the recursive ||r||^2 in a restart phase
     int32_t iters;    // completed iterations
     int32_t active;   // 1 while the shot still iterates
     int32_t status;   // lg_status of the shot
@@ -207,7 +209,20 @@ hipError_t launch_correct_idst(lg_plan* p, int init);
 hipError_t launch_residual_check(lg_plan* p, const double* b, const double* x);
 // finalize kernel over nparts per-block partials per shot: kind 0 (p, Ap)
 // -> alpha; 1 ||r||^2 -> convergence; 2 (r, z) * scale -> beta
-hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale);
+// (init 1, 4 of kind 1 also take tol2f, the squared requested tolerance, and
+// tol2r, the squared recursive tolerance of restart phases; both default to tol2)
+hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale,
+                           double tol2f = -1.0, double tol2r = -1.0);
+// Recursive-residual tolerance at which a CG phase stops.  Mixed plans run
+// iterative refinement: the first phase (start) stops at max(tol,
+// LG_MIXED_PHASE1_TOL), about where the FP32 recursion stops tracking the true
+// residual; each restart from the FP64 true residual then aims at
+// LG_MIXED_REFINE_FAC * tol, so that the true residual checked against tol
+// afterwards lands below it with margin.  FP64 plans use tol.
+// tol = 0 (a fixed iteration count) stays 0.
+double phase_tol(const lg_plan* p, double tol, bool restart);
+constexpr double LG_MIXED_PHASE1_TOL = 1e-7;
+constexpr double LG_MIXED_REFINE_FAC = 0.5;
 // 2.5D axisymmetric plans
 hipError_t cyl_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce);
 // corr (inverse only): apply the r-system Dichotomy correction to the input rows

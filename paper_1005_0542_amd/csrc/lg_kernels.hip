@@ -997,7 +997,9 @@ struct FinArgs {
     int nparts;
     int kind;
     int init;         // FIN_RR: start of a solve; FIN_RZ: 1 start, 2 iteration
-    double tol2;
+    double tol2;      // (init 1, 4) squared recursive tolerance of the first phase
+    double tol2f;     // (init 1, 4) squared requested tolerance
+    double tol2r;     // (init 1, 4) squared recursive tolerance of restart phases
     int max_iter;
     double scale;     // FIN_RZ: b * 2/nx
 };
@@ -1035,6 +1037,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         if (a.init == 4) {                   // start from a given x: r = b - A x, ||b||^2 second
             c.bb = bbt;
             c.tol2 = a.tol2 * bbt;
+            c.tol2f = a.tol2f * bbt;
+            c.tol2r = a.tol2r * bbt;
             c.iters = 0;
             c.fresh = 0;                     // x and r are stored
             c.max_iter = a.max_iter;
@@ -1043,7 +1047,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             if (!isfinite(tot) || !isfinite(bbt)) {
                 c.status = LG_ERR_NONFINITE;
                 c.active = 0;
-            } else if (bbt == 0.0 || tot <= c.tol2) {
+            } else if (bbt == 0.0 || tot <= c.tol2f) {
                 c.status = LG_OK;            // b = 0: the host sets x = 0
                 c.active = 0;
             } else {
@@ -1056,10 +1060,11 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             if (c.status != LG_OK || c.bb == 0.0) return;
             c.alpha = 0.0;
             c.beta = 0.0;
+            c.tol2 = c.tol2r;                // the restart phase's recursive target
             if (!isfinite(tot)) {
                 c.status = LG_ERR_NONFINITE;
                 c.active = 0;
-            } else if (tot <= c.tol2) {
+            } else if (tot <= c.tol2f) {
                 c.status = LG_OK;
                 c.active = 0;
             } else if (c.iters >= c.max_iter) {
@@ -1072,6 +1077,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         } else if (a.init) {
             c.bb = tot;
             c.tol2 = a.tol2 * tot;
+            c.tol2f = a.tol2f * tot;
+            c.tol2r = a.tol2r * tot;
             c.iters = 0;
             c.max_iter = a.max_iter;
             c.alpha = 0.0;
@@ -1246,8 +1253,11 @@ __global__ __launch_bounds__(256) void traces_kernel(const double* __restrict__ 
 // ===========================================================================
 namespace {
 
-hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale) {
+hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale,
+                    double tol2f = -1.0, double tol2r = -1.0) {
     FinArgs f;
+    f.tol2f = tol2f < 0.0 ? tol2 : tol2f;
+    f.tol2r = tol2r < 0.0 ? tol2 : tol2r;
     f.ctl = p->ctl;
     f.partial = p->partial;
     f.pstride = p->partial_stride;
@@ -1488,8 +1498,8 @@ hipError_t rs_T(lg_plan* p, int bi, const T* rhat, T* y, int nfields, int mode, 
 }  // namespace
 
 hipError_t launch_finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter,
-                           double scale) {
-    return finalize(p, kind, nparts, init, tol2, max_iter, scale);
+                           double scale, double tol2f, double tol2r) {
+    return finalize(p, kind, nparts, init, tol2, max_iter, scale, tol2f, tol2r);
 }
 
 hipError_t launch_stencil(lg_plan* p, const void* x, void* y, bool reduce_pq) {
@@ -1561,7 +1571,11 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
         bpf = a.bpf;
     }
     if (e != hipSuccess) return e;
-    return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, tol * tol, max_iter, 0.0);   // init 2, 3: restart; 4: given x
+    // init 1: start; 4: start from a given x; 2, 3: restart from the true
+    // residual (the thresholds set at the start apply).  Each phase stops at
+    // phase_tol; the true residual is checked against tol.
+    const double t1 = phase_tol(p, tol, false), tr = phase_tol(p, tol, true);
+    return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, t1 * t1, max_iter, 0.0, tol * tol, tr * tr);
 }
 
 hipError_t launch_correct_idst(lg_plan* p, int init) {

@@ -74,6 +74,11 @@ int severity(int s) {
 
 }  // namespace
 
+double phase_tol(const lg_plan* p, double tol, bool restart) {
+    if (p->prec != LG_MIXED || tol <= 0.0) return tol;
+    return restart ? LG_MIXED_REFINE_FAC * tol : std::max(tol, LG_MIXED_PHASE1_TOL);
+}
+
 void pcg_release(lg_plan* p) {
     if (p->cg_graph) (void)hipGraphExecDestroy(p->cg_graph);
     p->cg_graph = nullptr;
