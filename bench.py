@@ -36,18 +36,21 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True, medium: int = 2):
+def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True, medium: int = 2,
+                 held: bool = False):
     """Algorithmic HBM bytes per shot-point for each kernel of one CG iteration
     (every array touched once per launch; medium arrays shared by all shots).
     fused: the update recomputes A p, so the operator kernel stores no q.
     medium: operator tables per point (kappa, w; the fourth-order operator
-    reads its x- and z-face tables and w)."""
+    reads its x- and z-face tables and w).  held: the update leaves x alone
+    (held search directions; the flush pass is counted by flush_bytes)."""
+    xb = 0 if held else 16                                    # x in/out (f64)
     if fused:
         op = ws + 2 * ws / shots                              # p in; kappa, w once per batch
-        upd = 32 + 2 * ws + 2 * ws / shots                    # x, r in/out (f64); p in; rhat out; medium
+        upd = xb + 16 + 2 * ws + 2 * ws / shots               # r in/out (f64); p in; rhat out; medium
     else:
         op = 2 * ws + medium * ws / shots                     # p in, q out; medium once per batch
-        upd = 32 + 3 * ws                                     # x, r in/out (f64); p, q in; rhat out
+        upd = xb + 16 + 3 * ws                                # r in/out (f64); p, q in; rhat out
     return {
         "operator": op,
         "update_fdst": upd,
@@ -55,6 +58,13 @@ def kernel_bytes(ws: int, shots: int, seg_len: int, fused: bool = True, medium: 
         "interfaces": (2 * ws + 24.0) / seg_len,              # separator rows, segment data
         "correct_idst": 3 * ws,                               # y in, p in/out
     }
+
+
+def flush_bytes(ws: int, mean_iters: float, phases: int) -> float:
+    """Held search directions: the flush passes' bytes per shot-point per CG
+    iteration: every direction read once; x written once after the cold
+    start's phase and read and written once after each later phase."""
+    return ws + (8.0 + 16.0 * (phases - 1)) / max(mean_iters, 1.0)
 
 
 def cyl_kernel_bytes(ws: int, shots: int, fused: bool = True, dichotomy: bool = True):
@@ -167,7 +177,8 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     run = AcousticRun(w, precision=precision, shots=shots, n_harm=max(n_harm, 2),
                       segments=tuned.get("segments", 0), graph_iters=tuned.get("graph_iters", 0),
                       op_shots=tuned.get("op_shots", 0), seg_per_wave=tuned.get("seg_per_wave", 0),
-                      op_fusion=tuned.get("op_fusion", 0), top=top, geometry=geometry, order=order)
+                      op_fusion=tuned.get("op_fusion", 0), top=top, geometry=geometry, order=order,
+                      x_ring=tuned.get("x_ring", 0))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     cyl = geometry == "cylindrical"
@@ -195,6 +206,8 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     seg, seg_len = run.plan.layout()
     out["segments"] = seg
     ws = 8 if precision == "fp64" else 4
+    x_ring = run.plan.x_ring()
+    held = x_ring > 1
     # the library's default op_fusion: stored q for FP64 axisymmetric plans
     # and the fourth-order operator, else recomputed in the update
     fusion = tuned.get("op_fusion", 0) or (2 if (cyl and precision == "fp64") or order == 4 else 1)
@@ -203,12 +216,14 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     elif order == 4:
         kb = kernel_bytes(ws, shots, seg_len, fused=False, medium=3)
     else:
-        kb = kernel_bytes(ws, shots, seg_len, fusion != 2)
+        kb = kernel_bytes(ws, shots, seg_len, fusion != 2, held=held)
     slots = [0, 1, 2, 4] if cyl else [0, 1, 2, 3, 4]          # the profile helper's kernel slots
-    per_iter_bytes = sum(kb.values()) * npts * shots
     mean_it = max(out["mean_iters"], 1e-9)
+    fb = flush_bytes(ws, mean_it, 2 if precision == "mixed" else 1) if held else 0.0
+    per_iter_bytes = (sum(kb.values()) + fb) * npts * shots
     t_iter = el / (steps * mean_it)
-    out["alg_bytes_per_point_iter"] = sum(kb.values())
+    out["x_ring"] = x_ring
+    out["alg_bytes_per_point_iter"] = sum(kb.values()) + fb
     out["whole_iteration_GBps"] = per_iter_bytes / t_iter / 1e9   # includes per-harmonic overheads
     if profile:
         # per-kernel durations on the same plan and stream, with the last timed
@@ -400,9 +415,11 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="library defaults instead of autotuned tiles")
     ap.add_argument("--elastic-only", action="store_true",
                     help="only the elastic GMRES(10) harmonics (for kernel traces of the elastic path)")
-    ap.add_argument("--op-shots", type=int, default=0, help="override (profile-only)")
-    ap.add_argument("--seg-per-wave", type=int, default=0, help="override (profile-only)")
-    ap.add_argument("--op-fusion", type=int, default=0, help="override (profile-only): 1 fused, 2 stored q")
+    ap.add_argument("--op-shots", type=int, default=0, help="override the tuned value")
+    ap.add_argument("--seg-per-wave", type=int, default=0, help="override the tuned value")
+    ap.add_argument("--op-fusion", type=int, default=0, help="override the tuned value: 1 fused, 2 stored q")
+    ap.add_argument("--x-ring", type=int, default=0,
+                    help="held CG search directions (1: x updated in every iteration; 0: library default)")
     ap.add_argument("--geometry", default="cartesian", choices=("cartesian", "cylindrical"),
                     help="profile-only: the 2D Cartesian or the 2.5D axisymmetric problem")
     ap.add_argument("--order", type=int, default=2, choices=(2, 4),
@@ -437,7 +454,8 @@ def main():
         # --profile-iters launches of each iteration kernel with all shots active
         geo = args.geometry
         tp = tuned_params(args.workload, prec, shots, not args.no_tune and geo == "cartesian")
-        tp.update({k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion") if getattr(args, k)})
+        tp.update({k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion", "x_ring")
+                   if getattr(args, k)})
         if args.order == 4:
             tp["op_fusion"] = 2
         v = run_variant(args.workload, prec, shots, args.steps, args.warmup, segments=args.segments,
@@ -449,6 +467,8 @@ def main():
                                                                          "profile_iterations": args.profile_iters}))
         return
     head_tuned = tuned_params(args.workload, prec, shots, not args.no_tune)
+    head_tuned.update({k: getattr(args, k) for k in ("op_shots", "seg_per_wave", "op_fusion", "x_ring")
+                       if getattr(args, k)})
     head = run_variant(args.workload, prec, shots, args.steps, args.warmup,
                        segments=args.segments, graph_iters=args.graph_iters, tuned=head_tuned,
                        profile_iters=args.profile_iters)

@@ -152,14 +152,28 @@ typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
  *                (p, A p); 2 = stored by the operator kernel and read back.
  *                Both give bitwise the same iterates.  0 = default: 1, except
  *                2 for FP64 axisymmetric plans (faster there) and for the
- *                fourth-order operator (which has only the stored form). */
+ *                fourth-order operator (which has only the stored form).
+ *  x_ring        search directions held before they are added into x
+ *                (Cartesian second-order acoustic CG): iteration k keeps
+ *                p_k and alpha_k, and x += alpha_j p_j is applied in order,
+ *                in FP64, by one pass at the end of each CG phase (or before
+ *                a held direction would be overwritten), so the update does
+ *                not read and write x in every iteration; the iterates are
+ *                bitwise those of the in-place update.  1 = x updated in
+ *                every iteration (the only form of the other plans); else
+ *                more than graph_iters (8 without a graph) and at most 64
+ *                directions (memory: x_ring copies of p); 0 = default:
+ *                max(16, graph_iters + 1), halved (not below graph_iters + 1)
+ *                while the copies would pass 64 GiB, 1 if they still do.
+ *  reserved      must be 0. */
 typedef struct {
     int32_t segments;
     int32_t graph_iters;
     int32_t op_shots;
     int32_t seg_per_wave;
     int32_t op_fusion;
-    int32_t reserved[3];
+    int32_t x_ring;
+    int32_t reserved[2];
 } lg_tuning;
 
 typedef struct lg_plan lg_plan;
@@ -193,6 +207,10 @@ lg_status lg_plan_set_sources(lg_plan* plan, const int32_t* src_ij_host /*[S][2]
 
 /* Segments P and segment length nz/P actually used by the plan. */
 lg_status lg_plan_layout(const lg_plan* plan, int32_t* segments, int32_t* seg_len);
+
+/* Search directions the plan's CG holds before adding them into x (lg_tuning
+ * x_ring as resolved at plan creation; 1 = x updated in every iteration). */
+lg_status lg_plan_x_ring(const lg_plan* plan, int32_t* x_ring);
 
 /* ---------------------------------------------------------------------------
  * Host helpers for the Laguerre transform (Sec. 2.1, eq. series_lag)

@@ -48,7 +48,8 @@ class SolveInfo(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("segments", c_int32), ("graph_iters", c_int32), ("op_shots", c_int32),
-                ("seg_per_wave", c_int32), ("op_fusion", c_int32), ("reserved", c_int32 * 3)]
+                ("seg_per_wave", c_int32), ("op_fusion", c_int32), ("x_ring", c_int32),
+                ("reserved", c_int32 * 2)]
 
 
 _PLAN = c_void_p
@@ -59,6 +60,7 @@ _SIGNATURES = {
     "lg_plan_set_stream": [_PLAN, c_void_p],
     "lg_plan_set_sources": [_PLAN, POINTER(c_int32)],
     "lg_plan_layout": [_PLAN, POINTER(c_int32), POINTER(c_int32)],
+    "lg_plan_x_ring": [_PLAN, POINTER(c_int32)],
     "lg_source_coeffs": [c_int32, c_double, c_double, c_double, POINTER(Laguerre), POINTER(c_double)],
     "lg_laguerre_weights": [POINTER(Laguerre), POINTER(c_double), c_int32, POINTER(c_double)],
     "lg_status_string": [c_int32],

@@ -60,7 +60,7 @@ class Plan:
                  n: int, medium: np.ndarray, precision: str = "fp64", nshots: int = 1,
                  segments: int = 0, graph_iters: int = 0, op_shots: int = 0, seg_per_wave: int = 0,
                  op_fusion: int = 0, top: str = "dirichlet", geometry: str = "cartesian",
-                 order: int = 2, stream=None):
+                 order: int = 2, x_ring: int = 0, stream=None):
         import torch
         self.lib = _lib.load()
         self.kind = kind
@@ -79,7 +79,7 @@ class Plan:
         grid = _lib.Grid(nx, nz, dx, dz, _lib.LG_TOP_FREE if top == "free" else _lib.LG_TOP_DIRICHLET,
                          _lib.LG_CYLINDRICAL if geometry == "cylindrical" else _lib.LG_CARTESIAN, order, 0)
         lag = _lib.Laguerre(alpha, h, n)
-        tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion)
+        tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion, x_ring)
         if stream is None:
             stream = torch.cuda.current_stream()
         self.stream = stream
@@ -117,6 +117,11 @@ class Plan:
         a, b = ctypes.c_int32(), ctypes.c_int32()
         check(self.lib.lg_plan_layout(self.handle, ctypes.byref(a), ctypes.byref(b)), "lg_plan_layout")
         return a.value, b.value
+
+    def x_ring(self) -> int:
+        a = ctypes.c_int32()
+        check(self.lib.lg_plan_x_ring(self.handle, ctypes.byref(a)), "lg_plan_x_ring")
+        return a.value
 
     def set_sources(self, src_ij: np.ndarray):
         s = np.ascontiguousarray(np.asarray(src_ij, dtype=np.int32).reshape(self.nshots, 2))

@@ -51,6 +51,8 @@ struct StArgs {
     ShotCtl* ctl;
     double* partial;
     size_t pstride;
+    int pring;           // > 1 (with ctl): p of a shot at slot iters % pring
+    size_t pslot;        // elements per slot
 };
 
 // The medium (kappa at the nodes the column touches, w) is loaded once into
@@ -77,9 +79,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
     const int s0 = bz * a.nsh;
     const int ns = min(a.nsh, a.nfields - s0);
     __shared__ int act[ST_MAXSH];
+    __shared__ int pslot[ST_MAXSH];                 // held directions: the shot's slot of p
     int mine = 0;
     if (threadIdx.x < ns) {
-        act[threadIdx.x] = (a.ctl != nullptr && !RESN) ? a.ctl[s0 + threadIdx.x].active : 1;
+        const bool cg = a.ctl != nullptr && !RESN;
+        act[threadIdx.x] = cg ? a.ctl[s0 + threadIdx.x].active : 1;
+        pslot[threadIdx.x] = (cg && a.pring > 1) ? a.ctl[s0 + threadIdx.x].iters % a.pring : 0;
         mine = act[threadIdx.x];
     }
     if (__syncthreads_or(mine != 0) == 0) return;   // (also the barrier for act) uniform per block
@@ -124,7 +129,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
         const int field = s0 + k;
         if (act[k] == 0) continue;              // uniform per block
         const size_t fb = (size_t)field * nx1 * nz1;
-        const rsrc_t rp = buf_rsrc(a.p + fb, fbytes);
+        const size_t ps = (size_t)pslot[k] * a.pslot;
+        const rsrc_t rp = buf_rsrc(a.p + ps + fb, fbytes);
         T pv[ST_RPT + 2], pe[ST_RPT], pw[ST_RPT];
 #pragma unroll
         for (int r = 0; r < ST_RPT + 2; ++r) pv[r] = bload<T>(rp, oc[r]);
@@ -216,7 +222,9 @@ struct DstArgs {
     double** xslot;
     double* r;
     const double* b;       // UPDATE init: right-hand side
-    const T* p;            // UPDATE: search direction
+    const T* p;            // UPDATE: search direction (slot 0)
+    int pring;             // > 1: held directions, p_k at slot k % pring; x not touched
+    size_t pslot;          // elements per slot
     const T* q;            // UPDATE: A p
     const T* kap;          // UPDATE_OP: node kappa, (nz+1) x (nx+1)
     const T* wsh;          // UPDATE_OP: interior shift
@@ -319,14 +327,19 @@ dst_kernel(DstArgs<T> a) {
     const int j0 = 2 * pair, j1 = j0 + 1;
     const bool has1 = live && (j1 < a.nz1);
 
+    int kit = 0;                               // completed iterations of the shot
     if constexpr (UPD || MODE == DST_CORRECT) {
         bool skip = a.ctl[field].active == 0;
         if (UPD && a.init) skip = false;
         if (skip) return;   // uniform per block: blocks never span fields
+        kit = a.ctl[field].iters;
     }
 
     cpx<T>* buf = lds + fid * LL;
     const size_t fbase = (size_t)field * a.nz1 * NX1;
+    // CORRECT with held directions: p_{k+1} (or the first direction of a
+    // phase) goes to slot iters % pring
+    T* const outp = a.out + ((MODE == DST_CORRECT && a.pring > 1) ? (size_t)(kit % a.pring) * a.pslot : 0);
     const size_t o0 = fbase + (size_t)j0 * NX1;
     const size_t o1 = fbase + (size_t)j1 * NX1;
     double rr = 0.0, bb = 0.0;
@@ -407,11 +420,15 @@ dst_kernel(DstArgs<T> a) {
             double* const Xb = wave_uniform(X != nullptr ? X + fbase : a.r);
             const double* const Rb =
                 wave_uniform(init == 1 ? a.b + fbase : (B0 != nullptr ? B0 + fbase : a.r + fbase));
-            const rsrc_t rX = buf_rsrc(Xb, (init == 0 && !fresh) ? nfe * 8u : 0u);
-            const rsrc_t rXs = buf_rsrc(Xb, init == 0 ? nfe * 8u : 0u);
+            // held directions: x is neither read nor written here (the flush
+            // pass adds alpha_k p_k later); p_k sits at slot k % pring
+            const bool xin = a.pring == 1;
+            const rsrc_t rX = buf_rsrc(Xb, (init == 0 && !fresh && xin) ? nfe * 8u : 0u);
+            const rsrc_t rXs = buf_rsrc(Xb, (init == 0 && xin) ? nfe * 8u : 0u);
             const rsrc_t rR = buf_rsrc(Rb, nfe * 8u);
             const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 0 ? nfe * 8u : 0u);
-            const rsrc_t rP = buf_rsrc(a.p + fbase, init == 0 ? nfe * SZ : 0u);
+            const size_t pofs = (init == 0 && a.pring > 1) ? (size_t)(kit % a.pring) * a.pslot : 0;
+            const rsrc_t rP = buf_rsrc(a.p + pofs + fbase, init == 0 ? nfe * SZ : 0u);
             const rsrc_t rQ = buf_rsrc(a.q + fbase, (init == 0 && MODE == DST_UPDATE) ? nfe * SZ : 0u);
 #pragma unroll
             for (int cb = 0; cb < NIT; cb += CH) {
@@ -529,8 +546,10 @@ dst_kernel(DstArgs<T> a) {
                     }
                 }
             }
-            // p of the outputs this thread will write (read now, used after the FFT)
-            const rsrc_t rPo = buf_rsrc(a.out + fbase, a.init ? 0u : nfe * SZ);
+            // p of the outputs this thread will write (read now, used after the
+            // FFT): p_k, at slot k % pring with k = iters - 1 (held directions)
+            const size_t rofs = (!a.init && a.pring > 1) ? (size_t)((kit + a.pring - 1) % a.pring) * a.pslot : 0;
+            const rsrc_t rPo = buf_rsrc(a.out + rofs + fbase, a.init ? 0u : nfe * SZ);
 #pragma unroll
             for (int u = 0; u < NOUT; ++u) {
                 const int col = HALF ? t + u * TPF : t + (u / (RL / 2)) * TPF + (u % (RL / 2)) * NSL - 1;
@@ -649,22 +668,22 @@ dst_kernel(DstArgs<T> a) {
                 const cpx<T> F = buf[lpad(col)];
                 T x0 = F.x, x1 = F.y;
                 if constexpr (MODE == DST_FWD || UPD) {
-                    a.out[o0 + col] = x0;
-                    if (has1) a.out[o1 + col] = x1;
+                    outp[o0 + col] = x0;
+                    if (has1) outp[o1 + col] = x1;
                 } else if constexpr (MODE == DST_INV) {
                     const T sc = (T)(2.0 / NX);
-                    a.out[o0 + col] = x0 * sc;
-                    if (has1) a.out[o1 + col] = x1 * sc;
+                    outp[o0 + col] = x0 * sc;
+                    if (has1) outp[o1 + col] = x1 * sc;
                 } else {   // CORRECT: p = z + beta p  (init: p = z)
                     const T sc = (T)(2.0 / NX);
                     x0 *= sc;
                     x1 *= sc;
                     if (a.init) {
-                        a.out[o0 + col] = x0;
-                        if (has1) a.out[o1 + col] = x1;
+                        outp[o0 + col] = x0;
+                        if (has1) outp[o1 + col] = x1;
                     } else {
-                        a.out[o0 + col] = x0 + beta * pold0[u];
-                        if (has1) a.out[o1 + col] = x1 + beta * pold1[u];
+                        outp[o0 + col] = x0 + beta * pold0[u];
+                        if (has1) outp[o1 + col] = x1 + beta * pold1[u];
                     }
                 }
             }
@@ -690,23 +709,23 @@ dst_kernel(DstArgs<T> a) {
                     const cpx<T> V = v[qb * RL + u];
                     T x0 = -V.y * (T)0.5, x1 = V.x * (T)0.5;
                     if constexpr (MODE == DST_FWD || UPD) {
-                        a.out[o0 + col] = x0;
-                        if (has1) a.out[o1 + col] = x1;
+                        outp[o0 + col] = x0;
+                        if (has1) outp[o1 + col] = x1;
                     } else if constexpr (MODE == DST_INV) {
                         const T sc = (T)(2.0 / NX);
-                        a.out[o0 + col] = x0 * sc;
-                        if (has1) a.out[o1 + col] = x1 * sc;
+                        outp[o0 + col] = x0 * sc;
+                        if (has1) outp[o1 + col] = x1 * sc;
                     } else {   // CORRECT: p = z + beta p  (init: p = z)
                         const T sc = (T)(2.0 / NX);
                         const int oi = qb * (RL / 2) + u;
                         x0 *= sc;
                         x1 *= sc;
                         if (a.init) {
-                            a.out[o0 + col] = x0;
-                            if (has1) a.out[o1 + col] = x1;
+                            outp[o0 + col] = x0;
+                            if (has1) outp[o1 + col] = x1;
                         } else {
-                            a.out[o0 + col] = x0 + beta * pold0[oi];
-                            if (has1) a.out[o1 + col] = x1 + beta * pold1[oi];
+                            outp[o0 + col] = x0 + beta * pold0[oi];
+                            if (has1) outp[o1 + col] = x1 + beta * pold1[oi];
                         }
                     }
                 }
@@ -1002,6 +1021,8 @@ struct FinArgs {
     double tol2r;     // (init 1, 4) squared recursive tolerance of restart phases
     int max_iter;
     double scale;     // FIN_RZ: b * 2/nx
+    double* ahist;    // FIN_PQ with pring > 1: alpha_k kept at [field][k % pring]
+    int pring;
 };
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
@@ -1031,6 +1052,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.active = 0;
         } else {
             c.alpha = c.rz / tot;
+            if (a.pring > 1) a.ahist[(size_t)field * a.pring + c.iters % a.pring] = c.alpha;
         }
     } else if (a.kind == FIN_RR) {
         c.rr = tot;
@@ -1041,6 +1063,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.tol2r = a.tol2r * bbt;
             c.iters = 0;
             c.fresh = 0;                     // x and r are stored
+            c.xdone = 0;
+            c.xzero = 0;
             c.max_iter = a.max_iter;
             c.alpha = 0.0;
             c.beta = 0.0;
@@ -1084,6 +1108,8 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.alpha = 0.0;
             c.beta = 0.0;
             c.fresh = 1;                         // cold start: x = 0, r = b implied
+            c.xdone = 0;
+            c.xzero = 1;
             if (!isfinite(tot)) {
                 c.status = LG_ERR_NONFINITE;
                 c.active = 0;
@@ -1122,6 +1148,59 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.rz = rz;
         }
     }
+}
+
+// Held search directions: x += alpha_j p_j for j = xdone .. iters-1, in
+// order, with the FP64 product and sum of the in-place update (so x is
+// bitwise the same); x is taken as 0 while xzero (a cold start that has not
+// been flushed), which also writes x = 0 for a shot that never iterated.
+// One pass reads the held directions once and x once, writes x once.
+constexpr int FLUSH_EPT = 4;   // elements per thread
+template <typename T>
+__global__ __launch_bounds__(256) void flush_x_kernel(double* __restrict__ x, const T* __restrict__ pr,
+                                                      const double* __restrict__ ahist,
+                                                      const ShotCtl* __restrict__ ctl, int pring, size_t pslot,
+                                                      size_t npts, int bpf) {
+    const int field = blockIdx.x / bpf;
+    const int bif = blockIdx.x - field * bpf;
+    const int j0 = ctl[field].xdone;
+    const int n = ctl[field].iters - j0;
+    const bool zero = ctl[field].xzero != 0;
+    if (n <= 0 && !zero) return;                    // uniform per block
+    const size_t fb = (size_t)field * npts;
+    const size_t e0 = (size_t)bif * (256 * FLUSH_EPT) + threadIdx.x;
+    double v[FLUSH_EPT];
+#pragma unroll
+    for (int u = 0; u < FLUSH_EPT; ++u) {
+        const size_t e = e0 + (size_t)u * 256;
+        v[u] = (!zero && e < npts) ? x[fb + e] : 0.0;
+    }
+    for (int j = 0; j < n; ++j) {
+        const int sl = (j0 + j) % pring;
+        const double al = ahist[(size_t)field * pring + sl];
+        const T* ps = pr + (size_t)sl * pslot + fb;
+        T pv[FLUSH_EPT];
+#pragma unroll
+        for (int u = 0; u < FLUSH_EPT; ++u) {
+            const size_t e = e0 + (size_t)u * 256;
+            pv[u] = e < npts ? ps[e] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < FLUSH_EPT; ++u) v[u] = v[u] + al * (double)pv[u];
+    }
+#pragma unroll
+    for (int u = 0; u < FLUSH_EPT; ++u) {
+        const size_t e = e0 + (size_t)u * 256;
+        if (e < npts) x[fb + e] = v[u];
+    }
+}
+
+// after a flush: every held direction is in x
+__global__ __launch_bounds__(256) void flush_done_kernel(ShotCtl* ctl, int nf) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    ctl[f].xdone = ctl[f].iters;
+    ctl[f].xzero = 0;
 }
 
 // Standalone interface correction (the CG path fuses it into K5):
@@ -1267,6 +1346,8 @@ hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int
     f.tol2 = tol2;
     f.max_iter = max_iter;
     f.scale = scale;
+    f.ahist = p->ahist;
+    f.pring = p->pring;
     hipLaunchKernelGGL(finalize_kernel, dim3(p->S * p->C), dim3(256), 0, p->stream, f);
     return hipGetLastError();
 }
@@ -1286,6 +1367,8 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
     a.ctl = reduce ? p->ctl : nullptr;
+    a.pring = reduce ? p->pring : 1;
+    a.pslot = p->nvec;
     a.free_top = p->free_top ? 1 : 0;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
@@ -1314,6 +1397,8 @@ hipError_t residual_check_T(lg_plan* p, const double* b, const double* x) {
     a.idx2 = 1.0 / (p->g.dx * p->g.dx);
     a.idz2 = 1.0 / (p->g.dz * p->g.dz);
     a.ctl = p->ctl;
+    a.pring = 1;
+    a.pslot = 0;
     a.free_top = p->free_top ? 1 : 0;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
@@ -1370,6 +1455,8 @@ DstArgs<T> dst_args(lg_plan* p) {
     a.xslot = p->xslot;
     a.r = p->r;
     a.p = (const T*)p->p;
+    a.pring = p->pring;
+    a.pslot = p->nvec;
     a.q = (const T*)p->qv;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
@@ -1576,6 +1663,23 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
     // phase_tol; the true residual is checked against tol.
     const double t1 = phase_tol(p, tol, false), tr = phase_tol(p, tol, true);
     return finalize(p, FIN_RR, bpf, init == 3 ? 2 : init, t1 * t1, max_iter, 0.0, tol * tol, tr * tr);
+}
+
+hipError_t launch_flush_x(lg_plan* p, double* x) {
+    if (p->pring <= 1) return hipSuccess;
+    const int nf = p->S * p->C;
+    const int bpf = (int)((p->npts + 256 * FLUSH_EPT - 1) / (256 * FLUSH_EPT));
+    const dim3 grid((unsigned)bpf * (unsigned)nf);
+    if (p->prec == LG_FP64)
+        hipLaunchKernelGGL(flush_x_kernel<double>, grid, dim3(256), 0, p->stream, x, (const double*)p->p, p->ahist,
+                           p->ctl, p->pring, p->nvec, p->npts, bpf);
+    else
+        hipLaunchKernelGGL(flush_x_kernel<float>, grid, dim3(256), 0, p->stream, x, (const float*)p->p, p->ahist,
+                           p->ctl, p->pring, p->nvec, p->npts, bpf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(flush_done_kernel, dim3((nf + 255) / 256), dim3(256), 0, p->stream, p->ctl, nf);
+    return hipGetLastError();
 }
 
 hipError_t launch_correct_idst(lg_plan* p, int init) {

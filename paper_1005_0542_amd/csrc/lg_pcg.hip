@@ -105,6 +105,18 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
         LG_HIP(launch_correct_idst(p, 1));
     }
 
+    // Held search directions: x is brought up to date by a flush pass before
+    // anything reads it (the FP64 check and restart, the end of the solve) and
+    // before a batch could overwrite a direction not yet added (at most
+    // pring - 1 iterations between flushes; a batch is shorter).
+    const bool held = p->pring > 1;
+    int since = 0;                    // iterations queued since the last flush
+    auto flush = [&]() -> lg_status {
+        if (held) LG_HIP(launch_flush_x(p, x));
+        since = 0;
+        return LG_OK;
+    };
+
     // Replay batches of captured iterations until every shot has stopped.
     // Consecutive harmonics take similar iteration counts, so as many batches
     // as the previous solve needed in the same phase (up to the first stop,
@@ -115,6 +127,11 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
         const long cap = (long)o->max_iter + chunk;
         while (true) {
             for (long bt = 0; bt < ahead && launched < cap; ++bt) {
+                if (held && since + chunk > p->pring - 1) {
+                    const lg_status fs = flush();
+                    if (fs != LG_OK) return fs;
+                }
+                since += chunk;
                 if (use_graph) {
                     LG_HIP(hipGraphLaunch(p->cg_graph, p->stream));
                 } else {
@@ -165,6 +182,7 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
         for (int rep = 0; rep <= MAX_RESTARTS; ++rep) {
             bool any = false;
             const bool fused = !p->cyl && p->order == 2 && rep == 0;
+            if ((st = flush()) != LG_OK) return st;       // the check and the restart read x
             if (!fused) {
                 LG_HIP(launch_residual_check(p, b, x));       // axisymmetric, fourth order: stores r too
                 if ((st = any_active(any)) != LG_OK) return st;
@@ -190,7 +208,9 @@ lg_status pcg_solve(lg_plan* p, const double* b, double* x, const lg_solve_opts*
             if (rep == 0) after_restart = max_iters() - first_stop;
         }
     }
-    if (!o->x0_given) {                   // a cold start stores no x: a shot that never
+    if (held) {                           // the remaining directions; x = 0 for a cold-start
+        if ((st = flush()) != LG_OK) return st;   // shot that never iterated
+    } else if (!o->x0_given) {            // a cold start stores no x: a shot that never
         for (int s = 0; s < nf; ++s)      // iterated (b = 0, or not finite) gets x = 0
             if (p->ctl_host[s].iters == 0)
                 LG_HIP(hipMemsetAsync(x + (size_t)s * p->npts, 0, p->npts * sizeof(double), p->stream));
@@ -235,8 +255,16 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
     double acc[5] = {0, 0, 0, 0, 0};
     hipError_t e = hipSuccess;
     // iteration 0 is not timed: after a cold start the first update reads b
-    // for r and no x (fewer bytes than every later one)
+    // for r and no x (fewer bytes than every later one).  Held directions are
+    // flushed into x between timed iterations where needed, and at the end.
+    int since = 0;
     for (int it = 0; it <= iters && e == hipSuccess; ++it) {
+        if (!cy && p->pring > 1 && since + 1 > p->pring - 1) {
+            e = launch_flush_x(p, x);
+            since = 0;
+            if (e != hipSuccess) break;
+        }
+        ++since;
         e = hipEventRecord(ev[0], p->stream);
         if (e == hipSuccess) e = launch_stencil(p, p->p, p->fuse_op ? nullptr : p->qv, true);
         if (e == hipSuccess) e = hipEventRecord(ev[1], p->stream);
@@ -259,6 +287,7 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
         }
     }
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+    if (e == hipSuccess && !cy) e = launch_flush_x(p, x);
     if (e != hipSuccess) return hip_fail(e, "lg_pcg_profile");
     for (int k = 0; k < 5; ++k) ms[k] = (float)(acc[k] / iters);
     return LG_OK;

@@ -431,7 +431,7 @@ void free_plan(lg_plan* p) {
     if (!p) return;
     pcg_release(p);
     void* ptrs[] = {p->kap, p->lam, p->mu, p->w, p->rho64, p->kap64, p->w64, p->tw, p->src_dev, p->r, p->p, p->qv,
-                    p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->gm_V,
+                    p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->ahist, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
                     p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64,
@@ -604,14 +604,26 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if (order == 4 && (kind != LG_ACOUSTIC || cyl || grid->top_bc != LG_TOP_DIRICHLET))
         return fail(LG_ERR_UNSUPPORTED, "the fourth-order operator is implemented for Cartesian acoustic plans "
                                         "with Dirichlet sides");
-    int P = 0, gi = 8, osh = 8, spw = 0, fus = 1;
+    int P = 0, gi = 8, osh = 8, spw = 0, fus = 1, ring = 0;
     if (tuning != nullptr) {
         P = tuning->segments;
         if (tuning->graph_iters != 0) gi = tuning->graph_iters;
         if (tuning->op_shots != 0) osh = tuning->op_shots;
         spw = tuning->seg_per_wave;
         if (tuning->op_fusion != 0) fus = tuning->op_fusion;
+        ring = tuning->x_ring;
+        if (tuning->reserved[0] != 0 || tuning->reserved[1] != 0)
+            return fail(LG_ERR_INVALID_ARG, "lg_tuning.reserved must be 0");
     }
+    // held search directions: Cartesian second-order acoustic CG only
+    const bool ring_ok = kind == LG_ACOUSTIC && !cyl && order == 2;
+    if (ring < 0 || ring > 64) return fail(LG_ERR_INVALID_ARG, "x_ring must be in 0..64");
+    if (ring > 1 && !ring_ok)
+        return fail(LG_ERR_UNSUPPORTED, "x_ring > 1 is implemented for Cartesian second-order acoustic plans");
+    // a batch of CG iterations between flushes (graph_iters, or 8 without a
+    // graph) must leave a free slot for the next direction
+    const int batch = gi > 0 ? gi : 8;
+    if (ring > 1 && ring <= batch) return fail(LG_ERR_INVALID_ARG, "x_ring must exceed graph_iters (8 without a graph)");
     if (fus != 1 && fus != 2) return fail(LG_ERR_INVALID_ARG, "op_fusion must be 0, 1 or 2");
     // default form: the FP64 axisymmetric update is register-bound with A p
     // recomputed (measured faster with the stored q)
@@ -664,6 +676,15 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->td_spw = spw;
     p->order = order;
     p->fuse_op = (fus == 1) && order == 2;
+    if (ring == 0 && ring_ok) {
+        // default: 16 held directions (more than a batch), fewer where the
+        // slots would pass 64 GiB, none where fewer would not exceed a batch
+        const size_t slot = p->nvec * (prec == LG_FP64 ? 8 : 4);
+        ring = std::max(16, batch + 1);
+        while (ring > batch + 1 && (size_t)ring * slot > ((size_t)64 << 30)) ring = std::max(batch + 1, ring / 2);
+        if ((size_t)ring * slot > ((size_t)64 << 30) || ring < 4) ring = 1;
+    }
+    p->pring = std::max(1, ring);
     p->free_top = (grid->top_bc == LG_TOP_FREE) && !cyl && kind == LG_ACOUSTIC;
     p->el_free = (grid->top_bc == LG_TOP_FREE) && kind == LG_ELASTIC;
     p->src_scale = cyl ? 1.0 / (2.0 * 3.141592653589793 * grid->dx * grid->dz) : 1.0 / (grid->dx * grid->dz);
@@ -779,7 +800,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     const size_t ws = wsize(p);
     const int SC = p->S * p->C;
     if ((st = dev_alloc(p, &p->r, p->nvec * 8)) != LG_OK) return bail(st);
-    if ((st = dev_alloc(p, (char**)&p->p, p->nvec * ws)) != LG_OK) return bail(st);
+    if ((st = dev_alloc(p, (char**)&p->p, (size_t)p->pring * p->nvec * ws)) != LG_OK) return bail(st);
+    if ((st = dev_alloc(p, &p->ahist, (size_t)SC * p->pring * 8)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, (char**)&p->qv, p->nvec * ws)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, (char**)&p->rhat, p->nvec * ws)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, (char**)&p->y, p->nvec * ws)) != LG_OK) return bail(st);
@@ -833,6 +855,13 @@ lg_status lg_plan_layout(const lg_plan* plan, int32_t* segments, int32_t* seg_le
     LG_CHECK(check_plan(plan));
     if (segments) *segments = plan->blk[0].P;
     if (seg_len) *seg_len = plan->blk[0].Ls;
+    return LG_OK;
+}
+
+lg_status lg_plan_x_ring(const lg_plan* plan, int32_t* x_ring) {
+    LG_CHECK(check_plan(plan));
+    if (x_ring == nullptr) return fail(LG_ERR_INVALID_ARG, "NULL argument");
+    *x_ring = plan->pring;
     return LG_OK;
 }
 

@@ -31,7 +31,7 @@ class AcousticRun:
                  snapshots: bool = True, rec: bool = True, tol: Optional[float] = None,
                  max_iter: int = 10000, medium=None, op_shots: int = 0, seg_per_wave: int = 0,
                  op_fusion: int = 0, top: str = "dirichlet", warm_start: bool = False,
-                 geometry: str = "cartesian", order: int = 2):
+                 geometry: str = "cartesian", order: int = 2, x_ring: int = 0):
         import torch
         self.torch = torch
         self.w = w
@@ -58,7 +58,7 @@ class AcousticRun:
                              np.stack([kappa, rho]), precision=self.precision, nshots=self.shots,
                              segments=segments, graph_iters=graph_iters, op_shots=op_shots,
                              seg_per_wave=seg_per_wave, op_fusion=op_fusion, top=top, geometry=geometry,
-                             order=order)
+                             order=order, x_ring=x_ring)
         if self.shots == w.shots:
             src = inputs.sources_for(w)
         else:

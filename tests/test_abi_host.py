@@ -45,7 +45,7 @@ def test_status_strings():
 
 def _create(kind=_lib.LG_ACOUSTIC, nx=16, nz=16, dx=5.0, dz=5.0, alpha=9, h=200.0, n=8,
             prec=_lib.LG_FP64, shots=1, medium="ok", segments=0, graph_iters=0, top=0, op_shots=0,
-            seg_per_wave=0, op_fusion=0, geometry=0, order=0):
+            seg_per_wave=0, op_fusion=0, geometry=0, order=0, x_ring=0, reserved=(0, 0)):
     lib = _lib.load()
     F = 2 if kind == _lib.LG_ACOUSTIC else 3
     if isinstance(medium, str):
@@ -55,7 +55,8 @@ def _create(kind=_lib.LG_ACOUSTIC, nx=16, nz=16, dx=5.0, dz=5.0, alpha=9, h=200.
     med = np.ascontiguousarray(med, dtype=np.float64)
     grid = _lib.Grid(nx, nz, dx, dz, top, geometry, order)
     lag = _lib.Laguerre(alpha, h, n)
-    tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion)
+    tun = _lib.Tuning(segments, graph_iters, op_shots, seg_per_wave, op_fusion, x_ring)
+    tun.reserved[0], tun.reserved[1] = reserved
     handle = ctypes.c_void_p()
     st = lib.lg_plan_create(ctypes.byref(handle), kind, ctypes.byref(grid), ctypes.byref(lag), prec, shots,
                             med.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(tun), None)
@@ -69,6 +70,9 @@ def _create(kind=_lib.LG_ACOUSTIC, nx=16, nz=16, dx=5.0, dz=5.0, alpha=9, h=200.
     dict(graph_iters=1000), dict(top=2), dict(top=-1), dict(op_shots=65), dict(op_shots=-1),
     dict(seg_per_wave=3), dict(seg_per_wave=8), dict(op_fusion=3), dict(geometry=2), dict(geometry=-1),
     dict(order=3), dict(order=6), dict(order=-2),
+    dict(x_ring=-1), dict(x_ring=65), dict(reserved=(1, 0)), dict(reserved=(0, -3)),
+    # held search directions must outnumber a batch of iterations between flushes
+    dict(x_ring=2, graph_iters=2), dict(x_ring=8, graph_iters=-1), dict(x_ring=16, graph_iters=16),
 ])
 def test_plan_create_rejects_invalid_arguments(kw):
     assert _create(**kw) == _lib.LG_ERR_INVALID_ARG
@@ -95,6 +99,13 @@ def test_plan_create_unsupported_shapes():
     assert _create(kind=_lib.LG_ELASTIC, order=4) == _lib.LG_ERR_UNSUPPORTED
     assert _create(geometry=cyl, order=4) == _lib.LG_ERR_UNSUPPORTED
     assert _create(top=_lib.LG_TOP_FREE, order=4) == _lib.LG_ERR_UNSUPPORTED
+
+
+def test_plan_create_held_directions_unsupported_outside_cartesian_second_order_acoustic():
+    assert _create(x_ring=4, graph_iters=2, kind=_lib.LG_ELASTIC) == _lib.LG_ERR_UNSUPPORTED
+    assert _create(x_ring=4, graph_iters=2, geometry=_lib.LG_CYLINDRICAL) == _lib.LG_ERR_UNSUPPORTED
+    assert _create(x_ring=4, graph_iters=2, order=4) == _lib.LG_ERR_UNSUPPORTED
+    assert "x_ring" in _lib.load().lg_last_error().decode()
 
 
 def test_plan_create_rejects_vectors_of_2_to_the_32_elements():

@@ -1,0 +1,127 @@
+"""Held search directions (lg_tuning.x_ring > 1): CG keeps p_k and alpha_k and
+adds x += alpha_j p_j in order in a flush pass, instead of reading and
+writing x in every update.  The iterates must be bitwise those of the
+in-place update (x_ring = 1): the same FP64 products and sums in the same
+order.  Covered: FP64 and mixed precision (whose refinement reads x for the
+true residual), graphs and plain launches, flushes inside a phase (small
+rings), shots that stop at different iterations, a zero right-hand side, a
+start from a given x, the profile helper, and the solution against the
+oracle's PCG."""
+import numpy as np
+import pytest
+
+from oracle import operator, precond, krylov, OK
+
+from _gpu import heterogeneous, log, rel, to_dev, to_np, torch_cuda
+from paper_1005_0542_amd import api
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(nx, nz, kappa, rho, h, precision, shots, graph_iters=0, x_ring=0, segments=0):
+    med = np.stack([kappa, rho])
+    return api.Plan("acoustic", nx, nz, 10.0, 10.0, 9, h, 8, med, precision=precision, nshots=shots,
+                    segments=segments, graph_iters=graph_iters, x_ring=x_ring)
+
+
+def _rhs(nx, nz, shots, seed=21):
+    b = np.random.default_rng(seed).standard_normal((shots, nz - 1, nx - 1))
+    if shots > 1:
+        b[1] = 0.0                       # zero right-hand side: x = 0, no iteration
+    if shots > 2:
+        b[2] *= 1e-4
+    if shots > 3:
+        b[3, :, : (nx - 1) // 2] = 0.0   # a different spectrum: a different iteration count
+    return b
+
+
+def _solve(plan, b, tol, max_iter=400, x0=None):
+    torch = torch_cuda()
+    bd = to_dev(b, torch.float64)
+    xd = to_dev(x0, torch.float64) if x0 is not None else torch.full_like(bd, 3.0)
+    res = plan.pcg_solve(bd, xd, tol=tol, max_iter=max_iter, x0_given=x0 is not None)
+    return to_np(xd), res
+
+
+@pytest.mark.parametrize("precision,nx,nz,gi,ring", [
+    ("fp64", 128, 64, 0, 0), ("fp64", 128, 64, 2, 3), ("fp64", 64, 128, -1, 9), ("fp64", 256, 32, 4, 5),
+    ("mixed", 128, 64, 0, 0), ("mixed", 128, 64, 2, 3), ("mixed", 64, 128, -1, 9), ("mixed", 512, 64, 2, 0),
+])
+def test_held_directions_bitwise_equal_in_place_update(precision, nx, nz, gi, ring):
+    kappa, rho = heterogeneous(nx, nz)
+    h = 200.0
+    S = 4
+    b = _rhs(nx, nz, S)
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    ref_plan = _plan(nx, nz, kappa, rho, h, precision, S, graph_iters=gi, x_ring=1)
+    assert ref_plan.x_ring() == 1
+    log(f"held {precision} {nx}x{nz} graph_iters={gi}: in-place reference")
+    x1, r1 = _solve(ref_plan, b, tol)
+    plan = _plan(nx, nz, kappa, rho, h, precision, S, graph_iters=gi, x_ring=ring)
+    K = plan.x_ring()
+    assert K == (ring if ring else 16)
+    for rep in range(2):                 # the second solve reuses the plan's slots
+        log(f"held {precision} {nx}x{nz} graph_iters={gi} x_ring={K} solve {rep}")
+        x2, r2 = _solve(plan, b, tol)
+        assert r2.statuses == r1.statuses and r2.iters == r1.iters
+        assert r2.relres == r1.relres
+        assert np.array_equal(x2, x1)
+    assert r1.statuses[1] == OK and r1.iters[1] == 0 and not x1[1].any()
+    print(f"iterations per shot: {r1.iters}")
+    if gi == 2 and ring == 3:
+        assert max(r1.iters) > 2 * (K - 1)                         # several flushes inside the phase
+
+
+def test_held_directions_solution_matches_oracle_fp64():
+    nx, nz = 128, 64
+    kappa, rho = heterogeneous(nx, nz)
+    h = 200.0
+    b = np.random.default_rng(4).standard_normal((nz - 1, nx - 1))
+    w = operator.shift_coeff(rho, h)
+    B = precond.acoustic_preconditioner(kappa, rho, h, nx, nz, 10.0, 10.0)
+    xo, ito, _, sto = krylov.pcg(lambda y: operator.apply_A(y, kappa, w, 10.0, 10.0), B.solve, b, 1e-11, 500)
+    plan = _plan(nx, nz, kappa, rho, h, "fp64", 1, graph_iters=2, x_ring=3)
+    log("held fp64 128x64 x_ring=3 against the oracle")
+    x, res = _solve(plan, b[None], 1e-11)
+    assert res.statuses == [OK] and sto == OK and res.iters[0] == ito
+    assert rel(x[0], xo) < 1e-12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_held_directions_start_from_given_x(precision):
+    nx, nz = 128, 64
+    kappa, rho = heterogeneous(nx, nz)
+    b = _rhs(nx, nz, 3, seed=8)
+    x0 = np.random.default_rng(9).standard_normal(b.shape) * 1e-3
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    out = {}
+    for ring in (1, 3):
+        plan = _plan(nx, nz, kappa, rho, 200.0, precision, 3, graph_iters=2, x_ring=ring)
+        log(f"held {precision} start from x0, x_ring={ring}")
+        out[ring] = _solve(plan, b, tol, x0=x0)
+    (xa, ra), (xb, rb) = out[1], out[3]
+    assert ra.iters == rb.iters and ra.statuses == rb.statuses
+    assert np.array_equal(xa, xb)
+    assert not xa[1].any()                                          # b = 0 from a given x: x = 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_held_directions_profile_helper_iterate(precision):
+    """The profile helper runs a fixed count of eager iterations (here more
+    than a 16-slot ring holds, so it flushes between them) and leaves x up to
+    date: the same x as with the in-place update."""
+    torch = torch_cuda()
+    nx, nz = 256, 64
+    kappa, rho = heterogeneous(nx, nz)
+    b = _rhs(nx, nz, 2, seed=5)
+    b[1] = b[0] * 0.5
+    xs = {}
+    for ring in (1, 0):
+        plan = _plan(nx, nz, kappa, rho, 200.0, precision, 2, x_ring=ring)
+        log(f"held profile helper {precision} x_ring={plan.x_ring()}")
+        bd = to_dev(b, torch.float64)
+        xd = torch.empty_like(bd)
+        ms = plan.pcg_profile(bd, xd, iters=20)
+        assert all(m > 0 for m in ms)
+        xs[ring] = to_np(xd)
+    assert np.array_equal(xs[1], xs[0])
