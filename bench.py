@@ -185,12 +185,14 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     npts = (w.n_cells - 1) * (w.n_cells if cyl else w.n_cells - 1)
     for _ in range(warmup):
         run.step()
+    run.finish()                          # the warm-up harmonics' synthesis, untimed
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     iters = []
     for _ in range(steps):
         res = run.step()
         iters.append(res.iters)
+    run.finish()                          # the timed harmonics still pending synthesis
     torch.cuda.synchronize()
     el = time.perf_counter() - t1
     pt_iters = float(npts) * float(np.sum(iters))

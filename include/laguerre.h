@@ -308,6 +308,23 @@ lg_status lg_laguerre_synthesize(lg_plan* plan, int32_t m, const double* R_m,
                                  const double* W_snap_host, int32_t n_snap, double* snap_accum,
                                  int32_t rec_row, double* rec_coeff);
 
+/* Largest number of harmonics lg_laguerre_synthesize_batch takes per call. */
+#define LG_SYNTH_BATCH_MAX 8
+
+/* lg_laguerre_synthesize for the nb consecutive harmonics m0 .. m0+nb-1 in
+ * one pass over the accumulators (eq. series_lag):
+ *   snap_accum[s] += W[s][0] R_{m0} + ... + W[s][nb-1] R_{m0+nb-1},
+ * the terms added one harmonic at a time in that order, so the result is
+ * bitwise that of nb calls of lg_laguerre_synthesize; each harmonic's
+ * receiver row is stored as there.  The snapshots are read and written once
+ * instead of nb times.  R_host: host array of nb FP64 device vectors
+ * (R_host[b] = R_{m0+b}); W_snap_host: [n_snap][nb] (host).  1 <= nb <=
+ * LG_SYNTH_BATCH_MAX, 0 <= m0, m0 + nb <= n; other arguments as
+ * lg_laguerre_synthesize. */
+lg_status lg_laguerre_synthesize_batch(lg_plan* plan, int32_t m0, int32_t nb, const double* const* R_host,
+                                       const double* W_snap_host, int32_t n_snap, double* snap_accum,
+                                       int32_t rec_row, double* rec_coeff);
+
 /* Receiver traces from the stored coefficients:
  *   traces[shot][c][q][i] = sum_m W_host[q][m] rec_coeff[shot][c][m][i].
  * W_host: [nt][n] (host); rec_coeff: FP64 [S][C][n][nx-1]; traces: FP64

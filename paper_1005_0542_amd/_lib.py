@@ -25,6 +25,7 @@ LG_ACOUSTIC, LG_ELASTIC = 0, 1
 LG_TOP_DIRICHLET, LG_TOP_FREE = 0, 1
 LG_CARTESIAN, LG_CYLINDRICAL = 0, 1
 LG_RICKER, LG_GAUSS_SINE = 0, 1
+LG_SYNTH_BATCH_MAX = 8
 LG_TRACE_SCRATCH_MAX = 1 << 21
 
 
@@ -74,6 +75,8 @@ _SIGNATURES = {
     "lg_gmres_solve": [_PLAN, c_void_p, c_void_p, POINTER(SolveOpts), POINTER(SolveInfo)],
     "lg_laguerre_synthesize": [_PLAN, c_int32, c_void_p, POINTER(c_double), c_int32, c_void_p, c_int32,
                                c_void_p],
+    "lg_laguerre_synthesize_batch": [_PLAN, c_int32, c_int32, POINTER(c_void_p), POINTER(c_double), c_int32,
+                                     c_void_p, c_int32, c_void_p],
     "lg_trace_synthesize": [_PLAN, c_void_p, POINTER(c_double), c_int32, c_void_p],
     "lg_trace_synthesize_noalloc": [_PLAN, c_void_p, POINTER(c_double), c_int32, c_void_p],
     "lg_pcg_profile": [_PLAN, c_void_p, c_void_p, c_int32, POINTER(ctypes.c_float)],

@@ -196,6 +196,20 @@ class Plan:
             self._ptr(snap, torch.float64, "snap", len(w) * n) if len(w) else None, rec_row,
             self._ptr(rec, torch.float64, "rec")), "lg_laguerre_synthesize")
 
+    def laguerre_synthesize_batch(self, m0: int, Rs: Sequence, W_snap: np.ndarray, snap, rec_row: int = 1,
+                                  rec=None):
+        """Harmonics m0 .. m0+len(Rs)-1 in one pass; W_snap: [n_snap][len(Rs)]."""
+        import torch
+        nb = len(Rs)
+        w = np.ascontiguousarray(np.asarray(W_snap, dtype=np.float64).reshape(-1, nb))
+        ns = w.shape[0]
+        n = self._nvec()
+        ptrs = (ctypes.c_void_p * nb)(*[self._ptr(R, torch.float64, "R", n) for R in Rs])
+        check(self.lib.lg_laguerre_synthesize_batch(
+            self.handle, m0, nb, ptrs, _dptr(w) if ns else None, ns,
+            self._ptr(snap, torch.float64, "snap", ns * n) if ns else None, rec_row,
+            self._ptr(rec, torch.float64, "rec")), "lg_laguerre_synthesize_batch")
+
     def trace_synthesize(self, rec, W: np.ndarray, traces):
         import torch
         Wc = np.ascontiguousarray(np.asarray(W, dtype=np.float64))

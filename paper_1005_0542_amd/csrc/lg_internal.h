@@ -256,7 +256,9 @@ hipError_t ho_launch_stencil(lg_plan* p, const void* x, void* y, bool reduce);
 hipError_t ho_launch_residual(lg_plan* p, const double* b, const double* x);
 hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double* Qh,
                       const double* fsrc_host, double* rhs);
-hipError_t launch_synth(lg_plan* p, int m, const double* R, const double* Wsnap, int nsnap,
+// synthesis of harmonics m0 .. m0+nb-1 (nb <= 8) in one pass: R[b] their
+// solutions, Wsnap [nsnap][nb] (host)
+hipError_t launch_synth(lg_plan* p, int m0, int nb, const double* const* R, const double* Wsnap, int nsnap,
                         double* snap, int rec_row, double* rec);
 hipError_t launch_traces(lg_plan* p, const double* rec, const double* Wdev, int nt,
                          double* traces);

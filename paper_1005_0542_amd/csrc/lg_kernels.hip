@@ -1276,29 +1276,43 @@ __global__ void src_kernel(SrcArgs s, double* rhs) {
 // Synthesis (eq. series_lag): snapshots += W_s R_m; receiver-row coefficients.
 // ===========================================================================
 constexpr int MAX_SNAP = 8;
+constexpr int MAX_SB = 8;      // harmonics per synthesis pass
 struct SynArgs {
-    const double* R;
+    const double* R[MAX_SB];      // R_{m0 + b}, b < nb
     double* snap;
     double* rec;
-    double W[MAX_SNAP];
-    int nsnap, m, n, rec_row0, nx1, nz1;
+    double W[MAX_SNAP][MAX_SB];   // W[s][b]: snapshot s, harmonic m0 + b
+    int nsnap, m0, nb, n, rec_row0, nx1, nz1;
     size_t npts, total;
 };
 
+// snap[s] += W[s][0] R_{m0} + W[s][1] R_{m0+1} + ..., added one harmonic at a
+// time in order (the same FP64 operations as one pass per harmonic), so nb
+// harmonics read and write each snapshot once; receiver rows copied out.
 __global__ __launch_bounds__(256) void synth_kernel(SynArgs a) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= a.total) return;
-    const double R = a.R[e];
+    double R[MAX_SB];
 #pragma unroll
-    for (int s = 0; s < MAX_SNAP; ++s)
-        if (s < a.nsnap) a.snap[(size_t)s * a.total + e] += a.W[s] * R;
+    for (int b = 0; b < MAX_SB; ++b) R[b] = b < a.nb ? a.R[b][e] : 0.0;
+#pragma unroll
+    for (int s = 0; s < MAX_SNAP; ++s) {
+        if (s >= a.nsnap) break;
+        double v = a.snap[(size_t)s * a.total + e];
+#pragma unroll
+        for (int b = 0; b < MAX_SB; ++b)
+            if (b < a.nb) v += a.W[s][b] * R[b];
+        a.snap[(size_t)s * a.total + e] = v;
+    }
     if (a.rec != nullptr) {
         const size_t f = e / a.npts;
         const size_t pt = e - f * a.npts;
         const int j = (int)(pt / a.nx1);
         if (j == a.rec_row0) {
             const int i = (int)(pt - (size_t)j * a.nx1);
-            a.rec[(f * a.n + a.m) * a.nx1 + i] = R;
+#pragma unroll
+            for (int b = 0; b < MAX_SB; ++b)
+                if (b < a.nb) a.rec[(f * a.n + a.m0 + b) * a.nx1 + i] = R[b];
         }
     }
 }
@@ -1760,15 +1774,18 @@ hipError_t launch_rhs(lg_plan* p, int m, const double* Rprev, double* Ph, double
     return hipSuccess;
 }
 
-hipError_t launch_synth(lg_plan* p, int m, const double* R, const double* Wsnap, int nsnap,
+hipError_t launch_synth(lg_plan* p, int m0, int nb, const double* const* R, const double* Wsnap, int nsnap,
                         double* snap, int rec_row, double* rec) {
+    if (nb < 1 || nb > MAX_SB || nsnap > MAX_SNAP) return hipErrorInvalidValue;
     SynArgs a;
-    a.R = R;
+    for (int b = 0; b < MAX_SB; ++b) a.R[b] = b < nb ? R[b] : nullptr;
     a.snap = snap;
     a.rec = rec;
-    for (int s = 0; s < MAX_SNAP; ++s) a.W[s] = (s < nsnap) ? Wsnap[s] : 0.0;
+    for (int s = 0; s < MAX_SNAP; ++s)
+        for (int b = 0; b < MAX_SB; ++b) a.W[s][b] = (s < nsnap && b < nb) ? Wsnap[(size_t)s * nb + b] : 0.0;
     a.nsnap = nsnap;
-    a.m = m;
+    a.m0 = m0;
+    a.nb = nb;
     a.n = p->lag.n;
     a.rec_row0 = rec_row - 1;
     a.nx1 = p->nx1;

@@ -1020,7 +1020,27 @@ lg_status lg_laguerre_synthesize(lg_plan* plan, int32_t m, const double* R_m, co
     if (rec_coeff != nullptr && (rec_row < 1 || rec_row > plan->nz1))
         return fail(LG_ERR_INVALID_ARG, "rec_row out of range");
     LG_HIP(hipSetDevice(plan->device));
-    LG_HIP(launch_synth(plan, m, R_m, W_snap_host, n_snap, snap_accum, rec_row, rec_coeff));
+    LG_HIP(launch_synth(plan, m, 1, &R_m, W_snap_host, n_snap, snap_accum, rec_row, rec_coeff));
+    return LG_OK;
+}
+
+lg_status lg_laguerre_synthesize_batch(lg_plan* plan, int32_t m0, int32_t nb, const double* const* R_host,
+                                       const double* W_snap_host, int32_t n_snap, double* snap_accum,
+                                       int32_t rec_row, double* rec_coeff) {
+    LG_CHECK(check_plan(plan));
+    if (nb < 1 || nb > LG_SYNTH_BATCH_MAX) return fail(LG_ERR_INVALID_ARG, "nb must be in 1..8");
+    LG_CHECK(check_vec(R_host, "R_host"));
+    for (int b = 0; b < nb; ++b) LG_CHECK(check_vec(R_host[b], "R_host[b]"));
+    if (m0 < 0 || m0 > plan->lag.n - nb) return fail(LG_ERR_INVALID_ARG, "harmonics m0 .. m0+nb-1 out of range");
+    if (n_snap < 0 || n_snap > 8) return fail(LG_ERR_INVALID_ARG, "n_snap must be in 0..8");
+    if (n_snap > 0) {
+        LG_CHECK(check_vec(W_snap_host, "W_snap_host"));
+        LG_CHECK(check_vec(snap_accum, "snap_accum"));
+    }
+    if (rec_coeff != nullptr && (rec_row < 1 || rec_row > plan->nz1))
+        return fail(LG_ERR_INVALID_ARG, "rec_row out of range");
+    LG_HIP(hipSetDevice(plan->device));
+    LG_HIP(launch_synth(plan, m0, nb, R_host, W_snap_host, n_snap, snap_accum, rec_row, rec_coeff));
     return LG_OK;
 }
 

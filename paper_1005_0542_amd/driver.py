@@ -31,7 +31,7 @@ class AcousticRun:
                  snapshots: bool = True, rec: bool = True, tol: Optional[float] = None,
                  max_iter: int = 10000, medium=None, op_shots: int = 0, seg_per_wave: int = 0,
                  op_fusion: int = 0, top: str = "dirichlet", warm_start: bool = False,
-                 geometry: str = "cartesian", order: int = 2, x_ring: int = 0):
+                 geometry: str = "cartesian", order: int = 2, x_ring: int = 0, synth_batch: int = 4):
         import torch
         self.torch = torch
         self.w = w
@@ -77,26 +77,63 @@ class AcousticRun:
         self.ncol = ncol
         shape = (self.shots, 1, N - 1, ncol)
         f64 = torch.float64
-        self.R = torch.zeros(shape, dtype=f64, device=dev)
+        # The synthesis of `synth_batch` consecutive harmonics runs as one pass
+        # (lg_laguerre_synthesize_batch: the snapshots are read and written
+        # once per batch, bitwise the same sums), so the solutions R_m of a
+        # batch are kept in a ring; `snap`, `rec`, `traces` and checkpoints
+        # first synthesize the harmonics still pending.
+        self.synth_batch = max(1, min(int(synth_batch), 8)) if (snapshots or rec) else 1
+        self._Rs = [torch.zeros(shape, dtype=f64, device=dev) for _ in range(self.synth_batch)]
+        self._pending: List[int] = []
         self.Ph = torch.zeros(shape, dtype=f64, device=dev)
         self.Qh = torch.zeros(shape, dtype=f64, device=dev)
         self.rhs = torch.zeros(shape, dtype=f64, device=dev)
-        self.snap = torch.zeros((len(self.t_snap),) + shape, dtype=f64, device=dev) if snapshots else None
-        self.rec = torch.zeros((self.shots, 1, self.n_harm, ncol), dtype=f64, device=dev) if rec else None
+        self._snap = torch.zeros((len(self.t_snap),) + shape, dtype=f64, device=dev) if snapshots else None
+        self._rec = torch.zeros((self.shots, 1, self.n_harm, ncol), dtype=f64, device=dev) if rec else None
         self.iters: List[List[int]] = []
         self.status: List[int] = []
         self.m = 0
 
+    @property
+    def R(self):
+        """The latest solution R_{m-1} (before the first step: a zero vector)."""
+        return self._Rs[(self.m - 1) % self.synth_batch] if self.m > 0 else self._Rs[0]
+
+    @property
+    def snap(self):
+        self.finish()
+        return self._snap
+
+    @property
+    def rec(self):
+        self.finish()
+        return self._rec
+
+    def finish(self) -> None:
+        """Synthesize the harmonics still pending (the rest of a batch)."""
+        if not self._pending or (self._snap is None and self._rec is None):
+            self._pending = []
+            return
+        m0, nb = self._pending[0], len(self._pending)
+        Rs = [self._Rs[m % self.synth_batch] for m in self._pending]
+        W = self.W_snap[:, m0:m0 + nb] if self._snap is not None else np.zeros((0, nb))
+        self.plan.laguerre_synthesize_batch(m0, Rs, W, self._snap, self.w.rec_row, self._rec)
+        self._pending = []
+
     def step(self) -> api.SolveResult:
-        """Advance one harmonic (rhs, solve, synthesis)."""
+        """Advance one harmonic (rhs, solve; the synthesis once per batch)."""
         m = self.m
         fs = np.full(self.shots, self.f_m[m])
-        self.plan.laguerre_rhs(m, self.R if m else None, self.Ph, self.Qh, fs, self.rhs)
-        res = self.plan.pcg_solve(self.rhs, self.R, tol=self.tol, max_iter=self.max_iter,
-                                  x0_given=self.warm_start and m > 0)
-        if self.snap is not None or self.rec is not None:
-            ws = self.W_snap[:, m] if self.snap is not None else []
-            self.plan.laguerre_synthesize(m, self.R, ws, self.snap, self.w.rec_row, self.rec)
+        R_prev = self._Rs[(m - 1) % self.synth_batch] if m else None
+        R = self._Rs[m % self.synth_batch]
+        self.plan.laguerre_rhs(m, R_prev, self.Ph, self.Qh, fs, self.rhs)
+        warm = self.warm_start and m > 0
+        if warm and R is not R_prev:
+            R.copy_(R_prev)
+        res = self.plan.pcg_solve(self.rhs, R, tol=self.tol, max_iter=self.max_iter, x0_given=warm)
+        self._pending.append(m)
+        if len(self._pending) == self.synth_batch:
+            self.finish()
         self.iters.append(res.iters)
         self.status.append(res.status)
         self.m += 1
@@ -107,20 +144,21 @@ class AcousticRun:
         """Complete harmonic-loop state: the next harmonic m, the last solution
         R_{m-1}, the running history sums, the snapshot accumulators and the
         receiver coefficients (device tensors are copied to the host)."""
+        self.finish()
         out = {"m": self.m, "iters": [list(i) for i in self.iters], "status": list(self.status),
                "R": self.R.cpu(), "Ph": self.Ph.cpu(), "Qh": self.Qh.cpu()}
-        if self.snap is not None:
-            out["snap"] = self.snap.cpu()
-        if self.rec is not None:
-            out["rec"] = self.rec.cpu()
+        if self._snap is not None:
+            out["snap"] = self._snap.cpu()
+        if self._rec is not None:
+            out["rec"] = self._rec.cpu()
         return out
 
     def load_state_dict(self, st: dict) -> None:
         self.m = int(st["m"])
         self.iters = [list(i) for i in st["iters"]]
         self.status = list(st["status"])
-        for name in ("R", "Ph", "Qh", "snap", "rec"):
-            t = getattr(self, name)
+        self._pending = []
+        for name, t in (("R", self.R), ("Ph", self.Ph), ("Qh", self.Qh), ("snap", self._snap), ("rec", self._rec)):
             if t is not None and name in st:
                 t.copy_(st[name].to(t.device))
 
