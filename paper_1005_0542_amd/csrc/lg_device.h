@@ -233,6 +233,12 @@ __device__ __forceinline__ cpx<double> bload2<double>(rsrc_t r, uint32_t off) {
     return __builtin_bit_cast(cpx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0));
 }
 
+// a pair of consecutive doubles (one 16-byte store)
+__device__ __forceinline__ void bstore2(cpx<double> v, rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(__attribute__((ext_vector_type(4))) uint32_t, v), r,
+                                           (int)off, 0, 0);
+}
+
 template <typename T>
 __device__ __forceinline__ void bstore(T v, rsrc_t r, uint32_t off);
 template <>

@@ -234,14 +234,17 @@ __global__ __launch_bounds__(GM_BLK) void gm_multidot_kernel(const double* __res
         double acc[G];
 #pragma unroll
         for (int u = 0; u < G; ++u) acc[u] = 0.0;
-        for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) {
+        for (size_t e = lo + 2 * threadIdx.x; e < hi; e += 2 * GM_BLK) {   // element pairs (n_s, lo, hi even)
             const uint32_t off = (uint32_t)(e * 8);
-            const double wv = bload<double>(rw, off);
-            double vv[G];
+            const cpx<double> wv = bload2<double>(rw, off);
+            cpx<double> vv[G];
 #pragma unroll
-            for (int u = 0; u < G; ++u) vv[u] = bload<double>(rv[u], off);
+            for (int u = 0; u < G; ++u) vv[u] = bload2<double>(rv[u], off);
 #pragma unroll
-            for (int u = 0; u < G; ++u) acc[u] += vv[u] * wv;
+            for (int u = 0; u < G; ++u) {
+                acc[u] += vv[u].x * wv.x;
+                acc[u] += vv[u].y * wv.y;
+            }
         }
 #pragma unroll
         for (int u = 0; u < G; ++u) {
@@ -336,21 +339,28 @@ __global__ __launch_bounds__(GM_BLK) void gm_subdot_kernel(const double* __restr
     double acc[NA];
 #pragma unroll
     for (int u = 0; u < NA; ++u) acc[u] = 0.0;
-    for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) {
+    for (size_t e = lo + 2 * threadIdx.x; e < hi; e += 2 * GM_BLK) {   // element pairs (n_s, lo, hi even)
         const uint32_t off = (uint32_t)(e * 8);
-        double vv[MB];
+        cpx<double> vv[MB];
 #pragma unroll
-        for (int u = 0; u < MB; ++u) vv[u] = bload<double>(rv[u], off);
-        double wv = bload<double>(rw, off);
+        for (int u = 0; u < MB; ++u) vv[u] = bload2<double>(rv[u], off);
+        cpx<double> wv = bload2<double>(rw, off);
 #pragma unroll
         for (int u = 0; u < MB; ++u)
-            if (u < m) wv -= c[u] * vv[u];
-        bstore<double>(wv, rw, off);
+            if (u < m) {
+                wv.x -= c[u] * vv[u].x;
+                wv.y -= c[u] * vv[u].y;
+            }
+        bstore2(wv, rw, off);
         if constexpr (NORM) {
-            acc[0] += wv * wv;
+            acc[0] += wv.x * wv.x;
+            acc[0] += wv.y * wv.y;
         } else {
 #pragma unroll
-            for (int u = 0; u < MB; ++u) acc[u] += vv[u] * wv;
+            for (int u = 0; u < MB; ++u) {
+                acc[u] += vv[u].x * wv.x;
+                acc[u] += vv[u].y * wv.y;
+            }
         }
     }
 #pragma unroll
@@ -420,7 +430,15 @@ __global__ __launch_bounds__(GM_BLK) void gm_normalize_fused_kernel(const double
     if (b == 0 && threadIdx.x == 0) nrm2[(size_t)s * nrm_stride] = q;
     const size_t base = (size_t)s * n_s;
     const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
-    for (size_t e = lo + threadIdx.x; e < hi; e += GM_BLK) out[base + e] = q > 0.0 ? x[base + e] / sqrt(q) : 0.0;
+    const double* xs = x + base;
+    double* os = out + base;
+    for (size_t e = lo + 2 * threadIdx.x; e < hi; e += 2 * GM_BLK) {   // element pairs (n_s, lo, hi even)
+        const double2 v = *reinterpret_cast<const double2*>(xs + e);
+        double2 r;
+        r.x = q > 0.0 ? v.x / sqrt(q) : 0.0;
+        r.y = q > 0.0 ? v.y / sqrt(q) : 0.0;
+        *reinterpret_cast<double2*>(os + e) = r;
+    }
 }
 
 // out = sum_{i<m} y[s][i] V_i
@@ -529,6 +547,11 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                                          pin, g.w, n_s, g.active, pout, nblk);
             else hipLaunchKernelGGL((gm_subdot_kernel<8, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
                                     pin, g.w, n_s, g.active, pout, nblk);
+        } else if (m <= 12) {
+            if (norm) hipLaunchKernelGGL((gm_subdot_kernel<12, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
+                                         pin, g.w, n_s, g.active, pout, nblk);
+            else hipLaunchKernelGGL((gm_subdot_kernel<12, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
+                                    pin, g.w, n_s, g.active, pout, nblk);
         } else if (m <= 16) {
             if (norm) hipLaunchKernelGGL((gm_subdot_kernel<16, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
                                          pin, g.w, n_s, g.active, pout, nblk);
@@ -569,7 +592,9 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
     // ||b||, x = 0
     LG_HIP(push_active());
     LG_HIP(hipMemsetAsync(x, 0, nvec * 8, st));
-    LG_HIP(dot_into(b, 0, 1, b, 2 * (GM_MAXK + 1)));
+    // the sweeps load element pairs (16 bytes): ||b|| from an aligned copy of b
+    LG_HIP(hipMemcpyAsync(g.w, b, nvec * 8, hipMemcpyDeviceToDevice, st));
+    LG_HIP(dot_into(g.w, 0, 1, g.w, 2 * (GM_MAXK + 1)));
     LG_HIP(fetch_dots());
     for (int s = 0; s < S; ++s) {
         const double bb = dots_h[(size_t)s * DS + 2 * (GM_MAXK + 1)];
