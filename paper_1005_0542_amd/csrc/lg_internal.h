@@ -44,7 +44,6 @@ struct ShotCtl {
     int32_t max_iter;
     int32_t fresh;    // 1 from a cold start until the first update: x = 0 and r = b
                       // are implied, not stored (the update reads b, takes x as 0)
-    int32_t xdone;    // held-direction plans: iterations already added into x
     int32_t xzero;    // held-direction plans: 1 while x is implied 0 (cold start, no flush yet)
 };
 
@@ -155,7 +154,9 @@ struct lg_plan {
     // applied in order by a flush pass (phase ends, or before a slot would be
     // reused) instead of in every update.  pring = 1: x updated in place.
     int pring = 1;
-    double* ahist = nullptr;   // [S*C][pring] alpha_j of the held directions
+    double* ahist = nullptr;   // [S*C][pring] alpha_j of the held directions (0 where the shot was masked)
+    int* giter = nullptr;      // [0] CG iterations of the solve so far (one count for all shots: the
+                               // slot index), [1] iterations already added into x
     void* qv = nullptr;        // A p
     void* rhat = nullptr;      // DST(r)
     void* y = nullptr;         // Dichotomy output / spectral solution
@@ -210,9 +211,10 @@ hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter);
 hipError_t launch_correct_idst(lg_plan* p, int init);
-// Held-direction plans: x += sum_j alpha_j p_j over each shot's held
-// directions j = xdone .. iters-1, in order (x taken as 0 while xzero), then
-// xdone = iters, xzero = 0.  No-op for pring = 1.
+// Held-direction plans: x += alpha_j p_j for the iterations j = giter[1] ..
+// giter[0]-1, in order, skipping those where the shot was masked (alpha_j =
+// 0; x taken as 0 while xzero), then giter[1] = giter[0], xzero = 0.  No-op
+// for pring = 1.
 hipError_t launch_flush_x(lg_plan* p, double* x);
 // FP64 ||b - A x||^2 per shot and the finalize kernel's restart check: shots
 // that had met the tolerance on the recursive residual stop if the true one

@@ -51,8 +51,9 @@ struct StArgs {
     ShotCtl* ctl;
     double* partial;
     size_t pstride;
-    int pring;           // > 1 (with ctl): p of a shot at slot iters % pring
+    int pring;           // > 1 (with ctl): p at slot giter[0] % pring
     size_t pslot;        // elements per slot
+    const int* giter;    // held directions: the solve's iteration count
 };
 
 // The medium (kappa at the nodes the column touches, w) is loaded once into
@@ -79,12 +80,9 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
     const int s0 = bz * a.nsh;
     const int ns = min(a.nsh, a.nfields - s0);
     __shared__ int act[ST_MAXSH];
-    __shared__ int pslot[ST_MAXSH];                 // held directions: the shot's slot of p
     int mine = 0;
     if (threadIdx.x < ns) {
-        const bool cg = a.ctl != nullptr && !RESN;
-        act[threadIdx.x] = cg ? a.ctl[s0 + threadIdx.x].active : 1;
-        pslot[threadIdx.x] = (cg && a.pring > 1) ? a.ctl[s0 + threadIdx.x].iters % a.pring : 0;
+        act[threadIdx.x] = (a.ctl != nullptr && !RESN) ? a.ctl[s0 + threadIdx.x].active : 1;
         mine = act[threadIdx.x];
     }
     if (__syncthreads_or(mine != 0) == 0) return;   // (also the barrier for act) uniform per block
@@ -125,11 +123,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
         ow[r] = (c != BUF_OOB && i > 0) ? c - SZ : BUF_OOB;
     }
     const uint32_t fbytes = (uint32_t)nx1 * (uint32_t)nz1 * SZ;
+    // held directions: this iteration's p slot (one count for every shot)
+    const size_t ps = (!RESN && a.pring > 1) ? (size_t)(*a.giter % a.pring) * a.pslot : 0;
     for (int k = 0; k < ns; ++k) {
         const int field = s0 + k;
         if (act[k] == 0) continue;              // uniform per block
         const size_t fb = (size_t)field * nx1 * nz1;
-        const size_t ps = (size_t)pslot[k] * a.pslot;
         const rsrc_t rp = buf_rsrc(a.p + ps + fb, fbytes);
         T pv[ST_RPT + 2], pe[ST_RPT], pw[ST_RPT];
 #pragma unroll
@@ -223,8 +222,9 @@ struct DstArgs {
     double* r;
     const double* b;       // UPDATE init: right-hand side
     const T* p;            // UPDATE: search direction (slot 0)
-    int pring;             // > 1: held directions, p_k at slot k % pring; x not touched
+    int pring;             // > 1: held directions, p of iteration g at slot g % pring; x not touched
     size_t pslot;          // elements per slot
+    const int* giter;      // held directions: [0] the solve's iteration count g
     const T* q;            // UPDATE: A p
     const T* kap;          // UPDATE_OP: node kappa, (nz+1) x (nx+1)
     const T* wsh;          // UPDATE_OP: interior shift
@@ -327,13 +327,15 @@ dst_kernel(DstArgs<T> a) {
     const int j0 = 2 * pair, j1 = j0 + 1;
     const bool has1 = live && (j1 < a.nz1);
 
-    int kit = 0;                               // completed iterations of the shot
     if constexpr (UPD || MODE == DST_CORRECT) {
         bool skip = a.ctl[field].active == 0;
         if (UPD && a.init) skip = false;
         if (skip) return;   // uniform per block: blocks never span fields
-        kit = a.ctl[field].iters;
     }
+    // held directions: the solve's iteration count (the update of iteration
+    // g reads p_g; the correction after it, with g + 1 counted, reads p_g and
+    // writes p_{g+1}; a start or restart writes the first direction at g)
+    const int kit = ((UPD || MODE == DST_CORRECT) && a.pring > 1) ? *a.giter : 0;
 
     cpx<T>* buf = lds + fid * LL;
     const size_t fbase = (size_t)field * a.nz1 * NX1;
@@ -1021,8 +1023,9 @@ struct FinArgs {
     double tol2r;     // (init 1, 4) squared recursive tolerance of restart phases
     int max_iter;
     double scale;     // FIN_RZ: b * 2/nx
-    double* ahist;    // FIN_PQ with pring > 1: alpha_k kept at [field][k % pring]
+    double* ahist;    // FIN_PQ with pring > 1: alpha_g kept at [field][g % pring] (0: no update)
     int pring;
+    int* giter;       // pring > 1: [0] the solve's iteration count g, [1] iterations added into x
 };
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
@@ -1030,6 +1033,18 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     const int field = blockIdx.x;
     ShotCtl& c = a.ctl[field];
     const bool start_rr = (a.kind == FIN_RR && a.init);
+    if (a.pring > 1 && threadIdx.x == 0) {   // held directions (before the masked shots leave)
+        if (a.kind == FIN_PQ)                 // alpha_g stays 0 unless this shot's update runs
+            a.ahist[(size_t)field * a.pring + a.giter[0] % a.pring] = 0.0;
+        if (a.kind == FIN_RR && blockIdx.x == 0) {
+            if (a.init == 1 || a.init == 4) {   // a start: no iteration yet, none added
+                a.giter[0] = 0;
+                a.giter[1] = 0;
+            } else if (a.init == 0) {
+                a.giter[0] += 1;               // iteration g done, for every shot
+            }
+        }
+    }
     if (!start_rr && c.active == 0) return;                  // uniform per block
     double s = 0.0;
     const double* part = a.partial + (size_t)field * a.pstride;
@@ -1052,7 +1067,7 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.active = 0;
         } else {
             c.alpha = c.rz / tot;
-            if (a.pring > 1) a.ahist[(size_t)field * a.pring + c.iters % a.pring] = c.alpha;
+            if (a.pring > 1) a.ahist[(size_t)field * a.pring + *a.giter % a.pring] = c.alpha;
         }
     } else if (a.kind == FIN_RR) {
         c.rr = tot;
@@ -1063,7 +1078,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.tol2r = a.tol2r * bbt;
             c.iters = 0;
             c.fresh = 0;                     // x and r are stored
-            c.xdone = 0;
             c.xzero = 0;
             c.max_iter = a.max_iter;
             c.alpha = 0.0;
@@ -1108,7 +1122,6 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
             c.alpha = 0.0;
             c.beta = 0.0;
             c.fresh = 1;                         // cold start: x = 0, r = b implied
-            c.xdone = 0;
             c.xzero = 1;
             if (!isfinite(tot)) {
                 c.status = LG_ERR_NONFINITE;
@@ -1150,21 +1163,23 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
     }
 }
 
-// Held search directions: x += alpha_j p_j for j = xdone .. iters-1, in
-// order, with the FP64 product and sum of the in-place update (so x is
-// bitwise the same); x is taken as 0 while xzero (a cold start that has not
-// been flushed), which also writes x = 0 for a shot that never iterated.
-// One pass reads the held directions once and x once, writes x once.
+// Held search directions: x += alpha_j p_j for the iterations j = giter[1]
+// .. giter[0]-1, in order, with the FP64 product and sum of the in-place
+// update (so x is bitwise the same); iterations in which the shot was masked
+// (alpha_j = 0: no update ran) are skipped.  x is taken as 0 while xzero (a
+// cold start not yet flushed), which also writes x = 0 for a shot that never
+// iterated.  One pass reads each held direction once and x once, writes x
+// once.
 constexpr int FLUSH_EPT = 4;   // elements per thread
 template <typename T>
 __global__ __launch_bounds__(256) void flush_x_kernel(double* __restrict__ x, const T* __restrict__ pr,
                                                       const double* __restrict__ ahist,
-                                                      const ShotCtl* __restrict__ ctl, int pring, size_t pslot,
-                                                      size_t npts, int bpf) {
+                                                      const ShotCtl* __restrict__ ctl, const int* __restrict__ giter,
+                                                      int pring, size_t pslot, size_t npts, int bpf) {
     const int field = blockIdx.x / bpf;
     const int bif = blockIdx.x - field * bpf;
-    const int j0 = ctl[field].xdone;
-    const int n = ctl[field].iters - j0;
+    const int j0 = giter[1];
+    const int n = giter[0] - j0;
     const bool zero = ctl[field].xzero != 0;
     if (n <= 0 && !zero) return;                    // uniform per block
     const size_t fb = (size_t)field * npts;
@@ -1178,6 +1193,7 @@ __global__ __launch_bounds__(256) void flush_x_kernel(double* __restrict__ x, co
     for (int j = 0; j < n; ++j) {
         const int sl = (j0 + j) % pring;
         const double al = ahist[(size_t)field * pring + sl];
+        if (al == 0.0) continue;                    // masked in iteration j0 + j (uniform)
         const T* ps = pr + (size_t)sl * pslot + fb;
         T pv[FLUSH_EPT];
 #pragma unroll
@@ -1196,11 +1212,10 @@ __global__ __launch_bounds__(256) void flush_x_kernel(double* __restrict__ x, co
 }
 
 // after a flush: every held direction is in x
-__global__ __launch_bounds__(256) void flush_done_kernel(ShotCtl* ctl, int nf) {
+__global__ __launch_bounds__(256) void flush_done_kernel(ShotCtl* ctl, int* giter, int nf) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    ctl[f].xdone = ctl[f].iters;
-    ctl[f].xzero = 0;
+    if (f == 0) giter[1] = giter[0];
+    if (f < nf) ctl[f].xzero = 0;
 }
 
 // Standalone interface correction (the CG path fuses it into K5):
@@ -1362,6 +1377,7 @@ hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int
     f.scale = scale;
     f.ahist = p->ahist;
     f.pring = p->pring;
+    f.giter = p->giter;
     hipLaunchKernelGGL(finalize_kernel, dim3(p->S * p->C), dim3(256), 0, p->stream, f);
     return hipGetLastError();
 }
@@ -1383,6 +1399,7 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.ctl = reduce ? p->ctl : nullptr;
     a.pring = reduce ? p->pring : 1;
     a.pslot = p->nvec;
+    a.giter = p->giter;
     a.free_top = p->free_top ? 1 : 0;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
@@ -1413,6 +1430,7 @@ hipError_t residual_check_T(lg_plan* p, const double* b, const double* x) {
     a.ctl = p->ctl;
     a.pring = 1;
     a.pslot = 0;
+    a.giter = p->giter;
     a.free_top = p->free_top ? 1 : 0;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
@@ -1471,6 +1489,7 @@ DstArgs<T> dst_args(lg_plan* p) {
     a.p = (const T*)p->p;
     a.pring = p->pring;
     a.pslot = p->nvec;
+    a.giter = p->giter;
     a.q = (const T*)p->qv;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
@@ -1686,13 +1705,13 @@ hipError_t launch_flush_x(lg_plan* p, double* x) {
     const dim3 grid((unsigned)bpf * (unsigned)nf);
     if (p->prec == LG_FP64)
         hipLaunchKernelGGL(flush_x_kernel<double>, grid, dim3(256), 0, p->stream, x, (const double*)p->p, p->ahist,
-                           p->ctl, p->pring, p->nvec, p->npts, bpf);
+                           p->ctl, p->giter, p->pring, p->nvec, p->npts, bpf);
     else
         hipLaunchKernelGGL(flush_x_kernel<float>, grid, dim3(256), 0, p->stream, x, (const float*)p->p, p->ahist,
-                           p->ctl, p->pring, p->nvec, p->npts, bpf);
+                           p->ctl, p->giter, p->pring, p->nvec, p->npts, bpf);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(flush_done_kernel, dim3((nf + 255) / 256), dim3(256), 0, p->stream, p->ctl, nf);
+    hipLaunchKernelGGL(flush_done_kernel, dim3((nf + 255) / 256), dim3(256), 0, p->stream, p->ctl, p->giter, nf);
     return hipGetLastError();
 }
 

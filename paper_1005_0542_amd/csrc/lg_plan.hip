@@ -431,7 +431,7 @@ void free_plan(lg_plan* p) {
     if (!p) return;
     pcg_release(p);
     void* ptrs[] = {p->kap, p->lam, p->mu, p->w, p->rho64, p->kap64, p->w64, p->tw, p->src_dev, p->r, p->p, p->qv,
-                    p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->ahist, p->gm_V,
+                    p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->ahist, p->giter, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
                     p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64,
@@ -802,6 +802,8 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     if ((st = dev_alloc(p, &p->r, p->nvec * 8)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, (char**)&p->p, (size_t)p->pring * p->nvec * ws)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, &p->ahist, (size_t)SC * p->pring * 8)) != LG_OK) return bail(st);
+    if ((st = dev_alloc(p, (char**)&p->giter, 2 * sizeof(int))) != LG_OK) return bail(st);
+    if ((he = hipMemset(p->giter, 0, 2 * sizeof(int))) != hipSuccess) return bail(hip_fail(he, "hipMemset"));
     if ((st = dev_alloc(p, (char**)&p->qv, p->nvec * ws)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, (char**)&p->rhat, p->nvec * ws)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, (char**)&p->y, p->nvec * ws)) != LG_OK) return bail(st);
