@@ -6,13 +6,15 @@
 // z-systems of consecutive wavenumbers sit in consecutive addresses and every
 // sweep over z loads one coalesced row segment per step.
 //
-// Kernels (one pass of the preconditioned CG iteration is K1..K5):
-//   K1 stencil_kernel      q = A p, partial (p, q); last block: alpha
-//   K2 dst_kernel UPDATE   x += alpha p, r -= alpha q, ||r||^2, rhat = DST(r);
-//                          last block: convergence test
+// Kernels (one pass of the preconditioned CG iteration is K1..K5; each
+// reduction is per-block partials, summed in a fixed order by finalize_kernel):
+//   K1 stencil_kernel      partials of (p, A p); finalize: alpha
+//   K2 dst_kernel UPDATE   A p recomputed, r -= alpha A p (x += alpha p, or the
+//                          direction held for the flush pass), ||r||^2,
+//                          rhat = DST(r); finalize: convergence test
 //   K3 td_kernel           Dichotomy segments: local Thomas solves
 //   K4 rs_kernel           interface (reduced) systems by recursive halving
-//                          across the lanes of a wave; (r, z); last block: beta
+//                          across the lanes of a wave; (r, z); finalize: beta
 //   K5 dst_kernel CORRECT  segment correction, z = (2/nx) DST(zhat), p = z + beta p
 #include <hip/hip_runtime.h>
 
