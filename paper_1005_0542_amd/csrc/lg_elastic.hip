@@ -478,7 +478,8 @@ struct GmState {
     int* active = nullptr;     // [S]
 };
 
-constexpr int DS = 2 * (GM_MAXK + 1) + 2;   // h (k+1), h2 (k+1), norm^2, spare
+constexpr int DS = 2 * (GM_MAXK + 1) + 2;   // h (k+1), h2 (k+1), norm^2, restart beta^2
+constexpr int GM_BETA_SLOT = DS - 1;
 
 inline unsigned nblocks(size_t n) { return (unsigned)((n + GM_BLK - 1) / GM_BLK); }
 
@@ -629,31 +630,19 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             LG_HIP(hipGetLastError());
         }
         first = false;
-        LG_HIP(dot_into(V0, 0, 1, V0, 2 * (GM_MAXK + 1)));
-        LG_HIP(fetch_dots());
+        // beta^2 goes to its own slot (the steps' sweeps do not touch it): V_0 =
+        // r / beta is formed on the device and step 0 is queued at once; the
+        // host reads beta with step 0's products and only then drops shots
+        // whose residual already meets the tolerance (their step 0 and the
+        // step queued after it write only their own unused basis vectors).
+        LG_HIP(dot_into(V0, 0, 1, V0, GM_BETA_SLOT));
+        hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, V0, g.dots + GM_BETA_SLOT, DS,
+                           V0, n_s, S, g.active);
+        LG_HIP(hipGetLastError());
         for (int s = 0; s < S; ++s) {
             cyc[s] = act[s];
             jused[s] = 0;
-            if (!act[s]) continue;
-            const double beta = std::sqrt(dots_h[(size_t)s * DS + 2 * (GM_MAXK + 1)]);
-            if (!std::isfinite(beta)) {
-                status[s] = LG_ERR_NONFINITE;
-                act[s] = cyc[s] = 0;
-                est[s] = NAN;
-            } else if (beta <= tol * bnorm[s]) {
-                status[s] = LG_OK;
-                act[s] = cyc[s] = 0;
-                est[s] = beta / bnorm[s];
-            } else {
-                std::fill(gv.begin() + (size_t)s * (k + 1), gv.begin() + (size_t)(s + 1) * (k + 1), 0.0);
-                gv[(size_t)s * (k + 1)] = beta;
-            }
         }
-        LG_HIP(push_active());
-        // V_0 = r / beta
-        hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, V0, g.dots + 2 * (GM_MAXK + 1), DS,
-                           V0, n_s, S, g.active);
-        LG_HIP(hipGetLastError());
         std::vector<int> inner = act;   // shots still in this cycle's Arnoldi
         // Arnoldi step j on the device: w = C K^{-1} v_j, classical Gram-Schmidt
         // twice, v_{j+1} = w / ||w||; its inner products then go to pinned host
@@ -711,6 +700,26 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             LG_HIP(hipEventSynchronize(p->gm_ev[j & 1]));
             const double* dset = p->gm_hb + (size_t)(j & 1) * S * DS;
             bool stopped = false;
+            if (j == 0) {                // the restart residual's norm (see above)
+                for (int s = 0; s < S; ++s) {
+                    if (!inner[s]) continue;
+                    const double beta = std::sqrt(dset[(size_t)s * DS + GM_BETA_SLOT]);
+                    if (!std::isfinite(beta)) {
+                        status[s] = LG_ERR_NONFINITE;
+                        act[s] = cyc[s] = inner[s] = 0;
+                        est[s] = NAN;
+                        stopped = true;
+                    } else if (beta <= tol * bnorm[s]) {
+                        status[s] = LG_OK;
+                        act[s] = cyc[s] = inner[s] = 0;
+                        est[s] = beta / bnorm[s];
+                        stopped = true;
+                    } else {
+                        std::fill(gv.begin() + (size_t)s * (k + 1), gv.begin() + (size_t)(s + 1) * (k + 1), 0.0);
+                        gv[(size_t)s * (k + 1)] = beta;
+                    }
+                }
+            }
             for (int s = 0; s < S; ++s) {
                 if (!inner[s]) continue;
                 const double* d = &dset[(size_t)s * DS];
@@ -801,7 +810,7 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
         LG_HIP(launch_elastic_precond(p, g.w, g.z));
         hipLaunchKernelGGL(gm_axpy_kernel, dim3(nb), dim3(GM_BLK), 0, st, x, 1.0, g.z, x, n_s, S, g.active);
         LG_HIP(hipGetLastError());
-        LG_HIP(hipStreamSynchronize(st));
+        // no wait here: the next cycle's work is stream-ordered after this update
     }
     LG_HIP(hipStreamSynchronize(st));
     return fin(LG_OK);
