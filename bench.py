@@ -216,7 +216,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     if cyl:
         kb = cyl_kernel_bytes(ws, shots, fusion != 2, seg > 1)
     elif order == 4:
-        kb = kernel_bytes(ws, shots, seg_len, fused=False, medium=3)
+        kb = kernel_bytes(ws, shots, seg_len, fused=False, medium=3, held=held)
     else:
         kb = kernel_bytes(ws, shots, seg_len, fusion != 2, held=held)
     slots = [0, 1, 2, 4] if cyl else [0, 1, 2, 3, 4]          # the profile helper's kernel slots

@@ -154,7 +154,7 @@ typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
  *                2 for FP64 axisymmetric plans (faster there) and for the
  *                fourth-order operator (which has only the stored form).
  *  x_ring        search directions held before they are added into x
- *                (Cartesian second-order acoustic CG): iteration k keeps
+ *                (Cartesian acoustic CG, either operator order): iteration k keeps
  *                p_k and alpha_k, and x += alpha_j p_j is applied in order,
  *                in FP64, by one pass at the end of each CG phase (or before
  *                a held direction would be overwritten), so the update does

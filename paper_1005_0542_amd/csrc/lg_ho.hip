@@ -44,6 +44,9 @@ struct HoArgs {
     ShotCtl* ctl;        // nullptr: plain application
     double* partial;
     size_t pstride;
+    int pring;           // > 1 (CG): p at slot giter[0] % pring (held search directions)
+    size_t pslot;        // elements per slot
+    const int* giter;
 };
 
 // A4 contribution of one axis at one node from the 7 node values v[0..6]
@@ -125,8 +128,10 @@ __global__ __launch_bounds__(256) void ho_stencil_kernel(HoArgs<T> a) {
         toff[u] = in ? (uint32_t)((nj - 1) * nx1 + ni - 1) * SZ : BUF_OOB;
         tsgn[u] = sgn;
     }
+    // held directions: this iteration's p slot (one count for every shot)
+    const size_t ps = (!RES && a.pring > 1) ? (size_t)(*a.giter % a.pring) * a.pslot : 0;
     auto load_tile = [&](int f, T* v) {
-        const rsrc_t rp = buf_rsrc(a.p + (size_t)f * nf, nf * SZ);
+        const rsrc_t rp = buf_rsrc(a.p + ps + (size_t)f * nf, nf * SZ);
 #pragma unroll
         for (int u = 0; u < HO_LPT; ++u) v[u] = bload<T>(rp, toff[u]);
     };
@@ -207,6 +212,9 @@ hipError_t ho_T(lg_plan* p, const T* x, T* y, bool reduce, const T* kx, const T*
     a.ctl = reduce ? p->ctl : nullptr;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
+    a.pring = (reduce && !RES) ? p->pring : 1;
+    a.pslot = p->nvec;
+    a.giter = p->giter;
     const int groups = (a.nfields + a.nsh - 1) / a.nsh;
     hipLaunchKernelGGL((ho_stencil_kernel<T, RES>), dim3(a.gx * a.gy * groups), dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();

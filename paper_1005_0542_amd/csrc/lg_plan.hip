@@ -615,11 +615,11 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         if (tuning->reserved[0] != 0 || tuning->reserved[1] != 0)
             return fail(LG_ERR_INVALID_ARG, "lg_tuning.reserved must be 0");
     }
-    // held search directions: Cartesian second-order acoustic CG only
-    const bool ring_ok = kind == LG_ACOUSTIC && !cyl && order == 2;
+    // held search directions: Cartesian acoustic CG (second- or fourth-order operator)
+    const bool ring_ok = kind == LG_ACOUSTIC && !cyl;
     if (ring < 0 || ring > 64) return fail(LG_ERR_INVALID_ARG, "x_ring must be in 0..64");
     if (ring > 1 && !ring_ok)
-        return fail(LG_ERR_UNSUPPORTED, "x_ring > 1 is implemented for Cartesian second-order acoustic plans");
+        return fail(LG_ERR_UNSUPPORTED, "x_ring > 1 is implemented for Cartesian acoustic plans");
     // a batch of CG iterations between flushes (graph_iters, or 8 without a
     // graph) must leave a free slot for the next direction
     const int batch = gi > 0 ? gi : 8;

@@ -18,10 +18,10 @@ from paper_1005_0542_amd import api
 pytestmark = pytest.mark.gpu
 
 
-def _plan(nx, nz, kappa, rho, h, precision, shots, graph_iters=0, x_ring=0, segments=0):
+def _plan(nx, nz, kappa, rho, h, precision, shots, graph_iters=0, x_ring=0, segments=0, order=2):
     med = np.stack([kappa, rho])
     return api.Plan("acoustic", nx, nz, 10.0, 10.0, 9, h, 8, med, precision=precision, nshots=shots,
-                    segments=segments, graph_iters=graph_iters, x_ring=x_ring)
+                    segments=segments, graph_iters=graph_iters, x_ring=x_ring, order=order)
 
 
 def _rhs(nx, nz, shots, seed=21):
@@ -70,6 +70,26 @@ def test_held_directions_bitwise_equal_in_place_update(precision, nx, nz, gi, ri
     print(f"iterations per shot: {r1.iters}")
     if gi == 2 and ring == 3:
         assert max(r1.iters) > 2 * (K - 1)                         # several flushes inside the phase
+
+
+@pytest.mark.parametrize("precision,gi,ring", [("fp64", 0, 0), ("fp64", 2, 3), ("mixed", 0, 0), ("mixed", 2, 3)])
+def test_held_directions_fourth_order_bitwise_equal_in_place_update(precision, gi, ring):
+    """The fourth-order operator (stored A p; its FP64 residual reads x after
+    the flush) with held directions: bitwise the in-place update."""
+    nx, nz = 128, 64
+    kappa, rho = heterogeneous(nx, nz)
+    b = _rhs(nx, nz, 3, seed=33)
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    ref = _plan(nx, nz, kappa, rho, 200.0, precision, 3, graph_iters=gi, x_ring=1, order=4)
+    log(f"held fourth order {precision} graph_iters={gi}: in-place reference")
+    x1, r1 = _solve(ref, b, tol)
+    plan = _plan(nx, nz, kappa, rho, 200.0, precision, 3, graph_iters=gi, x_ring=ring, order=4)
+    assert plan.x_ring() == (ring if ring else 16)
+    log(f"held fourth order {precision} graph_iters={gi} x_ring={plan.x_ring()}")
+    x2, r2 = _solve(plan, b, tol)
+    assert r2.statuses == r1.statuses and r2.iters == r1.iters and r2.relres == r1.relres
+    assert np.array_equal(x2, x1)
+    assert r1.statuses[1] == OK and not x1[1].any()
 
 
 def test_held_directions_solution_matches_oracle_fp64():
