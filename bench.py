@@ -67,20 +67,22 @@ def flush_bytes(ws: int, mean_iters: float, phases: int) -> float:
     return ws + (8.0 + 16.0 * (phases - 1)) / max(mean_iters, 1.0)
 
 
-def cyl_kernel_bytes(ws: int, shots: int, fused: bool = True, dichotomy: bool = True):
+def cyl_kernel_bytes(ws: int, shots: int, fused: bool = True, dichotomy: bool = True, held: bool = False):
     """The same for the axisymmetric iteration (Sec. 2.3): fused, the update
     recomputes A p (stored-q form: the operator writes q, the update reads it);
     the r-systems read rhat and write zhat once (the Thomas sweep's
     intermediate, or the Dichotomy's three values per segment, are not
     counted); the face tables, shift and r-system factors are shared by all
     shots; with the Dichotomy the inverse transform also reads the two
-    separator responses of every row (shared by all shots)."""
+    separator responses of every row (shared by all shots).  held: the update
+    leaves x alone (the flush pass is counted by flush_bytes)."""
+    xb = 0 if held else 16                                    # x in/out (f64)
     if fused:
         op = ws + 3 * ws / shots                              # p in; a1, a2, w once per batch
-        upd = 32 + 2 * ws + 3 * ws / shots                    # x, r in/out (f64); p in; rhat out; medium
+        upd = xb + 16 + 2 * ws + 3 * ws / shots               # r in/out (f64); p in; rhat out; medium
     else:
         op = 2 * ws + 3 * ws / shots                          # p in, q out; a1, a2, w once per batch
-        upd = 32 + 3 * ws                                     # x, r in/out (f64); p, q in; rhat out
+        upd = xb + 16 + 3 * ws                                # r in/out (f64); p, q in; rhat out
     return {
         "operator": op,
         "update_fdct": upd,
@@ -214,7 +216,7 @@ def run_variant(name, precision, shots, steps, warmup, segments=0, graph_iters=0
     # and the fourth-order operator, else recomputed in the update
     fusion = tuned.get("op_fusion", 0) or (2 if (cyl and precision == "fp64") or order == 4 else 1)
     if cyl:
-        kb = cyl_kernel_bytes(ws, shots, fusion != 2, seg > 1)
+        kb = cyl_kernel_bytes(ws, shots, fusion != 2, seg > 1, held=held)
     elif order == 4:
         kb = kernel_bytes(ws, shots, seg_len, fused=False, medium=3, held=held)
     else:

@@ -154,7 +154,7 @@ typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
  *                2 for FP64 axisymmetric plans (faster there) and for the
  *                fourth-order operator (which has only the stored form).
  *  x_ring        search directions held before they are added into x
- *                (Cartesian acoustic CG, either operator order): iteration k keeps
+ *                (acoustic CG, every geometry and order): iteration k keeps
  *                p_k and alpha_k, and x += alpha_j p_j is applied in order,
  *                in FP64, by one pass at the end of each CG phase (or before
  *                a held direction would be overwritten), so the update does
@@ -163,8 +163,9 @@ typedef struct { int32_t iters; int32_t status; double relres; } lg_solve_info;
  *                every iteration (the only form of the other plans); else
  *                more than graph_iters (8 without a graph) and at most 64
  *                directions (memory: x_ring copies of p); 0 = default:
- *                max(16, graph_iters + 1), halved (not below graph_iters + 1)
- *                while the copies would pass 64 GiB, 1 if they still do.
+ *                max(16, graph_iters + 1) (32 for axisymmetric plans),
+ *                halved (not below graph_iters + 1) while the copies would
+ *                pass 64 GiB, 1 if they still do.
  *  reserved      must be 0. */
 typedef struct {
     int32_t segments;

@@ -66,6 +66,9 @@ struct CylStArgs {
     ShotCtl* ctl;        // nullptr: plain application
     double* partial;
     size_t pstride;
+    int pring;           // > 1 (CG): p at slot giter[0] % pring (held search directions)
+    size_t pslot;        // elements per slot
+    const int* giter;
 };
 
 // The waves-per-EU bound leaves the register room to keep every load of a
@@ -127,11 +130,13 @@ cyl_stencil_kernel(CylStArgs<T> a) {
         fr[r] = bload<T>(r2, ok ? (e2 + 1) * SZ : BUF_OOB);
         wv[r] = bload<T>(rw, oc[r + 1]);
     }
+    // held directions: this iteration's p slot (one count for every shot)
+    const size_t ps = (!RES && a.pring > 1) ? (size_t)(*a.giter % a.pring) * a.pslot : 0;
     // per field: loads, A p, store, per-wave (p, Ap); one barrier at the end
     for (int kf = 0; kf < ns; ++kf) {
         if (act[kf] == 0) continue;                 // uniform per block
         const size_t fo = (size_t)(f0 + kf) * nf;
-        const rsrc_t rp = buf_rsrc(a.p + fo, nf * SZ);
+        const rsrc_t rp = buf_rsrc(a.p + ps + fo, nf * SZ);
         T pv[CY_RPT + 2], pe[CY_RPT], pw[CY_RPT];
 #pragma unroll
         for (int r = 0; r < CY_RPT + 2; ++r) pv[r] = bload<T>(rp, oc[r]);
@@ -206,6 +211,9 @@ struct CylDctArgs {
     double* partial;
     size_t pstride;
     int init;
+    int pring;             // > 1: held directions, p of iteration g at slot g % pring; x not touched
+    size_t pslot;          // elements per slot
+    const int* giter;      // [0] the solve's iteration count g
 };
 
 template <typename T, int M, int R, int FPB, int MODE>
@@ -237,6 +245,10 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
     if constexpr (UPD || CORRM) {
         if (!a.init && a.ctl[field].active == 0) return;   // uniform per block
     }
+    // held directions: the solve's iteration count (the update of iteration g
+    // reads p_g; the correction after it reads p_g and writes p_{g+1}; a start
+    // or restart writes the first direction at g)
+    const int kit = ((UPD || CORRM) && a.pring > 1) ? *a.giter : 0;
     cpx<T>* buf = lds + fid * LL;
     constexpr uint32_t SZ = sizeof(T);
     const uint32_t nfe = (uint32_t)a.nz1 * (uint32_t)N;
@@ -266,12 +278,16 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
                 }
                 double* const X = wave_uniform(init ? a.x : a.xslot[0]);
                 const double alpha = init ? 0.0 : a.ctl[field].alpha;
-                const rsrc_t rX = buf_rsrc(X + fbase, (init == 0 && !fresh) ? nfe * 8u : 0u);
-                const rsrc_t rXs = buf_rsrc(X + fbase, init == 0 ? nfe * 8u : 0u);
+                // held directions: x is neither read nor written (the flush pass
+                // adds alpha_g p_g later)
+                const bool xin = a.pring == 1;
+                const rsrc_t rX = buf_rsrc(X + fbase, (init == 0 && !fresh && xin) ? nfe * 8u : 0u);
+                const rsrc_t rXs = buf_rsrc(X + fbase, (init == 0 && xin) ? nfe * 8u : 0u);
                 const rsrc_t rR = buf_rsrc(
                     wave_uniform(init == 1 ? a.b + fbase : (B0 != nullptr ? B0 + fbase : a.r + fbase)), nfe * 8u);
                 const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 0 ? nfe * 8u : 0u);
-                const rsrc_t rP = buf_rsrc(a.p + fbase, init ? 0u : nfe * SZ);
+                const size_t pofs = (init == 0 && a.pring > 1) ? (size_t)(kit % a.pring) * a.pslot : 0;
+                const rsrc_t rP = buf_rsrc(a.p + pofs + fbase, init ? 0u : nfe * SZ);
                 const rsrc_t rQ = buf_rsrc(a.q + fbase, (init || MODE == CY_UPDATE_OP) ? 0u : nfe * SZ);
                 const rsrc_t rA1 = buf_rsrc(a.a1, MODE == CY_UPDATE_OP ? nfe * SZ : 0u);
                 const rsrc_t rA2 = buf_rsrc(a.a2, MODE == CY_UPDATE_OP ? (uint32_t)a.nz1 * (N + 1) * SZ : 0u);
@@ -376,7 +392,8 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
             }
             if (t == 0) buf[lpad(N)] = {(T)0, (T)0};
             if constexpr (CORRM) {
-                const rsrc_t rPo = buf_rsrc(a.out + fbase, a.init ? 0u : nfe * SZ);
+                const size_t rofs = (!a.init && a.pring > 1) ? (size_t)((kit + a.pring - 1) % a.pring) * a.pslot : 0;
+                const rsrc_t rPo = buf_rsrc(a.out + rofs + fbase, a.init ? 0u : nfe * SZ);
 #pragma unroll
                 for (int qb = 0; qb < NBL; ++qb)
 #pragma unroll
@@ -400,6 +417,8 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
     if (live) {
         T beta = (T)0;
         if constexpr (CORRM) beta = (T)a.ctl[field].beta;
+        // CORRECT with held directions: the new direction goes to slot g % pring
+        T* const outp = a.out + ((CORRM && a.pring > 1) ? (size_t)(kit % a.pring) * a.pslot : 0);
         const size_t o0 = fbase + (size_t)j0 * N, o1 = fbase + (size_t)j1 * N;
 #pragma unroll
         for (int qb = 0; qb < NBL; ++qb)
@@ -423,8 +442,8 @@ __global__ __launch_bounds__(FPB*(M / R)) void cyl_dct_kernel(CylDctArgs<T> a) {
                         x1 += beta * pold1[oi];
                     }
                 }
-                a.out[o0 + K] = x0;
-                if (has1) a.out[o1 + K] = x1;
+                outp[o0 + K] = x0;
+                if (has1) outp[o1 + K] = x1;
             }
     }
     if constexpr (UPD) {
@@ -712,6 +731,9 @@ hipError_t cyl_stencil_T(lg_plan* p, const T* x, T* y, bool reduce, int nfields,
     a.ctl = reduce ? p->ctl : nullptr;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
+    a.pring = (reduce && !RES) ? p->pring : 1;
+    a.pslot = p->nvec;
+    a.giter = p->giter;
     const int groups = (nfields + a.nsh - 1) / a.nsh;
     hipLaunchKernelGGL((cyl_stencil_kernel<T, RES>), dim3(a.gx * a.gy * groups), dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
@@ -771,6 +793,9 @@ CylDctArgs<T> cyl_dct_args(lg_plan* p) {
     a.P = p->blk[0].P;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
+    a.pring = p->pring;
+    a.pslot = p->nvec;
+    a.giter = p->giter;
     return a;
 }
 

@@ -149,7 +149,7 @@ struct lg_plan {
     // Krylov workspace
     double* r = nullptr;       // FP64 residual
     void* p = nullptr;         // working type: pring slots of nvec values
-    // Held search directions (Cartesian acoustic PCG): iteration
+    // Held search directions (acoustic PCG): iteration
     // k reads p_k from slot k % pring and keeps alpha_k; x += alpha_j p_j is
     // applied in order by a flush pass (phase ends, or before a slot would be
     // reused) instead of in every update.  pring = 1: x updated in place.

@@ -1183,7 +1183,11 @@ __global__ __launch_bounds__(256) void flush_x_kernel(double* __restrict__ x, co
     const int j0 = giter[1];
     const int n = giter[0] - j0;
     const bool zero = ctl[field].xzero != 0;
-    if (n <= 0 && !zero) return;                    // uniform per block
+    // nothing to add (no iteration, or the shot was masked in all of them):
+    // x stays as it is, unless it is still the implied 0 of a cold start
+    bool any = zero;
+    for (int j = 0; j < n && !any; ++j) any = ahist[(size_t)field * pring + (j0 + j) % pring] != 0.0;
+    if (!any) return;                               // uniform per block
     const size_t fb = (size_t)field * npts;
     const size_t e0 = (size_t)bif * (256 * FLUSH_EPT) + threadIdx.x;
     double v[FLUSH_EPT];

@@ -259,7 +259,7 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
     // flushed into x between timed iterations where needed, and at the end.
     int since = 0;
     for (int it = 0; it <= iters && e == hipSuccess; ++it) {
-        if (!cy && p->pring > 1 && since + 1 > p->pring - 1) {
+        if (p->pring > 1 && since + 1 > p->pring - 1) {
             e = launch_flush_x(p, x);
             since = 0;
             if (e != hipSuccess) break;
@@ -287,7 +287,7 @@ lg_status pcg_profile(lg_plan* p, const double* b, double* x, int iters, float* 
         }
     }
     for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
-    if (e == hipSuccess && !cy) e = launch_flush_x(p, x);
+    if (e == hipSuccess) e = launch_flush_x(p, x);
     if (e != hipSuccess) return hip_fail(e, "lg_pcg_profile");
     for (int k = 0; k < 5; ++k) ms[k] = (float)(acc[k] / iters);
     return LG_OK;

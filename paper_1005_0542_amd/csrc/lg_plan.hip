@@ -615,11 +615,11 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         if (tuning->reserved[0] != 0 || tuning->reserved[1] != 0)
             return fail(LG_ERR_INVALID_ARG, "lg_tuning.reserved must be 0");
     }
-    // held search directions: Cartesian acoustic CG (second- or fourth-order operator)
-    const bool ring_ok = kind == LG_ACOUSTIC && !cyl;
+    // held search directions: acoustic CG (every geometry and operator order)
+    const bool ring_ok = kind == LG_ACOUSTIC;
     if (ring < 0 || ring > 64) return fail(LG_ERR_INVALID_ARG, "x_ring must be in 0..64");
     if (ring > 1 && !ring_ok)
-        return fail(LG_ERR_UNSUPPORTED, "x_ring > 1 is implemented for Cartesian acoustic plans");
+        return fail(LG_ERR_UNSUPPORTED, "x_ring > 1 is implemented for acoustic plans");
     // a batch of CG iterations between flushes (graph_iters, or 8 without a
     // graph) must leave a free slot for the next direction
     const int batch = gi > 0 ? gi : 8;
@@ -677,10 +677,12 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
     p->order = order;
     p->fuse_op = (fus == 1) && order == 2;
     if (ring == 0 && ring_ok) {
-        // default: 16 held directions (more than a batch), fewer where the
-        // slots would pass 64 GiB, none where fewer would not exceed a batch
+        // default: 16 held directions (32 for axisymmetric plans, whose solves
+        // run two to three times longer: fewer flushes inside a phase), more
+        // than a batch; fewer where the slots would pass 64 GiB, none where
+        // fewer would not exceed a batch
         const size_t slot = p->nvec * (prec == LG_FP64 ? 8 : 4);
-        ring = std::max(16, batch + 1);
+        ring = std::max(cyl ? 32 : 16, batch + 1);
         while (ring > batch + 1 && (size_t)ring * slot > ((size_t)64 << 30)) ring = std::max(batch + 1, ring / 2);
         if ((size_t)ring * slot > ((size_t)64 << 30) || ring < 4) ring = 1;
     }

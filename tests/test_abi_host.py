@@ -101,9 +101,8 @@ def test_plan_create_unsupported_shapes():
     assert _create(top=_lib.LG_TOP_FREE, order=4) == _lib.LG_ERR_UNSUPPORTED
 
 
-def test_plan_create_held_directions_unsupported_outside_cartesian_acoustic():
+def test_plan_create_held_directions_unsupported_for_elastic_plans():
     assert _create(x_ring=4, graph_iters=2, kind=_lib.LG_ELASTIC) == _lib.LG_ERR_UNSUPPORTED
-    assert _create(x_ring=4, graph_iters=2, geometry=_lib.LG_CYLINDRICAL) == _lib.LG_ERR_UNSUPPORTED
     assert "x_ring" in _lib.load().lg_last_error().decode()
 
 

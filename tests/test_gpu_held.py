@@ -18,10 +18,11 @@ from paper_1005_0542_amd import api
 pytestmark = pytest.mark.gpu
 
 
-def _plan(nx, nz, kappa, rho, h, precision, shots, graph_iters=0, x_ring=0, segments=0, order=2):
+def _plan(nx, nz, kappa, rho, h, precision, shots, graph_iters=0, x_ring=0, segments=0, order=2,
+          geometry="cartesian"):
     med = np.stack([kappa, rho])
     return api.Plan("acoustic", nx, nz, 10.0, 10.0, 9, h, 8, med, precision=precision, nshots=shots,
-                    segments=segments, graph_iters=graph_iters, x_ring=x_ring, order=order)
+                    segments=segments, graph_iters=graph_iters, x_ring=x_ring, order=order, geometry=geometry)
 
 
 def _rhs(nx, nz, shots, seed=21):
@@ -87,6 +88,35 @@ def test_held_directions_fourth_order_bitwise_equal_in_place_update(precision, g
     assert plan.x_ring() == (ring if ring else 16)
     log(f"held fourth order {precision} graph_iters={gi} x_ring={plan.x_ring()}")
     x2, r2 = _solve(plan, b, tol)
+    assert r2.statuses == r1.statuses and r2.iters == r1.iters and r2.relres == r1.relres
+    assert np.array_equal(x2, x1)
+    assert r1.statuses[1] == OK and not x1[1].any()
+
+
+@pytest.mark.parametrize("precision,gi,ring,P", [("fp64", 0, 0, 0), ("fp64", 2, 3, 4), ("mixed", 0, 0, 0),
+                                                 ("mixed", 2, 3, 1)])
+def test_held_directions_axisymmetric_bitwise_equal_in_place_update(precision, gi, ring, P):
+    """The axisymmetric problem (cosine transform along z, r-systems by
+    Thomas or the Dichotomy) with held directions: bitwise the in-place update."""
+    torch = torch_cuda()
+    nr, nzc = 64, 128                     # plan nx = N_z (transform axis), nz = N_r
+    kappa, rho = heterogeneous(nzc, nr)
+    kappa, rho = np.ascontiguousarray(kappa[:nr, :nzc]), np.ascontiguousarray(rho[:nr, :nzc])
+    S = 3
+    b = np.random.default_rng(44).standard_normal((S, 1, nr - 1, nzc))
+    b[1] = 0.0
+    tol = 1e-10 if precision == "fp64" else 1e-9
+    out = {}
+    for r in (1, ring):
+        plan = _plan(nzc, nr, kappa, rho, 200.0, precision, S, graph_iters=gi, x_ring=r, segments=P,
+                     geometry="cylindrical")
+        assert plan.x_ring() == (r if r else 32)
+        log(f"held axisymmetric {precision} graph_iters={gi} x_ring={plan.x_ring()} segments={P}")
+        bd = to_dev(b, torch.float64)
+        xd = torch.full_like(bd, 3.0)
+        res = plan.pcg_solve(bd, xd, tol=tol, max_iter=400)
+        out[r] = (to_np(xd), res)
+    (x1, r1), (x2, r2) = out[1], out[ring]
     assert r2.statuses == r1.statuses and r2.iters == r1.iters and r2.relres == r1.relres
     assert np.array_equal(x2, x1)
     assert r1.statuses[1] == OK and not x1[1].any()
