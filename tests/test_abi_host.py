@@ -168,3 +168,11 @@ def test_host_helpers_reject_bad_parameters():
     t = np.array([-1.0])
     assert lib.lg_laguerre_weights(ctypes.byref(lag), t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1,
                                    p) == _lib.LG_ERR_INVALID_ARG
+
+
+def test_tuner_keeps_the_smallest_graph_batch_within_the_trial_spread():
+    from paper_1005_0542_amd import tune
+    t = lambda *ms: [{"graph_iters": g, "solve_ms": m} for g, m in zip(tune.GRAPH_ITERS_CANDIDATES, ms)]
+    assert tune.pick_graph_iters(t(100.0, 97.0, 96.0, 99.0)) == 2          # 4 % faster: within the spread
+    assert tune.pick_graph_iters(t(100.0, 99.0, 90.0, 93.0)) == 8          # 10 % faster
+    assert tune.pick_graph_iters(t(100.0, 120.0, 130.0, 140.0)) == 2
