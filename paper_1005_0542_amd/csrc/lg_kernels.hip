@@ -847,8 +847,9 @@ __global__ __launch_bounds__(256) void td_kernel(TdArgs<T> a) {
 // subdomain's inverse, prepared once) plus the response to the two known
 // boundary values; the sums are segmented reductions across the lanes of the
 // wave (one lane per separator).  The wave also forms this system's share of
-// (rhat, zhat) = b (sum_s g^T T^{-1} g + sum_s x_s G_s), and the last block of
-// a field turns the total into (r, z) = (2/nx) (rhat, zhat) and beta.
+// (rhat, zhat) = b (sum_s g^T T^{-1} g + sum_s x_s G_s), one partial per
+// block; the finalize kernel turns their sum into (r, z) = (2/nx) (rhat, zhat)
+// and beta.
 // mode 0: interface only; 1: CG start (rz); 2: CG iteration (beta, rz).
 // ===========================================================================
 template <typename T>
