@@ -363,7 +363,9 @@ lg_status lg_trace_synthesize_noalloc(lg_plan* plan, const double* rec_coeff, co
  * Axisymmetric plans (LG_CYLINDRICAL) report 0 operator, 1 update + forward
  * cosine transform, 2 the r-systems (+ (r,z), beta), 3 zero (no interface
  * stage), 4 inverse cosine transform + p update.
- * x is overwritten with the iterate after iters + 1 iterations.  Acoustic
+ * With held search directions the flush pass (x += alpha_j p_j) runs between
+ * timed iterations where the ring is full and at the end, outside the timed
+ * intervals.  x is overwritten with the iterate after iters + 1 iterations.  Acoustic
  * plans only. */
 lg_status lg_pcg_profile(lg_plan* plan, const double* b, double* x, int32_t iters, float* ms_host);
 
