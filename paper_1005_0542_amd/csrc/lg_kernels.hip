@@ -1031,8 +1031,37 @@ struct FinArgs {
     int* giter;       // pring > 1: [0] the solve's iteration count g, [1] iterations added into x
 };
 
-__global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
-    __shared__ double red[4];
+// Each thread of the one block per field loads FIN_UNROLL partials (strided
+// by the block size) before adding them, so a pass costs one memory latency.
+// The block size follows the partial count (a large block only where there
+// are many partials: launching one costs more), so the order of the
+// additions depends on the partial count alone.
+constexpr int FIN_UNROLL = 8;
+constexpr int FIN_SMALL = 256, FIN_LARGE = 1024;
+constexpr int FIN_SMALL_MAX = FIN_UNROLL * FIN_SMALL;     // partials one pass of the small block covers
+
+template <int NT>
+__device__ __forceinline__ double fin_sum(const double* __restrict__ part, int n, double* red) {
+    double s = 0.0;
+    for (int i0 = threadIdx.x; i0 < n; i0 += FIN_UNROLL * NT) {
+        double v[FIN_UNROLL];
+#pragma unroll
+        for (int u = 0; u < FIN_UNROLL; ++u) {
+            const int i = i0 + u * NT;
+            v[u] = i < n ? part[i] : 0.0;
+        }
+#pragma unroll
+        for (int w = FIN_UNROLL / 2; w > 0; w /= 2)
+#pragma unroll
+            for (int u = 0; u < w; ++u) v[u] += v[u + w];
+        s += v[0];
+    }
+    return block_sum(s, red);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void finalize_kernel(FinArgs a) {
+    __shared__ double red[NT / 64];
     const int field = blockIdx.x;
     ShotCtl& c = a.ctl[field];
     const bool start_rr = (a.kind == FIN_RR && a.init);
@@ -1049,16 +1078,10 @@ __global__ __launch_bounds__(256) void finalize_kernel(FinArgs a) {
         }
     }
     if (!start_rr && c.active == 0) return;                  // uniform per block
-    double s = 0.0;
     const double* part = a.partial + (size_t)field * a.pstride;
-    for (int i = threadIdx.x; i < a.nparts; i += blockDim.x) s += part[i];
-    const double tot = block_sum(s, red);
+    const double tot = fin_sum<NT>(part, a.nparts, red);
     double bbt = 0.0;                                        // FIN_RR init 4: ||b||^2 after the rr set
-    if (a.kind == FIN_RR && a.init == 4) {
-        double sb = 0.0;
-        for (int i = threadIdx.x; i < a.nparts; i += blockDim.x) sb += part[a.nparts + i];
-        bbt = block_sum(sb, red);
-    }
+    if (a.kind == FIN_RR && a.init == 4) bbt = fin_sum<NT>(part + a.nparts, a.nparts, red);
     if (threadIdx.x != 0) return;
     if (a.kind == FIN_PQ) {
         c.pq = tot;
@@ -1385,7 +1408,10 @@ hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int
     f.ahist = p->ahist;
     f.pring = p->pring;
     f.giter = p->giter;
-    hipLaunchKernelGGL(finalize_kernel, dim3(p->S * p->C), dim3(256), 0, p->stream, f);
+    if (nparts <= FIN_SMALL_MAX)
+        hipLaunchKernelGGL(finalize_kernel<FIN_SMALL>, dim3(p->S * p->C), dim3(FIN_SMALL), 0, p->stream, f);
+    else
+        hipLaunchKernelGGL(finalize_kernel<FIN_LARGE>, dim3(p->S * p->C), dim3(FIN_LARGE), 0, p->stream, f);
     return hipGetLastError();
 }
 
