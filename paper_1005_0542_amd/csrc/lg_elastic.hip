@@ -38,25 +38,53 @@ struct ElArgs {
     T idx2, idz2, ixz;   // 1/dx^2, 1/dz^2, 1/(4 dx dz)
 };
 
+// One block computes a tile of EL_TX x EL_TZ points of one shot from LDS
+// copies of both components and of the node-sampled lambda and mu over the
+// tile and its one-point rim (interior values outside the grid staged as 0).
+constexpr int EL_TX = 64, EL_TZ = 4;
+constexpr int EL_HX = EL_TX + 2, EL_HZ = EL_TZ + 2;
+
 template <typename T>
-__global__ __launch_bounds__(256) void elastic_stencil_kernel(ElArgs<T> a) {
-    const size_t npts = (size_t)a.nx1 * a.nz1;
-    const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= npts * a.S) return;
-    const size_t s = e / npts;
-    const size_t pt = e - s * npts;
-    const int j = (int)(pt / a.nx1), i = (int)(pt - (size_t)j * a.nx1);
+__global__ __launch_bounds__(EL_TX * EL_TZ) void elastic_stencil_kernel(ElArgs<T> a) {
+    __shared__ T sux[EL_HZ][EL_HX], suz[EL_HZ][EL_HX], slam[EL_HZ][EL_HX], smu[EL_HZ][EL_HX];
     const int nx1 = a.nx1, nz1 = a.nz1, NXN = nx1 + 2;
+    const size_t npts = (size_t)nx1 * nz1;
+    // blocks in (shot, tile row, tile column) order
+    const unsigned xb = (unsigned)(nx1 + EL_TX - 1) / EL_TX;
+    const unsigned tiles = xb * (unsigned)((nz1 + EL_TZ - 1) / EL_TZ);
+    const unsigned s = blockIdx.x / tiles;
+    const unsigned rt = blockIdx.x - s * tiles;
+    const unsigned tzb = rt / xb;
+    const int i0 = (int)(rt - tzb * xb) * EL_TX, j0 = (int)tzb * EL_TZ;
+    const T* gux = a.u + (size_t)s * 2 * npts;
+    const T* guz = gux + npts;
+    // rim entry (hz, hx) holds interior point (i0 - 1 + hx, j0 - 1 + hz), whose
+    // node is (i0 + hx, j0 + hz)
+    for (int q = threadIdx.x; q < EL_HZ * EL_HX; q += EL_TX * EL_TZ) {
+        const int hz = q / EL_HX, hx = q - hz * EL_HX;
+        const int ii = i0 - 1 + hx, jj = j0 - 1 + hz;
+        const bool in = ii >= 0 && ii < nx1 && jj >= 0 && jj < nz1;
+        const size_t o = in ? (size_t)jj * nx1 + ii : 0;
+        sux[hz][hx] = in ? gux[o] : (T)0;
+        suz[hz][hx] = in ? guz[o] : (T)0;
+        const bool nin = ii <= nx1 && jj <= nz1;            // node index within [0, n + 1]
+        const size_t on = nin ? (size_t)(jj + 1) * NXN + (ii + 1) : 0;
+        slam[hz][hx] = nin ? a.lam[on] : (T)0;
+        smu[hz][hx] = nin ? a.mu[on] : (T)0;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x % EL_TX, tz = threadIdx.x / EL_TX;
+    const int i = i0 + tx, j = j0 + tz;
+    if (i >= nx1 || j >= nz1) return;
+    const size_t pt = (size_t)j * nx1 + i;
     const int I = i + 1, J = j + 1;
-    const T* ux = a.u + s * 2 * npts;
-    const T* uz = ux + npts;
-    // interior value of a component at node (Ii, Jj), zero on the boundary
-    auto U = [&](const T* f, int Ii, int Jj) -> T {
-        if (Ii < 1 || Ii > nx1 || Jj < 1 || Jj > nz1) return (T)0;
-        return f[(size_t)(Jj - 1) * nx1 + (Ii - 1)];
-    };
-    auto L = [&](int Ii, int Jj) -> T { return a.lam[(size_t)Jj * NXN + Ii]; };
-    auto Mu = [&](int Ii, int Jj) -> T { return a.mu[(size_t)Jj * NXN + Ii]; };
+    // value of a component (interior, zero on the boundary), lambda and mu at
+    // node (Ii, Jj) within one node of (I, J)
+    const T(*const ux)[EL_HX] = sux;
+    const T(*const uz)[EL_HX] = suz;
+    auto U = [&](const T(*f)[EL_HX], int Ii, int Jj) -> T { return f[tz + 1 + (Jj - J)][tx + 1 + (Ii - I)]; };
+    auto L = [&](int Ii, int Jj) -> T { return slam[tz + 1 + (Jj - J)][tx + 1 + (Ii - I)]; };
+    auto Mu = [&](int Ii, int Jj) -> T { return smu[tz + 1 + (Jj - J)][tx + 1 + (Ii - I)]; };
     const T h = (T)0.5;
     const T l0 = L(I, J), m0 = Mu(I, J);
     const T p0 = l0 + 2 * m0;
@@ -126,8 +154,8 @@ hipError_t el_stencil_T(lg_plan* p, const T* x, T* y) {
     a.idx2 = (T)(1.0 / (p->g.dx * p->g.dx));
     a.idz2 = (T)(1.0 / (p->g.dz * p->g.dz));
     a.ixz = (T)(1.0 / (4.0 * p->g.dx * p->g.dz));
-    const size_t total = p->npts * p->S;
-    hipLaunchKernelGGL(elastic_stencil_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+    const size_t tiles = (size_t)((p->nx1 + EL_TX - 1) / EL_TX) * ((p->nz1 + EL_TZ - 1) / EL_TZ);
+    hipLaunchKernelGGL(elastic_stencil_kernel<T>, dim3((unsigned)(tiles * p->S)), dim3(EL_TX * EL_TZ), 0,
                        p->stream, a);
     return hipGetLastError();
 }
