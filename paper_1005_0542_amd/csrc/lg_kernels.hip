@@ -245,6 +245,7 @@ struct DstArgs {
     // CORRECT: Dichotomy segment correction
     const T* y;
     const T* utab;
+    const T* utab2;        // non-null: odd fields take this second block's table (elastic K)
     int Ls, P;
 };
 
@@ -330,7 +331,7 @@ dst_kernel(DstArgs<T> a) {
     const bool has1 = live && (j1 < a.nz1);
 
     if constexpr (UPD || MODE == DST_CORRECT) {
-        bool skip = a.ctl[field].active == 0;
+        bool skip = a.ctl != nullptr && a.ctl[field].active == 0;   // CORRECT without ctl: no mask
         if (UPD && a.init) skip = false;
         if (skip) return;   // uniform per block: blocks never span fields
     }
@@ -483,7 +484,8 @@ dst_kernel(DstArgs<T> a) {
             // (separator rows, the first / last segment) read 0.
             const int Ls = a.Ls, P = a.P;
             const rsrc_t rY = buf_rsrc(a.y + fbase, nfe * SZ);
-            const rsrc_t rU = buf_rsrc(a.utab, (uint32_t)Ls * (uint32_t)NX1 * SZ);
+            const rsrc_t rU = buf_rsrc((a.utab2 != nullptr && (field & 1)) ? a.utab2 : a.utab,
+                                       (uint32_t)Ls * (uint32_t)NX1 * SZ);
             const int rs0 = (j0 + 1) & (Ls - 1), sg0 = (j0 + 1) / Ls;
             const int rs1 = (j1 + 1) & (Ls - 1);
             const bool c0 = rs0 != 0, c1 = has1 && rs1 != 0;
@@ -664,7 +666,7 @@ dst_kernel(DstArgs<T> a) {
         // ---- outputs: LDS -> global, column t + u TPF ----------------------------
         if (live) {
             T beta = (T)0;
-            if constexpr (MODE == DST_CORRECT) beta = (T)a.ctl[field].beta;
+            if constexpr (MODE == DST_CORRECT) beta = a.init ? (T)0 : (T)a.ctl[field].beta;
 #pragma unroll
             for (int u = 0; u < NOUT; ++u) {
                 const int col = t + u * TPF;
@@ -702,7 +704,7 @@ dst_kernel(DstArgs<T> a) {
         // ---- outputs: registers -> global (first half of the spectrum) ---------
         if (live) {
             T beta = (T)0;
-            if constexpr (MODE == DST_CORRECT) beta = (T)a.ctl[field].beta;
+            if constexpr (MODE == DST_CORRECT) beta = a.init ? (T)0 : (T)a.ctl[field].beta;
 #pragma unroll
             for (int qb = 0; qb < NBL; ++qb)
 #pragma unroll
@@ -1759,6 +1761,28 @@ hipError_t launch_correct_idst(lg_plan* p, int init) {
     a.out = (float*)p->p;
     a.init = init;
     return dst_dispatch<float, DST_CORRECT>(p, a, p->S * p->C);
+}
+
+// Elastic K^{-1} (Dirichlet top, P > 1): the segment correction of both
+// blocks (field parity) fused into the inverse transform, z = DST^{-1} zhat;
+// no masking and no search-direction update.
+hipError_t launch_correct_inv(lg_plan* p, void* z, int nfields) {
+    if (p->prec == LG_FP64) {
+        DstArgs<double> a = dst_args<double>(p);
+        a.out = (double*)z;
+        a.init = 1;
+        a.ctl = nullptr;
+        a.free_top = 0;
+        a.utab2 = (const double*)p->blk[1].utab;
+        return dst_dispatch<double, DST_CORRECT>(p, a, nfields);
+    }
+    DstArgs<float> a = dst_args<float>(p);
+    a.out = (float*)z;
+    a.init = 1;
+    a.ctl = nullptr;
+    a.free_top = 0;
+    a.utab2 = (const float*)p->blk[1].utab;
+    return dst_dispatch<float, DST_CORRECT>(p, a, nfields);
 }
 
 hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked,
