@@ -287,119 +287,233 @@ __global__ __launch_bounds__(GM_BLK) void gm_multidot_kernel(const double* __res
     }
 }
 
-// Sum over the nblk per-block partials of product i of shot s, in the fixed
-// order of gm_reduce_kernel (every thread of the block gets the value), so a
-// consumer kernel can take a grid-wide result without a reduction launch.
-__device__ __forceinline__ double partial_total(const double* __restrict__ partial, int s, int i, int nblk,
-                                                double* red) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += GM_BLK) v += partial[((size_t)s * (GM_MAXK + 1) + i) * nblk + b];
-    return block_sum(v, red);
-}
+// ---------------------------------------------------------------------------
+// Arnoldi with delayed reorthogonalisation: classical Gram-Schmidt twice, the
+// second pass (and the normalisation) of q_j carried out inside step j + 1's
+// two sweeps, so a step reads the basis twice instead of three times.
+//
+// Step j starts from q_0..q_{j-1} (final, orthonormal) and t = V_j, which is
+// A q_{j-1} after one projection pass (t = A q_{j-1} - Q h, h the pass-1
+// coefficients of column j-1), neither reprojected nor normalised; at j = 0,
+// t = q_0 itself (final).  With u = A t (the operator applied to t):
+//   sweep 1:  a_i = (q_i, t) and b_i = (q_i, u) for i < j, (t, t), (t, u);
+//   q_j = (t - Q a) / rho with rho^2 = (t, t) - |a|^2 (at j = 0: rho = 1,
+//     a = 0), so column j-1 of H is final: H[i][j-1] = h_i + a_i (i < j),
+//     H[j][j-1] = rho;
+//   A q_j = (u - Q_{j+1} d) / rho with d = H[0..j][0..j-1] a (from the
+//     Arnoldi relation of the earlier columns); its pass-1 coefficients
+//     g_i = (q_i, A q_j) are (b_i - d_i) / rho for i < j and
+//     g_j = ((t, u) - a.b) / rho^2 - d_j / rho;
+//   sweep 2:  q_j stored over t, and step j + 1's
+//     t' = A q_j - Q_{j+1} g = u / rho - Q_{j+1} c,  c = d / rho + g.
+// rho^2 is a difference of a squared norm and the squares of the small
+// second-pass coefficients (t is already orthogonal to Q up to rounding), so
+// no cancellation occurs.  The end of a cycle runs sweep 1 without u and the
+// coefficient step only, to finalise the last column.
+// ---------------------------------------------------------------------------
+constexpr int GM_NS = 2 * GM_MAXK + 2;           // products per shot: a, b, (t,t), (t,u)
+constexpr int GM_HDS = (GM_MAXK + 1) * (GM_MAXK + 1);   // per shot: H (k+1) x k, then h
 
-// partial_total for products 0..m-1 at once (m <= MB): one pass over the
-// partials and one barrier; per product the same order as partial_total.
-template <int MB>
-__device__ __forceinline__ void partial_totals(const double* __restrict__ partial, int s, int m, int nblk,
-                                               double (*red)[GM_BLK / 64], double* c) {
-    double v[MB];
-#pragma unroll
-    for (int u = 0; u < MB; ++u) v[u] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += GM_BLK) {
-#pragma unroll
-        for (int u = 0; u < MB; ++u)
-            if (u < m) v[u] += partial[((size_t)s * (GM_MAXK + 1) + u) * nblk + b];
-    }
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-#pragma unroll
-    for (int u = 0; u < MB; ++u) {
-        v[u] = wave_sum(v[u]);
-        if (lane == 0) red[u][wave] = v[u];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < MB; ++u) {
-        double t = 0.0;
-        for (int i = 0; i < GM_BLK / 64; ++i) t += red[u][i];
-        c[u] = u < m ? t : 0.0;
-    }
-    __syncthreads();   // red may be reused by the caller
-}
-
-// Classical Gram-Schmidt twice, with each subtraction fused into the sweep
-// that follows it (one read of the basis instead of two):
-//   NORM = false: w -= sum_{i<m} coef[s][i] V_i, then the block partials of
-//                 (V_i, w) for i < m (the second pass's inner products);
-//   NORM = true:  w -= sum_{i<m} coef[s][i] V_i, then the block partial of
-//                 (w, w) in slot 0.
-// Per element the subtraction is gm_subtract_kernel's and the products and
-// per-thread sums are gm_multidot_kernel's, in the same order, so the
-// results are those of the separate kernels.  MB >= m bounds the unroll.
-// The coefficients are the previous sweep's products: with pin != nullptr
-// every block sums them from that sweep's per-block partials (pin) and block
-// 0 of the shot also stores them to coef (for the host's Hessenberg column);
-// with pin == nullptr they are read from coef.
-template <int MB, bool NORM>
-__global__ __launch_bounds__(GM_BLK) void gm_subdot_kernel(const double* __restrict__ V, size_t vstride, int m,
-                                                           double* __restrict__ coef, int coef_stride,
-                                                           const double* __restrict__ pin,
-                                                           double* __restrict__ w, size_t n_s,
-                                                           const int* __restrict__ active,
-                                                           double* __restrict__ partial, int nblk) {
+// Sweep 1: per-block partials of the products of step j (u == nullptr: a and
+// (t, t) only).  Basis vectors 8 at a time; t, u and (t, t), (t, u) in the
+// first group.  Partials at pd[(s GM_NS + slot) nblk + b]: a_i at slot i,
+// b_i at GM_MAXK + i, (t, t) at 2 GM_MAXK, (t, u) at 2 GM_MAXK + 1.
+__global__ __launch_bounds__(GM_BLK) void gm_dcgs_dots_kernel(const double* __restrict__ V, size_t vstride, int j,
+                                                              const double* __restrict__ u, size_t n_s,
+                                                              const int* __restrict__ active,
+                                                              double* __restrict__ pd, int nblk) {
+    constexpr int G = 8;
     __shared__ double red[GM_BLK / 64];
     const int s = blockIdx.y, b = blockIdx.x;
     if (active[s] == 0) return;
     const size_t base = (size_t)s * n_s;
     const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
     const uint32_t nbytes = (uint32_t)(n_s * 8);
-    const rsrc_t rw = buf_rsrc(w + base, nbytes);
-    __shared__ double redm[MB][GM_BLK / 64];
-    rsrc_t rv[MB];
-    double c[MB];
-    if (pin != nullptr) {                          // uniform over the launch
-        partial_totals<MB>(pin, s, m, nblk, redm, c);
-        if (b == 0 && threadIdx.x == 0)
-            for (int u = 0; u < m; ++u) coef[(size_t)s * coef_stride + u] = c[u];
-    }
+    const bool hu = u != nullptr;
+    const rsrc_t rt = buf_rsrc(V + (size_t)j * vstride + base, nbytes);
+    const rsrc_t ru = buf_rsrc(hu ? u + base : V, hu ? nbytes : 0u);
+    double* const ps = pd + (size_t)s * GM_NS * nblk + b;
+    for (int i0 = 0; i0 == 0 || i0 < j; i0 += G) {   // uniform over the block
+        rsrc_t rv[G];
 #pragma unroll
-    for (int u = 0; u < MB; ++u) {
-        rv[u] = buf_rsrc(V + (size_t)u * vstride + base, u < m ? nbytes : 0u);
-        if (pin == nullptr) c[u] = u < m ? coef[(size_t)s * coef_stride + u] : 0.0;
-    }
-    constexpr int NA = NORM ? 1 : MB;
-    double acc[NA];
+        for (int q = 0; q < G; ++q) rv[q] = buf_rsrc(V + (size_t)(i0 + q) * vstride + base, i0 + q < j ? nbytes : 0u);
+        double aa[G], ab[G], tt = 0.0, tu = 0.0;
 #pragma unroll
-    for (int u = 0; u < NA; ++u) acc[u] = 0.0;
+        for (int q = 0; q < G; ++q) aa[q] = ab[q] = 0.0;
+        for (size_t e = lo + 2 * threadIdx.x; e < hi; e += 2 * GM_BLK) {   // element pairs (n_s, lo, hi even)
+            const uint32_t off = (uint32_t)(e * 8);
+            const cpx<double> tv = bload2<double>(rt, off);
+            const cpx<double> uv = bload2<double>(ru, off);
+            cpx<double> vv[G];
+#pragma unroll
+            for (int q = 0; q < G; ++q) vv[q] = bload2<double>(rv[q], off);
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                aa[q] += vv[q].x * tv.x;
+                aa[q] += vv[q].y * tv.y;
+                ab[q] += vv[q].x * uv.x;
+                ab[q] += vv[q].y * uv.y;
+            }
+            if (i0 == 0) {
+                tt += tv.x * tv.x;
+                tt += tv.y * tv.y;
+                tu += tv.x * uv.x;
+                tu += tv.y * uv.y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < G; ++q) {
+            if (i0 + q < j) {                       // uniform over the block
+                const double sa = block_sum(aa[q], red);
+                if (threadIdx.x == 0) ps[(size_t)(i0 + q) * nblk] = sa;
+                if (hu) {
+                    const double sb = block_sum(ab[q], red);
+                    if (threadIdx.x == 0) ps[(size_t)(GM_MAXK + i0 + q) * nblk] = sb;
+                }
+            }
+        }
+        if (i0 == 0) {
+            const double st = block_sum(tt, red);
+            if (threadIdx.x == 0) ps[(size_t)(2 * GM_MAXK) * nblk] = st;
+            if (hu) {
+                const double su = block_sum(tu, red);
+                if (threadIdx.x == 0) ps[(size_t)(2 * GM_MAXK + 1) * nblk] = su;
+            }
+        }
+    }
+}
+
+// Coefficients of step j, one block per shot: the products summed from the
+// partials (one wave per product, lanes over the blocks in a fixed order),
+// then rho, the final column j-1 of H (into Hd and, for the host, dots[0..j]),
+// and (fin == 0) the sweep-2 coefficients coef = [a (GM_MAXK), c (GM_MAXK + 1),
+// 1/rho] and g as the next column's h.  rho = 0 (t in the span of Q: an exact
+// solution) gives 1/rho = 0 and c = g = 0; the host stops the shot there.
+__global__ __launch_bounds__(GM_BLK) void gm_dcgs_coef_kernel(const double* __restrict__ pd, int nblk, int j,
+                                                              int fin, const int* __restrict__ active,
+                                                              double* __restrict__ Hd, double* __restrict__ coef,
+                                                              double* __restrict__ dots, int dstride) {
+    __shared__ double sv[GM_NS];
+    __shared__ double scol[GM_MAXK + 1];
+    __shared__ double sd[GM_MAXK + 1];
+    __shared__ double srho, sab;
+    const int s = blockIdx.x;
+    if (active[s] == 0) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const double* ps = pd + (size_t)s * GM_NS * nblk;
+    for (int v = wave; v < GM_NS; v += GM_BLK / 64) {   // uniform per wave
+        const bool need = (v < GM_MAXK) ? v < j
+                        : (v < 2 * GM_MAXK) ? (!fin && v - GM_MAXK < j)
+                        : (v == 2 * GM_MAXK || !fin);
+        if (!need) continue;
+        double acc = 0.0;
+        for (int b = lane; b < nblk; b += 64) acc += ps[(size_t)v * nblk + b];
+        acc = wave_sum(acc);
+        if (lane == 0) sv[v] = acc;
+    }
+    __syncthreads();
+    double* H = Hd + (size_t)s * GM_HDS;         // H[r][c] at r GM_MAXK + c
+    double* h = H + (GM_MAXK + 1) * GM_MAXK;     // pass-1 coefficients of the latest column
+    if (threadIdx.x == 0) {
+        double rho = 1.0;
+        if (j > 0) {
+            double aa = 0.0, ab = 0.0;
+            for (int i = 0; i < j; ++i) {
+                aa += sv[i] * sv[i];
+                if (!fin) ab += sv[i] * sv[GM_MAXK + i];
+            }
+            const double r2 = sv[2 * GM_MAXK] - aa;
+            rho = r2 > 0.0 ? sqrt(r2) : (r2 == 0.0 || isfinite(r2) ? 0.0 : r2);   // NaN passes to the host
+            for (int i = 0; i < j; ++i) scol[i] = h[i] + sv[i];
+            scol[j] = rho;
+            for (int i = 0; i <= j; ++i) {
+                H[(size_t)i * GM_MAXK + (j - 1)] = scol[i];
+                dots[(size_t)s * dstride + i] = scol[i];
+            }
+            sab = ab;
+        } else {
+            sab = 0.0;
+        }
+        srho = rho;
+    }
+    __syncthreads();
+    if (fin) return;
+    const double rho = srho;
+    const bool ok = rho > 0.0;                    // false also for NaN
+    const double ir = ok ? 1.0 / rho : 0.0;
+    // d = H[0..j][0..j-1] a (Hessenberg: row r has columns c >= r - 1)
+    const int r = threadIdx.x;
+    if (r <= j) {
+        double d = 0.0;
+        for (int c = (r > 0 ? r - 1 : 0); c < j; ++c)
+            d += (c == j - 1 ? scol[r] : H[(size_t)r * GM_MAXK + c]) * sv[c];
+        sd[r] = d;
+    }
+    __syncthreads();
+    if (r <= j) {
+        const double d = sd[r];
+        double g = r < j ? (sv[GM_MAXK + r] - d) * ir : ((sv[2 * GM_MAXK + 1] - sab) * ir - d) * ir;
+        double c = d * ir + g;
+        if (!ok) g = c = 0.0;
+        h[r] = g;
+        coef[(size_t)s * GM_NS + GM_MAXK + r] = c;
+        if (r < j) coef[(size_t)s * GM_NS + r] = sv[r];
+    }
+    if (r == 0) coef[(size_t)s * GM_NS + 2 * GM_MAXK + 1] = ir;
+}
+
+// Sweep 2 of step j: q_j = (t - Q a) / rho over V_j and t' = u / rho - Q c
+// - c_j q_j into V_{j+1}, coefficients from gm_dcgs_coef_kernel.
+__global__ __launch_bounds__(GM_BLK) void gm_dcgs_update_kernel(double* __restrict__ V, size_t vstride, int j,
+                                                                const double* __restrict__ u,
+                                                                const double* __restrict__ coef, size_t n_s,
+                                                                const int* __restrict__ active) {
+    constexpr int G = 8;
+    __shared__ double sa[GM_MAXK], sc[GM_MAXK + 1];
+    const int s = blockIdx.y, b = blockIdx.x;
+    if (active[s] == 0) return;
+    const double* cs = coef + (size_t)s * GM_NS;
+    if (threadIdx.x < j) sa[threadIdx.x] = cs[threadIdx.x];
+    if (threadIdx.x <= j) sc[threadIdx.x] = cs[GM_MAXK + threadIdx.x];
+    const double ir = cs[2 * GM_MAXK + 1];
+    __syncthreads();
+    const size_t base = (size_t)s * n_s;
+    const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
+    const uint32_t nbytes = (uint32_t)(n_s * 8);
+    const rsrc_t rt = buf_rsrc(V + (size_t)j * vstride + base, nbytes);
+    const rsrc_t rn = buf_rsrc(V + (size_t)(j + 1) * vstride + base, nbytes);
+    const rsrc_t ru = buf_rsrc(u + base, nbytes);
+    const double cj = sc[j];
     for (size_t e = lo + 2 * threadIdx.x; e < hi; e += 2 * GM_BLK) {   // element pairs (n_s, lo, hi even)
         const uint32_t off = (uint32_t)(e * 8);
-        cpx<double> vv[MB];
+        const cpx<double> tv = bload2<double>(rt, off);
+        const cpx<double> uv = bload2<double>(ru, off);
+        cpx<double> qa = {0.0, 0.0}, qc = {0.0, 0.0};
+        for (int i0 = 0; i0 < j; i0 += G) {
+            cpx<double> vv[G];
 #pragma unroll
-        for (int u = 0; u < MB; ++u) vv[u] = bload2<double>(rv[u], off);
-        cpx<double> wv = bload2<double>(rw, off);
-#pragma unroll
-        for (int u = 0; u < MB; ++u)
-            if (u < m) {
-                wv.x -= c[u] * vv[u].x;
-                wv.y -= c[u] * vv[u].y;
+            for (int q = 0; q < G; ++q) {
+                const rsrc_t rv = buf_rsrc(V + (size_t)(i0 + q) * vstride + base, i0 + q < j ? nbytes : 0u);
+                vv[q] = bload2<double>(rv, off);
             }
-        bstore2(wv, rw, off);
-        if constexpr (NORM) {
-            acc[0] += wv.x * wv.x;
-            acc[0] += wv.y * wv.y;
-        } else {
 #pragma unroll
-            for (int u = 0; u < MB; ++u) {
-                acc[u] += vv[u].x * wv.x;
-                acc[u] += vv[u].y * wv.y;
+            for (int q = 0; q < G; ++q) {
+                if (i0 + q < j) {
+                    const double ai = sa[i0 + q], ci = sc[i0 + q];
+                    qa.x += ai * vv[q].x;
+                    qa.y += ai * vv[q].y;
+                    qc.x += ci * vv[q].x;
+                    qc.y += ci * vv[q].y;
+                }
             }
         }
-    }
-#pragma unroll
-    for (int u = 0; u < NA; ++u) {
-        if (u < (NORM ? 1 : m)) {                  // uniform over the block
-            const double t = block_sum(acc[u], red);
-            if (threadIdx.x == 0) partial[((size_t)s * (GM_MAXK + 1) + u) * nblk + b] = t;
-        }
+        cpx<double> qj, tn;
+        qj.x = (tv.x - qa.x) * ir;
+        qj.y = (tv.y - qa.y) * ir;
+        tn.x = uv.x * ir - qc.x - cj * qj.x;
+        tn.y = uv.y * ir - qc.y - cj * qj.y;
+        bstore2(qj, rt, off);
+        bstore2(tn, rn, off);
     }
 }
 
@@ -418,20 +532,6 @@ __global__ __launch_bounds__(GM_BLK) void gm_reduce_kernel(const double* __restr
     }
 }
 
-// w -= sum_{i<m} coef[s][i] V_i   (per-shot coefficients in device memory)
-__global__ __launch_bounds__(GM_BLK) void gm_subtract_kernel(const double* __restrict__ V, size_t vstride, int m,
-                                                             const double* __restrict__ coef, int coef_stride,
-                                                             double* __restrict__ w, size_t n_s, int S,
-                                                             const int* __restrict__ active) {
-    const size_t e = (size_t)blockIdx.x * GM_BLK + threadIdx.x;
-    if (e >= n_s * S) return;
-    const int s = (int)(e / n_s);
-    if (active[s] == 0) return;
-    double acc = w[e];
-    for (int i = 0; i < m; ++i) acc -= coef[(size_t)s * coef_stride + i] * V[i * vstride + e];
-    w[e] = acc;
-}
-
 // out = x * (1/sqrt(nrm2[s])) when nrm2 > 0
 __global__ __launch_bounds__(GM_BLK) void gm_normalize_kernel(const double* __restrict__ x,
                                                               const double* __restrict__ nrm2, int nrm_stride,
@@ -443,33 +543,6 @@ __global__ __launch_bounds__(GM_BLK) void gm_normalize_kernel(const double* __re
     if (active[s] == 0) return;
     const double q = nrm2[(size_t)s * nrm_stride];
     out[e] = q > 0.0 ? x[e] / sqrt(q) : 0.0;
-}
-
-// out = x / sqrt(||x||^2) over the shot's chunk, ||x||^2 summed by every block
-// from the previous sweep's partials (product 0); block 0 of the shot stores
-// it to nrm2 (the host's Hessenberg entry).  The arithmetic is that of
-// gm_normalize_kernel after gm_reduce_kernel.
-__global__ __launch_bounds__(GM_BLK) void gm_normalize_fused_kernel(const double* __restrict__ x,
-                                                                    const double* __restrict__ pin,
-                                                                    double* __restrict__ nrm2, int nrm_stride,
-                                                                    double* __restrict__ out, size_t n_s,
-                                                                    const int* __restrict__ active, int nblk) {
-    __shared__ double red[GM_BLK / 64];
-    const int s = blockIdx.y, b = blockIdx.x;
-    if (active[s] == 0) return;
-    const double q = partial_total(pin, s, 0, nblk, red);
-    if (b == 0 && threadIdx.x == 0) nrm2[(size_t)s * nrm_stride] = q;
-    const size_t base = (size_t)s * n_s;
-    const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
-    const double* xs = x + base;
-    double* os = out + base;
-    for (size_t e = lo + 2 * threadIdx.x; e < hi; e += 2 * GM_BLK) {   // element pairs (n_s, lo, hi even)
-        const double2 v = *reinterpret_cast<const double2*>(xs + e);
-        double2 r;
-        r.x = q > 0.0 ? v.x / sqrt(q) : 0.0;
-        r.y = q > 0.0 ? v.y / sqrt(q) : 0.0;
-        *reinterpret_cast<double2*>(os + e) = r;
-    }
 }
 
 // out = sum_{i<m} y[s][i] V_i
@@ -503,13 +576,14 @@ struct GmState {
     double* V = nullptr;       // [k+1][nvec]
     double* w = nullptr;       // [nvec]
     double* z = nullptr;       // [nvec]
-    double* partial = nullptr; // [S][MAXK+1][nblk]
-    double* partial2 = nullptr;  // a second set
+    double* partial = nullptr; // [S][MAXK+1][nblk] (single products); [S][GM_NS][nblk] (Arnoldi steps)
     double* dots = nullptr;    // [S][DS]
+    double* coef = nullptr;    // [S][GM_NS]: a step's sweep-2 coefficients
+    double* Hd = nullptr;      // [S][GM_HDS]: H and the latest pass-1 coefficients
     int* active = nullptr;     // [S]
 };
 
-constexpr int DS = 2 * (GM_MAXK + 1) + 2;   // h (k+1), h2 (k+1), norm^2, restart beta^2
+constexpr int DS = 2 * (GM_MAXK + 1) + 2;   // a final Hessenberg column (k+1), ..., restart beta^2
 constexpr int GM_BETA_SLOT = DS - 1;
 
 inline unsigned nblocks(size_t n) { return (unsigned)((n + GM_BLK - 1) / GM_BLK); }
@@ -533,8 +607,9 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
     }
     if (!p->gm_w) LG_HIP(hipMalloc((void**)&p->gm_w, nvec * 8));
     if (!p->gm_z) LG_HIP(hipMalloc((void**)&p->gm_z, nvec * 8));
-    if (!p->gm_x)   // two partial sets (a sweep reads one while writing the other), dots, flags
-        LG_HIP(hipMalloc((void**)&p->gm_x, (2 * (size_t)S * (GM_MAXK + 1) * nblk + (size_t)S * DS) * 8 + S * 4 + 64));
+    if (!p->gm_x)   // partials, dots, step coefficients, H, flags
+        LG_HIP(hipMalloc((void**)&p->gm_x,
+                         ((size_t)S * GM_NS * nblk + (size_t)S * (DS + GM_NS + GM_HDS)) * 8 + S * 4 + 64));
     if (!p->gm_hb) LG_HIP(hipHostMalloc((void**)&p->gm_hb, (size_t)2 * S * DS * 8, hipHostMallocDefault));
     for (hipEvent_t& e : p->gm_ev)
         if (!e) LG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -543,9 +618,10 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
     g.w = p->gm_w;
     g.z = p->gm_z;
     g.partial = p->gm_x;
-    g.partial2 = g.partial + (size_t)S * (GM_MAXK + 1) * nblk;
-    g.dots = g.partial2 + (size_t)S * (GM_MAXK + 1) * nblk;
-    g.active = (int*)(g.dots + (size_t)S * DS);
+    g.dots = g.partial + (size_t)S * GM_NS * nblk;
+    g.coef = g.dots + (size_t)S * DS;
+    g.Hd = g.coef + (size_t)S * GM_NS;
+    g.active = (int*)(g.Hd + (size_t)S * GM_HDS);
     hipStream_t st = p->stream;
     const unsigned nb = nblocks(nvec);
 
@@ -561,45 +637,6 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(gm_reduce_kernel, dim3(S), dim3(GM_BLK), 0, st, g.partial, m, nblk, g.active,
                            g.dots + slot, DS);
-        return hipGetLastError();
-    };
-    // one classical Gram-Schmidt subtraction fused with the sweep after it
-    // (the inner products of the second pass, or the norm).  pin: the
-    // previous sweep's per-block partials, from which every block sums the
-    // coefficients (and stores them to dots at coef_slot), or nullptr (the
-    // coefficients are read from dots); pout: this sweep's partials; reduce:
-    // sum them into dots at out_slot with a separate kernel.  m > 16 takes
-    // the separate kernels (coefficients from dots).
-    auto subdot = [&](int m, int coef_slot, bool norm, int out_slot, const double* pin, double* pout,
-                      bool reduce) -> hipError_t {
-        const dim3 grid(nblk, S);
-        double* cf = g.dots + coef_slot;
-        if (m <= 8) {
-            if (norm) hipLaunchKernelGGL((gm_subdot_kernel<8, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                         pin, g.w, n_s, g.active, pout, nblk);
-            else hipLaunchKernelGGL((gm_subdot_kernel<8, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                    pin, g.w, n_s, g.active, pout, nblk);
-        } else if (m <= 12) {
-            if (norm) hipLaunchKernelGGL((gm_subdot_kernel<12, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                         pin, g.w, n_s, g.active, pout, nblk);
-            else hipLaunchKernelGGL((gm_subdot_kernel<12, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                    pin, g.w, n_s, g.active, pout, nblk);
-        } else if (m <= 16) {
-            if (norm) hipLaunchKernelGGL((gm_subdot_kernel<16, true>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                         pin, g.w, n_s, g.active, pout, nblk);
-            else hipLaunchKernelGGL((gm_subdot_kernel<16, false>), grid, dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS,
-                                    pin, g.w, n_s, g.active, pout, nblk);
-        } else {
-            hipLaunchKernelGGL(gm_subtract_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.V, nvec, m, cf, DS, g.w, n_s, S,
-                               g.active);
-            hipError_t e = hipGetLastError();
-            if (e != hipSuccess) return e;
-            return norm ? dot_into(g.w, 0, 1, g.w, out_slot) : dot_into(g.V, nvec, m, g.w, out_slot);
-        }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess || !reduce) return e;
-        hipLaunchKernelGGL(gm_reduce_kernel, dim3(S), dim3(GM_BLK), 0, st, pout, norm ? 1 : m, nblk, g.active,
-                           g.dots + out_slot, DS);
         return hipGetLastError();
     };
     auto fetch_dots = [&]() -> hipError_t {
@@ -675,44 +712,34 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             jused[s] = 0;
         }
         std::vector<int> inner = act;   // shots still in this cycle's Arnoldi
-        // Arnoldi step j on the device: w = C K^{-1} v_j, classical Gram-Schmidt
-        // twice, v_{j+1} = w / ||w||; its inner products then go to pinned host
-        // set j % 2 and an event marks them.  Step j + 1 needs only v_{j+1}, so
-        // it is queued before the host waits for step j's numbers (the GPU
-        // works through it meanwhile).  A shot that stops at step j still runs
-        // through that queued step (with the mask of step j), which writes only
-        // v_{j+2} and scratch of that shot, never used for it.
+        // Arnoldi step j on the device (delayed reorthogonalisation, see the
+        // kernels): u = C K^{-1} t_j, sweep 1, the coefficients, sweep 2 (q_j
+        // final, t_{j+1}); step k (the end of the cycle) only finalises column
+        // k-1.  Event j marks the final column j-1 (j >= 1) in pinned host set
+        // j % 2.  Step j + 1 needs nothing from the host, so it is queued
+        // before the host waits for event j (the GPU works through it
+        // meanwhile).  A shot that stops at event j still runs through the
+        // steps already queued (with the mask of step j), which write only its
+        // basis vectors past the ones in use and scratch, never used for it.
         auto queue_step = [&](int j) -> hipError_t {
-            double* Vj = g.V + (size_t)j * nvec;
-            double* Vn = g.V + (size_t)(j + 1) * nvec;
-            hipError_t e = launch_elastic_precond(p, Vj, g.z);
-            if (e == hipSuccess) e = launch_elastic_stencil(p, g.z, g.w);
-            const int m = j + 1;
-            if (m <= 16) {
-                // no reduction launches: pass-1 products (partials A); the pass-1
-                // subtraction with the pass-2 products (coefficients summed from A,
-                // partials B); the pass-2 subtraction with ||w||^2 (from B, partials
-                // A); the normalisation (||w||^2 summed from A).  Each consumer
-                // stores the sums it formed into dots for the host.
-                if (e == hipSuccess) {
-                    hipLaunchKernelGGL(gm_multidot_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, g.V, nvec, m, g.w, n_s,
-                                       g.active, g.partial, nblk);
-                    e = hipGetLastError();
-                }
-                if (e == hipSuccess) e = subdot(m, 0, false, GM_MAXK + 1, g.partial, g.partial2, false);
-                if (e == hipSuccess) e = subdot(m, GM_MAXK + 1, true, 2 * (GM_MAXK + 1), g.partial2, g.partial, false);
+            const bool fin = j == k;
+            hipError_t e = hipSuccess;
+            if (!fin) {
+                e = launch_elastic_precond(p, g.V + (size_t)j * nvec, g.z);
+                if (e == hipSuccess) e = launch_elastic_stencil(p, g.z, g.w);
                 if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(gm_normalize_fused_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, g.w, g.partial,
-                                   g.dots + 2 * (GM_MAXK + 1), DS, Vn, n_s, g.active, nblk);
-            } else {
-                if (e == hipSuccess) e = dot_into(g.V, nvec, m, g.w, 0);                                 // pass 1
-                if (e == hipSuccess) e = subdot(m, 0, false, GM_MAXK + 1, nullptr, g.partial, true);     // pass 2
-                if (e == hipSuccess) e = subdot(m, GM_MAXK + 1, true, 2 * (GM_MAXK + 1), nullptr, g.partial, true);
-                if (e != hipSuccess) return e;
-                hipLaunchKernelGGL(gm_normalize_kernel, dim3(nb), dim3(GM_BLK), 0, st, g.w,
-                                   g.dots + 2 * (GM_MAXK + 1), DS, Vn, n_s, S, g.active);
             }
+            hipLaunchKernelGGL(gm_dcgs_dots_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, g.V, nvec, j,
+                               fin ? nullptr : g.w, n_s, g.active, g.partial, nblk);
             if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(gm_dcgs_coef_kernel, dim3(S), dim3(GM_BLK), 0, st, g.partial, nblk, j, fin ? 1 : 0,
+                               g.active, g.Hd, g.coef, g.dots, DS);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if (!fin) {
+                hipLaunchKernelGGL(gm_dcgs_update_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, g.V, nvec, j, g.w,
+                                   g.coef, n_s, g.active);
+                if ((e = hipGetLastError()) != hipSuccess) return e;
+            }
             e = hipMemcpyAsync(p->gm_hb + (size_t)(j & 1) * S * DS, g.dots, (size_t)S * DS * 8,
                                hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipEventRecord(p->gm_ev[j & 1], st);
@@ -723,11 +750,12 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             for (int s = 0; s < S; ++s) anyin = anyin || inner[s];
             if (anyin) LG_HIP(queue_step(0));
         }
-        for (int j = 0; j < k; ++j) {
+        // event j: the restart norm (j = 0) or the final column j - 1 of H
+        for (int j = 0; j <= k; ++j) {
             bool anyin = false;
             for (int s = 0; s < S; ++s) anyin = anyin || inner[s];
             if (!anyin) break;
-            if (j + 1 < k) LG_HIP(queue_step(j + 1));
+            if (j + 1 <= k) LG_HIP(queue_step(j + 1));
             LG_HIP(hipEventSynchronize(p->gm_ev[j & 1]));
             const double* dset = p->gm_hb + (size_t)(j & 1) * S * DS;
             bool stopped = false;
@@ -751,25 +779,25 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                     }
                 }
             }
-            for (int s = 0; s < S; ++s) {
+            const int c = j - 1;         // the column this event completes
+            for (int s = 0; s < S && c >= 0; ++s) {
                 if (!inner[s]) continue;
                 const double* d = &dset[(size_t)s * DS];
                 double* Hs = &H[(size_t)s * (k + 1) * k];
-                auto Hc = [&](int r, int c) -> double& { return Hs[(size_t)r * k + c]; };
-                for (int i = 0; i <= j; ++i) Hc(i, j) = d[i] + d[GM_MAXK + 1 + i];
-                Hc(j + 1, j) = std::sqrt(d[2 * (GM_MAXK + 1)]);
+                auto Hc = [&](int r, int cc) -> double& { return Hs[(size_t)r * k + cc]; };
+                for (int i = 0; i <= c + 1; ++i) Hc(i, c) = d[i];
                 double* csv = &cs[(size_t)s * k];
                 double* snv = &sn[(size_t)s * k];
                 double* gs = &gv[(size_t)s * (k + 1)];
-                for (int i = 0; i < j; ++i) {
-                    const double tmp = csv[i] * Hc(i, j) + snv[i] * Hc(i + 1, j);
-                    Hc(i + 1, j) = -snv[i] * Hc(i, j) + csv[i] * Hc(i + 1, j);
-                    Hc(i, j) = tmp;
+                for (int i = 0; i < c; ++i) {
+                    const double tmp = csv[i] * Hc(i, c) + snv[i] * Hc(i + 1, c);
+                    Hc(i + 1, c) = -snv[i] * Hc(i, c) + csv[i] * Hc(i + 1, c);
+                    Hc(i, c) = tmp;
                 }
-                const double hj1 = Hc(j + 1, j);
-                const double den = std::hypot(Hc(j, j), hj1);
+                const double hj1 = Hc(c + 1, c);
+                const double den = std::hypot(Hc(c, c), hj1);
                 total[s] += 1;
-                jused[s] = j + 1;
+                jused[s] = c + 1;
                 if (den == 0.0) {
                     status[s] = LG_ERR_BREAKDOWN;
                     act[s] = inner[s] = cyc[s] = 0;
@@ -777,13 +805,13 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
                     stopped = true;
                     continue;
                 }
-                csv[j] = Hc(j, j) / den;
-                snv[j] = hj1 / den;
-                Hc(j, j) = den;
-                Hc(j + 1, j) = 0.0;
-                gs[j + 1] = -snv[j] * gs[j];
-                gs[j] = csv[j] * gs[j];
-                est[s] = std::fabs(gs[j + 1]) / bnorm[s];
+                csv[c] = Hc(c, c) / den;
+                snv[c] = hj1 / den;
+                Hc(c, c) = den;
+                Hc(c + 1, c) = 0.0;
+                gs[c + 1] = -snv[c] * gs[c];
+                gs[c] = csv[c] * gs[c];
+                est[s] = std::fabs(gs[c + 1]) / bnorm[s];
                 if (!std::isfinite(est[s])) {
                     status[s] = LG_ERR_NONFINITE;
                     act[s] = inner[s] = cyc[s] = 0;
