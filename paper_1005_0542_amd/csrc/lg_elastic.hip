@@ -323,13 +323,15 @@ __global__ __launch_bounds__(GM_BLK) void gm_dcgs_dots_kernel(const double* __re
                                                               const int* __restrict__ active,
                                                               double* __restrict__ pd, int nblk) {
     constexpr int G = 8;
-    __shared__ double red[GM_BLK / 64];
+    constexpr int NV = 2 * G + 2;                 // products of one group: a, b, (t,t), (t,u)
+    __shared__ double red[NV][GM_BLK / 64];
     const int s = blockIdx.y, b = blockIdx.x;
     if (active[s] == 0) return;
     const size_t base = (size_t)s * n_s;
     const size_t lo = (size_t)b * GM_CHUNK, hi = min(lo + GM_CHUNK, n_s);
     const uint32_t nbytes = (uint32_t)(n_s * 8);
     const bool hu = u != nullptr;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const rsrc_t rt = buf_rsrc(V + (size_t)j * vstride + base, nbytes);
     const rsrc_t ru = buf_rsrc(hu ? u + base : V, hu ? nbytes : 0u);
     double* const ps = pd + (size_t)s * GM_NS * nblk + b;
@@ -361,25 +363,39 @@ __global__ __launch_bounds__(GM_BLK) void gm_dcgs_dots_kernel(const double* __re
                 tu += tv.y * uv.y;
             }
         }
+        // block sums (wave trees, then the waves in order): value v of the
+        // group is a_{i0+v} (v < G), b_{i0+v-G} (v < 2G), (t,t), (t,u)
 #pragma unroll
         for (int q = 0; q < G; ++q) {
-            if (i0 + q < j) {                       // uniform over the block
-                const double sa = block_sum(aa[q], red);
-                if (threadIdx.x == 0) ps[(size_t)(i0 + q) * nblk] = sa;
-                if (hu) {
-                    const double sb = block_sum(ab[q], red);
-                    if (threadIdx.x == 0) ps[(size_t)(GM_MAXK + i0 + q) * nblk] = sb;
-                }
+            aa[q] = wave_sum(aa[q]);
+            ab[q] = wave_sum(ab[q]);
+        }
+        tt = wave_sum(tt);
+        tu = wave_sum(tu);
+        if (lane == 0) {
+#pragma unroll
+            for (int q = 0; q < G; ++q) {
+                red[q][wave] = aa[q];
+                red[G + q][wave] = ab[q];
+            }
+            red[2 * G][wave] = tt;
+            red[2 * G + 1][wave] = tu;
+        }
+        __syncthreads();
+        const int v = threadIdx.x;
+        if (v < NV) {
+            const bool isa = v < G, isb = v >= G && v < 2 * G;
+            const int i = isa ? i0 + v : i0 + v - G;
+            const bool want = (isa && i < j) || (isb && hu && i < j) || (i0 == 0 && v == 2 * G) ||
+                              (i0 == 0 && hu && v == 2 * G + 1);
+            if (want) {
+                double t = 0.0;
+                for (int w = 0; w < GM_BLK / 64; ++w) t += red[v][w];
+                const int slot = isa ? i : isb ? GM_MAXK + i : 2 * GM_MAXK + (v - 2 * G);
+                ps[(size_t)slot * nblk] = t;
             }
         }
-        if (i0 == 0) {
-            const double st = block_sum(tt, red);
-            if (threadIdx.x == 0) ps[(size_t)(2 * GM_MAXK) * nblk] = st;
-            if (hu) {
-                const double su = block_sum(tu, red);
-                if (threadIdx.x == 0) ps[(size_t)(2 * GM_MAXK + 1) * nblk] = su;
-            }
-        }
+        __syncthreads();                           // red is reused by the next group
     }
 }
 
@@ -389,7 +405,8 @@ __global__ __launch_bounds__(GM_BLK) void gm_dcgs_dots_kernel(const double* __re
 // and (fin == 0) the sweep-2 coefficients coef = [a (GM_MAXK), c (GM_MAXK + 1),
 // 1/rho] and g as the next column's h.  rho = 0 (t in the span of Q: an exact
 // solution) gives 1/rho = 0 and c = g = 0; the host stops the shot there.
-__global__ __launch_bounds__(GM_BLK) void gm_dcgs_coef_kernel(const double* __restrict__ pd, int nblk, int j,
+constexpr int GM_COEF_THREADS = 1024;
+__global__ __launch_bounds__(GM_COEF_THREADS) void gm_dcgs_coef_kernel(const double* __restrict__ pd, int nblk, int j,
                                                               int fin, const int* __restrict__ active,
                                                               double* __restrict__ Hd, double* __restrict__ coef,
                                                               double* __restrict__ dots, int dstride) {
@@ -401,13 +418,20 @@ __global__ __launch_bounds__(GM_BLK) void gm_dcgs_coef_kernel(const double* __re
     if (active[s] == 0) return;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const double* ps = pd + (size_t)s * GM_NS * nblk;
-    for (int v = wave; v < GM_NS; v += GM_BLK / 64) {   // uniform per wave
+    for (int v = wave; v < GM_NS; v += GM_COEF_THREADS / 64) {   // uniform per wave
         const bool need = (v < GM_MAXK) ? v < j
                         : (v < 2 * GM_MAXK) ? (!fin && v - GM_MAXK < j)
                         : (v == 2 * GM_MAXK || !fin);
         if (!need) continue;
+        // lane sums blocks lane, lane + 64, ... in that order, 8 loads in flight
         double acc = 0.0;
-        for (int b = lane; b < nblk; b += 64) acc += ps[(size_t)v * nblk + b];
+        for (int b0 = lane; b0 < nblk; b0 += 64 * 8) {
+            double x[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) x[q] = b0 + 64 * q < nblk ? ps[(size_t)v * nblk + b0 + 64 * q] : 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += x[q];
+        }
         acc = wave_sum(acc);
         if (lane == 0) sv[v] = acc;
     }
@@ -732,7 +756,8 @@ lg_status gmres_solve(lg_plan* p, const double* b, double* x, const lg_solve_opt
             hipLaunchKernelGGL(gm_dcgs_dots_kernel, dim3(nblk, S), dim3(GM_BLK), 0, st, g.V, nvec, j,
                                fin ? nullptr : g.w, n_s, g.active, g.partial, nblk);
             if ((e = hipGetLastError()) != hipSuccess) return e;
-            hipLaunchKernelGGL(gm_dcgs_coef_kernel, dim3(S), dim3(GM_BLK), 0, st, g.partial, nblk, j, fin ? 1 : 0,
+            hipLaunchKernelGGL(gm_dcgs_coef_kernel, dim3(S), dim3(GM_COEF_THREADS), 0, st, g.partial, nblk, j,
+                               fin ? 1 : 0,
                                g.active, g.Hd, g.coef, g.dots, DS);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if (!fin) {
