@@ -8,10 +8,11 @@
 //   (C u)_z = -Dx+(m Dx- uz) - Dz+((l+2m) Dz- uz) - Dzc(l Dxc ux) - Dxc(m Dzc ux) + w uz
 //
 // GMRES(k) is right-preconditioned by K = diag(B1, B2); the Arnoldi basis is
-// orthogonalised by classical Gram-Schmidt applied twice (all inner products
-// of one pass in a single sweep over the basis), every vector operation and
-// inner product runs on the device, and only the (k+1) x k Hessenberg matrix
-// with its Givens rotations lives on the host.
+// orthogonalised by classical Gram-Schmidt applied twice, with the second pass
+// of each vector delayed into the next step (two sweeps over the basis per
+// step).  Every vector operation and inner product runs on the device, which
+// also keeps the Hessenberg columns it needs for the delayed pass; the host
+// applies the Givens rotations to its copy and tests convergence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
