@@ -107,6 +107,34 @@ def test_gmres_parity_fp64(nx, nz, k):
         assert rel(to_np(xf)[0], ref) < 1e-12, (cap, rel(to_np(xf)[0], ref))
 
 
+@pytest.mark.parametrize("k,shots", [(1, 1), (8, 1), (9, 2), (32, 1)])
+def test_gmres_restart_lengths_fixed_counts(k, shots):
+    """Restart lengths at the edges of the Arnoldi sweeps' groups of 8 basis
+    vectors and of the supported range (1 and 32): at a fixed iteration count
+    (one full cycle and part of a second) the solution is the oracle's
+    modified Gram-Schmidt GMRES minimiser to rounding, for every shot."""
+    torch = torch_cuda()
+    nx = nz = 32
+    d, h = 5.0, 300.0
+    lam, mu, rho = _medium(nx, nz, d)
+    plan = _plan(nx, nz, d, lam, mu, rho, h=h, shots=shots)
+    w = rho[1:-1, 1:-1] * h * h / 4
+    B1, B2 = elastic.block_preconditioner(lam, mu, rho, h, nx, nz, d, d)
+    Cop = lambda u: elastic.apply_C(u, lam, mu, w, d, d)
+    Kop = lambda u: elastic.apply_Kinv(u, B1, B2)
+    b = np.random.default_rng(100 + k).standard_normal((shots, 2, nz - 1, nx - 1))
+    cap = k + (k + 1) // 2
+    log(f"gmres restart {k}, {shots} shot(s), fixed {cap} iterations")
+    bd = to_dev(b, torch.float64)
+    xd = torch.empty_like(bd)
+    res = plan.gmres_solve(bd, xd, tol=0.0, max_iter=cap, restart=k)
+    assert res.statuses == [NOT_CONVERGED] * shots and res.iters == [cap] * shots
+    for s in range(shots):
+        ref, itc, _, stc = krylov.gmres(Cop, Kop, b[s], 0.0, k, max_iter=cap)
+        assert itc == cap and stc == NOT_CONVERGED
+        assert rel(to_np(xd)[s], ref) < 1e-12, (k, s, rel(to_np(xd)[s], ref))
+
+
 def test_gmres_status_and_batched_shots():
     torch = torch_cuda()
     nx = nz = 16
