@@ -227,9 +227,13 @@ hipError_t launch_elastic_precond(lg_plan* p, const void* r, void* z) {
     hipError_t e = launch_dst(p, 0, r, p->rhat, S * 2);
     if (e == hipSuccess) e = launch_td(p, -1, p->rhat, p->y, S * 2, 0, 1, 0);
     if (e == hipSuccess && p->blk[0].P > 1) e = launch_rs(p, -1, p->rhat, p->y, S * 2, 0, 1, 0);
-    // Dirichlet top: the segment correction inside the inverse transform; the
-    // traction-free surface needs the corrected surface row first
-    if (!p->el_free && p->blk[0].P > 1) return e == hipSuccess ? launch_correct_inv(p, z, S * 2) : e;
+    // P > 1: the segment correction inside the inverse transform; with the
+    // traction-free surface also its rank-one term, whose coefficients come
+    // from the corrected row 1 (formed from the uncorrected result first)
+    if (p->blk[0].P > 1) {
+        if (e == hipSuccess && p->el_free) e = launch_surface_coef_fused(p, p->y, S * 2);
+        return e == hipSuccess ? launch_correct_inv(p, z, S * 2, p->el_free) : e;
+    }
     if (e == hipSuccess && p->blk[0].P > 1) e = launch_correct(p, -1, p->y, S * 2, 1, 0);
     if (e == hipSuccess) e = launch_surface_rows(p, -1, p->y, S * 2, 1, 0);
     if (e == hipSuccess) e = launch_dst(p, 1, p->y, z, S * 2);

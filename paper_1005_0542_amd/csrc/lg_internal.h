@@ -211,7 +211,8 @@ hipError_t launch_correct(lg_plan* p, int blk, void* y, int nfields, int fstride
 hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, double tol,
                               int max_iter);
 hipError_t launch_correct_idst(lg_plan* p, int init);
-hipError_t launch_correct_inv(lg_plan* p, void* z, int nfields);
+hipError_t launch_correct_inv(lg_plan* p, void* z, int nfields, bool surface);
+hipError_t launch_surface_coef_fused(lg_plan* p, const void* y, int nfields);
 // Held-direction plans: x += alpha_j p_j for the iterations j = giter[1] ..
 // giter[0]-1, in order, skipping those where the shot was masked (alpha_j =
 // 0; x taken as 0 while xzero), then giter[1] = giter[0], xzero = 0.  No-op

@@ -236,6 +236,7 @@ struct DstArgs {
     double idx2d, idz2d;
     int free_top;          // free surface (operator face; CORRECT: rank-one term)
     const T* smg;          // CORRECT (free surface): g_k rows
+    const T* smg2;         // non-null: odd fields take these g_k rows (elastic K, second block)
     const double* smc;     // CORRECT (free surface): coef_k per field
     double* partial;
     size_t pstride;
@@ -526,7 +527,7 @@ dst_kernel(DstArgs<T> a) {
                     v1[u] = c1 ? yv1[u] + xl0[u] * ua1[u] + xr0[u] * ub1[u] : yv1[u];
                 }
                 if (a.free_top) {                  // + coef_k g_k(j): the free-surface rank-one term
-                    const rsrc_t rG = buf_rsrc(a.smg, nfe * SZ);
+                    const rsrc_t rG = buf_rsrc((a.smg2 != nullptr && (field & 1)) ? a.smg2 : a.smg, nfe * SZ);
                     const rsrc_t rC = buf_rsrc(a.smc + (size_t)field * NX1, (uint32_t)NX1 * 8u);
                     T cf[CH], g0[CH], g1[CH];
 #pragma unroll
@@ -1281,6 +1282,46 @@ __global__ __launch_bounds__(256) void correct_kernel(T* y, const T* utab, const
     Y[pt] = Y[pt] + xl * u[(size_t)rs * nx1 + k] + xr * u[(size_t)(Ls - rs) * nx1 + k] + sm;
 }
 
+// Elastic traction-free surface, with the correction fused into the inverse
+// transform: coef_k = zhat(row 1, k) / (1 - g_k(1)) per field from the
+// uncorrected Dichotomy result, zhat(row 1) formed as correct_kernel forms it
+// (odd fields: the second block's tables).
+template <typename T>
+__global__ __launch_bounds__(256) void surface_coef_fused_kernel(const T* __restrict__ y, const T* __restrict__ utab,
+                                                                 const T* __restrict__ utab2,
+                                                                 const double* __restrict__ t0,
+                                                                 const double* __restrict__ t1,
+                                                                 double* __restrict__ coef, int nx1, int Ls, int P,
+                                                                 size_t npts, int nfields) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (size_t)nfields * nx1) return;
+    const size_t f = e / nx1;
+    const int k = (int)(e - f * nx1);
+    const T* Y = y + f * npts;
+    const size_t pt = (size_t)nx1 + k;             // row 1
+    const int rs = 2 & (Ls - 1);                   // its position in the first segment
+    T v = Y[pt];
+    if (rs != 0 && P > 1) {                        // no left separator in the first segment
+        const T* __restrict__ u = (utab2 != nullptr && (f & 1)) ? utab2 : utab;
+        v = v + Y[(size_t)(Ls - 1) * nx1 + k] * u[(size_t)(Ls - rs) * nx1 + k];
+    }
+    coef[f * nx1 + k] = (double)v * ((f & 1) ? t1 : t0)[k];
+}
+
+hipError_t launch_surface_coef_fused(lg_plan* p, const void* y, int nfields) {
+    const PrecBlock& B = p->blk[0];
+    const dim3 grid((unsigned)(((size_t)nfields * p->nx1 + 255) / 256));
+    if (p->prec == LG_FP64)
+        hipLaunchKernelGGL(surface_coef_fused_kernel<double>, grid, dim3(256), 0, p->stream, (const double*)y,
+                           (const double*)B.utab, (const double*)p->blk[1].utab, p->es_t[0], p->es_t[1], p->sm_c,
+                           p->nx1, B.Ls, B.P, p->npts, nfields);
+    else
+        hipLaunchKernelGGL(surface_coef_fused_kernel<float>, grid, dim3(256), 0, p->stream, (const float*)y,
+                           (const float*)B.utab, (const float*)p->blk[1].utab, p->es_t[0], p->es_t[1], p->sm_c,
+                           p->nx1, B.Ls, B.P, p->npts, nfields);
+    return hipGetLastError();
+}
+
 // ===========================================================================
 // Right-hand side of harmonic m (eq. laguerre_h, SPD sign):
 //   P_{m-1} = sqrt((m-1)/(m-1+a)) P_{m-2} + R_{m-1}
@@ -1763,26 +1804,27 @@ hipError_t launch_correct_idst(lg_plan* p, int init) {
     return dst_dispatch<float, DST_CORRECT>(p, a, p->S * p->C);
 }
 
-// Elastic K^{-1} (Dirichlet top, P > 1): the segment correction of both
-// blocks (field parity) fused into the inverse transform, z = DST^{-1} zhat;
-// no masking and no search-direction update.
-hipError_t launch_correct_inv(lg_plan* p, void* z, int nfields) {
-    if (p->prec == LG_FP64) {
-        DstArgs<double> a = dst_args<double>(p);
-        a.out = (double*)z;
-        a.init = 1;
-        a.ctl = nullptr;
-        a.free_top = 0;
-        a.utab2 = (const double*)p->blk[1].utab;
-        return dst_dispatch<double, DST_CORRECT>(p, a, nfields);
-    }
-    DstArgs<float> a = dst_args<float>(p);
-    a.out = (float*)z;
+// Elastic K^{-1} (P > 1): the segment correction of both blocks (field
+// parity) fused into the inverse transform, z = DST^{-1} zhat; no masking and
+// no search-direction update.  surface: also + coef_k g_k(j) on every row (the
+// traction-free surface's rank-one term, coef_k from surface_coef_fused_kernel).
+template <typename T>
+hipError_t correct_inv_T(lg_plan* p, T* z, int nfields, bool surface) {
+    DstArgs<T> a = dst_args<T>(p);
+    a.out = z;
     a.init = 1;
     a.ctl = nullptr;
-    a.free_top = 0;
-    a.utab2 = (const float*)p->blk[1].utab;
-    return dst_dispatch<float, DST_CORRECT>(p, a, nfields);
+    a.utab2 = (const T*)p->blk[1].utab;
+    a.free_top = surface ? 1 : 0;
+    a.smg = surface ? (const T*)p->es_g[0] : nullptr;
+    a.smg2 = surface ? (const T*)p->es_g[1] : nullptr;
+    a.smc = p->sm_c;
+    return dst_dispatch<T, DST_CORRECT>(p, a, nfields);
+}
+
+hipError_t launch_correct_inv(lg_plan* p, void* z, int nfields, bool surface) {
+    if (p->prec == LG_FP64) return correct_inv_T<double>(p, (double*)z, nfields, surface);
+    return correct_inv_T<float>(p, (float*)z, nfields, surface);
 }
 
 hipError_t launch_td(lg_plan* p, int blk, const void* rhat, void* y, int nfields, int masked,
