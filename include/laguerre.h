@@ -128,7 +128,8 @@ typedef struct {
 typedef struct { int32_t alpha; double h; int32_t n; } lg_laguerre;
 
 /* Krylov options: stop when ||r||_2 <= tol ||b||_2 (tol >= 0); max_iter >= 1
- * (CG iterations, or GMRES inner iterations); restart = GMRES k >= 1.
+ * (CG iterations, or GMRES inner iterations); restart = GMRES k, 1 <= k <= 32
+ * (a larger k is LG_ERR_UNSUPPORTED).
  * x0_given (PCG only): 0 = start from x0 = 0; 1 = x holds the initial guess
  * on entry (the previous harmonic, say). */
 typedef struct { double tol; int32_t max_iter; int32_t restart; int32_t x0_given; int32_t reserved; } lg_solve_opts;
@@ -296,7 +297,9 @@ lg_status lg_pcg_solve(lg_plan* plan, const double* b, double* x, const lg_solve
 
 /* Right-preconditioned restarted GMRES(k) (Sec. 2.3) for the elastic C x = b,
  * K = diag(B1, B2) (eq. precond2), from x0 = 0 (x0_given must be 0); stops when the Givens
- * estimate of ||b - Cx|| <= tol ||b||.  b, x: FP64 vectors ([S][2][..]). */
+ * estimate of ||b - Cx|| <= tol ||b||.  b, x: FP64 vectors ([S][2][..]).  The
+ * Arnoldi basis is orthogonalised by classical Gram-Schmidt twice, each
+ * vector's second pass taken in the next Arnoldi step. */
 lg_status lg_gmres_solve(lg_plan* plan, const double* b, double* x, const lg_solve_opts* opts,
                          lg_solve_info* info_host);
 

@@ -135,6 +135,21 @@ def test_gmres_restart_lengths_fixed_counts(k, shots):
         assert rel(to_np(xd)[s], ref) < 1e-12, (k, s, rel(to_np(xd)[s], ref))
 
 
+def test_gmres_rejects_unsupported_restart_lengths():
+    torch = torch_cuda()
+    nx = nz = 16
+    d = 5.0
+    lam, mu, rho = _medium(nx, nz, d)
+    plan = _plan(nx, nz, d, lam, mu, rho)
+    bd = to_dev(np.ones((1, 2, nz - 1, nx - 1)), torch.float64)
+    xd = torch.zeros_like(bd)
+    for k in (0, 33):
+        log(f"gmres restart {k} rejected")
+        with pytest.raises(RuntimeError):
+            plan.gmres_solve(bd, xd, tol=1e-10, max_iter=10, restart=k)
+    assert not to_np(xd).any()
+
+
 def test_gmres_status_and_batched_shots():
     torch = torch_cuda()
     nx = nz = 16
