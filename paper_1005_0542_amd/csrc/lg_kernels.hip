@@ -1527,7 +1527,10 @@ hipError_t dst_launch_M(lg_plan* pl, DstArgs<T>& a, int nfields) {
     constexpr int M = H ? NX : 2 * NX;         // FFT length
     constexpr int R = M >= 16 ? 16 : M;
     constexpr int TPF = M / R;
-    constexpr int FPB = TPF >= 256 ? 1 : 256 / TPF;
+    // the FP32 update with A p recomputed takes two row pairs of 256 threads
+    // per block (their p halo and medium rows overlap: 1.69 -> 1.67 ms at 64
+    // shots 2048^2; four pairs, or two in the correction, measured slower)
+    constexpr int FPB = (MODE == DST_UPDATE_OP && TPF == 256 && sizeof(T) == 4) ? 2 : (TPF >= 256 ? 1 : 256 / TPF);
     const int npairs = (a.nz1 + 1) / 2;
     a.bpf = (npairs + FPB - 1) / FPB;
     const dim3 grid(a.bpf * nfields);
