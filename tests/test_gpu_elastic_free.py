@@ -26,7 +26,7 @@ def _plan(nx, nz, d, lam, mu, rho, h=300.0, shots=1, precision="fp64", segments=
 
 
 @pytest.mark.parametrize("prec", ["fp64", "mixed"])
-@pytest.mark.parametrize("nx,nz,shots", [(16, 16, 1), (64, 32, 2), (8, 128, 1), (16, 2, 3)])
+@pytest.mark.parametrize("nx,nz,shots", [(16, 16, 1), (64, 32, 2), (8, 128, 1), (16, 2, 3), (256, 8, 2)])
 def test_free_elastic_operator_parity(prec, nx, nz, shots):
     torch = torch_cuda()
     d, h = 5.0, 300.0
