@@ -162,6 +162,7 @@ struct lg_plan {
     void* y = nullptr;         // Dichotomy output / spectral solution
     double* E = nullptr;       // per-segment endpoint data [S*C][P][3][nx-1]
     double* partial = nullptr; // per-block partial sums
+    double* partial_pq = nullptr;  // the operator's (p, A p) partials where the update sums them itself
     size_t partial_stride = 0; // per shot
     lg::ShotCtl* ctl = nullptr;    // [S*C]
     lg::ShotCtl* ctl_host = nullptr;  // pinned mirror
@@ -189,6 +190,8 @@ namespace lg {
 
 // element size of the working type
 inline size_t wsize(const lg_plan* p) { return p->prec == LG_FP64 ? 8 : 4; }
+// blocks per field of the row-transform kernels (one or more row pairs each)
+int dst_blocks_per_field(int nx, int nz1, int ws);
 
 // The row DST-I of nx-cell rows runs as one complex FFT of length nx per row
 // pair (with a pre- and post-pass) where the 2 nx-point odd extension would

@@ -208,7 +208,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(StArgs<T> a) {
 // instead of read from a stored q.  DST_RESTART (mixed precision) forms the
 // FP64 true residual r = b - A x from x, b and the FP64 medium, stores it and
 // transforms it: the restart of CG from the true residual in one pass.
-enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3, DST_UPDATE_OP = 4, DST_RESTART = 5 };
+// DST_UPDATE_PQ is DST_UPDATE that also forms (p, A p) and alpha from the
+// operator's per-block partials in every block (the finalize kernel's sum,
+// in its order), for fields with few such partials: one launch less per
+// iteration where launches, not bytes, set the time.
+enum DstMode { DST_FWD = 0, DST_INV = 1, DST_UPDATE = 2, DST_CORRECT = 3, DST_UPDATE_OP = 4, DST_RESTART = 5,
+               DST_UPDATE_PQ = 6 };
 
 template <typename T>
 struct DstArgs {
@@ -240,6 +245,9 @@ struct DstArgs {
     const double* smc;     // CORRECT (free surface): coef_k per field
     double* partial;
     size_t pstride;
+    const double* pqpart;  // UPDATE_PQ: the operator's (p, A p) partials [field][pstride]
+    int pq_nparts;         // UPDATE_PQ: their count per field
+    double* ahist;         // UPDATE_PQ with held directions: alpha_g at [field][g % pring]
     double tol2;           // tol^2 (init)
     int max_iter;          // (init)
     int init;
@@ -249,6 +257,34 @@ struct DstArgs {
     const T* utab2;        // non-null: odd fields take this second block's table (elastic K)
     int Ls, P;
 };
+
+// Each thread of the one block per field loads FIN_UNROLL partials (strided
+// by the block size) before adding them, so a pass costs one memory latency.
+// The block size follows the partial count (a large block only where there
+// are many partials: launching one costs more), so the order of the
+// additions depends on the partial count alone.
+constexpr int FIN_UNROLL = 8;
+constexpr int FIN_SMALL = 256, FIN_LARGE = 1024;
+constexpr int FIN_SMALL_MAX = FIN_UNROLL * FIN_SMALL;     // partials one pass of the small block covers
+
+template <int NT>
+__device__ __forceinline__ double fin_sum(const double* __restrict__ part, int n, double* red) {
+    double s = 0.0;
+    for (int i0 = threadIdx.x; i0 < n; i0 += FIN_UNROLL * NT) {
+        double v[FIN_UNROLL];
+#pragma unroll
+        for (int u = 0; u < FIN_UNROLL; ++u) {
+            const int i = i0 + u * NT;
+            v[u] = i < n ? part[i] : 0.0;
+        }
+#pragma unroll
+        for (int w = FIN_UNROLL / 2; w > 0; w /= 2)
+#pragma unroll
+            for (int u = 0; u < w; ++u) v[u] += v[u + w];
+        s += v[0];
+    }
+    return block_sum(s, red);
+}
 
 // A p on the rows j0 and j0 + 1 of a row pair at column i, with the operator
 // kernel's face coefficients and stencil_point, so the values are bitwise
@@ -293,7 +329,7 @@ __device__ __forceinline__ void apply_pair(rsrc_t rP, const T* __restrict__ kap,
 // more of their loads in flight (measured 1.8 % faster at 64 shots 2048^2).
 template <typename T, int M, int R, int FPB, int MODE, bool HALF>
 __global__ __launch_bounds__(FPB*(M / R)) __attribute__((amdgpu_waves_per_eu(
-    1, (MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART) ? 3 : 8))) void
+    1, (MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART || MODE == DST_UPDATE_PQ) ? 3 : 8))) void
 dst_kernel(DstArgs<T> a) {
     using FP = FftPlan<M, R>;
     constexpr int TPF = M / R;
@@ -312,7 +348,8 @@ dst_kernel(DstArgs<T> a) {
     // takes every element of the row pair at once
     constexpr int CHMAX = (MODE == DST_UPDATE_OP && sizeof(T) == 8) ? 2 : (MODE == DST_CORRECT && sizeof(T) == 4) ? 8 : 4;
     constexpr int CH = NIT < CHMAX ? NIT : CHMAX;
-    constexpr bool UPD = MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART;
+    constexpr bool UPD = MODE == DST_UPDATE || MODE == DST_UPDATE_OP || MODE == DST_RESTART || MODE == DST_UPDATE_PQ;
+    static_assert(MODE != DST_UPDATE_PQ || FPB * (M / R) == FIN_SMALL, "the finalize kernel's summation order");
     __shared__ cpx<T> lds[FPB * LL];
     __shared__ double red[NWAVE];
     __shared__ cpx<T> wtot[NWAVE];             // per-wave totals of the prefix sum
@@ -331,10 +368,36 @@ dst_kernel(DstArgs<T> a) {
     const int j0 = 2 * pair, j1 = j0 + 1;
     const bool has1 = live && (j1 < a.nz1);
 
+    if constexpr (MODE == DST_UPDATE_PQ) {   // held directions: alpha_g stays 0 unless the update runs
+        if (a.pring > 1 && bif == 0 && threadIdx.x == 0)
+            a.ahist[(size_t)field * a.pring + *a.giter % a.pring] = 0.0;
+    }
     if constexpr (UPD || MODE == DST_CORRECT) {
         bool skip = a.ctl != nullptr && a.ctl[field].active == 0;   // CORRECT without ctl: no mask
         if (UPD && a.init) skip = false;
         if (skip) return;   // uniform per block: blocks never span fields
+    }
+    double alpha_pq = 0.0;
+    if constexpr (MODE == DST_UPDATE_PQ) {
+        // (p, A p) and alpha as the finalize kernel forms them; block 0 of the
+        // field records them (a breakdown stops the shot in every block alike)
+        const double tot = fin_sum<FIN_SMALL>(a.pqpart + (size_t)field * a.pstride, a.pq_nparts, red);
+        ShotCtl& c = a.ctl[field];
+        if (bif == 0 && threadIdx.x == 0) {
+            c.pq = tot;
+            if (!isfinite(tot)) {
+                c.status = LG_ERR_NONFINITE;
+                c.active = 0;
+            } else if (tot <= 0.0) {
+                c.status = LG_ERR_BREAKDOWN;
+                c.active = 0;
+            } else {
+                c.alpha = c.rz / tot;
+                if (a.pring > 1) a.ahist[(size_t)field * a.pring + *a.giter % a.pring] = c.alpha;
+            }
+        }
+        if (!isfinite(tot) || tot <= 0.0) return;
+        alpha_pq = c.rz / tot;
     }
     // held directions: the solve's iteration count (the update of iteration
     // g reads p_g; the correction after it, with g + 1 counted, reads p_g and
@@ -417,7 +480,7 @@ dst_kernel(DstArgs<T> a) {
                 }
             } else if (init == 0) {
                 X = wave_uniform(a.xslot[0]);
-                alpha = a.ctl[field].alpha;
+                alpha = MODE == DST_UPDATE_PQ ? alpha_pq : a.ctl[field].alpha;
                 fresh = a.ctl[field].fresh != 0;                     // uniform per block
                 if (fresh) B0 = wave_uniform(a.xslot[1]);
             }
@@ -435,7 +498,8 @@ dst_kernel(DstArgs<T> a) {
             const rsrc_t rRs = buf_rsrc(a.r + fbase, init == 0 ? nfe * 8u : 0u);
             const size_t pofs = (init == 0 && a.pring > 1) ? (size_t)(kit % a.pring) * a.pslot : 0;
             const rsrc_t rP = buf_rsrc(a.p + pofs + fbase, init == 0 ? nfe * SZ : 0u);
-            const rsrc_t rQ = buf_rsrc(a.q + fbase, (init == 0 && MODE == DST_UPDATE) ? nfe * SZ : 0u);
+            const rsrc_t rQ =
+                buf_rsrc(a.q + fbase, (init == 0 && (MODE == DST_UPDATE || MODE == DST_UPDATE_PQ)) ? nfe * SZ : 0u);
 #pragma unroll
             for (int cb = 0; cb < NIT; cb += CH) {
                 // loads of a chunk first (memory-level parallelism), then update
@@ -1034,34 +1098,6 @@ struct FinArgs {
     int* giter;       // pring > 1: [0] the solve's iteration count g, [1] iterations added into x
 };
 
-// Each thread of the one block per field loads FIN_UNROLL partials (strided
-// by the block size) before adding them, so a pass costs one memory latency.
-// The block size follows the partial count (a large block only where there
-// are many partials: launching one costs more), so the order of the
-// additions depends on the partial count alone.
-constexpr int FIN_UNROLL = 8;
-constexpr int FIN_SMALL = 256, FIN_LARGE = 1024;
-constexpr int FIN_SMALL_MAX = FIN_UNROLL * FIN_SMALL;     // partials one pass of the small block covers
-
-template <int NT>
-__device__ __forceinline__ double fin_sum(const double* __restrict__ part, int n, double* red) {
-    double s = 0.0;
-    for (int i0 = threadIdx.x; i0 < n; i0 += FIN_UNROLL * NT) {
-        double v[FIN_UNROLL];
-#pragma unroll
-        for (int u = 0; u < FIN_UNROLL; ++u) {
-            const int i = i0 + u * NT;
-            v[u] = i < n ? part[i] : 0.0;
-        }
-#pragma unroll
-        for (int w = FIN_UNROLL / 2; w > 0; w /= 2)
-#pragma unroll
-            for (int u = 0; u < w; ++u) v[u] += v[u + w];
-        s += v[0];
-    }
-    return block_sum(s, red);
-}
-
 template <int NT>
 __global__ __launch_bounds__(NT) void finalize_kernel(FinArgs a) {
     __shared__ double red[NT / 64];
@@ -1432,6 +1468,18 @@ __global__ __launch_bounds__(256) void traces_kernel(const double* __restrict__ 
 // ===========================================================================
 // launchers
 // ===========================================================================
+// Blocks per field of the row-transform kernels with one row pair per 256
+// threads (the FP32 update with A p recomputed takes two pairs per block, so
+// fewer): the partial buffer's stride and the stored-q update's grid.
+int dst_blocks_per_field(int nx, int nz1, int ws) {
+    const int M = dst_half_form(nx, ws) ? nx : 2 * nx;   // FFT length of the row transform
+    const int R = M >= 16 ? 16 : M;
+    const int TPF = M / R;
+    const int FPB = TPF >= 256 ? 1 : 256 / TPF;
+    const int npairs = (nz1 + 1) / 2;
+    return (npairs + FPB - 1) / FPB;
+}
+
 namespace {
 
 hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int max_iter, double scale,
@@ -1458,6 +1506,17 @@ hipError_t finalize(lg_plan* p, int kind, int nparts, int init, double tol2, int
     return hipGetLastError();
 }
 
+// The stored-q update sums the operator's (p, A p) partials itself
+// (DST_UPDATE_PQ) where a field has at most FIN_SMALL_MAX of them and the
+// update's blocks re-read at most 32 MB of them in all: a finalize launch
+// less per iteration for small batches, where launch latency sets the time.
+bool fold_pq(const lg_plan* p) {
+    if (p->cyl || p->order != 2 || p->fuse_op) return false;
+    const size_t np = (size_t)((p->nx1 + 63) / 64) * ((p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT));
+    const size_t bpf = (size_t)dst_blocks_per_field(p->g.nx, p->nz1, (int)wsize(p));
+    return np <= (size_t)FIN_SMALL_MAX && (size_t)p->S * p->C * bpf * np * 8 <= ((size_t)32 << 20);
+}
+
 template <typename T>
 hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     // y == nullptr with reduce: only the (p, A p) partials (the update kernel
@@ -1477,7 +1536,8 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     a.pslot = p->nvec;
     a.giter = p->giter;
     a.free_top = p->free_top ? 1 : 0;
-    a.partial = p->partial;
+    const bool fold = reduce && fold_pq(p);      // the update sums these partials itself
+    a.partial = fold ? p->partial_pq : p->partial;
     a.pstride = p->partial_stride;
     a.nfields = p->S * p->C;
     a.nsh = std::min(a.nfields, p->op_shots);
@@ -1486,7 +1546,7 @@ hipError_t stencil_T(lg_plan* p, const T* x, T* y, bool reduce) {
     const dim3 grid(a.gx * a.gy * ((a.nfields + a.nsh - 1) / a.nsh));
     hipLaunchKernelGGL((stencil_kernel<T, false>), grid, dim3(256), 0, p->stream, a);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !reduce) return e;
+    if (e != hipSuccess || !reduce || fold) return e;
     return finalize(p, FIN_PQ, a.gx * a.gy, 0, 0.0, 0, 0.0);
 }
 
@@ -1572,6 +1632,9 @@ DstArgs<T> dst_args(lg_plan* p) {
     a.q = (const T*)p->qv;
     a.partial = p->partial;
     a.pstride = p->partial_stride;
+    a.pqpart = p->partial_pq;
+    a.ahist = p->ahist;
+    a.pq_nparts = ((p->nx1 + 63) / 64) * ((p->nz1 + 4 * ST_RPT - 1) / (4 * ST_RPT));   // operator blocks per field
     a.y = (const T*)p->y;
     a.kap = (const T*)p->kap;
     a.wsh = (const T*)p->w;
@@ -1750,6 +1813,8 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
             e = dst_dispatch<double, DST_RESTART>(p, a, p->S * p->C);
         else if (p->fuse_op && init == 0)
             e = dst_dispatch<double, DST_UPDATE_OP>(p, a, p->S * p->C);
+        else if (init == 0 && fold_pq(p))
+            e = dst_dispatch<double, DST_UPDATE_PQ>(p, a, p->S * p->C);
         else
             e = dst_dispatch<double, DST_UPDATE>(p, a, p->S * p->C);
         bpf = a.bpf;
@@ -1765,6 +1830,8 @@ hipError_t launch_update_fdst(lg_plan* p, int init, const double* b, double* x, 
             e = dst_dispatch<float, DST_RESTART>(p, a, p->S * p->C);
         else if (p->fuse_op && init == 0)
             e = dst_dispatch<float, DST_UPDATE_OP>(p, a, p->S * p->C);
+        else if (init == 0 && fold_pq(p))
+            e = dst_dispatch<float, DST_UPDATE_PQ>(p, a, p->S * p->C);
         else
             e = dst_dispatch<float, DST_UPDATE>(p, a, p->S * p->C);
         bpf = a.bpf;

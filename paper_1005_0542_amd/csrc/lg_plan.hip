@@ -431,7 +431,7 @@ void free_plan(lg_plan* p) {
     if (!p) return;
     pcg_release(p);
     void* ptrs[] = {p->kap, p->lam, p->mu, p->w, p->rho64, p->kap64, p->w64, p->tw, p->src_dev, p->r, p->p, p->qv,
-                    p->rhat, p->y, p->E, p->partial, p->ctl, p->xslot, p->ahist, p->giter, p->gm_V,
+                    p->rhat, p->y, p->E, p->partial, p->partial_pq, p->ctl, p->xslot, p->ahist, p->giter, p->gm_V,
                     p->gm_w, p->gm_z, p->gm_x, p->gm_dots, p->blk[0].etab, p->blk[0].utab,
                     p->blk[0].red, p->blk[1].etab, p->blk[1].utab, p->blk[1].red, p->sm_g, p->sm_t,
                     p->sm_c, p->cy_a1, p->cy_a2, p->cy_ctw, p->cy_cp, p->cy_invden, p->cy_lowr, p->cy_a1_64, p->cy_a2_64,
@@ -445,15 +445,6 @@ void free_plan(lg_plan* p) {
         if (e) (void)hipEventDestroy(e);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     delete p;
-}
-
-int dst_blocks_per_field(int nx, int nz1, int ws) {
-    const int M = dst_half_form(nx, ws) ? nx : 2 * nx;   // FFT length of the row transform
-    const int R = M >= 16 ? 16 : M;
-    const int TPF = M / R;
-    const int FPB = TPF >= 256 ? 1 : 256 / TPF;
-    const int npairs = (nz1 + 1) / 2;
-    return (npairs + FPB - 1) / FPB;
 }
 
 lg_status check_vec(const void* p, const char* name) {
@@ -818,6 +809,7 @@ lg_status lg_plan_create(lg_plan** out, lg_kind kind, const lg_grid* grid, const
         p->partial_stride = std::max(sb, std::max(2 * db, rb));
     }
     if ((st = dev_alloc(p, &p->partial, (size_t)SC * p->partial_stride * 8)) != LG_OK) return bail(st);
+    if ((st = dev_alloc(p, &p->partial_pq, (size_t)SC * p->partial_stride * 8)) != LG_OK) return bail(st);
     if ((st = dev_alloc(p, &p->ctl, (size_t)SC * sizeof(ShotCtl))) != LG_OK) return bail(st);
     if ((he = hipMemset(p->ctl, 0, (size_t)SC * sizeof(ShotCtl))) != hipSuccess)
         return bail(hip_fail(he, "hipMemset"));
