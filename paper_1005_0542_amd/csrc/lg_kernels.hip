@@ -1589,8 +1589,14 @@ hipError_t dst_launch_M(lg_plan* pl, DstArgs<T>& a, int nfields) {
     constexpr int TPF = M / R;
     // the FP32 update with A p recomputed takes two row pairs of 256 threads
     // per block (their p halo and medium rows overlap: 1.69 -> 1.67 ms at 64
-    // shots 2048^2; four pairs, or two in the correction, measured slower)
-    constexpr int FPB = (MODE == DST_UPDATE_OP && TPF == 256 && sizeof(T) == 4) ? 2 : (TPF >= 256 ? 1 : 256 / TPF);
+    // shots 2048^2; four pairs, or two in the correction, measured slower);
+    // the FP64 N-point transforms of nx = 2048 outside the CG update take one
+    // pair of 128 threads (more blocks in flight: GMRES(10) cycle at 1024^2
+    // 1.434 -> 1.422 ms, FP64 64 shots 2048^2 78.3 -> 75.6-77.6 ms per harmonic)
+    constexpr int FPB = (MODE == DST_UPDATE_OP && TPF == 256 && sizeof(T) == 4) ? 2
+                      : ((MODE == DST_FWD || MODE == DST_INV || MODE == DST_CORRECT) && TPF == 128 && sizeof(T) == 8)
+                          ? 1
+                          : (TPF >= 256 ? 1 : 256 / TPF);
     const int npairs = (a.nz1 + 1) / 2;
     a.bpf = (npairs + FPB - 1) / FPB;
     const dim3 grid(a.bpf * nfields);
